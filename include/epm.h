@@ -1,0 +1,210 @@
+/*
+ * epm.h -- exact epipolar-guided matching on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the data-parallel hot path of Nasypanyi & Rameau,
+ * "Pixel-Accurate Epipolar Guided Matching":
+ *
+ *   1. epm_build_intervals   every image-2 keypoint's tolerance circle becomes
+ *                            the angular interval between its two tangents
+ *                            seen from the epipole (Sec. 4.1-4.2, Eq. 5-6,
+ *                            Algorithm 1 preprocessing, Sec. 4.4 special
+ *                            cases), laid out on the device sorted by angle;
+ *   2. epm_query_candidates  every image-1 keypoint's epipolar line
+ *                            l = F (x, y, 1)^T (Eq. 2) stabs those intervals
+ *                            with its angle (Eq. 7, mod pi); each retrieved
+ *                            candidate is confirmed by the FP64 point-line
+ *                            test of Eq. 3, so the output is exactly the set
+ *                            of Eq. 4, as CSR;
+ *   3. epm_match             nearest-neighbour descriptor selection over each
+ *                            candidate set, with an optional Lowe ratio test
+ *                            (Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller (for
+ *    instance the data_ptr() of a torch tensor).  The library never
+ *    allocates device memory: all of its scratch lives in the caller's
+ *    workspace (see epm_workspace_bytes).  Host-side bookkeeping lives in the
+ *    opaque epm_index, released with epm_index_destroy.
+ *  - `pairs` is a HOST array.  A batch of image pairs is concatenated along
+ *    the keypoint axis: pair p owns image-1 rows [q_begin, q_begin + m) of
+ *    kp1/desc1 and image-2 rows [k_begin, k_begin + n) of kp2/eps2/desc2.
+ *    Slices must be in increasing order, contiguous and non-overlapping,
+ *    starting at 0 (q_begin[0] = k_begin[0] = 0).
+ *  - Keypoints are FP32 pixel coordinates (x, y), row-major [N][2], used as
+ *    given (no half-pixel shift); keypoints outside the image are legal.
+ *  - Work is enqueued on `stream` (0 = the null stream) and runs
+ *    asynchronously, except where a call documents a host synchronisation.
+ *  - Every call returns an epm_status and never throws.  Arguments are
+ *    validated on the host before anything is launched; a failed validation
+ *    launches nothing.
+ *  - Column indices in the CSR are local to their pair (0 <= j < n_p).
+ *  - Limits: num_pairs <= 65535; every m, n < 2^31; the batch totals of m and
+ *    of n are each < 2^32.
+ */
+#ifndef EPM_H
+#define EPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EPM_OK = 0,
+  EPM_ERR_ARG = 1,            /* null pointer, bad size or layout, bad option     */
+  EPM_ERR_DEGENERATE_F = 2,   /* F non-finite, zero, or of rank <= 1: no epipole  */
+  EPM_ERR_CAPACITY = 3,       /* col_indices too small; *nnz_host = required size */
+  EPM_ERR_WORKSPACE = 4,      /* workspace too small or misaligned                */
+  EPM_ERR_HIP = 5,            /* a HIP runtime call or kernel launch failed       */
+  EPM_ERR_UNSUPPORTED = 6     /* valid request this build does not implement      */
+} epm_status;
+
+typedef enum {
+  EPM_F32 = 0,       /* 128 x float32 per descriptor                              */
+  EPM_BF16 = 1,      /* 128 x bfloat16 (uint16 bit patterns)                      */
+  EPM_FP8_E4M3 = 2,  /* 128 x OCP float8 e4m3fn codes + one float32 scale per row */
+  EPM_BIN256 = 3     /* 256-bit binary descriptor, 8 x uint32 per row             */
+} epm_dtype;
+
+/* Matching algorithm, passed in epm_match_opts.algo. */
+typedef enum {
+  EPM_ALGO_AUTO = 0,   /* tiled path for float types, gather path for binary       */
+  EPM_ALGO_PLAIN = 1,  /* one wavefront per query, per-candidate descriptor gathers */
+  EPM_ALGO_TILED = 2   /* angle-sorted query tiles against LDS-staged windows      */
+} epm_algo;
+
+/* One image pair, in host memory; an array of these is a batch. */
+typedef struct {
+  double F[9];        /* row-major F12: l2 = F (x1, y1, 1)^T, x2^T F x1 = 0 (Eq. 1-2) */
+  int32_t w2, h2;     /* image-2 size in pixels: used for numerical normalisation only */
+  int64_t q_begin, m; /* this pair's slice of the image-1 arrays                       */
+  int64_t k_begin, n; /* this pair's slice of the image-2 arrays                       */
+} epm_pair;
+
+typedef struct epm_index epm_index;
+
+/*
+ * Device workspace needed to build an index over `pairs` and to run
+ * epm_query_candidates / epm_match on it (bytes; the base must be 256-byte
+ * aligned).  Returns 0 if `pairs` is invalid.
+ */
+size_t epm_workspace_bytes(const epm_pair* pairs, int32_t num_pairs);
+
+/*
+ * Preprocessing of Algorithm 1 (Sec. 4.2, Eq. 5-6; Sec. 4.4).
+ *
+ * kp2_xy    [N2][2] float32, N2 = sum of n over the batch.
+ * eps2      [N2] float32 tolerance in pixels per image-2 keypoint, or NULL to
+ *           use eps_scalar for every keypoint.  A tolerance that is not a
+ *           positive finite number is accepted and handled exactly like the
+ *           definition (such keypoints are simply always tested).
+ * workspace device buffer of at least epm_workspace_bytes(pairs, num_pairs)
+ *           bytes; it must stay alive and untouched while the index is used.
+ * out       receives a new index (host object); release with
+ *           epm_index_destroy.  On error *out is left NULL.
+ *
+ * Errors: EPM_ERR_ARG (null pointers, bad slices, eps_scalar not positive
+ * finite when eps2 is NULL), EPM_ERR_DEGENERATE_F (pair without a finite or
+ * infinite epipole: F non-finite, zero, or rank <= 1), EPM_ERR_WORKSPACE,
+ * EPM_ERR_HIP.  The caller's kp2/eps2 buffers are only read while the work
+ * enqueued here runs.
+ */
+epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
+                               const float* eps2, float eps_scalar, void* workspace,
+                               size_t workspace_bytes, epm_index** out, hipStream_t stream);
+
+/*
+ * Matching loop of Algorithm 1, candidate half (Sec. 4.2, Eq. 2-4, 7).
+ *
+ * kp1_xy       [N1][2] float32, N1 = sum of m over the batch.
+ * row_offsets  [N1 + 1] int64 output: query i's candidates are
+ *              col_indices[row_offsets[i] .. row_offsets[i+1]), ascending j.
+ * col_indices  [capacity] int32 output, image-2 index local to the pair.
+ * nnz_host     host pointer receiving the total number of candidates.
+ *
+ * The result is exactly { j : |a x_j + b y_j + c| <= eps_j sqrt(a^2 + b^2) }
+ * evaluated in FP64 with a = (F0 x + F1 y) + F2, b, c alike (no FMA
+ * contraction) -- Eq. 3-4 multiplied through by the positive denominator,
+ * closed boundary.  A query whose line has a = b = 0 gets an empty row.
+ *
+ * Synchronises the host with `stream` once (to read nnz).  If the total
+ * exceeds `capacity`, returns EPM_ERR_CAPACITY with *nnz_host set to the
+ * required size and writes nothing at or beyond col_indices[capacity];
+ * row_offsets is complete, and a retry with a larger buffer is valid.
+ */
+epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                                hipStream_t stream);
+
+typedef struct {
+  epm_algo algo;   /* EPM_ALGO_AUTO by default                                   */
+  int32_t tile_q;  /* tiled path: queries per tile (16, 32 or 64; 0 = default)   */
+  int32_t window;  /* tiled path: LDS window chunk in records (0 = default)      */
+  int32_t reserved[5];
+} epm_match_opts;
+
+/*
+ * Descriptor half of the matching loop (Sec. 4.3): for each query the
+ * nearest candidate and the second-nearest distance.
+ *
+ * row_offsets/col_indices  the CSR written by epm_query_candidates for idx.
+ * dtype, dim   EPM_F32/EPM_BF16/EPM_FP8_E4M3 with dim = 128, or EPM_BIN256
+ *              with dim = 256 (bits).
+ * desc1, desc2 [N1][..] / [N2][..] rows in the stored format.
+ * scale1/2     FP8 per-row float32 scales (dequantised value = code * scale);
+ *              NULL for other types.
+ * desc1_f32/desc2_f32  float32 masters [N1][128] / [N2][128]; required for
+ *              BF16/FP8 (final ranking is done on them), ignored otherwise.
+ * ratio        0 = off; else Lowe's tau: accept iff best < (tau*tau) * second
+ *              (float, FP32 arithmetic) or best < tau * second (binary).
+ * best_idx     [N1] int32: local image-2 index, or -1 (empty row / rejected).
+ * best_dist, second_dist  [N1] float32: squared L2 (canonical FP32 order:
+ *              t = a_k - b_k, acc = fmaf(t, t, acc), k ascending) for float
+ *              types, Hamming count for binary; +inf where absent.
+ *              Ties are broken by the lower image-2 index.
+ * opts         may be NULL (defaults).
+ *
+ * Errors: EPM_ERR_ARG, EPM_ERR_HIP.  Asynchronous.
+ */
+epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
+                     const int32_t* col_indices, epm_dtype dtype, int32_t dim,
+                     const void* desc1, const void* desc2, const float* scale1,
+                     const float* scale2, const float* desc1_f32, const float* desc2_f32,
+                     float ratio, int32_t* best_idx, float* best_dist, float* second_dist,
+                     const epm_match_opts* opts, hipStream_t stream);
+
+/*
+ * The two sides of the point-line test of Eq. 3 (multiplied through by the
+ * denominator) for listed (query, keypoint) pairs, exactly as the candidate
+ * search evaluates them on the device:
+ *   num[t] = |a x_j + b y_j + c|,  rhs[t] = eps_j * sqrt(a*a + b*b),
+ * with (a, b, c) = F (x_i, y_i, 1)^T as in epm_query_candidates.
+ * F is a host array [9]; kp1/kp2/eps2/qi/kj/num/rhs are device arrays
+ * (qi, kj index kp1 and kp2 directly); eps2 may be NULL (eps_scalar used).
+ * A diagnostic for checking the FP64 arithmetic of the device against a
+ * reference; it is not needed by the matching path.  Asynchronous.
+ */
+epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
+                                const float* eps2, float eps_scalar, const int64_t* qi,
+                                const int64_t* kj, int64_t count, double* num, double* rhs,
+                                hipStream_t stream);
+
+/* Releases the host object; the device workspace stays owned by the caller. */
+void epm_index_destroy(epm_index* idx);
+
+/* Static, never NULL. */
+const char* epm_status_string(epm_status s);
+
+/* Library version string, static. */
+const char* epm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPM_H */

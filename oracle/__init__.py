@@ -70,6 +70,8 @@ class OracleLib:
         lib.oracle_desc_dist_f64_pairs.argtypes = [P, P, ctypes.c_int, P, P, i64, P]
         lib.oracle_desc_dist_f64_pairs.restype = None
         lib.oracle_default_threads.restype = ctypes.c_int
+        lib.oracle_candidate_terms.argtypes = [P, P, P, P, ctypes.c_float, P, P, i64, P, P]
+        lib.oracle_candidate_terms.restype = None
         self.lib = lib
         self.path = path
 
@@ -118,6 +120,24 @@ class OracleLib:
         self.lib.oracle_point_line_dist(_ptr(F), _ptr(kp1), _ptr(kp2), _ptr(qi), _ptr(kj),
                                         len(qi), _ptr(out))
         return out
+
+    def candidate_terms(self, F, kp1, kp2, eps, qi, kj):
+        """Both sides of the Eq. 3 comparison, (|a x + b y + c|, eps sqrt(a^2+b^2)),
+        for listed (i, j) pairs; j is a candidate of i iff num <= rhs."""
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(9)
+        kp1 = np.ascontiguousarray(kp1, dtype=np.float32)
+        kp2 = np.ascontiguousarray(kp2, dtype=np.float32)
+        if np.ndim(eps) == 0:
+            e_arr, e_s = None, float(np.float32(eps))
+        else:
+            e_arr, e_s = np.ascontiguousarray(eps, dtype=np.float32), 0.0
+        qi = np.ascontiguousarray(qi, dtype=np.int64)
+        kj = np.ascontiguousarray(kj, dtype=np.int64)
+        num = np.zeros(len(qi), np.float64)
+        rhs = np.zeros(len(qi), np.float64)
+        self.lib.oracle_candidate_terms(_ptr(F), _ptr(kp1), _ptr(kp2), _ptr(e_arr), e_s,
+                                        _ptr(qi), _ptr(kj), len(qi), _ptr(num), _ptr(rhs))
+        return num, rhs
 
     def match(self, desc1, desc2, row_offsets, col_indices, ratio=0.0, binary=False,
               col_base=None, row_base1=None, nthreads=0):
@@ -204,6 +224,10 @@ def point_line_dist(*a, **k):
 
 def match(*a, **k):
     return _lib().match(*a, **k)
+
+
+def candidate_terms(*a, **k):
+    return _lib().candidate_terms(*a, **k)
 
 
 def desc_dist_f32(*a, **k):

@@ -192,6 +192,20 @@ void oracle_point_line_dist(const double F[9], const float* kp1, const float* kp
     }
 }
 
+/* Both sides of the Eq. 3 comparison for listed (i, j) pairs. */
+void oracle_candidate_terms(const double F[9], const float* kp1, const float* kp2,
+                            const float* eps2, float eps_scalar, const int64_t* qi,
+                            const int64_t* kj, int64_t count, double* num, double* rhs) {
+    for (int64_t t = 0; t < count; ++t) {
+        double a, b, c;
+        int64_t i = qi[t], j = kj[t];
+        double eps = (double)(eps2 ? eps2[j] : eps_scalar);
+        epipolar_line(F, (double)kp1[2 * i], (double)kp1[2 * i + 1], &a, &b, &c);
+        num[t] = fabs(a * (double)kp2[2 * j] + b * (double)kp2[2 * j + 1] + c);
+        rhs[t] = eps * sqrt(a * a + b * b);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Descriptor distances.                                               */
 

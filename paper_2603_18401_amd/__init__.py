@@ -1,0 +1,240 @@
+"""Python binding of libepm: exact epipolar-guided matching on MI355X.
+
+Argument marshalling only.  Every step of the matching path runs in the HIP
+kernels of libepm.so (built in-tree by paper_2603_18401_amd.build); torch is
+used for device memory and streams.  Importing this package does not load the
+library; the first call does, and fails loudly if it has not been built or if
+no GPU is present -- there is no CPU fallback.
+
+The three entry points mirror include/epm.h:
+
+    idx = Index(pairs, kp2, eps2=None, eps=2.0)      # epm_build_intervals
+    offs, cols = idx.query(kp1)                       # epm_query_candidates
+    best, d1, d2 = idx.match(offs, cols, desc1, desc2)  # epm_match
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["EpmError", "Index", "PairSpec", "load_library", "library_path", "point_line_terms",
+           "DTYPES", "ALGOS"]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libepm.so")
+_lib = None
+
+STATUS = {0: "EPM_OK", 1: "EPM_ERR_ARG", 2: "EPM_ERR_DEGENERATE_F", 3: "EPM_ERR_CAPACITY",
+          4: "EPM_ERR_WORKSPACE", 5: "EPM_ERR_HIP", 6: "EPM_ERR_UNSUPPORTED"}
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "bin256": 3}
+ALGOS = {"auto": 0, "plain": 1, "tiled": 2}
+EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates", "epm_match",
+           "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms"]
+
+
+class EpmError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{what}: {self.name}" if what else self.name)
+
+
+class _Pair(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double * 9), ("w2", ctypes.c_int32), ("h2", ctypes.c_int32),
+                ("q_begin", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("k_begin", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
+class _MatchOpts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("tile_q", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library(path=None):
+    """Loads libepm.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: run `python -m paper_2603_18401_amd.build`")
+    lib = ctypes.CDLL(p)
+    V, P, i64, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.epm_workspace_bytes.argtypes = [P, i32]
+    lib.epm_workspace_bytes.restype = ctypes.c_size_t
+    lib.epm_build_intervals.argtypes = [P, i32, V, V, ctypes.c_float, V, ctypes.c_size_t,
+                                        ctypes.POINTER(V), V]
+    lib.epm_build_intervals.restype = ctypes.c_int
+    lib.epm_query_candidates.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V]
+    lib.epm_query_candidates.restype = ctypes.c_int
+    lib.epm_match.argtypes = [V, V, V, ctypes.c_int, i32, V, V, V, V, V, V, ctypes.c_float,
+                              V, V, V, P, V]
+    lib.epm_match.restype = ctypes.c_int
+    lib.epm_index_destroy.argtypes = [V]
+    lib.epm_index_destroy.restype = None
+    lib.epm_status_string.argtypes = [ctypes.c_int]
+    lib.epm_status_string.restype = ctypes.c_char_p
+    lib.epm_version.restype = ctypes.c_char_p
+    lib.epm_point_line_terms.argtypes = [P, V, V, V, ctypes.c_float, V, V, i64, V, V, V]
+    lib.epm_point_line_terms.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libepm needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(torch, device, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(st, what):
+    if st != 0:
+        raise EpmError(st, what)
+
+
+class PairSpec:
+    """One image pair: F (3x3, row-major), image-2 size, keypoint counts."""
+
+    def __init__(self, F, w2, h2, m, n):
+        self.F = np.asarray(F, dtype=np.float64).reshape(9)
+        self.w2, self.h2, self.m, self.n = int(w2), int(h2), int(m), int(n)
+
+
+def _pair_array(specs):
+    arr = (_Pair * len(specs))()
+    q = k = 0
+    for a, s in zip(arr, specs):
+        a.F[:] = [float(v) for v in s.F]
+        a.w2, a.h2 = s.w2, s.h2
+        a.q_begin, a.m, a.k_begin, a.n = q, s.m, k, s.n
+        q += s.m
+        k += s.n
+    return arr, q, k
+
+
+class Index:
+    """epm_build_intervals over a batch of pairs; owns its device workspace."""
+
+    def __init__(self, pairs, kp2, eps2=None, eps=0.0, stream=None, workspace=None):
+        torch = _torch()
+        self._torch = torch
+        self.lib = load_library()
+        self.device = kp2.device
+        self.specs = list(pairs)
+        self._pairs, self.n1, self.n2 = _pair_array(self.specs)
+        if tuple(kp2.shape) != (self.n2, 2) or kp2.dtype != torch.float32 or not kp2.is_contiguous():
+            raise ValueError("kp2 must be a contiguous float32 [N2, 2] device tensor")
+        if eps2 is not None and (tuple(eps2.shape) != (self.n2,) or eps2.dtype != torch.float32):
+            raise ValueError("eps2 must be a float32 [N2] device tensor")
+        nbytes = self.lib.epm_workspace_bytes(self._pairs, len(self.specs))
+        if nbytes == 0:
+            raise EpmError(1, "epm_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        self._keep = (kp2, eps2)
+        h = ctypes.c_void_p()
+        st = self.lib.epm_build_intervals(self._pairs, len(self.specs), _dptr(kp2), _dptr(eps2),
+                                          float(eps), _dptr(workspace), workspace.numel(),
+                                          ctypes.byref(h), _stream(torch, self.device, stream))
+        _check(st, "epm_build_intervals")
+        self.handle = h
+        self.stream = stream
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.epm_index_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, kp1, capacity=None, row_offsets=None, col_indices=None, sync=True):
+        """Candidate CSR (row_offsets int64 [N1+1], col_indices int32 [nnz]).
+
+        capacity: initial guess for nnz (grown and retried on EPM_ERR_CAPACITY).
+        sync=False with preallocated row_offsets/col_indices skips the host
+        synchronisation (the caller guarantees the capacity)."""
+        torch = self._torch
+        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
+            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
+        if row_offsets is None:
+            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=self.device)
+        if col_indices is None:
+            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
+            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        st_ptr = _stream(torch, self.device, self.stream)
+        if not sync:
+            st = self.lib.epm_query_candidates(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                               _dptr(col_indices), col_indices.numel(), None,
+                                               st_ptr)
+            _check(st, "epm_query_candidates")
+            return row_offsets, col_indices
+        nnz = ctypes.c_int64(0)
+        st = self.lib.epm_query_candidates(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                           _dptr(col_indices), col_indices.numel(),
+                                           ctypes.byref(nnz), st_ptr)
+        if st == 3:
+            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=self.device)
+            st = self.lib.epm_query_candidates(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                               _dptr(col_indices), col_indices.numel(),
+                                               ctypes.byref(nnz), st_ptr)
+        _check(st, "epm_query_candidates")
+        return row_offsets, col_indices[: nnz.value]
+
+    def match(self, row_offsets, col_indices, desc1, desc2, dtype="f32", scale1=None,
+              scale2=None, desc1_f32=None, desc2_f32=None, ratio=0.0, algo="auto", tile_q=0,
+              window=0, out=None):
+        """Nearest neighbour per query: (best_idx int32, best_dist f32, second_dist f32)."""
+        torch = self._torch
+        dim = 256 if dtype == "bin256" else 128
+        if out is None:
+            best = torch.empty(self.n1, dtype=torch.int32, device=self.device)
+            bd = torch.empty(self.n1, dtype=torch.float32, device=self.device)
+            sd = torch.empty(self.n1, dtype=torch.float32, device=self.device)
+        else:
+            best, bd, sd = out
+        opts = _MatchOpts()
+        opts.algo = ALGOS[algo]
+        opts.tile_q = int(tile_q)
+        opts.window = int(window)
+        st = self.lib.epm_match(self.handle, _dptr(row_offsets), _dptr(col_indices), DTYPES[dtype],
+                                dim, _dptr(desc1), _dptr(desc2), _dptr(scale1), _dptr(scale2),
+                                _dptr(desc1_f32), _dptr(desc2_f32), float(ratio), _dptr(best),
+                                _dptr(bd), _dptr(sd), ctypes.byref(opts),
+                                _stream(torch, self.device, self.stream))
+        _check(st, "epm_match")
+        return best, bd, sd
+
+
+def point_line_terms(F, kp1, kp2, qi, kj, eps2=None, eps=0.0, stream=None):
+    """Device values of both sides of the Eq. 3 test for listed pairs."""
+    torch = _torch()
+    lib = load_library()
+    Fh = (ctypes.c_double * 9)(*[float(v) for v in np.asarray(F, np.float64).reshape(9)])
+    num = torch.empty(qi.numel(), dtype=torch.float64, device=kp1.device)
+    rhs = torch.empty(qi.numel(), dtype=torch.float64, device=kp1.device)
+    st = lib.epm_point_line_terms(Fh, _dptr(kp1), _dptr(kp2), _dptr(eps2), float(eps),
+                                  _dptr(qi), _dptr(kj), qi.numel(), _dptr(num), _dptr(rhs),
+                                  _stream(torch, kp1.device, stream))
+    _check(st, "epm_point_line_terms")
+    return num, rhs

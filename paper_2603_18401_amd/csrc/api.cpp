@@ -1,0 +1,470 @@
+// C ABI of libepm: argument validation, FP64 per-pair setup, workspace
+// carving and kernel enqueue.  See include/epm.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "epm.h"
+#include "epm_internal.h"
+#include "launch.h"
+
+using namespace epm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Offsets of every device buffer inside the caller's workspace.
+struct Layout {
+  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, hist;
+  size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
+  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials;
+  size_t total;
+};
+
+Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  const size_t N1 = (size_t)n1, N2 = (size_t)n2;
+  L.pairs = take(sizeof(PairDev) * P);
+  L.qstart = take(sizeof(int64_t) * (P + 1));
+  L.kstart = take(sizeof(int64_t) * (P + 1));
+  L.rtiles = take(sizeof(SortTile) * tr);
+  L.rsegs = take(sizeof(SortSeg) * P);
+  L.qtiles = take(sizeof(SortTile) * tq);
+  L.qsegs = take(sizeof(SortSeg) * P);
+  L.hist = take(sizeof(uint32_t) * 256 * (size_t)(tr > tq ? tr : tq));
+  L.rk0 = take(4 * N2);
+  L.rv0 = take(4 * N2);
+  L.rk1 = take(4 * N2);
+  L.rv1 = take(4 * N2);
+  L.recC = take(4 * N2);
+  L.recH = take(4 * N2);
+  L.rC = take(4 * N2);
+  L.rH = take(4 * N2);
+  L.rj = take(4 * N2);
+  L.rxy = take(8 * N2);
+  L.reps = take(4 * N2);
+  L.rinv = take(4 * N2);
+  L.class_begin = take(sizeof(int64_t) * kClassSlots * P);
+  L.qkey = take(4 * N1);
+  L.qflag = take(4 * N1);
+  L.qk0 = take(4 * N1);
+  L.qv0 = take(4 * N1);
+  L.qk1 = take(4 * N1);
+  L.qv1 = take(4 * N1);
+  L.counts = take(4 * N1);
+  L.partials = take(sizeof(int64_t) * (size_t)scan_partials_count(n1));
+  L.total = off;
+  return L;
+}
+
+int64_t tiles_of(int64_t count) { return (count + kSortTile - 1) / kSortTile; }
+
+bool validate_pairs(const epm_pair* pairs, int32_t num_pairs, int64_t* n1, int64_t* n2) {
+  if (!pairs || num_pairs < 1 || num_pairs > 65535) return false;
+  int64_t q = 0, k = 0;
+  for (int p = 0; p < num_pairs; ++p) {
+    const epm_pair& e = pairs[p];
+    if (e.m < 0 || e.n < 0 || e.m >= (int64_t(1) << 31) || e.n >= (int64_t(1) << 31)) return false;
+    if (e.q_begin != q || e.k_begin != k) return false;
+    if (e.w2 <= 0 || e.h2 <= 0) return false;
+    q += e.m;
+    k += e.n;
+  }
+  if (q >= (int64_t(1) << 32) || k >= (int64_t(1) << 32)) return false;
+  *n1 = q;
+  *n2 = k;
+  return true;
+}
+
+void cross3(const double* a, const double* b, double* r) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+double norm3(const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// FP64 setup of one pair: image-2 normalisation, epipole e2 = null(F^T)
+// (Algorithm 1, preprocessing) as a unit vector in normalised line space,
+// and an orthonormal basis (u, v) of the pencil of lines through it.
+epm_status setup_pair(const epm_pair& in, PairDev& pd) {
+  const double* F = in.F;
+  double fn = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(F[k])) return EPM_ERR_DEGENERATE_F;
+    fn += F[k] * F[k];
+  }
+  if (!(fn > 0.0) || !std::isfinite(fn)) return EPM_ERR_DEGENERATE_F;
+  std::memset(&pd, 0, sizeof(pd));
+  for (int k = 0; k < 9; ++k) pd.F[k] = F[k];
+  const double w = in.w2, h = in.h2;
+  pd.s = 2.0 / (w > h ? w : h);
+  pd.cx = 0.5 * w;
+  pd.cy = 0.5 * h;
+  // columns of N F with l^ = (a, b, s (a cx + b cy + c)), each scaled to unit
+  // length (a right scaling does not move the left null space)
+  double col[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const double a = F[k], b = F[3 + k], c = F[6 + k];
+    col[k][0] = a;
+    col[k][1] = b;
+    col[k][2] = pd.s * (a * pd.cx + b * pd.cy + c);
+    const double nk = norm3(col[k]);
+    for (int d = 0; d < 3; ++d) col[k][d] = nk > 0.0 ? col[k][d] / nk : 0.0;
+  }
+  // the left null vector is orthogonal to every column: the cross product of
+  // the best-conditioned pair of columns
+  double best[3] = {0, 0, 0}, bn = 0.0;
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int t = 0; t < 3; ++t) {
+    double cr[3];
+    cross3(col[pa[t]], col[pb[t]], cr);
+    const double cn = norm3(cr);
+    if (cn > bn) {
+      bn = cn;
+      for (int d = 0; d < 3; ++d) best[d] = cr[d];
+    }
+  }
+  if (!(bn > 1e-12)) return EPM_ERR_DEGENERATE_F;  // rank <= 1: no pencil
+  for (int d = 0; d < 3; ++d) pd.e[d] = best[d] / bn;
+  // u: e x (the axis least aligned with e), v = e x u
+  int ax = 0;
+  for (int d = 1; d < 3; ++d)
+    if (std::fabs(pd.e[d]) < std::fabs(pd.e[ax])) ax = d;
+  double axis[3] = {0, 0, 0};
+  axis[ax] = 1.0;
+  cross3(pd.e, axis, pd.u);
+  const double un = norm3(pd.u);
+  for (int d = 0; d < 3; ++d) pd.u[d] /= un;
+  cross3(pd.e, pd.u, pd.v);
+  const double vn = norm3(pd.v);
+  for (int d = 0; d < 3; ++d) pd.v[d] /= vn;
+  pd.G11 = pd.u[0] * pd.u[0] + pd.u[1] * pd.u[1];
+  pd.G12 = pd.u[0] * pd.v[0] + pd.u[1] * pd.v[1];
+  pd.G22 = pd.v[0] * pd.v[0] + pd.v[1] * pd.v[1];
+  pd.e12 = std::sqrt(pd.e[0] * pd.e[0] + pd.e[1] * pd.e[1]);
+  pd.kappa = kKappaBuild;
+  pd.q_begin = in.q_begin;
+  pd.m = in.m;
+  pd.k_begin = in.k_begin;
+  pd.n = in.n;
+  return EPM_OK;
+}
+
+void make_tiles(const std::vector<int64_t>& starts, int P, std::vector<SortTile>& tiles,
+                std::vector<SortSeg>& segs) {
+  tiles.clear();
+  segs.resize(P);
+  for (int p = 0; p < P; ++p) {
+    const int64_t b = starts[p], cnt = starts[p + 1] - starts[p];
+    segs[p].begin = b;
+    segs[p].count = cnt;
+    segs[p].tile_begin = (int32_t)tiles.size();
+    for (int64_t o = 0; o < cnt; o += kSortTile) {
+      SortTile t;
+      t.begin = b + o;
+      t.count = (int32_t)(cnt - o < kSortTile ? cnt - o : kSortTile);
+      t.seg = p;
+      tiles.push_back(t);
+    }
+    segs[p].tile_count = (int32_t)tiles.size() - segs[p].tile_begin;
+  }
+}
+
+}  // namespace
+
+struct epm_index {
+  int P = 0;
+  int64_t N1 = 0, N2 = 0;
+  std::vector<PairDev> pairs;
+  std::vector<int64_t> qstart, kstart;
+  std::vector<SortTile> rtiles, qtiles;
+  std::vector<SortSeg> rsegs, qsegs;
+  char* ws = nullptr;
+  Layout L;
+  size_t skey_off = 0;  // sorted record keys (one of the sort buffers)
+  bool have_qperm = false;
+  const uint32_t* qperm = nullptr;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+#define EPM_HIP(call)                         \
+  do {                                        \
+    if ((call) != hipSuccess) return EPM_ERR_HIP; \
+  } while (0)
+
+extern "C" {
+
+size_t epm_workspace_bytes(const epm_pair* pairs, int32_t num_pairs) {
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return 0;
+  int64_t tr = 0, tq = 0;
+  for (int p = 0; p < num_pairs; ++p) {
+    tr += tiles_of(pairs[p].n);
+    tq += tiles_of(pairs[p].m);
+  }
+  return make_layout(num_pairs, n1, n2, tr, tq).total;
+}
+
+epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
+                               const float* eps2, float eps_scalar, void* workspace,
+                               size_t workspace_bytes, epm_index** out, hipStream_t stream) {
+  if (!out) return EPM_ERR_ARG;
+  *out = nullptr;
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
+  if (n2 > 0 && !kp2_xy) return EPM_ERR_ARG;
+  if (!eps2 && !(eps_scalar > 0.0f && std::isfinite(eps_scalar))) return EPM_ERR_ARG;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1))) return EPM_ERR_WORKSPACE;
+
+  epm_index* idx = new (std::nothrow) epm_index();
+  if (!idx) return EPM_ERR_ARG;
+  idx->P = num_pairs;
+  idx->N1 = n1;
+  idx->N2 = n2;
+  idx->pairs.resize(num_pairs);
+  idx->qstart.resize(num_pairs + 1);
+  idx->kstart.resize(num_pairs + 1);
+  for (int p = 0; p < num_pairs; ++p) {
+    const epm_status st = setup_pair(pairs[p], idx->pairs[p]);
+    if (st != EPM_OK) {
+      delete idx;
+      return st;
+    }
+    idx->qstart[p] = pairs[p].q_begin;
+    idx->kstart[p] = pairs[p].k_begin;
+  }
+  idx->qstart[num_pairs] = n1;
+  idx->kstart[num_pairs] = n2;
+  make_tiles(idx->kstart, num_pairs, idx->rtiles, idx->rsegs);
+  make_tiles(idx->qstart, num_pairs, idx->qtiles, idx->qsegs);
+  for (int p = 0; p < num_pairs; ++p) {
+    PairDev& pd = idx->pairs[p];
+    pd.rtile_begin = idx->rsegs[p].tile_begin;
+    pd.rtile_count = idx->rsegs[p].tile_count;
+    pd.qtile_begin = idx->qsegs[p].tile_begin;
+    pd.qtile_count = idx->qsegs[p].tile_count;
+  }
+  idx->L = make_layout(num_pairs, n1, n2, (int64_t)idx->rtiles.size(), (int64_t)idx->qtiles.size());
+  if (workspace_bytes < idx->L.total) {
+    delete idx;
+    return EPM_ERR_WORKSPACE;
+  }
+  idx->ws = static_cast<char*>(workspace);
+  const Layout& L = idx->L;
+
+  auto fail = [&](epm_status s) {
+    delete idx;
+    return s;
+  };
+  auto h2d = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(idx->ws + off, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  if (h2d(L.pairs, idx->pairs.data(), sizeof(PairDev) * num_pairs) != hipSuccess ||
+      h2d(L.qstart, idx->qstart.data(), sizeof(int64_t) * (num_pairs + 1)) != hipSuccess ||
+      h2d(L.kstart, idx->kstart.data(), sizeof(int64_t) * (num_pairs + 1)) != hipSuccess ||
+      h2d(L.rtiles, idx->rtiles.data(), sizeof(SortTile) * idx->rtiles.size()) != hipSuccess ||
+      h2d(L.rsegs, idx->rsegs.data(), sizeof(SortSeg) * num_pairs) != hipSuccess ||
+      h2d(L.qtiles, idx->qtiles.data(), sizeof(SortTile) * idx->qtiles.size()) != hipSuccess ||
+      h2d(L.qsegs, idx->qsegs.data(), sizeof(SortSeg) * num_pairs) != hipSuccess)
+    return fail(EPM_ERR_HIP);
+
+  const PairDev* dpairs = idx->at<PairDev>(L.pairs);
+  const int64_t* dkstart = idx->at<int64_t>(L.kstart);
+  if (launch_intervals(dpairs, dkstart, num_pairs, n2, kp2_xy, eps2, eps_scalar,
+                       idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
+                       idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH), stream) != hipSuccess)
+    return fail(EPM_ERR_HIP);
+  bool in1 = false;
+  if (segmented_radix_sort(idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
+                           idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
+                           idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
+                           idx->at<SortSeg>(L.rsegs), num_pairs, idx->at<uint32_t>(L.hist),
+                           kSortBits, &in1, stream) != hipSuccess)
+    return fail(EPM_ERR_HIP);
+  const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
+  const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
+  if (launch_gather_records(dkstart, num_pairs, n2, sval, kp2_xy, eps2, eps_scalar,
+                            idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH),
+                            idx->at<uint32_t>(L.rC), idx->at<uint32_t>(L.rH),
+                            idx->at<int32_t>(L.rj), idx->at<float2>(L.rxy),
+                            idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv), stream) != hipSuccess)
+    return fail(EPM_ERR_HIP);
+  idx->skey_off = in1 ? L.rk1 : L.rk0;
+  if (launch_class_bounds(dkstart, num_pairs, skey,
+                          idx->at<int64_t>(L.class_begin), stream) != hipSuccess)
+    return fail(EPM_ERR_HIP);
+  *out = idx;
+  return EPM_OK;
+}
+
+epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                                hipStream_t stream) {
+  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
+  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  const Layout& L = idx->L;
+  const int64_t n1 = idx->N1;
+  if (n1 == 0) {
+    static const int64_t zero = 0;
+    EPM_HIP(hipMemcpyAsync(row_offsets, &zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    if (nnz_host) {
+      EPM_HIP(hipStreamSynchronize(stream));
+      *nnz_host = 0;
+    }
+    return EPM_OK;
+  }
+  const PairDev* dpairs = idx->at<PairDev>(L.pairs);
+  const int64_t* dqstart = idx->at<int64_t>(L.qstart);
+  EPM_HIP(launch_query_keys(dpairs, dqstart, idx->P, n1, kp1_xy, idx->at<uint32_t>(L.qkey),
+                            idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
+                            idx->at<uint32_t>(L.qv0), stream));
+  bool in1 = false;
+  EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
+                               idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
+                               idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
+                               idx->at<SortSeg>(L.qsegs), idx->P, idx->at<uint32_t>(L.hist), 16,
+                               &in1, stream));
+  idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
+  idx->have_qperm = true;
+
+  StabArgs A;
+  A.pairs = dpairs;
+  A.qstart = dqstart;
+  A.num_pairs = idx->P;
+  A.n1 = n1;
+  A.kp1 = kp1_xy;
+  A.qkey = idx->at<uint32_t>(L.qkey);
+  A.qflag = idx->at<uint32_t>(L.qflag);
+  A.qperm = idx->qperm;
+  A.class_begin = idx->at<int64_t>(L.class_begin);
+  A.skey = idx->at<uint32_t>(idx->skey_off);
+  A.rC = idx->at<uint32_t>(L.rC);
+  A.rH = idx->at<uint32_t>(L.rH);
+  A.rj = idx->at<int32_t>(L.rj);
+  A.rxy = idx->at<float2>(L.rxy);
+  A.reps = idx->at<float>(L.reps);
+  A.rinv = idx->at<uint32_t>(L.rinv);
+  A.counts = idx->at<uint32_t>(L.counts);
+  A.row_offsets = row_offsets;
+  A.cols = col_indices;
+  A.capacity = capacity;
+  EPM_HIP(launch_stab_count(A, stream));
+  EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
+  if (nnz_host) {
+    int64_t nnz = 0;
+    EPM_HIP(hipMemcpyAsync(&nnz, row_offsets + n1, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    EPM_HIP(hipStreamSynchronize(stream));
+    *nnz_host = nnz;
+    if (nnz > capacity) return EPM_ERR_CAPACITY;
+  }
+  EPM_HIP(launch_stab_fill(A, stream));
+  return EPM_OK;
+}
+
+epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
+                     const int32_t* col_indices, epm_dtype dtype, int32_t dim,
+                     const void* desc1, const void* desc2, const float* scale1,
+                     const float* scale2, const float* desc1_f32, const float* desc2_f32,
+                     float ratio, int32_t* best_idx, float* best_dist, float* second_dist,
+                     const epm_match_opts* opts, hipStream_t stream) {
+  (void)scale1;
+  (void)scale2;
+  (void)desc1_f32;
+  (void)desc2_f32;
+  if (!idx || !row_offsets) return EPM_ERR_ARG;
+  if (!(ratio >= 0.0f) || !std::isfinite(ratio)) return EPM_ERR_ARG;
+  const int64_t n1 = idx->N1;
+  if (n1 > 0 && (!best_idx || !best_dist || !second_dist || !desc1)) return EPM_ERR_ARG;
+  if (idx->N2 > 0 && !desc2) return EPM_ERR_ARG;
+  epm_algo algo = opts ? opts->algo : EPM_ALGO_AUTO;
+  if (algo != EPM_ALGO_AUTO && algo != EPM_ALGO_PLAIN && algo != EPM_ALGO_TILED) return EPM_ERR_ARG;
+  switch (dtype) {
+    case EPM_F32:
+    case EPM_BF16:
+    case EPM_FP8_E4M3:
+      if (dim != 128) return EPM_ERR_ARG;
+      break;
+    case EPM_BIN256:
+      if (dim != 256) return EPM_ERR_ARG;
+      break;
+    default:
+      return EPM_ERR_ARG;
+  }
+  if (n1 == 0) return EPM_OK;
+  const Layout& L = idx->L;
+  MatchArgs A;
+  A.qstart = idx->at<int64_t>(L.qstart);
+  A.kstart = idx->at<int64_t>(L.kstart);
+  A.num_pairs = idx->P;
+  A.n1 = n1;
+  A.qperm = idx->have_qperm ? idx->qperm : nullptr;
+  A.row_offsets = row_offsets;
+  A.cols = col_indices;
+  A.desc1 = desc1;
+  A.desc2 = desc2;
+  A.ratio = ratio;
+  A.best_idx = best_idx;
+  A.best_dist = best_dist;
+  A.second_dist = second_dist;
+  switch (dtype) {
+    case EPM_F32:
+      EPM_HIP(launch_match_plain_f32(A, stream));
+      return EPM_OK;
+    case EPM_BIN256:
+      EPM_HIP(launch_match_plain_bin256(A, stream));
+      return EPM_OK;
+    default:
+      return EPM_ERR_UNSUPPORTED;
+  }
+}
+
+epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
+                                const float* eps2, float eps_scalar, const int64_t* qi,
+                                const int64_t* kj, int64_t count, double* num, double* rhs,
+                                hipStream_t stream) {
+  if (count < 0 || !F) return EPM_ERR_ARG;
+  if (count == 0) return EPM_OK;
+  if (!kp1_xy || !kp2_xy || !qi || !kj || !num || !rhs) return EPM_ERR_ARG;
+  EPM_HIP(launch_point_line_terms(F, kp1_xy, kp2_xy, eps2, eps_scalar, qi, kj, count, num, rhs,
+                                  stream));
+  return EPM_OK;
+}
+
+void epm_index_destroy(epm_index* idx) { delete idx; }
+
+const char* epm_status_string(epm_status s) {
+  switch (s) {
+    case EPM_OK: return "EPM_OK";
+    case EPM_ERR_ARG: return "EPM_ERR_ARG: invalid argument";
+    case EPM_ERR_DEGENERATE_F: return "EPM_ERR_DEGENERATE_F: F has no epipole (non-finite, zero or rank <= 1)";
+    case EPM_ERR_CAPACITY: return "EPM_ERR_CAPACITY: col_indices too small";
+    case EPM_ERR_WORKSPACE: return "EPM_ERR_WORKSPACE: workspace too small or misaligned";
+    case EPM_ERR_HIP: return "EPM_ERR_HIP: HIP runtime error";
+    case EPM_ERR_UNSUPPORTED: return "EPM_ERR_UNSUPPORTED: not implemented in this build";
+  }
+  return "EPM_ERR_UNKNOWN";
+}
+
+const char* epm_version(void) { return "epm 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Device helpers shared by the libepm kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "epm_internal.h"
+
+namespace epm {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Last pair p with starts[p] <= idx (pairs own contiguous, ordered slices).
+__device__ __forceinline__ int find_pair(const int64_t* __restrict__ starts, int num_pairs,
+                                         int64_t idx) {
+  int lo = 0, hi = num_pairs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= idx) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Eq. 2: the epipolar line of (x, y), every product and sum rounded once,
+// left to right -- the same operations as the definition of the candidate set.
+__device__ __forceinline__ void epipolar_line(const double* __restrict__ F, float xf, float yf,
+                                              double& a, double& b, double& c) {
+  const double x = (double)xf, y = (double)yf;
+  a = __dadd_rn(__dadd_rn(__dmul_rn(F[0], x), __dmul_rn(F[1], y)), F[2]);
+  b = __dadd_rn(__dadd_rn(__dmul_rn(F[3], x), __dmul_rn(F[4], y)), F[5]);
+  c = __dadd_rn(__dadd_rn(__dmul_rn(F[6], x), __dmul_rn(F[7], y)), F[8]);
+}
+
+// Eq. 3-4 multiplied through by sqrt(a^2 + b^2): the only FP64 step of the
+// per-candidate path.  Closed boundary.
+__device__ __forceinline__ bool within_tolerance(double a, double b, double c, float xf,
+                                                 float yf, float ef) {
+  const double num =
+      fabs(__dadd_rn(__dadd_rn(__dmul_rn(a, (double)xf), __dmul_rn(b, (double)yf)), c));
+  const double rhs =
+      __dmul_rn((double)ef, __dsqrt_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b))));
+  return num <= rhs;
+}
+
+// Circular distance between two angle keys (mod 2^32 == mod pi).
+__device__ __forceinline__ uint32_t key_distance(uint32_t p, uint32_t c) {
+  const uint32_t d = p - c;
+  const uint32_t e = c - p;
+  return d < e ? d : e;
+}
+
+__device__ __forceinline__ int width_class(uint32_t half) {
+  const int c = 32 - __clz(half);
+  return c > kWideClass ? kWideClass : c;
+}
+
+// First index in [lo, hi) whose key is >= target (keys ascending); the whole
+// wavefront cooperates, every lane gets the result.
+__device__ __forceinline__ int64_t wave_lower_bound(const uint32_t* __restrict__ keys,
+                                                    int64_t lo, int64_t hi, uint32_t target) {
+  const int lane = lane_id();
+  while (hi - lo > kWave) {
+    const int64_t len = hi - lo;
+    // 64 probes splitting [lo, hi) into 65 parts
+    const int64_t pos = lo + (len * (lane + 1)) / (kWave + 1);
+    const bool below = keys[pos] < target;
+    const uint64_t m = ballot(below);
+    const int cnt = __popcll(m);  // probes are ascending: a prefix is below
+    const int64_t nlo = cnt == 0 ? lo : lo + (len * cnt) / (kWave + 1) + 1;
+    const int64_t nhi = cnt == kWave ? hi : lo + (len * (cnt + 1)) / (kWave + 1) + 1;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+  }
+  const int64_t pos = lo + lane;
+  const bool below = pos < hi && keys[pos] < target;
+  return lo + __popcll(ballot(below));
+}
+
+}  // namespace epm

@@ -1,0 +1,227 @@
+// Angular intervals of the image-2 tolerance circles and the angle keys of
+// the image-1 epipolar lines.
+//
+// Sec. 4.1-4.2 (Eq. 5-6): seen from the epipole, the circle of radius eps_j
+// around p_j subtends the interval of line directions between its two
+// tangents.  The kernels express line directions in a pencil basis (u, v) of
+// the lines through the epipole e (u, v, e orthonormal in normalised line
+// space), which covers a finite epipole inside or outside the image and an
+// epipole at infinity with one formula: the pencil line at angle phi is
+// l(phi) = cos(phi) u + sin(phi) v, and p_j lies within eps of it iff
+//     (w_j . c)^2 <= eps^2 c^T G c,   c = (cos phi, sin phi),
+// with w_j = (u . p~_j, v . p~_j) and G the Gram matrix of (u_12, v_12).
+// The solution set is the arc around the eigenvector of the negative
+// eigenvalue of M_j = w_j w_j^T - eps^2 G, half-width atan(sqrt(-l-/l+));
+// with an orthonormal basis of a finite epipole this is theta_j +- delta_j of
+// Eq. 5-6.  A circle containing the epipole gives a negative semidefinite
+// M_j: the full interval (Sec. 4.4).  Angles are stored mod pi as u32 keys,
+// which makes the 0/pi wrap-around implicit.
+#include "device_common.h"
+#include "launch.h"
+
+namespace epm {
+
+namespace {
+
+__device__ __forceinline__ uint32_t angle_key(double phi) {
+  // phi in [0, pi) -> round(phi * 2^32 / pi) mod 2^32
+  const double k = nearbyint(phi * kKeyPerRad);
+  const uint64_t u = (uint64_t)(int64_t)k;
+  return (uint32_t)u;
+}
+
+// Conservative interval of one keypoint: centre key and half-width key.
+__device__ void circle_interval(const PairDev& pd, float xf, float yf, float ef, uint32_t& C,
+                                uint32_t& H) {
+  const double px = pd.s * ((double)xf - pd.cx);
+  const double py = pd.s * ((double)yf - pd.cy);
+  const double w1 = pd.u[0] * px + pd.u[1] * py + pd.u[2];
+  const double w2 = pd.v[0] * px + pd.v[1] * py + pd.v[2];
+  const double ep = fabs(pd.e[0] * px + pd.e[1] * py + pd.e[2]);
+  // tolerance in normalised units, inflated by the rounding slack and by the
+  // largest line-to-epipole miss a query may have before it scans the pair
+  double epsn = pd.s * ((double)ef * (1.0 + kEpsRelSlack) + kEpsAbsSlackPx);
+  epsn += pd.kappa * (epsn * pd.e12 + ep);
+  const double e2 = epsn * epsn;
+  const double A = w1 * w1 - e2 * pd.G11;
+  const double B = w1 * w2 - e2 * pd.G12;
+  const double D = w2 * w2 - e2 * pd.G22;
+  const double detG = pd.G11 * pd.G22 - pd.G12 * pd.G12;
+  const double wadj = pd.G22 * w1 * w1 - 2.0 * pd.G12 * w1 * w2 + pd.G11 * w2 * w2;
+  const double det = e2 * (e2 * detG - wadj);  // det M without cancellation
+  if (!(det < 0.0)) {
+    // both eigenvalues <= 0: the circle holds the epipole, every line hits it
+    // (a positive definite M cannot occur; it is also treated as full)
+    C = 0;
+    H = kFullHalf;
+    return;
+  }
+  const double half = 0.5 * (A - D);
+  const double disc = sqrt(half * half + B * B);
+  const double lp = 0.5 * (A + D) + disc;  // > 0
+  const double lm = det / lp;              // < 0
+  double vx, vy;                           // eigenvector of lp
+  if (A >= D) {
+    vx = half + disc;
+    vy = B;
+  } else {
+    vx = B;
+    vy = disc - half;
+  }
+  // interval centre: the eigenvector of lm, (-vy, vx)
+  double psi = atan2(vx, -vy);
+  if (psi < 0.0) psi += M_PI;
+  if (psi >= M_PI) psi -= M_PI;
+  const double h = atan(sqrt(-lm / lp));
+  const double hk = ceil(h * kKeyPerRad) + (double)kGuard;
+  if (!(hk < (double)(kFullHalf - 2 * kGuard))) {
+    C = 0;
+    H = kFullHalf;
+    return;
+  }
+  C = angle_key(psi);
+  H = (uint32_t)hk;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_intervals(
+    const PairDev* __restrict__ pairs, const int64_t* __restrict__ kstart, int num_pairs,
+    int64_t n2, const float* __restrict__ kp2, const float* __restrict__ eps2, float eps_scalar,
+    uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val, uint32_t* __restrict__ recC,
+    uint32_t* __restrict__ recH) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  const int p = find_pair(kstart, num_pairs, r);
+  const PairDev& pd = pairs[p];
+  const float xf = kp2[2 * r], yf = kp2[2 * r + 1];
+  const float ef = eps2 ? eps2[r] : eps_scalar;
+  uint32_t C = 0, H = kFullHalf;
+  // keypoints the interval formula cannot describe are always scanned and
+  // left to the exact test
+  if (ef > 0.0f && isfinite(ef) && isfinite(xf) && isfinite(yf)) circle_interval(pd, xf, yf, ef, C, H);
+  const uint32_t cls = (uint32_t)width_class(H);
+  sort_key[r] = (cls << kCentreBits) | (C >> kCentreShift);
+  sort_val[r] = (uint32_t)r;
+  recC[r] = C;
+  recH[r] = H;
+}
+
+// Eq. 2 and Eq. 7: the angle of each query's epipolar line in the pencil,
+// reduced mod pi (an undirected line).
+__global__ __launch_bounds__(256) void k_query_keys(
+    const PairDev* __restrict__ pairs, const int64_t* __restrict__ qstart, int num_pairs,
+    int64_t n1, const float* __restrict__ kp1, uint32_t* __restrict__ qkey,
+    uint32_t* __restrict__ qflag, uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n1) return;
+  const int p = find_pair(qstart, num_pairs, i);
+  const PairDev& pd = pairs[p];
+  double a, b, c;
+  epipolar_line(pd.F, kp1[2 * i], kp1[2 * i + 1], a, b, c);
+  uint32_t flag = kQueryNormal, key = 0;
+  if (a == 0.0 && b == 0.0) {
+    flag = kQueryEmpty;
+  } else if (!isfinite(a) || !isfinite(b) || !isfinite(c)) {
+    flag = kQueryBrute;
+  } else {
+    // the same line in normalised image-2 coordinates (scaled by 1/s)
+    const double l3 = pd.s * (a * pd.cx + b * pd.cy + c);
+    const double lam = pd.u[0] * a + pd.u[1] * b + pd.u[2] * l3;
+    const double mu = pd.v[0] * a + pd.v[1] * b + pd.v[2] * l3;
+    const double nu = pd.e[0] * a + pd.e[1] * b + pd.e[2] * l3;
+    const double n1c = lam * pd.u[0] + mu * pd.v[0];
+    const double n2c = lam * pd.u[1] + mu * pd.v[1];
+    const double nrm = sqrt(n1c * n1c + n2c * n2c);
+    if (!(fabs(nu) <= pd.kappa * nrm)) {
+      flag = kQueryBrute;  // the line misses the epipole by more than absorbed
+    } else {
+      double phi = atan2(mu, lam);
+      if (phi < 0.0) phi += M_PI;
+      if (phi >= M_PI) phi -= M_PI;
+      key = angle_key(phi);
+    }
+  }
+  qkey[i] = key;
+  qflag[i] = flag;
+  sort_key[i] = key >> 16;
+  sort_val[i] = (uint32_t)i;
+}
+
+// Sorted layout: structure-of-arrays in angle order, plus the inverse
+// permutation (record -> sorted position).
+__global__ __launch_bounds__(256) void k_gather_records(
+    const int64_t* __restrict__ kstart, int num_pairs, int64_t n2,
+    const uint32_t* __restrict__ sorted_val, const float* __restrict__ kp2,
+    const float* __restrict__ eps2, float eps_scalar, const uint32_t* __restrict__ recC,
+    const uint32_t* __restrict__ recH, uint32_t* __restrict__ rC, uint32_t* __restrict__ rH,
+    int32_t* __restrict__ rj, float2* __restrict__ rxy, float* __restrict__ reps,
+    uint32_t* __restrict__ rinv) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n2) return;
+  const uint32_t r = sorted_val[pos];
+  const int p = find_pair(kstart, num_pairs, (int64_t)r);
+  rC[pos] = recC[r];
+  rH[pos] = recH[r];
+  rj[pos] = (int32_t)((int64_t)r - kstart[p]);
+  rxy[pos] = make_float2(kp2[2 * (int64_t)r], kp2[2 * (int64_t)r + 1]);
+  reps[pos] = eps2 ? eps2[r] : eps_scalar;
+  rinv[r] = (uint32_t)pos;
+}
+
+// Start of every width class inside each pair's sorted segment.
+__global__ __launch_bounds__(64) void k_class_bounds(const int64_t* __restrict__ kstart,
+                                                     const uint32_t* __restrict__ skey,
+                                                     int64_t* __restrict__ class_begin) {
+  const int p = blockIdx.x;
+  const int64_t lo = kstart[p], hi = kstart[p + 1];
+  const int c = lane_id();
+  // every lane runs the same cooperative search for its own class in turn
+  for (int cc = 0; cc < kClassSlots; ++cc) {
+    const int64_t b = cc == kNumClasses ? hi : wave_lower_bound(skey, lo, hi, (uint32_t)cc << kCentreBits);
+    if (c == 0) class_begin[(int64_t)p * kClassSlots + cc] = b;
+  }
+}
+
+hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num_pairs,
+                            int64_t n2, const float* kp2, const float* eps2, float eps_scalar,
+                            uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,
+                            uint32_t* recH, hipStream_t s) {
+  if (n2 == 0) return hipSuccess;
+  const int64_t blocks = (n2 + 255) / 256;
+  hipLaunchKernelGGL(k_intervals, dim3((unsigned)blocks), dim3(256), 0, s, pairs, kstart,
+                     num_pairs, n2, kp2, eps2, eps_scalar, sort_key, sort_val, recC, recH);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
+                             int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
+                             uint32_t* sort_key, uint32_t* sort_val, hipStream_t s) {
+  if (n1 == 0) return hipSuccess;
+  const int64_t blocks = (n1 + 255) / 256;
+  hipLaunchKernelGGL(k_query_keys, dim3((unsigned)blocks), dim3(256), 0, s, pairs, qstart,
+                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n2,
+                                 const uint32_t* sorted_val, const float* kp2, const float* eps2,
+                                 float eps_scalar, const uint32_t* recC, const uint32_t* recH,
+                                 uint32_t* rC, uint32_t* rH, int32_t* rj, float2* rxy,
+                                 float* reps, uint32_t* rinv, hipStream_t s) {
+  if (n2 == 0) return hipSuccess;
+  const int64_t blocks = (n2 + 255) / 256;
+  hipLaunchKernelGGL(k_gather_records, dim3((unsigned)blocks), dim3(256), 0, s, kstart,
+                     num_pairs, n2, sorted_val, kp2, eps2, eps_scalar, recC, recH, rC, rH, rj,
+                     rxy, reps, rinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_bounds(const int64_t* kstart, int num_pairs, const uint32_t* skey,
+                               int64_t* class_begin, hipStream_t s) {
+  if (num_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_bounds, dim3(num_pairs), dim3(64), 0, s, kstart, skey, class_begin);
+  return hipGetLastError();
+}
+
+}  // namespace epm

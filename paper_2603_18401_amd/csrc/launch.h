@@ -1,0 +1,93 @@
+// Host-side launchers of the libepm kernels (one per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "epm_internal.h"
+
+namespace epm {
+
+hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num_pairs,
+                            int64_t n2, const float* kp2, const float* eps2, float eps_scalar,
+                            uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,
+                            uint32_t* recH, hipStream_t s);
+
+hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
+                             int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
+                             uint32_t* sort_key, uint32_t* sort_val, hipStream_t s);
+
+hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n2,
+                                 const uint32_t* sorted_val, const float* kp2, const float* eps2,
+                                 float eps_scalar, const uint32_t* recC, const uint32_t* recH,
+                                 uint32_t* rC, uint32_t* rH, int32_t* rj, float2* rxy,
+                                 float* reps, uint32_t* rinv, hipStream_t s);
+
+hipError_t launch_class_bounds(const int64_t* kstart, int num_pairs, const uint32_t* skey,
+                               int64_t* class_begin, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) u32 pairs inside every segment, over
+// the low `bits` bits of the keys, 8 bits per pass.  Ping-pongs between
+// (k0, v0) and (k1, v1); returns through *sorted_in_1 whether the result
+// ended in (k1, v1).
+hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                                const SortTile* tiles, int num_tiles, const SortSeg* segs,
+                                int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
+                                hipStream_t s);
+
+struct StabArgs {
+  const PairDev* pairs;
+  const int64_t* qstart;
+  int num_pairs;
+  int64_t n1;
+  const float* kp1;
+  const uint32_t* qkey;
+  const uint32_t* qflag;
+  const uint32_t* qperm;
+  const int64_t* class_begin;
+  const uint32_t* skey;
+  const uint32_t* rC;
+  const uint32_t* rH;
+  const int32_t* rj;
+  const float2* rxy;
+  const float* reps;
+  const uint32_t* rinv;
+  uint32_t* counts;
+  const int64_t* row_offsets;
+  int32_t* cols;
+  int64_t capacity;
+};
+
+hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
+hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s);
+
+// Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
+hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,
+                              int64_t* partials, hipStream_t s);
+int64_t scan_partials_count(int64_t n);
+
+struct MatchArgs {
+  const int64_t* qstart;
+  const int64_t* kstart;
+  int num_pairs;
+  int64_t n1;
+  const uint32_t* qperm;  // processing order (angle-sorted); NULL = natural order
+  const int64_t* row_offsets;
+  const int32_t* cols;
+  const void* desc1;
+  const void* desc2;
+  float ratio;
+  int32_t* best_idx;
+  float* best_dist;
+  float* second_dist;
+};
+
+hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
+
+hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
+                                  const float* eps2, float eps_scalar, const int64_t* qi,
+                                  const int64_t* kj, int64_t count, double* num, double* rhs,
+                                  hipStream_t s);
+
+}  // namespace epm

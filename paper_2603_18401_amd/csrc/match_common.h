@@ -1,0 +1,97 @@
+// Selection helpers shared by the matching kernels.
+#pragma once
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace epm {
+
+// One step of the canonical FP32 squared distance over four dimensions,
+// k ascending: t = a - b (rounded), acc = fmaf(t, t, acc).
+__device__ __forceinline__ float canonical_step4(float acc, const float4& a, const float4& b) {
+  float t = a.x - b.x;
+  acc = __builtin_fmaf(t, t, acc);
+  t = a.y - b.y;
+  acc = __builtin_fmaf(t, t, acc);
+  t = a.z - b.z;
+  acc = __builtin_fmaf(t, t, acc);
+  t = a.w - b.w;
+  acc = __builtin_fmaf(t, t, acc);
+  return acc;
+}
+
+// (distance, j) ordered lexicographically: the tie goes to the lower j.
+__device__ __forceinline__ bool before(float d1, int32_t j1, float d2, int32_t j2) {
+  return d1 < d2 || (d1 == d2 && j1 < j2);
+}
+
+struct Top2 {
+  float bd = __builtin_inff();
+  int32_t bj = INT32_MAX;
+  float sd = __builtin_inff();
+  int32_t sj = INT32_MAX;
+
+  __device__ __forceinline__ void insert(float d, int32_t j) {
+    if (before(d, j, bd, bj)) {
+      sd = bd;
+      sj = bj;
+      bd = d;
+      bj = j;
+    } else if (before(d, j, sd, sj)) {
+      sd = d;
+      sj = j;
+    }
+  }
+};
+
+// Merge of two top-2 lists holding distinct candidates.
+__device__ __forceinline__ Top2 merge_top2(const Top2& x, const Top2& y) {
+  Top2 r;
+  const bool xf = before(x.bd, x.bj, y.bd, y.bj);
+  r.bd = xf ? x.bd : y.bd;
+  r.bj = xf ? x.bj : y.bj;
+  // runner-up: the other list's best or the winner list's second
+  const float od = xf ? y.bd : x.bd;
+  const int32_t oj = xf ? y.bj : x.bj;
+  const float wd = xf ? x.sd : y.sd;
+  const int32_t wj = xf ? x.sj : y.sj;
+  const bool of = before(od, oj, wd, wj);
+  r.sd = of ? od : wd;
+  r.sj = of ? oj : wj;
+  return r;
+}
+
+__device__ __forceinline__ Top2 wave_merge_top2(Top2 t) {
+  #pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    Top2 o;
+    o.bd = __shfl_xor(t.bd, off);
+    o.bj = __shfl_xor(t.bj, off);
+    o.sd = __shfl_xor(t.sd, off);
+    o.sj = __shfl_xor(t.sj, off);
+    t = merge_top2(t, o);
+  }
+  return t;
+}
+
+// Output convention: empty row -> -1 / +inf / +inf; ratio rejection -> -1
+// with both distances kept.
+__device__ __forceinline__ void write_match(const MatchArgs& A, int64_t i, const Top2& t,
+                                            bool binary) {
+  int32_t idx = t.bj == INT32_MAX ? -1 : t.bj;
+  if (idx >= 0 && A.ratio > 0.0f) {
+    bool accept;
+    if (binary) {
+      accept = t.bd < A.ratio * t.sd;
+    } else {
+      const float thr = A.ratio * A.ratio;
+      accept = t.bd < thr * t.sd;
+    }
+    if (!accept) idx = -1;
+  }
+  A.best_idx[i] = idx;
+  A.best_dist[i] = t.bd;
+  A.second_dist[i] = t.sd;
+}
+
+}  // namespace epm

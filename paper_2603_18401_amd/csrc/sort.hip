@@ -1,0 +1,130 @@
+// Segmented, stable LSD radix sort of (u32 key, u32 value) pairs.
+//
+// Builds the angle-sorted interval layout that replaces the paper's centred
+// segment tree (Sec. 4.4): every pair's records are one segment.  Each
+// segment is cut into tiles of kSortTile elements that never straddle two
+// segments, so the per-pass digit offsets are a scan over (digit, tile)
+// inside one segment and no cross-segment work is needed.
+//
+// Per 8-bit pass: k_sort_hist (per-tile digit counts), k_sort_offsets (one
+// workgroup per segment turns the counts into global start offsets, in place)
+// and k_sort_scatter (stable ranking with wavefront ballots, then the write).
+#include "device_common.h"
+#include "launch.h"
+
+namespace epm {
+
+namespace {
+
+constexpr int kRadix = 256;
+constexpr int kWavesPerBlock = kSortThreads / kWave;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys,
+                                                            const SortTile* __restrict__ tiles,
+                                                            int shift,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kRadix];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const SortTile t = tiles[blockIdx.x];
+  for (int k = tid; k < t.count; k += kSortThreads)
+    atomicAdd(&h[(keys[t.begin + k] >> shift) & (kRadix - 1)], 1u);
+  __syncthreads();
+  hist[(int64_t)blockIdx.x * kRadix + tid] = h[tid];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __restrict__ segs,
+                                                               uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sc[kRadix];
+  const SortSeg sg = segs[blockIdx.x];
+  const int d = threadIdx.x;
+  uint32_t total = 0;
+  for (int t = 0; t < sg.tile_count; ++t) total += hist[(int64_t)(sg.tile_begin + t) * kRadix + d];
+  // exclusive scan over the 256 digits (Hillis-Steele in LDS)
+  sc[d] = total;
+  __syncthreads();
+  for (int off = 1; off < kRadix; off <<= 1) {
+    const uint32_t v = d >= off ? sc[d - off] : 0u;
+    __syncthreads();
+    sc[d] += v;
+    __syncthreads();
+  }
+  uint32_t run = (uint32_t)sg.begin + sc[d] - total;
+  for (int t = 0; t < sg.tile_count; ++t) {
+    const int64_t h = (int64_t)(sg.tile_begin + t) * kRadix + d;
+    const uint32_t c = hist[h];
+    hist[h] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const SortTile* __restrict__ tiles,
+    int shift, const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t run[kRadix];
+  __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const SortTile t = tiles[blockIdx.x];
+  run[tid] = offs[(int64_t)blockIdx.x * kRadix + tid];
+  for (int base = 0; base < t.count; base += kSortThreads) {
+    const int idx = base + tid;
+    const bool valid = idx < t.count;
+    const uint32_t key = valid ? kin[t.begin + idx] : 0u;
+    const uint32_t val = valid ? vin[t.begin + idx] : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    // lanes of this wavefront holding the same digit
+    uint64_t same = ballot(valid);
+    #pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = ballot(valid && bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t rank = lanes_below(same);
+    #pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    #pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                                const SortTile* tiles, int num_tiles, const SortSeg* segs,
+                                int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
+                                hipStream_t s) {
+  *sorted_in_1 = false;
+  if (num_tiles == 0) return hipSuccess;
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, shift,
+                       hist);
+    hipLaunchKernelGGL(k_sort_offsets, dim3(num_segs), dim3(kSortThreads), 0, s, segs, hist);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
+                       tiles, shift, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* tk = ki; ki = ko; ko = tk;
+    uint32_t* tv = vi; vi = vo; vo = tv;
+    *sorted_in_1 = !*sorted_in_1;
+  }
+  return hipSuccess;
+}
+
+}  // namespace epm
