@@ -132,10 +132,13 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
  * contraction) -- Eq. 3-4 multiplied through by the positive denominator,
  * closed boundary.  A query whose line has a = b = 0 gets an empty row.
  *
- * Synchronises the host with `stream` once (to read nnz).  If the total
- * exceeds `capacity`, returns EPM_ERR_CAPACITY with *nnz_host set to the
- * required size and writes nothing at or beyond col_indices[capacity];
- * row_offsets is complete, and a retry with a larger buffer is valid.
+ * Synchronises the host with `stream` once (to read nnz) when nnz_host is
+ * not NULL.  If the total exceeds `capacity`, returns EPM_ERR_CAPACITY with
+ * *nnz_host set to the required size and writes nothing at or beyond
+ * col_indices[capacity]; row_offsets is complete, and a retry with a larger
+ * buffer is valid.  With nnz_host == NULL nothing synchronises: the rows are
+ * written up to `capacity` and row_offsets[N1] tells the caller whether the
+ * buffer was large enough.
  */
 epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
                                 int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
@@ -193,6 +196,24 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,
                                 hipStream_t stream);
+
+/* Counters of the last epm_query_candidates call on an index. */
+typedef struct {
+  int64_t queries;          /* image-1 queries                                       */
+  int64_t empty_queries;    /* zero lines (a = b = 0): empty rows                     */
+  int64_t scanned_queries;  /* lines missing the epipole by more than the intervals
+                               absorb: tested against every keypoint of their pair   */
+  int64_t records_scanned;  /* (query, record) pairs read from the angle windows     */
+  int64_t angle_hits;       /* of those, inside the record's angular interval        */
+  int64_t candidates;       /* confirmed by the FP64 test (= nnz)                     */
+} epm_query_stats;
+
+/*
+ * Reads the counters of the last epm_query_candidates on idx (waits for the
+ * stream that call used).  angle_hits >= candidates always holds; the ratio
+ * is the selectivity of the angular filter.
+ */
+epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out);
 
 /* Releases the host object; the device workspace stays owned by the caller. */
 void epm_index_destroy(epm_index* idx);

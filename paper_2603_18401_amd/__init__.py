@@ -30,7 +30,8 @@ STATUS = {0: "EPM_OK", 1: "EPM_ERR_ARG", 2: "EPM_ERR_DEGENERATE_F", 3: "EPM_ERR_
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "bin256": 3}
 ALGOS = {"auto": 0, "plain": 1, "tiled": 2}
 EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates", "epm_match",
-           "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms"]
+           "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms",
+           "epm_get_query_stats"]
 
 
 class EpmError(RuntimeError):
@@ -44,6 +45,11 @@ class _Pair(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double * 9), ("w2", ctypes.c_int32), ("h2", ctypes.c_int32),
                 ("q_begin", ctypes.c_int64), ("m", ctypes.c_int64),
                 ("k_begin", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
+class _QueryStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("queries", "empty_queries", "scanned_queries",
+                                               "records_scanned", "angle_hits", "candidates")]
 
 
 class _MatchOpts(ctypes.Structure):
@@ -82,6 +88,8 @@ def load_library(path=None):
     lib.epm_version.restype = ctypes.c_char_p
     lib.epm_point_line_terms.argtypes = [P, V, V, V, ctypes.c_float, V, V, i64, V, V, V]
     lib.epm_point_line_terms.restype = ctypes.c_int
+    lib.epm_get_query_stats.argtypes = [V, ctypes.POINTER(_QueryStats)]
+    lib.epm_get_query_stats.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -200,6 +208,12 @@ class Index:
                                                ctypes.byref(nnz), st_ptr)
         _check(st, "epm_query_candidates")
         return row_offsets, col_indices[: nnz.value]
+
+    def stats(self):
+        """Counters of the last query (dict; waits for its stream)."""
+        st = _QueryStats()
+        _check(self.lib.epm_get_query_stats(self.handle, ctypes.byref(st)), "epm_get_query_stats")
+        return {k: int(getattr(st, k)) for k, _ in st._fields_}
 
     def match(self, row_offsets, col_indices, desc1, desc2, dtype="f32", scale1=None,
               scale2=None, desc1_f32=None, desc2_f32=None, ratio=0.0, algo="auto", tile_q=0,

@@ -22,13 +22,13 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Offsets of every device buffer inside the caller's workspace.
 struct Layout {
-  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, hist;
+  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
-  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials;
+  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats;
   size_t total;
 };
 
-Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq) {
+Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_t ts) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -44,6 +44,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq) {
   L.rsegs = take(sizeof(SortSeg) * P);
   L.qtiles = take(sizeof(SortTile) * tq);
   L.qsegs = take(sizeof(SortSeg) * P);
+  L.stiles = take(sizeof(StabTile) * ts);
   L.hist = take(sizeof(uint32_t) * 256 * (size_t)(tr > tq ? tr : tq));
   L.rk0 = take(4 * N2);
   L.rv0 = take(4 * N2);
@@ -66,11 +67,14 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq) {
   L.qv1 = take(4 * N1);
   L.counts = take(4 * N1);
   L.partials = take(sizeof(int64_t) * (size_t)scan_partials_count(n1));
+  L.staging = take(sizeof(int32_t) * kStage * N1);
+  L.stats = take(sizeof(unsigned long long) * kNumStats);
   L.total = off;
   return L;
 }
 
 int64_t tiles_of(int64_t count) { return (count + kSortTile - 1) / kSortTile; }
+int64_t stab_tiles_of(int64_t m) { return (m + kTileQ - 1) / kTileQ; }
 
 bool validate_pairs(const epm_pair* pairs, int32_t num_pairs, int64_t* n1, int64_t* n2) {
   if (!pairs || num_pairs < 1 || num_pairs > 65535) return false;
@@ -114,19 +118,34 @@ epm_status setup_pair(const epm_pair& in, PairDev& pd) {
   pd.s = 2.0 / (w > h ? w : h);
   pd.cx = 0.5 * w;
   pd.cy = 0.5 * h;
-  // columns of N F with l^ = (a, b, s (a cx + b cy + c)), each scaled to unit
-  // length (a right scaling does not move the left null space)
-  double col[3][3];
-  for (int k = 0; k < 3; ++k) {
-    const double a = F[k], b = F[3 + k], c = F[6 + k];
-    col[k][0] = a;
-    col[k][1] = b;
-    col[k][2] = pd.s * (a * pd.cx + b * pd.cy + c);
-    const double nk = norm3(col[k]);
-    for (int d = 0; d < 3; ++d) col[k][d] = nk > 0.0 ? col[k][d] / nk : 0.0;
+  // M = N F T^-1: lines in normalised image-2 coordinates, l^ = N l with
+  // l^ = (a, b, s (a cx + b cy + c)), as functions of normalised image-1
+  // coordinates (T^-1 undoes the same normalisation on the image-1 side, which
+  // balances the columns; a right factor does not move the left null space)
+  double M[3][3];
+  {
+    const double Ti[3][3] = {{1.0 / pd.s, 0.0, pd.cx}, {0.0, 1.0 / pd.s, pd.cy}, {0.0, 0.0, 1.0}};
+    double NF[3][3];
+    for (int k = 0; k < 3; ++k) {
+      NF[0][k] = F[k];
+      NF[1][k] = F[3 + k];
+      NF[2][k] = pd.s * (F[k] * pd.cx + F[3 + k] * pd.cy + F[6 + k]);
+    }
+    double mx = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) {
+        M[r][k] = NF[r][0] * Ti[0][k] + NF[r][1] * Ti[1][k] + NF[r][2] * Ti[2][k];
+        mx = std::fmax(mx, std::fabs(M[r][k]));
+      }
+    if (!(mx > 0.0) || !std::isfinite(mx)) return EPM_ERR_DEGENERATE_F;
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) M[r][k] /= mx;
   }
-  // the left null vector is orthogonal to every column: the cross product of
-  // the best-conditioned pair of columns
+  double col[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) col[k][d] = M[d][k];
+  // the left null vector is orthogonal to every column: the largest cross
+  // product of two columns (a column that is only rounding residue never wins)
   double best[3] = {0, 0, 0}, bn = 0.0;
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
   for (int t = 0; t < 3; ++t) {
@@ -193,11 +212,16 @@ struct epm_index {
   std::vector<int64_t> qstart, kstart;
   std::vector<SortTile> rtiles, qtiles;
   std::vector<SortSeg> rsegs, qsegs;
+  std::vector<StabTile> stiles;
+  std::vector<char> head;  // host image of the table region of the workspace
   char* ws = nullptr;
   Layout L;
   size_t skey_off = 0;  // sorted record keys (one of the sort buffers)
   bool have_qperm = false;
   const uint32_t* qperm = nullptr;
+  hipStream_t last_stream = nullptr;  // stream of the last query call
+  const int64_t* last_offsets = nullptr;
+  bool have_stats = false;
 
   template <typename T>
   T* at(size_t off) const {
@@ -215,12 +239,13 @@ extern "C" {
 size_t epm_workspace_bytes(const epm_pair* pairs, int32_t num_pairs) {
   int64_t n1, n2;
   if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return 0;
-  int64_t tr = 0, tq = 0;
+  int64_t tr = 0, tq = 0, ts = 0;
   for (int p = 0; p < num_pairs; ++p) {
     tr += tiles_of(pairs[p].n);
     tq += tiles_of(pairs[p].m);
+    ts += stab_tiles_of(pairs[p].m);
   }
-  return make_layout(num_pairs, n1, n2, tr, tq).total;
+  return make_layout(num_pairs, n1, n2, tr, tq, ts).total;
 }
 
 epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
@@ -262,7 +287,17 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
     pd.qtile_begin = idx->qsegs[p].tile_begin;
     pd.qtile_count = idx->qsegs[p].tile_count;
   }
-  idx->L = make_layout(num_pairs, n1, n2, (int64_t)idx->rtiles.size(), (int64_t)idx->qtiles.size());
+  for (int p = 0; p < num_pairs; ++p) {
+    for (int64_t o = 0; o < pairs[p].m; o += kTileQ) {
+      StabTile t;
+      t.begin = pairs[p].q_begin + o;
+      t.count = (int32_t)(pairs[p].m - o < kTileQ ? pairs[p].m - o : kTileQ);
+      t.pair = p;
+      idx->stiles.push_back(t);
+    }
+  }
+  idx->L = make_layout(num_pairs, n1, n2, (int64_t)idx->rtiles.size(), (int64_t)idx->qtiles.size(),
+                       (int64_t)idx->stiles.size());
   if (workspace_bytes < idx->L.total) {
     delete idx;
     return EPM_ERR_WORKSPACE;
@@ -274,17 +309,22 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
     delete idx;
     return s;
   };
-  auto h2d = [&](size_t off, const void* src, size_t bytes) {
-    if (bytes == 0) return hipSuccess;
-    return hipMemcpyAsync(idx->ws + off, src, bytes, hipMemcpyHostToDevice, stream);
+  // every host table goes up in one copy: they sit at the head of the
+  // workspace, in front of the histogram buffer
+  idx->head.assign(L.hist, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(idx->head.data() + off, src, bytes);
   };
-  if (h2d(L.pairs, idx->pairs.data(), sizeof(PairDev) * num_pairs) != hipSuccess ||
-      h2d(L.qstart, idx->qstart.data(), sizeof(int64_t) * (num_pairs + 1)) != hipSuccess ||
-      h2d(L.kstart, idx->kstart.data(), sizeof(int64_t) * (num_pairs + 1)) != hipSuccess ||
-      h2d(L.rtiles, idx->rtiles.data(), sizeof(SortTile) * idx->rtiles.size()) != hipSuccess ||
-      h2d(L.rsegs, idx->rsegs.data(), sizeof(SortSeg) * num_pairs) != hipSuccess ||
-      h2d(L.qtiles, idx->qtiles.data(), sizeof(SortTile) * idx->qtiles.size()) != hipSuccess ||
-      h2d(L.qsegs, idx->qsegs.data(), sizeof(SortSeg) * num_pairs) != hipSuccess)
+  put(L.pairs, idx->pairs.data(), sizeof(PairDev) * num_pairs);
+  put(L.qstart, idx->qstart.data(), sizeof(int64_t) * (num_pairs + 1));
+  put(L.kstart, idx->kstart.data(), sizeof(int64_t) * (num_pairs + 1));
+  put(L.rtiles, idx->rtiles.data(), sizeof(SortTile) * idx->rtiles.size());
+  put(L.rsegs, idx->rsegs.data(), sizeof(SortSeg) * num_pairs);
+  put(L.qtiles, idx->qtiles.data(), sizeof(SortTile) * idx->qtiles.size());
+  put(L.qsegs, idx->qsegs.data(), sizeof(SortSeg) * num_pairs);
+  put(L.stiles, idx->stiles.data(), sizeof(StabTile) * idx->stiles.size());
+  if (hipMemcpyAsync(idx->ws, idx->head.data(), L.hist, hipMemcpyHostToDevice, stream) !=
+      hipSuccess)
     return fail(EPM_ERR_HIP);
 
   const PairDev* dpairs = idx->at<PairDev>(L.pairs);
@@ -368,7 +408,15 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
   A.row_offsets = row_offsets;
   A.cols = col_indices;
   A.capacity = capacity;
-  EPM_HIP(launch_stab_count(A, stream));
+  A.tiles = idx->at<StabTile>(L.stiles);
+  A.num_tiles = (int)idx->stiles.size();
+  A.staging = idx->at<int32_t>(L.staging);
+  A.stats = idx->at<unsigned long long>(L.stats);
+  idx->last_stream = stream;
+  idx->last_offsets = row_offsets;
+  idx->have_stats = true;
+  EPM_HIP(launch_clear_stats(A.stats, stream));
+  EPM_HIP(launch_stab_tiles(A, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   if (nnz_host) {
     int64_t nnz = 0;
@@ -377,7 +425,7 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
     *nnz_host = nnz;
     if (nnz > capacity) return EPM_ERR_CAPACITY;
   }
-  EPM_HIP(launch_stab_fill(A, stream));
+  EPM_HIP(launch_fill_rows(A, stream));
   return EPM_OK;
 }
 
@@ -447,6 +495,26 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
   if (!kp1_xy || !kp2_xy || !qi || !kj || !num || !rhs) return EPM_ERR_ARG;
   EPM_HIP(launch_point_line_terms(F, kp1_xy, kp2_xy, eps2, eps_scalar, qi, kj, count, num, rhs,
                                   stream));
+  return EPM_OK;
+}
+
+epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
+  if (!idx || !out) return EPM_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->queries = idx->N1;
+  if (!idx->have_stats) return EPM_OK;
+  unsigned long long c[kNumStats] = {0, 0, 0, 0};
+  int64_t nnz = 0;
+  EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.stats), sizeof(c),
+                         hipMemcpyDeviceToHost, idx->last_stream));
+  EPM_HIP(hipMemcpyAsync(&nnz, idx->last_offsets + idx->N1, sizeof(nnz), hipMemcpyDeviceToHost,
+                         idx->last_stream));
+  EPM_HIP(hipStreamSynchronize(idx->last_stream));
+  out->candidates = nnz;
+  out->scanned_queries = (int64_t)c[0];
+  out->records_scanned = (int64_t)c[1];
+  out->angle_hits = (int64_t)c[2];
+  out->empty_queries = (int64_t)c[3];
   return EPM_OK;
 }
 

@@ -76,4 +76,19 @@ constexpr int kClassSlots = kNumClasses + 1;  // class_begin entries per pair
 // ascending j order by a direct scan of the pair.
 constexpr int kRowSortMax = 2048;
 
+// Stabbing tiles: kTileQ consecutive angle-sorted queries of one pair share
+// one window search per width class; the window's records are staged in LDS
+// kChunk at a time.  Rows of up to kStage candidates are finished inside the
+// tile kernel (sorted, parked in a staging buffer); longer rows are rebuilt
+// by the fill kernel.
+constexpr int kTileQ = 64;
+constexpr int kStage = 64;
+constexpr int kChunk = 512;
+
+struct StabTile {
+  int64_t begin;  // first angle-sorted query position of the tile
+  int32_t count;  // queries in the tile (<= kTileQ)
+  int32_t pair;
+};
+
 }  // namespace epm

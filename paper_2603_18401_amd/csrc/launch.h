@@ -56,10 +56,21 @@ struct StabArgs {
   const int64_t* row_offsets;
   int32_t* cols;
   int64_t capacity;
+  const StabTile* tiles;
+  int num_tiles;
+  int32_t* staging;  // [n1][kStage], indexed by the original query index
+  unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
 };
+
+constexpr int kNumStats = 4;  // scanned queries, records scanned, angle hits, empty
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
 
 hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
 hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s);
+// Tiled count pass (also parks rows of <= kStage candidates, sorted).
+hipError_t launch_stab_tiles(const StabArgs& a, hipStream_t s);
+// Fill pass after launch_stab_tiles: copies parked rows, rebuilds the rest.
+hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,

@@ -128,31 +128,12 @@ __device__ uint32_t stab_query(const StabArgs& A, const PairDev& pd, int pair, c
   return total;
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
-  __shared__ int32_t rowbuf[FILL ? kWaves : 1][FILL ? kRowSortMax : 1];
-  const int lane = lane_id(), wave = wave_id();
-  const int64_t qs = (int64_t)blockIdx.x * kWaves + wave;
-  if (qs >= A.n1) return;
-  const int64_t i = A.qperm ? (int64_t)A.qperm[qs] : qs;
+// Writes query i's CSR row in ascending j (rows of any length).
+__device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
+  const int lane = lane_id();
   const int pair = find_pair(A.qstart, A.num_pairs, i);
   const PairDev& pd = A.pairs[pair];
   const uint32_t flag = A.qflag[i];
-  int32_t* buf = rowbuf[FILL ? wave : 0];
-
-  if (!FILL) {
-    uint32_t total = 0;
-    if (flag != kQueryEmpty) {
-      QueryCtx q;
-      epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], q.a, q.b, q.c);
-      q.key = A.qkey[i];
-      q.brute = flag == kQueryBrute;
-      total = stab_query<false>(A, pd, pair, q, buf);
-    }
-    if (lane == 0) A.counts[i] = total;
-    return;
-  }
-
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len == 0 || flag == kQueryEmpty) return;
@@ -196,6 +177,273 @@ __global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
     for (int t = lane; t < n; t += kWave)
       if (o0 + t < A.capacity) A.cols[o0 + t] = buf[t];
   }
+  wave_sync_lds();
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
+  __shared__ int32_t rowbuf[FILL ? kWaves : 1][FILL ? kRowSortMax : 1];
+  const int lane = lane_id(), wave = wave_id();
+  const int64_t qs = (int64_t)blockIdx.x * kWaves + wave;
+  if (qs >= A.n1) return;
+  const int64_t i = A.qperm ? (int64_t)A.qperm[qs] : qs;
+  if (FILL) {
+    fill_row(A, i, rowbuf[wave]);
+    return;
+  }
+  const int pair = find_pair(A.qstart, A.num_pairs, i);
+  const PairDev& pd = A.pairs[pair];
+  const uint32_t flag = A.qflag[i];
+  uint32_t total = 0;
+  if (flag != kQueryEmpty) {
+    QueryCtx q;
+    epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], q.a, q.b, q.c);
+    q.key = A.qkey[i];
+    q.brute = flag == kQueryBrute;
+    total = stab_query<false>(A, pd, pair, q, nullptr);
+  }
+  if (lane == 0) A.counts[i] = total;
+}
+
+// ------------------------------------------------------------- tiled pass
+constexpr int kQPerWave = kTileQ / kWaves;
+constexpr int kSlots = 2 * kNumClasses;  // up to two record ranges per class
+
+__device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict__ keys,
+                                                      int64_t lo, int64_t hi, uint32_t target) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  #pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  #pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Counts every row of a tile of kTileQ angle-sorted queries and parks rows of
+// up to kStage candidates (sorted by j) in the staging buffer.  Per width
+// class the tile needs one window, [min key - 2^c + 1, max key + 2^c - 1],
+// found by one lane per class; the windows' records are staged in LDS and
+// every query of the tile tests them with the angle test and the FP64 test.
+__global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
+  __shared__ uint32_t sC[kChunk], sH[kChunk];
+  __shared__ float2 sXY[kChunk];
+  __shared__ float sE[kChunk];
+  __shared__ int32_t sJ[kChunk];
+  __shared__ int32_t hits[kTileQ][kStage];
+  __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ];
+  __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
+  __shared__ int64_t qidx[kTileQ];
+  __shared__ int64_t slot_b[kSlots], slot_pref[kSlots + 1];
+
+  const StabTile T = A.tiles[blockIdx.x];
+  const PairDev& pd = A.pairs[T.pair];
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+
+  if (wave == 0) {
+    const bool live = lane < T.count;
+    int64_t i = 0;
+    uint32_t flag = kQueryEmpty, key = 0;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (live) {
+      i = A.qperm[T.begin + lane];
+      flag = A.qflag[i];
+      key = A.qkey[i];
+      if (flag != kQueryEmpty) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
+    }
+    qa[lane] = a;
+    qb[lane] = b;
+    qc[lane] = c;
+    qk[lane] = key;
+    qmode[lane] = live ? flag : kQueryEmpty;
+    qidx[lane] = i;
+    cnt[lane] = 0;
+    const bool normal = live && flag == kQueryNormal;
+    const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
+    const uint32_t kmax = wave_max_u32(normal ? key : 0u);
+    const bool any = ballot(normal) != 0;
+    // lane c < 32 finds class c's record ranges for the whole tile
+    int64_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
+    if (lane < kNumClasses && any) {
+      const int64_t* cb = A.class_begin + (int64_t)T.pair * kClassSlots;
+      const int64_t beg = cb[lane], end = cb[lane + 1];
+      if (beg < end) {
+        const uint32_t span = lane == kWideClass ? 0u : (1u << lane) - 1u;
+        const uint64_t width = (uint64_t)(kmax - kmin) + 2ull * span;
+        if (lane == kWideClass || width >= 0xFFFFE000ull) {
+          b0 = beg;
+          l0 = end - beg;
+        } else {
+          const uint32_t lo = kmin - span, hi = kmax + span;
+          const uint32_t cls = (uint32_t)lane << kCentreBits;
+          const uint32_t blo = cls | (lo >> kCentreShift), bhi = cls | (hi >> kCentreShift);
+          if (lo <= hi) {
+            const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
+            const int64_t r1 = lower_bound_scalar(A.skey, r0, end, bhi + 1u);
+            b0 = r0;
+            l0 = r1 - r0;
+          } else {
+            const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
+            const int64_t r1 = lower_bound_scalar(A.skey, beg, r0, bhi + 1u);
+            b0 = r0;
+            l0 = end - r0;
+            b1 = beg;
+            l1 = r1 - beg;
+          }
+        }
+      }
+    }
+    if (lane < kNumClasses) {
+      slot_b[2 * lane] = b0;
+      slot_b[2 * lane + 1] = b1;
+    }
+    // inclusive scan of the 64 slot lengths (slot s = class s/2, part s%2)
+    const int64_t mylen_even = l0, mylen_odd = l1;
+    int64_t len = 0;
+    {
+      const int src = lane >> 1;
+      const int64_t le = __shfl(mylen_even, src), lo_ = __shfl(mylen_odd, src);
+      len = (lane & 1) ? lo_ : le;
+    }
+    int64_t incl = len;
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int64_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    slot_pref[lane + 1] = incl;
+    if (lane == 0) slot_pref[0] = 0;
+  }
+  __syncthreads();
+
+  const int64_t total_len = slot_pref[kSlots];
+  uint64_t scanned = 0, angle_hits = 0, brute = 0;
+  for (int64_t base = 0; base < total_len; base += kChunk) {
+    const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
+    for (int v = tid; v < clen; v += kThreads) {
+      const int64_t virt = base + v;
+      int s = 0;  // last slot with slot_pref[s] <= virt
+      #pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (s + step <= kSlots && slot_pref[s + step] <= virt) s += step;
+      const int64_t pos = slot_b[s] + (virt - slot_pref[s]);
+      sC[v] = A.rC[pos];
+      sH[v] = A.rH[pos];
+      sXY[v] = A.rxy[pos];
+      sE[v] = A.reps[pos];
+      sJ[v] = A.rj[pos];
+    }
+    __syncthreads();
+    for (int qq = 0; qq < kQPerWave; ++qq) {
+      const int q = wave * kQPerWave + qq;
+      if (qmode[q] != kQueryNormal) continue;
+      const uint32_t key = qk[q];
+      const double a = qa[q], b = qb[q], c = qc[q];
+      uint32_t c0 = cnt[q];
+      scanned += (uint64_t)clen;
+      for (int r0 = 0; r0 < clen; r0 += kWave) {
+        const int r = r0 + lane;
+        bool hit = false;
+        const bool ang = r < clen && key_distance(key, sC[r]) <= sH[r];
+        if (ang) {
+          const float2 xy = sXY[r];
+          hit = within_tolerance(a, b, c, xy.x, xy.y, sE[r]);
+        }
+        angle_hits += (uint64_t)__popcll(ballot(ang));
+        const uint64_t m = ballot(hit);
+        if (hit) {
+          const uint32_t slot = c0 + lanes_below(m);
+          if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
+        }
+        c0 += (uint32_t)__popcll(m);
+      }
+      if (lane == 0) cnt[q] = c0;
+    }
+    __syncthreads();
+  }
+
+  // queries whose line misses the epipole too far: exact scan of the pair
+  for (int qq = 0; qq < kQPerWave; ++qq) {
+    const int q = wave * kQPerWave + qq;
+    if (qmode[q] != kQueryBrute) continue;
+    const double a = qa[q], b = qb[q], c = qc[q];
+    uint32_t c0 = 0;
+    brute += 1;
+    scanned += (uint64_t)pd.n;
+    angle_hits += (uint64_t)pd.n;
+    for (int64_t base = pd.k_begin; base < pd.k_begin + pd.n; base += kWave) {
+      const int64_t pos = base + lane;
+      bool hit = false;
+      if (pos < pd.k_begin + pd.n) {
+        const float2 xy = A.rxy[pos];
+        hit = within_tolerance(a, b, c, xy.x, xy.y, A.reps[pos]);
+      }
+      const uint64_t m = ballot(hit);
+      if (hit) {
+        const uint32_t slot = c0 + lanes_below(m);
+        if (slot < (uint32_t)kStage) hits[q][slot] = A.rj[pos];
+      }
+      c0 += (uint32_t)__popcll(m);
+    }
+    if (lane == 0) cnt[q] = c0;
+  }
+  wave_sync_lds();
+  if (lane == 0 && A.stats) {
+    uint64_t empty = 0;
+    for (int qq = 0; qq < kQPerWave; ++qq) {
+      const int q = wave * kQPerWave + qq;
+      if (q < T.count && qmode[q] == kQueryEmpty) ++empty;
+    }
+    if (brute) atomicAdd(&A.stats[0], (unsigned long long)brute);
+    if (scanned) atomicAdd(&A.stats[1], (unsigned long long)scanned);
+    if (angle_hits) atomicAdd(&A.stats[2], (unsigned long long)angle_hits);
+    if (empty) atomicAdd(&A.stats[3], (unsigned long long)empty);
+  }
+
+  // finish: row lengths, and the short rows sorted into the staging buffer
+  for (int qq = 0; qq < kQPerWave; ++qq) {
+    const int q = wave * kQPerWave + qq;
+    if (q >= T.count) break;
+    const int64_t i = qidx[q];
+    const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
+    if (lane == 0) A.counts[i] = n;
+    if (n > 0 && n <= (uint32_t)kStage) {
+      const int32_t v = wave_sort64(lane < (int)n ? hits[q][lane] : INT32_MAX);
+      if (lane < (int)n) A.staging[i * kStage + lane] = v;
+    }
+  }
+}
+
+// Fill pass: one wavefront per query in natural order; short rows are copied
+// from the staging buffer, longer ones rebuilt.
+__global__ __launch_bounds__(kThreads) void k_fill_rows(StabArgs A) {
+  __shared__ int32_t rowbuf[kWaves][kRowSortMax];
+  const int lane = lane_id(), wave = wave_id();
+  const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
+  if (i >= A.n1) return;
+  const int64_t o0 = A.row_offsets[i];
+  const int64_t len = A.row_offsets[i + 1] - o0;
+  if (len <= kStage) {
+    if (lane < len && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
+    return;
+  }
+  fill_row(A, i, rowbuf[wave]);
 }
 
 // ------------------------------------------------------------------ scan
@@ -285,6 +533,28 @@ hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
   hipLaunchKernelGGL(k_stab<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_clear_stats(unsigned long long* stats) {
+  if (threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(64), 0, s, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_stab_tiles(const StabArgs& a, hipStream_t s) {
+  if (a.num_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stab_tile, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
+  if (a.n1 == 0) return hipSuccess;
+  const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

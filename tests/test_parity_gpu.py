@@ -56,11 +56,18 @@ def test_cfg1_candidates_full_size(motion, eps):
     """6048x4032, 20000 keypoints per image (the at-scale workload)."""
     p = synth.cfg1_pair(motion)
     log(f"cfg1 {motion} eps={eps}")
-    o, c, _ = run_candidates([p], eps)
+    o, c, idx = run_candidates([p], eps)
     ro, rc, _ = oracle.candidates(p.F, p.kp1, p.kp2, eps)
     assert_csr_equal((o, c), (ro, rc), f"{motion} eps={eps}")
     kbar = len(rc) / p.m
     assert kbar > 5
+    st = idx.stats()
+    log(f"  stats {st}")
+    # the angular index is used for every query (no whole-pair scans) and its
+    # hits are a superset of the exact set
+    assert st["scanned_queries"] == 0
+    assert st["candidates"] == len(rc) <= st["angle_hits"] <= st["records_scanned"]
+    assert st["angle_hits"] <= 1.2 * st["candidates"] + p.m
 
 
 def test_cfg1_batched_equals_per_pair():
@@ -76,9 +83,12 @@ def test_cfg3_mixed_batch():
     """Uneven pairs with far, infinite, inside and general epipoles."""
     pairs = [synth.cfg3_pair(r, max_kp=4000) for r in range(24)]
     log("cfg3 mixed batch of 24")
-    o, c, _ = run_candidates(pairs, 2.0)
+    o, c, idx = run_candidates(pairs, 2.0)
     ro, rc, _ = oracle_batch(pairs, 2.0)
     assert_csr_equal((o, c), (ro, rc), "cfg3 mixed")
+    st = idx.stats()
+    log(f"  stats {st}")
+    assert st["scanned_queries"] == 0
 
 
 def test_per_keypoint_eps_and_invalid_values():
