@@ -24,7 +24,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
-  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats;
+  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
+  size_t digit_base;
   size_t total;
 };
 
@@ -69,6 +70,8 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.partials = take(sizeof(int64_t) * (size_t)scan_partials_count(n1));
   L.staging = take(sizeof(int32_t) * kStage * N1);
   L.stats = take(sizeof(unsigned long long) * kNumStats);
+  L.long_rows = take(sizeof(uint32_t) * N1);
+  L.digit_base = take(sizeof(uint32_t) * 256 * P);
   L.total = off;
   return L;
 }
@@ -338,7 +341,7 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
                            idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
                            idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
                            idx->at<SortSeg>(L.rsegs), num_pairs, idx->at<uint32_t>(L.hist),
-                           kSortBits, &in1, stream) != hipSuccess)
+                           kSortBits, &in1, stream, idx->at<uint32_t>(L.digit_base)) != hipSuccess)
     return fail(EPM_ERR_HIP);
   const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
   const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
@@ -349,9 +352,12 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
                             idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv), stream) != hipSuccess)
     return fail(EPM_ERR_HIP);
   idx->skey_off = in1 ? L.rk1 : L.rk0;
-  if (launch_class_bounds(dkstart, num_pairs, skey,
-                          idx->at<int64_t>(L.class_begin), stream) != hipSuccess)
-    return fail(EPM_ERR_HIP);
+  const hipError_t cb =
+      n2 > 0 ? launch_class_bounds_from_digits(dkstart, num_pairs, idx->at<uint32_t>(L.digit_base),
+                                               idx->at<int64_t>(L.class_begin), stream)
+             : launch_class_bounds(dkstart, num_pairs, skey, idx->at<int64_t>(L.class_begin),
+                                   stream);
+  if (cb != hipSuccess) return fail(EPM_ERR_HIP);
   *out = idx;
   return EPM_OK;
 }
@@ -412,6 +418,7 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
   A.num_tiles = (int)idx->stiles.size();
   A.staging = idx->at<int32_t>(L.staging);
   A.stats = idx->at<unsigned long long>(L.stats);
+  A.long_rows = idx->at<uint32_t>(L.long_rows);
   idx->last_stream = stream;
   idx->last_offsets = row_offsets;
   idx->have_stats = true;
@@ -474,12 +481,16 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   A.best_idx = best_idx;
   A.best_dist = best_dist;
   A.second_dist = second_dist;
+  A.tiles = idx->at<StabTile>(L.stiles);
+  A.num_tiles = (int)idx->stiles.size();
+  // the tiled kernels walk the angle tiles of the last query pass
+  const bool tiled = algo == EPM_ALGO_TILED && idx->have_qperm;
   switch (dtype) {
     case EPM_F32:
-      EPM_HIP(launch_match_plain_f32(A, stream));
+      EPM_HIP(tiled ? launch_match_tiled_f32(A, stream) : launch_match_plain_f32(A, stream));
       return EPM_OK;
     case EPM_BIN256:
-      EPM_HIP(launch_match_plain_bin256(A, stream));
+      EPM_HIP(tiled ? launch_match_tiled_bin256(A, stream) : launch_match_plain_bin256(A, stream));
       return EPM_OK;
     default:
       return EPM_ERR_UNSUPPORTED;
@@ -503,7 +514,7 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->queries = idx->N1;
   if (!idx->have_stats) return EPM_OK;
-  unsigned long long c[kNumStats] = {0, 0, 0, 0};
+  unsigned long long c[kNumStats] = {0, 0, 0, 0, 0};
   int64_t nnz = 0;
   EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.stats), sizeof(c),
                          hipMemcpyDeviceToHost, idx->last_stream));
@@ -511,10 +522,10 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
                          idx->last_stream));
   EPM_HIP(hipStreamSynchronize(idx->last_stream));
   out->candidates = nnz;
-  out->scanned_queries = (int64_t)c[0];
-  out->records_scanned = (int64_t)c[1];
-  out->angle_hits = (int64_t)c[2];
-  out->empty_queries = (int64_t)c[3];
+  out->scanned_queries = (int64_t)c[kStatScannedQueries];
+  out->records_scanned = (int64_t)c[kStatRecords];
+  out->angle_hits = (int64_t)c[kStatAngleHits];
+  out->empty_queries = (int64_t)c[kStatEmpty];
   return EPM_OK;
 }
 

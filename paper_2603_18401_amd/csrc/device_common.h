@@ -13,6 +13,17 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This maps dispatch order to a logical tile order in which consecutive
+// logical tiles -- neighbouring angle ranges that share candidates -- run on
+// the same XCD.  A bijection of [0, n).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_tile(int block, int n) {
+  const int x = block % kNumXcd, k = block / kNumXcd;
+  const int q = n / kNumXcd, r = n % kNumXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

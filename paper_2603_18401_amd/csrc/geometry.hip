@@ -183,6 +183,27 @@ __global__ __launch_bounds__(64) void k_class_bounds(const int64_t* __restrict__
   }
 }
 
+__global__ __launch_bounds__(64) void k_class_bounds_from_digits(
+    const int64_t* __restrict__ kstart, const uint32_t* __restrict__ digit_base,
+    int64_t* __restrict__ class_begin) {
+  const int p = blockIdx.x;
+  const int c = threadIdx.x;
+  if (c > kNumClasses) return;
+  const int64_t v = c == kNumClasses
+                        ? kstart[p + 1]
+                        : (int64_t)digit_base[(int64_t)p * 256 + (c << (kSortBits - 16 - kClassBits))];
+  class_begin[(int64_t)p * kClassSlots + c] = v;
+}
+
+hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
+                                           const uint32_t* digit_base, int64_t* class_begin,
+                                           hipStream_t s) {
+  if (num_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_bounds_from_digits, dim3(num_pairs), dim3(64), 0, s, kstart,
+                     digit_base, class_begin);
+  return hipGetLastError();
+}
+
 hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num_pairs,
                             int64_t n2, const float* kp2, const float* eps2, float eps_scalar,
                             uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,

@@ -25,15 +25,22 @@ hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n
 
 hipError_t launch_class_bounds(const int64_t* kstart, int num_pairs, const uint32_t* skey,
                                int64_t* class_begin, hipStream_t s);
+// Class starts from the digit bases of the last sort pass (digit = class << 3
+// | top three centre bits).
+hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
+                                           const uint32_t* digit_base, int64_t* class_begin,
+                                           hipStream_t s);
 
 // Stable LSD radix sort of (key, value) u32 pairs inside every segment, over
 // the low `bits` bits of the keys, 8 bits per pass.  Ping-pongs between
 // (k0, v0) and (k1, v1); returns through *sorted_in_1 whether the result
 // ended in (k1, v1).
+// last_digit_base (optional, [num_segs][256]): global start of every digit
+// value of the last pass inside each segment.
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
                                 int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
-                                hipStream_t s);
+                                hipStream_t s, uint32_t* last_digit_base = nullptr);
 
 struct StabArgs {
   const PairDev* pairs;
@@ -60,9 +67,12 @@ struct StabArgs {
   int num_tiles;
   int32_t* staging;  // [n1][kStage], indexed by the original query index
   unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
+  uint32_t* long_rows;        // [n1] queue of rows longer than kStage
 };
 
-constexpr int kNumStats = 4;  // scanned queries, records scanned, angle hits, empty
+constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
+              kStatLongRows = 4;
+constexpr int kNumStats = 5;
 hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
 
 hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
@@ -91,10 +101,14 @@ struct MatchArgs {
   int32_t* best_idx;
   float* best_dist;
   float* second_dist;
+  const StabTile* tiles;  // angle tiles of the last query pass (tiled kernels)
+  int num_tiles;
 };
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_tiled_f32(const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_tiled_bin256(const MatchArgs& a, hipStream_t s);
 
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,

@@ -35,7 +35,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __restrict__ segs,
-                                                               uint32_t* __restrict__ hist) {
+                                                               uint32_t* __restrict__ hist,
+                                                               uint32_t* __restrict__ seg_base) {
   __shared__ uint32_t sc[kRadix];
   const SortSeg sg = segs[blockIdx.x];
   const int d = threadIdx.x;
@@ -51,6 +52,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __
     __syncthreads();
   }
   uint32_t run = (uint32_t)sg.begin + sc[d] - total;
+  // start of every digit inside the segment (after the last pass: the sorted
+  // order's bucket boundaries)
+  if (seg_base) seg_base[(int64_t)blockIdx.x * kRadix + d] = run;
   for (int t = 0; t < sg.tile_count; ++t) {
     const int64_t h = (int64_t)(sg.tile_begin + t) * kRadix + d;
     const uint32_t c = hist[h];
@@ -108,14 +112,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
                                 int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
-                                hipStream_t s) {
+                                hipStream_t s, uint32_t* last_digit_base) {
   *sorted_in_1 = false;
   if (num_tiles == 0) return hipSuccess;
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, shift,
                        hist);
-    hipLaunchKernelGGL(k_sort_offsets, dim3(num_segs), dim3(kSortThreads), 0, s, segs, hist);
+    const bool last = shift + 8 >= bits;
+    hipLaunchKernelGGL(k_sort_offsets, dim3(num_segs), dim3(kSortThreads), 0, s, segs, hist,
+                       last ? last_digit_base : nullptr);
     hipLaunchKernelGGL(k_sort_scatter, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
                        tiles, shift, hist);
     hipError_t e = hipGetLastError();

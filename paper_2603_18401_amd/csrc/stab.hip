@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   __shared__ int64_t qidx[kTileQ];
   __shared__ int64_t slot_b[kSlots], slot_pref[kSlots + 1];
 
-  const StabTile T = A.tiles[blockIdx.x];
+  const StabTile T = A.tiles[xcd_tile(blockIdx.x, A.num_tiles)];
   const PairDev& pd = A.pairs[T.pair];
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
 
@@ -410,10 +410,10 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       const int q = wave * kQPerWave + qq;
       if (q < T.count && qmode[q] == kQueryEmpty) ++empty;
     }
-    if (brute) atomicAdd(&A.stats[0], (unsigned long long)brute);
-    if (scanned) atomicAdd(&A.stats[1], (unsigned long long)scanned);
-    if (angle_hits) atomicAdd(&A.stats[2], (unsigned long long)angle_hits);
-    if (empty) atomicAdd(&A.stats[3], (unsigned long long)empty);
+    if (brute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)brute);
+    if (scanned) atomicAdd(&A.stats[kStatRecords], (unsigned long long)scanned);
+    if (angle_hits) atomicAdd(&A.stats[kStatAngleHits], (unsigned long long)angle_hits);
+    if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
   }
 
   // finish: row lengths, and the short rows sorted into the staging buffer
@@ -430,10 +430,9 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   }
 }
 
-// Fill pass: one wavefront per query in natural order; short rows are copied
-// from the staging buffer, longer ones rebuilt.
-__global__ __launch_bounds__(kThreads) void k_fill_rows(StabArgs A) {
-  __shared__ int32_t rowbuf[kWaves][kRowSortMax];
+// Fill pass, part 1: one wavefront per query in natural order copies the
+// parked short rows; longer rows are queued for part 2.
+__global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int lane = lane_id(), wave = wave_id();
   const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
   if (i >= A.n1) return;
@@ -441,9 +440,21 @@ __global__ __launch_bounds__(kThreads) void k_fill_rows(StabArgs A) {
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len <= kStage) {
     if (lane < len && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
-    return;
+  } else if (lane == 0) {
+    const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
+    A.long_rows[slot] = (uint32_t)i;
   }
-  fill_row(A, i, rowbuf[wave]);
+}
+
+// Fill pass, part 2: rebuilds the queued long rows (grid-stride over the
+// queue, whose length only the device knows).
+__global__ __launch_bounds__(kThreads) void k_fill_long(StabArgs A) {
+  __shared__ int32_t rowbuf[kWaves][kRowSortMax];
+  const int wave = wave_id();
+  const uint64_t n = A.stats[kStatLongRows];
+  for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wave; t < n;
+       t += (uint64_t)gridDim.x * kWaves)
+    fill_row(A, (int64_t)A.long_rows[t], rowbuf[wave]);
 }
 
 // ------------------------------------------------------------------ scan
@@ -554,7 +565,9 @@ hipError_t launch_stab_tiles(const StabArgs& a, hipStream_t s) {
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  const int64_t lblocks = blocks < 512 ? blocks : 512;
+  hipLaunchKernelGGL(k_fill_long, dim3((unsigned)lblocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ def test_per_keypoint_eps_and_invalid_values():
     assert_csr_equal((o, c), (ro, rc), "eps2")
 
 
-def _match_parity(p, eps, ratio, binary=False):
+def _match_parity(p, eps, ratio, binary=False, algo="plain"):
     import paper_2603_18401_amd as E
     torch = torch_gpu()
     dev = torch.device("cuda:0")
@@ -112,10 +112,10 @@ def _match_parity(p, eps, ratio, binary=False):
     offs, cols = idx.query(k1)
     if binary:
         d1, d2 = torch.from_numpy(p.bin1).to(dev), torch.from_numpy(p.bin2).to(dev)
-        bi, bd, sd = idx.match(offs, cols, d1, d2, dtype="bin256", ratio=ratio)
+        bi, bd, sd = idx.match(offs, cols, d1, d2, dtype="bin256", ratio=ratio, algo=algo)
     else:
         d1, d2 = torch.from_numpy(p.desc1).to(dev), torch.from_numpy(p.desc2).to(dev)
-        bi, bd, sd = idx.match(offs, cols, d1, d2, dtype="f32", ratio=ratio, algo="plain")
+        bi, bd, sd = idx.match(offs, cols, d1, d2, dtype="f32", ratio=ratio, algo=algo)
     torch.cuda.synchronize()
     ro, rc, _ = oracle.candidates(p.F, p.kp1, p.kp2, eps)
     assert_csr_equal((offs.cpu().numpy(), cols.cpu().numpy()), (ro, rc), "csr")
@@ -129,20 +129,29 @@ def _match_parity(p, eps, ratio, binary=False):
     return rb
 
 
+@pytest.mark.parametrize("algo", ["plain", "tiled"])
 @pytest.mark.parametrize("ratio", [0.0, 0.8])
-def test_match_plain_f32_bit_exact(ratio):
+def test_match_f32_bit_exact(ratio, algo):
     p = synth.cfg1_pair("sideways", n_kp=8000)
-    log(f"match f32 ratio={ratio}")
-    rb = _match_parity(p, 2.0, ratio)
+    log(f"match f32 ratio={ratio} algo={algo}")
+    rb = _match_parity(p, 2.0, ratio, algo=algo)
     ok = (p.gt12 >= 0) & (rb >= 0)
     assert (rb[ok] == p.gt12[ok]).mean() > 0.9
 
 
-def test_match_binary_exact():
+@pytest.mark.parametrize("algo", ["plain", "tiled"])
+def test_match_binary_exact(algo):
     p = synth.cfg0_pair(4, binary=True)
-    log("match binary")
-    _match_parity(p, 3.0, 0.0, binary=True)
-    _match_parity(p, 3.0, 0.8, binary=True)
+    log(f"match binary {algo}")
+    _match_parity(p, 3.0, 0.0, binary=True, algo=algo)
+    _match_parity(p, 3.0, 0.8, binary=True, algo=algo)
+
+
+def test_match_f32_forward_wide_rows():
+    """Forward motion at eps 4: long rows and circles around the epipole."""
+    p = synth.cfg1_pair("forward", n_kp=12000)
+    log("match forward eps=4")
+    _match_parity(p, 4.0, 0.0, algo="tiled")
 
 
 def test_repeat_runs_identical():
