@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base;
+  size_t digit_base, windows;
   size_t total;
 };
 
@@ -72,6 +72,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.stats = take(sizeof(unsigned long long) * kNumStats);
   L.long_rows = take(sizeof(uint32_t) * N1);
   L.digit_base = take(sizeof(uint32_t) * 256 * P);
+  L.windows = take(sizeof(TileWindow) * ts);
   L.total = off;
   return L;
 }
@@ -422,7 +423,9 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
   idx->last_stream = stream;
   idx->last_offsets = row_offsets;
   idx->have_stats = true;
+  A.windows = idx->at<TileWindow>(L.windows);
   EPM_HIP(launch_clear_stats(A.stats, stream));
+  EPM_HIP(launch_tile_windows(A, stream));
   EPM_HIP(launch_stab_tiles(A, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   if (nnz_host) {
@@ -485,6 +488,8 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   A.num_tiles = (int)idx->stiles.size();
   // the tiled kernels walk the angle tiles of the last query pass
   const bool tiled = algo == EPM_ALGO_TILED && idx->have_qperm;
+  // AUTO: the gather kernel in angle order, blocks placed XCD-aware
+  A.xcd_order = algo == EPM_ALGO_AUTO;
   switch (dtype) {
     case EPM_F32:
       EPM_HIP(tiled ? launch_match_tiled_f32(A, stream) : launch_match_plain_f32(A, stream));

@@ -14,14 +14,20 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  This maps dispatch order to a logical tile order in which consecutive
-// logical tiles -- neighbouring angle ranges that share candidates -- run on
-// the same XCD.  A bijection of [0, n).
+// L2).  This maps dispatch order to a logical tile order in which groups of
+// kXcdGroup consecutive logical tiles -- neighbouring angle ranges that share
+// candidates -- run on one XCD, while successive groups rotate over the XCDs
+// so uneven work stays balanced.  A bijection of [0, n): the tail that does
+// not fill a whole round of groups keeps the identity order.
 constexpr int kNumXcd = 8;
+constexpr int kXcdGroup = 16;
 __device__ __forceinline__ int xcd_tile(int block, int n) {
+  constexpr int round = kNumXcd * kXcdGroup;
+  const int full = (n / round) * round;
+  if (block >= full) return block;
   const int x = block % kNumXcd, k = block / kNumXcd;
-  const int q = n / kNumXcd, r = n % kNumXcd;
-  return x * q + (x < r ? x : r) + k;
+  const int g = k / kXcdGroup, o = k % kXcdGroup;
+  return (g * kNumXcd + x) * kXcdGroup + o;
 }
 
 // Number of set bits of `mask` below this lane.

@@ -85,6 +85,15 @@ constexpr int kTileQ = 64;
 constexpr int kStage = 64;
 constexpr int kChunk = 512;
 
+// Per-tile record windows found by the window pass: up to two ranges of
+// sorted positions per width class (the second one when the window wraps
+// through angle 0), as start positions and a running prefix of lengths.
+constexpr int kSlots = 2 * kNumClasses;
+struct TileWindow {
+  uint32_t slot_b[kSlots];
+  uint32_t slot_pref[kSlots + 1];
+};
+
 struct StabTile {
   int64_t begin;  // first angle-sorted query position of the tile
   int32_t count;  // queries in the tile (<= kTileQ)

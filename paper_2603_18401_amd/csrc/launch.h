@@ -68,7 +68,11 @@ struct StabArgs {
   int32_t* staging;  // [n1][kStage], indexed by the original query index
   unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
   uint32_t* long_rows;        // [n1] queue of rows longer than kStage
+  TileWindow* windows;        // [num_tiles], written by launch_tile_windows
 };
+
+// One wavefront per tile finds the tile's window in every width class.
+hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
 
 constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
               kStatLongRows = 4;
@@ -103,6 +107,7 @@ struct MatchArgs {
   float* second_dist;
   const StabTile* tiles;  // angle tiles of the last query pass (tiled kernels)
   int num_tiles;
+  bool xcd_order;  // plain kernels: place consecutive blocks on one XCD
 };
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);

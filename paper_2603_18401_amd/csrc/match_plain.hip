@@ -21,7 +21,8 @@ constexpr int kWaves = kThreads / kWave;
 __global__ __launch_bounds__(kThreads) void k_match_plain_f32(MatchArgs A) {
   __shared__ float4 qdesc[kWaves][32];
   const int lane = lane_id(), wave = wave_id();
-  const int64_t qs = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t blk = A.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t qs = blk * kWaves + wave;
   if (qs >= A.n1) return;
   const int64_t i = A.qperm ? (int64_t)A.qperm[qs] : qs;
   const int pair = find_pair(A.qstart, A.num_pairs, i);

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
 
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
-constexpr int kSlots = 2 * kNumClasses;  // up to two record ranges per class
+static_assert(kTileQ == 64 && kStage == 64, "pair and staging indexing use 6-bit fields");
 
 __device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict__ keys,
                                                       int64_t lo, int64_t hi, uint32_t target) {
@@ -236,23 +236,92 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Window pass: for tile t, the record ranges of every width class whose
+// centres lie within [min key - 2^c + 1, max key + 2^c - 1] of the tile's
+// queries; lane c searches class c.  No LDS, so every tile's searches are in
+// flight at once.
+__global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
+  const int lane = lane_id();
+  const int t = blockIdx.x;
+  const StabTile T = A.tiles[t];
+  bool normal = false;
+  uint32_t key = 0;
+  if (lane < T.count) {
+    const int64_t i = A.qperm[T.begin + lane];
+    normal = A.qflag[i] == kQueryNormal;
+    key = A.qkey[i];
+  }
+  const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
+  const uint32_t kmax = wave_max_u32(normal ? key : 0u);
+  const bool any = ballot(normal) != 0;
+  int64_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
+  if (lane < kNumClasses && any) {
+    const int64_t* cb = A.class_begin + (int64_t)T.pair * kClassSlots;
+    const int64_t beg = cb[lane], end = cb[lane + 1];
+    if (beg < end) {
+      const uint32_t span = lane == kWideClass ? 0u : (1u << lane) - 1u;
+      const uint64_t width = (uint64_t)(kmax - kmin) + 2ull * span;
+      if (lane == kWideClass || width >= 0xFFFFE000ull) {
+        b0 = beg;
+        l0 = end - beg;
+      } else {
+        const uint32_t lo = kmin - span, hi = kmax + span;
+        const uint32_t cls = (uint32_t)lane << kCentreBits;
+        const uint32_t blo = cls | (lo >> kCentreShift), bhi = cls | (hi >> kCentreShift);
+        if (lo <= hi) {
+          const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
+          const int64_t r1 = lower_bound_scalar(A.skey, r0, end, bhi + 1u);
+          b0 = r0;
+          l0 = r1 - r0;
+        } else {
+          const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
+          const int64_t r1 = lower_bound_scalar(A.skey, beg, r0, bhi + 1u);
+          b0 = r0;
+          l0 = end - r0;
+          b1 = beg;
+          l1 = r1 - beg;
+        }
+      }
+    }
+  }
+  // slot s = class s/2, part s%2; inclusive scan of the 64 slot lengths
+  const int src = lane >> 1;
+  const int64_t be = __shfl(b0, src), bo = __shfl(b1, src);
+  const int64_t le = __shfl(l0, src), lo_ = __shfl(l1, src);
+  const int64_t myb = (lane & 1) ? bo : be;
+  int64_t incl = (lane & 1) ? lo_ : le;
+  #pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int64_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  TileWindow* w = A.windows + t;
+  w->slot_b[lane] = (uint32_t)myb;
+  w->slot_pref[lane + 1] = (uint32_t)incl;
+  if (lane == 0) w->slot_pref[0] = 0u;
+}
+
 // Counts every row of a tile of kTileQ angle-sorted queries and parks rows of
-// up to kStage candidates (sorted by j) in the staging buffer.  Per width
-// class the tile needs one window, [min key - 2^c + 1, max key + 2^c - 1],
-// found by one lane per class; the windows' records are staged in LDS and
-// every query of the tile tests them with the angle test and the FP64 test.
+// up to kStage candidates (in any order) in the staging buffer.  The window
+// records of the tile are staged in LDS, and every (query, record) pair of
+// the tile is an independent work item: thread -> pair with consecutive
+// threads on different queries of the same record (the record is an LDS
+// broadcast), angle test, FP64 test, and an LDS atomic slot in the query's
+// hit list.  No wavefront-wide dependency chains.
 __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   __shared__ uint32_t sC[kChunk], sH[kChunk];
   __shared__ float2 sXY[kChunk];
   __shared__ float sE[kChunk];
   __shared__ int32_t sJ[kChunk];
-  __shared__ int32_t hits[kTileQ][kStage];
+  __shared__ int32_t hits[kTileQ][kStage + 1];  // +1: rows start in different banks
   __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ];
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
-  __shared__ int64_t slot_b[kSlots], slot_pref[kSlots + 1];
+  __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
+  __shared__ unsigned long long tile_stats[3];
 
-  const StabTile T = A.tiles[xcd_tile(blockIdx.x, A.num_tiles)];
+  const int tile = xcd_tile(blockIdx.x, A.num_tiles);
+  const StabTile T = A.tiles[tile];
   const PairDev& pd = A.pairs[T.pair];
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
 
@@ -274,66 +343,17 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
     qmode[lane] = live ? flag : kQueryEmpty;
     qidx[lane] = i;
     cnt[lane] = 0;
-    const bool normal = live && flag == kQueryNormal;
-    const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
-    const uint32_t kmax = wave_max_u32(normal ? key : 0u);
-    const bool any = ballot(normal) != 0;
-    // lane c < 32 finds class c's record ranges for the whole tile
-    int64_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
-    if (lane < kNumClasses && any) {
-      const int64_t* cb = A.class_begin + (int64_t)T.pair * kClassSlots;
-      const int64_t beg = cb[lane], end = cb[lane + 1];
-      if (beg < end) {
-        const uint32_t span = lane == kWideClass ? 0u : (1u << lane) - 1u;
-        const uint64_t width = (uint64_t)(kmax - kmin) + 2ull * span;
-        if (lane == kWideClass || width >= 0xFFFFE000ull) {
-          b0 = beg;
-          l0 = end - beg;
-        } else {
-          const uint32_t lo = kmin - span, hi = kmax + span;
-          const uint32_t cls = (uint32_t)lane << kCentreBits;
-          const uint32_t blo = cls | (lo >> kCentreShift), bhi = cls | (hi >> kCentreShift);
-          if (lo <= hi) {
-            const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
-            const int64_t r1 = lower_bound_scalar(A.skey, r0, end, bhi + 1u);
-            b0 = r0;
-            l0 = r1 - r0;
-          } else {
-            const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
-            const int64_t r1 = lower_bound_scalar(A.skey, beg, r0, bhi + 1u);
-            b0 = r0;
-            l0 = end - r0;
-            b1 = beg;
-            l1 = r1 - beg;
-          }
-        }
-      }
-    }
-    if (lane < kNumClasses) {
-      slot_b[2 * lane] = b0;
-      slot_b[2 * lane + 1] = b1;
-    }
-    // inclusive scan of the 64 slot lengths (slot s = class s/2, part s%2)
-    const int64_t mylen_even = l0, mylen_odd = l1;
-    int64_t len = 0;
-    {
-      const int src = lane >> 1;
-      const int64_t le = __shfl(mylen_even, src), lo_ = __shfl(mylen_odd, src);
-      len = (lane & 1) ? lo_ : le;
-    }
-    int64_t incl = len;
-    #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int64_t o = __shfl_up(incl, off);
-      if (lane >= off) incl += o;
-    }
-    slot_pref[lane + 1] = incl;
-    if (lane == 0) slot_pref[0] = 0;
+    if (lane < 3) tile_stats[lane] = 0ull;
+  }
+  {
+    const TileWindow* w = A.windows + tile;
+    if (tid < kSlots) slot_b[tid] = w->slot_b[tid];
+    if (tid <= kSlots) slot_pref[tid] = w->slot_pref[tid];
   }
   __syncthreads();
 
   const int64_t total_len = slot_pref[kSlots];
-  uint64_t scanned = 0, angle_hits = 0, brute = 0;
+  uint32_t scanned = 0, angle_hits = 0;
   for (int64_t base = 0; base < total_len; base += kChunk) {
     const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
     for (int v = tid; v < clen; v += kThreads) {
@@ -350,43 +370,30 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       sJ[v] = A.rj[pos];
     }
     __syncthreads();
-    for (int qq = 0; qq < kQPerWave; ++qq) {
-      const int q = wave * kQPerWave + qq;
+    const int npairs = clen * kTileQ;
+    for (int p = tid; p < npairs; p += kThreads) {
+      const int q = p & (kTileQ - 1);
+      const int r = p >> 6;
       if (qmode[q] != kQueryNormal) continue;
-      const uint32_t key = qk[q];
-      const double a = qa[q], b = qb[q], c = qc[q];
-      uint32_t c0 = cnt[q];
-      scanned += (uint64_t)clen;
-      for (int r0 = 0; r0 < clen; r0 += kWave) {
-        const int r = r0 + lane;
-        bool hit = false;
-        const bool ang = r < clen && key_distance(key, sC[r]) <= sH[r];
-        if (ang) {
-          const float2 xy = sXY[r];
-          hit = within_tolerance(a, b, c, xy.x, xy.y, sE[r]);
-        }
-        angle_hits += (uint64_t)__popcll(ballot(ang));
-        const uint64_t m = ballot(hit);
-        if (hit) {
-          const uint32_t slot = c0 + lanes_below(m);
-          if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
-        }
-        c0 += (uint32_t)__popcll(m);
-      }
-      if (lane == 0) cnt[q] = c0;
+      ++scanned;
+      if (key_distance(qk[q], sC[r]) > sH[r]) continue;
+      ++angle_hits;
+      const float2 xy = sXY[r];
+      if (!within_tolerance(qa[q], qb[q], qc[q], xy.x, xy.y, sE[r])) continue;
+      const uint32_t slot = atomicAdd(&cnt[q], 1u);
+      if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
     }
     __syncthreads();
   }
 
   // queries whose line misses the epipole too far: exact scan of the pair
+  uint32_t brute = 0;
   for (int qq = 0; qq < kQPerWave; ++qq) {
     const int q = wave * kQPerWave + qq;
     if (qmode[q] != kQueryBrute) continue;
     const double a = qa[q], b = qb[q], c = qc[q];
     uint32_t c0 = 0;
     brute += 1;
-    scanned += (uint64_t)pd.n;
-    angle_hits += (uint64_t)pd.n;
     for (int64_t base = pd.k_begin; base < pd.k_begin + pd.n; base += kWave) {
       const int64_t pos = base + lane;
       bool hit = false;
@@ -403,30 +410,30 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
     }
     if (lane == 0) cnt[q] = c0;
   }
-  wave_sync_lds();
-  if (lane == 0 && A.stats) {
-    uint64_t empty = 0;
-    for (int qq = 0; qq < kQPerWave; ++qq) {
-      const int q = wave * kQPerWave + qq;
-      if (q < T.count && qmode[q] == kQueryEmpty) ++empty;
+  if (A.stats) {
+    if (scanned) atomicAdd(&tile_stats[0], (unsigned long long)scanned);
+    if (angle_hits) atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
+  }
+  __syncthreads();
+  if (A.stats && tid == 0) {
+    uint64_t empty = 0, nbrute = 0;
+    for (int q = 0; q < T.count; ++q) {
+      empty += qmode[q] == kQueryEmpty;
+      nbrute += qmode[q] == kQueryBrute;
     }
-    if (brute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)brute);
-    if (scanned) atomicAdd(&A.stats[kStatRecords], (unsigned long long)scanned);
-    if (angle_hits) atomicAdd(&A.stats[kStatAngleHits], (unsigned long long)angle_hits);
+    if (nbrute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nbrute);
+    atomicAdd(&A.stats[kStatRecords], tile_stats[0] + nbrute * (uint64_t)pd.n);
+    atomicAdd(&A.stats[kStatAngleHits], tile_stats[1] + nbrute * (uint64_t)pd.n);
     if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
   }
+  (void)brute;
 
-  // finish: row lengths, and the short rows sorted into the staging buffer
-  for (int qq = 0; qq < kQPerWave; ++qq) {
-    const int q = wave * kQPerWave + qq;
-    if (q >= T.count) break;
-    const int64_t i = qidx[q];
+  // row lengths, and short rows parked unsorted (the copy pass sorts them)
+  if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
+  for (int p = tid; p < T.count * kStage; p += kThreads) {
+    const int q = p >> 6, t = p & (kStage - 1);
     const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
-    if (lane == 0) A.counts[i] = n;
-    if (n > 0 && n <= (uint32_t)kStage) {
-      const int32_t v = wave_sort64(lane < (int)n ? hits[q][lane] : INT32_MAX);
-      if (lane < (int)n) A.staging[i * kStage + lane] = v;
-    }
+    if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
   }
 }
 
@@ -439,7 +446,12 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len <= kStage) {
-    if (lane < len && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
+    // rank sort of the parked row: the j are distinct, so each lane's rank
+    // is the number of smaller entries (readlane broadcasts, no LDS)
+    const int32_t v = lane < len ? A.staging[i * kStage + lane] : INT32_MAX;
+    uint32_t rank = 0;
+    for (int t = 0; t < (int)len; ++t) rank += __builtin_amdgcn_readlane(v, t) < v ? 1u : 0u;
+    if (lane < len && o0 + rank < A.capacity) A.cols[o0 + rank] = v;
   } else if (lane == 0) {
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
@@ -553,6 +565,12 @@ __global__ void k_clear_stats(unsigned long long* stats) {
 
 hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(64), 0, s, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
+  if (a.num_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_windows, dim3(a.num_tiles), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 
