@@ -486,16 +486,19 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   A.second_dist = second_dist;
   A.tiles = idx->at<StabTile>(L.stiles);
   A.num_tiles = (int)idx->stiles.size();
-  // the tiled kernels walk the angle tiles of the last query pass
-  const bool tiled = algo == EPM_ALGO_TILED && idx->have_qperm;
-  // AUTO: the gather kernel in angle order, blocks placed XCD-aware
-  A.xcd_order = algo == EPM_ALGO_AUTO;
+  A.windows = idx->at<TileWindow>(L.windows);
+  A.rinv = idx->at<uint32_t>(L.rinv);
+  A.rj = idx->at<int32_t>(L.rj);
+  A.xcd_order = false;
+  // the window kernel walks the angle tiles and windows of the last query
+  const bool tiled = algo != EPM_ALGO_PLAIN && idx->have_qperm;
   switch (dtype) {
     case EPM_F32:
-      EPM_HIP(tiled ? launch_match_tiled_f32(A, stream) : launch_match_plain_f32(A, stream));
+      EPM_HIP(tiled ? launch_match_window_f32(A, stream) : launch_match_plain_f32(A, stream));
       return EPM_OK;
     case EPM_BIN256:
-      EPM_HIP(tiled ? launch_match_tiled_bin256(A, stream) : launch_match_plain_bin256(A, stream));
+      // 32-byte rows: per-candidate gathers are already line-efficient
+      EPM_HIP(launch_match_plain_bin256(A, stream));
       return EPM_OK;
     default:
       return EPM_ERR_UNSUPPORTED;

@@ -107,13 +107,16 @@ struct MatchArgs {
   float* second_dist;
   const StabTile* tiles;  // angle tiles of the last query pass (tiled kernels)
   int num_tiles;
+  const TileWindow* windows;  // their record windows
+  const uint32_t* rinv;       // record -> angle-sorted position
+  const int32_t* rj;          // angle-sorted position -> image-2 index in the pair
   bool xcd_order;  // plain kernels: place consecutive blocks on one XCD
 };
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
-hipError_t launch_match_tiled_f32(const MatchArgs& a, hipStream_t s);
-hipError_t launch_match_tiled_bin256(const MatchArgs& a, hipStream_t s);
+// One workgroup per stabbing tile, window descriptor rows staged in LDS.
+hipError_t launch_match_window_f32(const MatchArgs& a, hipStream_t s);
 
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,

@@ -160,3 +160,36 @@ def test_repeat_runs_identical():
     a = run_candidates([p], 2.0)
     b = run_candidates([p], 2.0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_match_window_with_foreign_csr():
+    """A CSR that is not the index's own (extra candidates far from the line)
+    still matches exactly: entries outside the tile windows are gathered."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    dev = torch.device("cuda:0")
+    p = synth.cfg1_pair("forward_yaw", n_kp=6000)
+    log("foreign csr")
+    k1, k2 = torch.from_numpy(p.kp1).to(dev), torch.from_numpy(p.kp2).to(dev)
+    idx = E.Index([E.PairSpec(p.F, p.W, p.H, p.m, p.n)], k2, eps=2.0)
+    offs, cols = idx.query(k1)
+    o, c = offs.cpu().numpy(), cols.cpu().numpy()
+    rng = np.random.default_rng(11)
+    rows = []
+    for i in range(p.m):
+        r = set(c[o[i]:o[i + 1]].tolist())
+        if i % 3 == 0:
+            r.add(int(rng.integers(0, p.n)))
+        if i % 7 == 0:
+            r = set()
+        rows.append(sorted(r))
+    no = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    nc = np.array([j for r in rows for j in r], np.int32)
+    d1, d2 = torch.from_numpy(p.desc1).to(dev), torch.from_numpy(p.desc2).to(dev)
+    bi, bd, sd = idx.match(torch.from_numpy(no).to(dev), torch.from_numpy(nc).to(dev), d1, d2,
+                           dtype="f32", algo="auto")
+    torch.cuda.synchronize()
+    rb, rbd, rsd = oracle.match(p.desc1, p.desc2, no, nc)
+    assert np.array_equal(bi.cpu().numpy(), rb)
+    assert np.array_equal(bd.cpu().numpy().view(np.uint32), rbd.view(np.uint32))
+    assert np.array_equal(sd.cpu().numpy().view(np.uint32), rsd.view(np.uint32))
