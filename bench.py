@@ -41,7 +41,37 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4000,
                     help="queries per pair in the oracle sample")
     ap.add_argument("--algo", default="auto")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 2 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+KERNEL = "k_match_window_f32"
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_18401_amd", "csrc", "match_window.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_window_traffic.md")
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("source_sha256:", "traffic_bytes_per_launch:")))
+    if vals.get("source_sha256", "").strip() != source_hash(KERNEL_SRC):
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"].strip())
+    except (KeyError, ValueError):
+        return None
 
 
 def make_workload():
@@ -159,10 +189,20 @@ def main():
     b_desc = 512
     match_bytes = N1 * (b_desc + 16 + 12) + nnz * 4 + N2 * b_desc
     achieved = match_bytes / (match_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_match_plain_f32", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(match_avg_ms, 5),
-                "algorithmic_bytes_per_launch": int(match_bytes)}
+    roofline = {"bound": "hbm", "kernel": KERNEL if args.algo == "auto" else args.algo,
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if args.algo == "auto" else None,
+                "avg_launch_ms": round(match_avg_ms, 5),
+                "algorithmic_bytes_per_launch": int(match_bytes),
+                "kernel_source_sha256": source_hash(KERNEL_SRC)}
+
+    if args.calibrate_copy:
+        src = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     # ---- CPU oracle on a bounded sample of the same workload
     cpu = None
