@@ -215,6 +215,23 @@ typedef struct {
  */
 epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out);
 
+/* Counters of the last reduced-precision (BF16 / FP8) epm_match on an index. */
+typedef struct {
+  int64_t queries;        /* image-1 queries                                         */
+  int64_t reranked_rows;  /* rows of 1..64 candidates ranked on MFMA, top-4 re-ranked  */
+  int64_t fallback_rows;  /* of those, not certified: every candidate evaluated exactly */
+  int64_t long_rows;      /* rows longer than 64: every candidate evaluated exactly    */
+} epm_match_stats;
+
+/*
+ * Reads the counters of the last BF16/FP8 epm_match on idx (waits for the
+ * stream that call used).  fallback_rows / reranked_rows is the rate at which
+ * the four re-ranked candidates could not be certified to contain the exact
+ * best and second; those rows are then evaluated exactly, so results never
+ * depend on it.
+ */
+epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out);
+
 /* Releases the host object; the device workspace stays owned by the caller. */
 void epm_index_destroy(epm_index* idx);
 

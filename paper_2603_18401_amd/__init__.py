@@ -31,7 +31,7 @@ DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "bin256": 3}
 ALGOS = {"auto": 0, "plain": 1, "tiled": 2}
 EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates", "epm_match",
            "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms",
-           "epm_get_query_stats"]
+           "epm_get_query_stats", "epm_get_match_stats"]
 
 
 class EpmError(RuntimeError):
@@ -50,6 +50,11 @@ class _Pair(ctypes.Structure):
 class _QueryStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("queries", "empty_queries", "scanned_queries",
                                                "records_scanned", "angle_hits", "candidates")]
+
+
+class _MatchStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("queries", "reranked_rows", "fallback_rows",
+                                               "long_rows")]
 
 
 class _MatchOpts(ctypes.Structure):
@@ -90,6 +95,8 @@ def load_library(path=None):
     lib.epm_point_line_terms.restype = ctypes.c_int
     lib.epm_get_query_stats.argtypes = [V, ctypes.POINTER(_QueryStats)]
     lib.epm_get_query_stats.restype = ctypes.c_int
+    lib.epm_get_match_stats.argtypes = [V, ctypes.POINTER(_MatchStats)]
+    lib.epm_get_match_stats.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -213,6 +220,12 @@ class Index:
         """Counters of the last query (dict; waits for its stream)."""
         st = _QueryStats()
         _check(self.lib.epm_get_query_stats(self.handle, ctypes.byref(st)), "epm_get_query_stats")
+        return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def match_stats(self):
+        """Counters of the last BF16/FP8 match (dict; waits for its stream)."""
+        st = _MatchStats()
+        _check(self.lib.epm_get_match_stats(self.handle, ctypes.byref(st)), "epm_get_match_stats")
         return {k: int(getattr(st, k)) for k, _ in st._fields_}
 
     def match(self, row_offsets, col_indices, desc1, desc2, dtype="f32", scale1=None,

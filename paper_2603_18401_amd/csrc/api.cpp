@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows;
+  size_t digit_base, windows, match_stats;
   size_t total;
 };
 
@@ -73,6 +73,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.long_rows = take(sizeof(uint32_t) * N1);
   L.digit_base = take(sizeof(uint32_t) * 256 * P);
   L.windows = take(sizeof(TileWindow) * ts);
+  L.match_stats = take(sizeof(unsigned long long) * kNumMatchStats);
   L.total = off;
   return L;
 }
@@ -226,6 +227,8 @@ struct epm_index {
   hipStream_t last_stream = nullptr;  // stream of the last query call
   const int64_t* last_offsets = nullptr;
   bool have_stats = false;
+  bool have_match_stats = false;
+  hipStream_t match_stream = nullptr;
 
   template <typename T>
   T* at(size_t off) const {
@@ -445,10 +448,6 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
                      const float* scale2, const float* desc1_f32, const float* desc2_f32,
                      float ratio, int32_t* best_idx, float* best_dist, float* second_dist,
                      const epm_match_opts* opts, hipStream_t stream) {
-  (void)scale1;
-  (void)scale2;
-  (void)desc1_f32;
-  (void)desc2_f32;
   if (!idx || !row_offsets) return EPM_ERR_ARG;
   if (!(ratio >= 0.0f) || !std::isfinite(ratio)) return EPM_ERR_ARG;
   const int64_t n1 = idx->N1;
@@ -468,6 +467,9 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
     default:
       return EPM_ERR_ARG;
   }
+  const bool reduced = dtype == EPM_BF16 || dtype == EPM_FP8_E4M3;
+  if (reduced && n1 > 0 && (!desc1_f32 || (idx->N2 > 0 && !desc2_f32))) return EPM_ERR_ARG;
+  if (dtype == EPM_FP8_E4M3 && n1 > 0 && (!scale1 || (idx->N2 > 0 && !scale2))) return EPM_ERR_ARG;
   if (n1 == 0) return EPM_OK;
   const Layout& L = idx->L;
   MatchArgs A;
@@ -490,8 +492,28 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   A.rinv = idx->at<uint32_t>(L.rinv);
   A.rj = idx->at<int32_t>(L.rj);
   A.xcd_order = false;
-  // the window kernel walks the angle tiles and windows of the last query
+  A.scale1 = scale1;
+  A.scale2 = scale2;
+  A.desc1_f32 = desc1_f32;
+  A.desc2_f32 = desc2_f32;
+  A.match_stats = idx->at<unsigned long long>(L.match_stats);
+  // the window kernels walk the angle tiles and windows of the last query
   const bool tiled = algo != EPM_ALGO_PLAIN && idx->have_qperm;
+  if (reduced) {
+    epm_index* mi = const_cast<epm_index*>(idx);
+    mi->have_match_stats = true;
+    mi->match_stream = stream;
+    EPM_HIP(launch_clear_stats(A.match_stats, stream));
+    if (!tiled) {
+      // no angle tiles to stage: exact FP32 evaluation on the masters
+      A.desc1 = desc1_f32;
+      A.desc2 = desc2_f32;
+      EPM_HIP(launch_match_plain_f32(A, stream));
+      return EPM_OK;
+    }
+    EPM_HIP(launch_match_window_mfma(A, dtype == EPM_BF16 ? 0 : 1, stream));
+    return EPM_OK;
+  }
   switch (dtype) {
     case EPM_F32:
       EPM_HIP(tiled ? launch_match_window_f32(A, stream) : launch_match_plain_f32(A, stream));
@@ -534,6 +556,22 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
   out->records_scanned = (int64_t)c[kStatRecords];
   out->angle_hits = (int64_t)c[kStatAngleHits];
   out->empty_queries = (int64_t)c[kStatEmpty];
+  return EPM_OK;
+}
+
+epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out) {
+  if (!idx || !out) return EPM_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->queries = idx->N1;
+  if (!idx->have_match_stats) return EPM_OK;
+  unsigned long long c[kNumStats] = {0, 0, 0, 0, 0};
+  EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.match_stats),
+                         sizeof(unsigned long long) * kNumMatchStats, hipMemcpyDeviceToHost,
+                         idx->match_stream));
+  EPM_HIP(hipStreamSynchronize(idx->match_stream));
+  out->reranked_rows = (int64_t)c[0];
+  out->fallback_rows = (int64_t)c[1];
+  out->long_rows = (int64_t)c[2];
   return EPM_OK;
 }
 

@@ -111,7 +111,16 @@ struct MatchArgs {
   const uint32_t* rinv;       // record -> angle-sorted position
   const int32_t* rj;          // angle-sorted position -> image-2 index in the pair
   bool xcd_order;  // plain kernels: place consecutive blocks on one XCD
+  const float* scale1;        // FP8 row scales
+  const float* scale2;
+  const float* desc1_f32;     // FP32 masters (re-rank and exact fallback)
+  const float* desc2_f32;
+  unsigned long long* match_stats;  // [kNumMatchStats], cleared before the launch
 };
+
+constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallback), long rows
+// fmt 0: BF16, 1: FP8-E4M3 with row scales.
+hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, hipStream_t s);
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);

@@ -1,0 +1,423 @@
+// Reduced-precision descriptor matching with exact final results (Sec. 4.3).
+//
+// Descriptors stored as BF16 or as OCP FP8-E4M3 with a per-row FP32 scale are
+// compared on MFMA (dense query-tile x window-row score blocks, FP32
+// accumulation); the FP32 masters are used only to re-rank a few candidates.
+// Per workgroup (one angle tile of 64 queries):
+//   1. the tile's CSR rows are mapped to window indices (as in the FP32 window
+//      kernel);
+//   2. quantised query rows and, chunk by chunk, quantised window rows are
+//      staged in LDS; S = Q W^T on v_mfma_f32_16x16x32_{bf16,fp8_fp8};
+//   3. every candidate gets a rigorous lower bound LB on its exact canonical
+//      FP32 distance from the approximate distance |q^|^2 + |w^|^2 - 2 s S and
+//      the format's rounding bound;
+//   4. the four candidates with the smallest LB are re-ranked with canonical
+//      FP32 chains on the masters; when the smallest LB among the others
+//      exceeds the exact second distance (or the row has at most four
+//      candidates), best and second are certified exact;
+//   5. otherwise (and for rows longer than 64) every candidate is evaluated
+//      exactly -- the fallback, counted in the match statistics.
+// Final outputs therefore equal the FP32 path bit for bit.
+#include "device_common.h"
+#include "launch.h"
+#include "match_common.h"
+
+namespace epm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kChunkRows = 64;
+constexpr int kMaxPairs = kTileQ * kStage;
+constexpr uint32_t kPending = 0x80000000u;
+constexpr uint32_t kNoWindow = (1u << 19) - 1u;
+constexpr int kReRank = 4;
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+template <int FMT>
+struct Fmt;
+template <>
+struct Fmt<0> {  // BF16: 8 significant bits, round to nearest even
+  static constexpr int kRowBytes = 256;
+  static constexpr double kUnit = 1.0 / 256.0;  // |x^ - x| <= u |x|
+  static constexpr double kAbs = 0.0;
+  __device__ static float decode(const uint8_t* row, int k) {
+    const uint16_t h = reinterpret_cast<const uint16_t*>(row)[k];
+    return __uint_as_float((uint32_t)h << 16);
+  }
+};
+template <>
+struct Fmt<1> {  // OCP E4M3FN with a per-row scale: 4 significant bits
+  static constexpr int kRowBytes = 128;
+  static constexpr double kUnit = 1.0 / 16.0;
+  static constexpr double kAbs = 1.0 / 1024.0;  // half the subnormal spacing, times scale
+  __device__ static float decode(const uint8_t* row, int k) {
+    const uint32_t c = row[k];
+    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    float v = e == 0 ? (float)m * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return (c & 0x80u) ? -v : v;
+  }
+};
+// LDS row stride: 16 extra bytes start consecutive rows 4 banks apart, so the
+// 16-byte (BF16) or 8-byte (FP8) fragment reads of 16 rows are conflict free.
+template <int FMT>
+constexpr int row_stride() { return Fmt<FMT>::kRowBytes + 16; }
+
+__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t t, uint32_t v) {
+  return kPending | (v << 12) | (t << 6) | q;
+}
+
+__device__ __forceinline__ float exact_distance(const float4* __restrict__ a,
+                                                const float4* __restrict__ b) {
+  float acc = 0.0f;
+  #pragma unroll 8
+  for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, a[k], b[k]);
+  return acc;
+}
+
+// Quantisation error bound of a row from its quantised norm:
+// |x^ - x|_2 <= (u |x^| + a s sqrt(128)) / (1 - u), slightly inflated.
+template <int FMT>
+__device__ __forceinline__ double row_delta(double norm_hat, double scale) {
+  const double u = Fmt<FMT>::kUnit;
+  return (u * norm_hat + Fmt<FMT>::kAbs * scale * 11.313708498984761) / (1.0 - u) *
+         (1.0 + 1e-6) + 1e-30;
+}
+
+// Lower bound on the exact canonical FP32 distance of a candidate whose
+// approximate squared distance is dt (norms are of the quantised rows):
+//   |dt - |q^ - w^|^2| <= em = 3e-5 (|q^| + |w^|)^2   (FP32 accumulation),
+//   | |q^ - w^| - |q - w| | <= dq + dw,
+//   canonical >= (1 - 1e-5) |q - w|^2               (130 roundings of 2^-24).
+__device__ __forceinline__ double lower_bound(double dt, double nq, double nw, double dq,
+                                              double dw) {
+  const double s = nq + nw;
+  const double em = 3e-5 * s * s;
+  const double root = sqrt(fmax(dt - em, 0.0));
+  const double r = fmax(root - (dq + dw), 0.0);
+  return (1.0 - 1e-5) * r * r;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
+  constexpr int RS = row_stride<FMT>();
+  __shared__ __attribute__((aligned(16))) uint8_t qrows[kTileQ * RS];
+  constexpr int kScoreBytes = kTileQ * (kChunkRows + 1) * 4;
+  constexpr int kWBytes = kChunkRows * RS > kScoreBytes ? kChunkRows * RS : kScoreBytes;
+  __shared__ __attribute__((aligned(16))) uint8_t wrows[kWBytes];
+  __shared__ uint32_t ent[kMaxPairs];
+  __shared__ int32_t ent_j[kMaxPairs];
+  __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
+  __shared__ uint32_t ss_b[kSlots], ss_v[kSlots], ss_len[kSlots];
+  __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
+  __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1];
+  __shared__ float q_norm[kTileQ], q_scale[kTileQ], w_norm[kChunkRows], w_scale[kChunkRows];
+  __shared__ int32_t row_j[kChunkRows];
+  __shared__ uint32_t n_sorted_slots, n_fallback;
+  __shared__ uint16_t fallback_q[kTileQ];
+  __shared__ float4 qdesc[kWaves][32];
+  // re-rank scratch: per query the four chosen entries and the fifth bound
+  __shared__ uint32_t pick[kTileQ][kReRank];
+  __shared__ float pick_d[kTileQ][kReRank];
+  __shared__ float lb5[kTileQ];
+
+  const int tile = xcd_tile(blockIdx.x, A.num_tiles);
+  const StabTile T = A.tiles[tile];
+  const int64_t kb = A.kstart[T.pair];
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const TileWindow* W = A.windows + tile;
+  const uint8_t* d1 = reinterpret_cast<const uint8_t*>(A.desc1);
+  const uint8_t* d2 = reinterpret_cast<const uint8_t*>(A.desc2);
+  constexpr int RB = Fmt<FMT>::kRowBytes;
+
+  if (wave == 0) {
+    const int q = lane;
+    int64_t i = 0, o0 = 0, k = 0;
+    if (q < T.count) {
+      i = (int64_t)A.qperm[T.begin + q];
+      o0 = A.row_offsets[i];
+      k = A.row_offsets[i + 1] - o0;
+    }
+    q_i[q] = i;
+    q_o0[q] = o0;
+    q_k[q] = (uint32_t)k;
+    const uint32_t kk = k <= kStage ? (uint32_t)k : 0u;
+    uint32_t incl = kk;
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    q_off[q + 1] = incl;
+    if (lane == 0) {
+      q_off[0] = 0;
+      n_fallback = 0;
+    }
+    const uint32_t b = W->slot_b[lane];
+    const uint32_t p0 = W->slot_pref[lane], p1 = W->slot_pref[lane + 1];
+    slot_b[lane] = b;
+    slot_pref[lane] = p0;
+    if (lane == 0) slot_pref[kSlots] = W->slot_pref[kSlots];
+    const bool nonempty = p1 > p0;
+    const uint64_t ne = ballot(nonempty);
+    uint32_t rank = 0;
+    for (int s = 0; s < kWave; ++s) {
+      const uint32_t bs = __builtin_amdgcn_readlane(b, s);
+      if (((ne >> s) & 1ull) && (bs < b || (bs == b && s < lane))) ++rank;
+    }
+    if (nonempty) {
+      ss_b[rank] = b;
+      ss_v[rank] = p0;
+      ss_len[rank] = p1 - p0;
+    }
+    if (lane == 0) n_sorted_slots = (uint32_t)__popcll(ne);
+  }
+  __syncthreads();
+
+  // quantised query rows (zero rows past the tile end), their norms and scales
+  for (int f = tid; f < kTileQ * (RB / 16); f += kThreads) {
+    const int q = f / (RB / 16), c = f % (RB / 16);
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (q < T.count) v = reinterpret_cast<const uint4*>(d1 + q_i[q] * RB)[c];
+    *reinterpret_cast<uint4*>(qrows + q * RS + c * 16) = v;
+  }
+  // dense (query, candidate, window index) list
+  const uint32_t npairs = q_off[kTileQ];
+  const uint32_t nss = n_sorted_slots;
+  for (uint32_t e = tid; e < npairs; e += kThreads) {
+    uint32_t q = 0;
+    #pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (q + step < kTileQ && q_off[q + step] <= e) q += step;
+    const uint32_t t = e - q_off[q];
+    const int32_t j = A.cols[q_o0[q] + t];
+    const uint32_t pos = A.rinv[kb + j];
+    uint32_t v = kNoWindow;
+    if (nss > 0) {
+      uint32_t s = 0;
+      #pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (s + step < nss && ss_b[s + step] <= pos) s += step;
+      if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
+    }
+    if (v >= kNoWindow) v = kNoWindow;
+    ent[e] = pack_entry(q, t, v);
+    ent_j[e] = j;
+  }
+  __syncthreads();
+  if (tid < kTileQ) {
+    float n = 0.0f;
+    for (int k = 0; k < 128; ++k) {
+      const float x = Fmt<FMT>::decode(qrows + tid * RS, k);
+      n = __builtin_fmaf(x, x, n);
+    }
+    const float s = (FMT == 1 && tid < T.count) ? A.scale1[q_i[tid]] : 1.0f;
+    q_scale[tid] = s;
+    q_norm[tid] = n * s * s;  // squared norm of the dequantised row
+  }
+
+  const uint32_t wlen = slot_pref[kSlots];
+  float* score = reinterpret_cast<float*>(wrows);  // reused after the MFMA reads
+  for (uint32_t c0 = 0; c0 < wlen; c0 += kChunkRows) {
+    const uint32_t nr = wlen - c0 < (uint32_t)kChunkRows ? wlen - c0 : (uint32_t)kChunkRows;
+    for (uint32_t r = tid; r < kChunkRows; r += kThreads) {
+      int32_t j = -1;
+      if (r < nr) {
+        const uint32_t v = c0 + r;
+        uint32_t s = 0;
+        #pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (s + step <= kSlots && slot_pref[s + step] <= v) s += step;
+        j = A.rj[slot_b[s] + (v - slot_pref[s])];
+      }
+      row_j[r] = j;
+    }
+    __syncthreads();
+    for (int f = tid; f < kChunkRows * (RB / 16); f += kThreads) {
+      const int r = f / (RB / 16), c = f % (RB / 16);
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (row_j[r] >= 0) v = reinterpret_cast<const uint4*>(d2 + (kb + row_j[r]) * RB)[c];
+      *reinterpret_cast<uint4*>(wrows + r * RS + c * 16) = v;
+    }
+    __syncthreads();
+    if (tid < kChunkRows) {
+      float n = 0.0f;
+      for (int k = 0; k < 128; ++k) {
+        const float x = Fmt<FMT>::decode(wrows + tid * RS, k);
+        n = __builtin_fmaf(x, x, n);
+      }
+      const float s = (FMT == 1 && row_j[tid] >= 0) ? A.scale2[kb + row_j[tid]] : 1.0f;
+      w_scale[tid] = s;
+      w_norm[tid] = n * s * s;
+    }
+    // S = Q W^T: wavefront w owns queries 16w..16w+15 against all 64 rows
+    f32x4 acc[4];
+    #pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int arow = wave * 16 + (lane & 15);
+    #pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
+      if (FMT == 0) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * RS + koff * 2);
+        #pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(wrows + (cb * 16 + (lane & 15)) * RS + koff * 2);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+        }
+      } else {
+        const long a = *reinterpret_cast<const long*>(qrows + arow * RS + koff);
+        #pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const long b = *reinterpret_cast<const long*>(wrows + (cb * 16 + (lane & 15)) * RS + koff);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave has read wrows; the scores go there now
+    #pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      #pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = wave * 16 + (lane >> 4) * 4 + i;
+        const int r = cb * 16 + (lane & 15);
+        score[q * (kChunkRows + 1) + r] = acc[cb][i];
+      }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < npairs; e += kThreads) {
+      const uint32_t x = ent[e];
+      if (!(x & kPending)) continue;
+      const uint32_t v = (x >> 12) & kNoWindow;
+      if (v < c0 || v >= c0 + nr) continue;
+      const uint32_t q = x & 63u, r = v - c0;
+      const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
+      const double nq = sqrt((double)q_norm[q]) * (1.0 + 1e-5);
+      const double nw = sqrt((double)w_norm[r]) * (1.0 + 1e-5);
+      const double dt = (double)q_norm[q] + (double)w_norm[r] - 2.0 * s;
+      const double lb = lower_bound(dt, nq, nw, row_delta<FMT>(nq, q_scale[q]),
+                                    row_delta<FMT>(nw, w_scale[r]));
+      ent[e] = __float_as_uint((float)lb * (1.0f - 1e-6f));  // rounded down, >= 0
+    }
+    __syncthreads();
+  }
+  // candidates outside the window: bound 0 (always re-ranked or evaluated)
+  for (uint32_t e = tid; e < npairs; e += kThreads)
+    if (ent[e] & kPending) ent[e] = 0u;
+  __syncthreads();
+
+  // choose, per query, the four smallest bounds and the fifth bound
+  if (tid < T.count && q_k[tid] <= (uint32_t)kStage) {
+    const int q = tid;
+    float bd[kReRank + 1];
+    uint32_t be[kReRank + 1];
+    #pragma unroll
+    for (int u = 0; u <= kReRank; ++u) {
+      bd[u] = __builtin_inff();
+      be[u] = 0xFFFFFFFFu;
+    }
+    for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) {
+      float d = __uint_as_float(ent[e]);
+      uint32_t ee = e;
+      #pragma unroll
+      for (int u = 0; u <= kReRank; ++u) {
+        if (d < bd[u]) {
+          const float td = bd[u];
+          const uint32_t te = be[u];
+          bd[u] = d;
+          be[u] = ee;
+          d = td;
+          ee = te;
+        }
+      }
+    }
+    #pragma unroll
+    for (int u = 0; u < kReRank; ++u) pick[q][u] = be[u];
+    lb5[q] = bd[kReRank];
+  }
+  __syncthreads();
+  // exact canonical distances of the picks: thread = (query, pick)
+  {
+    const int q = tid >> 2, u = tid & 3;
+    float d = __builtin_inff();
+    if (q < T.count && q_k[q] <= (uint32_t)kStage && pick[q][u] != 0xFFFFFFFFu) {
+      const int32_t j = ent_j[pick[q][u]];
+      d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
+                         reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
+    }
+    pick_d[q][u] = d;
+  }
+  __syncthreads();
+  if (tid < T.count && q_k[tid] <= (uint32_t)kStage) {
+    const int q = tid;
+    Top2 t;
+    #pragma unroll
+    for (int u = 0; u < kReRank; ++u)
+      if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], ent_j[pick[q][u]]);
+    const uint32_t k = q_k[q];
+    // certified when every candidate left out has a bound above the second
+    const bool ok = k <= (uint32_t)kReRank || lb5[q] > t.sd;
+    if (ok) {
+      write_match(A, q_i[q], t, false);
+    } else {
+      const uint32_t slot = atomicAdd(&n_fallback, 1u);
+      fallback_q[slot] = (uint16_t)q;
+    }
+  }
+  __syncthreads();
+  if (A.match_stats && tid == 0) {
+    uint32_t longs = 0, reranked = 0;
+    for (int q = 0; q < T.count; ++q) {
+      longs += q_k[q] > (uint32_t)kStage;
+      reranked += q_k[q] <= (uint32_t)kStage && q_k[q] > 0;
+    }
+    atomicAdd(&A.match_stats[0], (unsigned long long)reranked);
+    atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
+    atomicAdd(&A.match_stats[2], (unsigned long long)longs);
+  }
+  // fallback and long rows: every candidate exactly, one wavefront per query
+  const uint32_t nfb = n_fallback;
+  for (int t0 = wave; t0 < T.count + (int)nfb; t0 += kWaves) {
+    int q;
+    if (t0 < (int)nfb) {
+      q = fallback_q[t0];
+    } else {
+      q = t0 - (int)nfb;
+      if (q_k[q] <= (uint32_t)kStage) continue;
+    }
+    const int64_t i = q_i[q];
+    if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1_f32)[i * 32 + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    Top2 t;
+    for (int64_t e = q_o0[q] + lane; e < q_o0[q] + q_k[q]; e += kWave) {
+      const int32_t j = A.cols[e];
+      const float4* r2 = reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32;
+      float acc = 0.0f;
+      #pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qdesc[wave][k], r2[k]);
+      t.insert(acc, j);
+    }
+    t = wave_merge_top2(t);
+    if (lane == 0) write_match(A, i, t, false);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, hipStream_t s) {
+  if (a.num_tiles == 0) return hipSuccess;
+  if (fmt == 0)
+    hipLaunchKernelGGL(k_match_window_mfma<0>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_match_window_mfma<1>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace epm
