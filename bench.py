@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--workload", default="scale", choices=["scale", "precision", "batch"],
+                    help="scale: six 20000-keypoint pairs (default); precision: one "
+                         "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs")
+    ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
     return ap.parse_args()
 
 
@@ -85,6 +89,145 @@ def make_workload():
     return pairs, eps_list
 
 
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def precision_workload(args):
+    """One 6048x4032 pair with 60000 keypoints per image, eps = 2 px:
+    retrieve + match with FP32 (window and plain), BF16 and FP8 (MFMA + FP32
+    re-rank) and 256-bit binary descriptors."""
+    import torch
+
+    import paper_2603_18401_amd as E
+    import synth
+    dev = torch.device("cuda:0")
+    p = synth.cfg2_pair(0)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    kp1, kp2 = g(p.kp1), g(p.kp2)
+    m1, m2 = g(p.desc1), g(p.desc2)
+    b1 = g(synth.f32_to_bf16(p.desc1).view(np.int16))
+    b2 = g(synth.f32_to_bf16(p.desc2).view(np.int16))
+    c1, s1 = synth.f32_to_fp8_e4m3(p.desc1)
+    c2, s2 = synth.f32_to_fp8_e4m3(p.desc2)
+    c1, s1, c2, s2 = g(c1), g(s1), g(c2), g(s2)
+    n1, n2 = g(p.bin1), g(p.bin2)
+    spec = [E.PairSpec(p.F, p.W, p.H, p.m, p.n)]
+    idx0 = E.Index(spec, kp2, eps=2.0)
+    ws = idx0.workspace
+    o, c = idx0.query(kp1)
+    nnz = int(o[-1].item())
+    offs = torch.empty(p.m + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(nnz, dtype=torch.int32, device=dev)
+    out = (torch.empty(p.m, dtype=torch.int32, device=dev),
+           torch.empty(p.m, dtype=torch.float32, device=dev),
+           torch.empty(p.m, dtype=torch.float32, device=dev))
+    variants = {
+        "f32": dict(desc1=m1, desc2=m2, dtype="f32"),
+        "f32_plain": dict(desc1=m1, desc2=m2, dtype="f32", algo="plain"),
+        "bf16": dict(desc1=b1, desc2=b2, dtype="bf16", desc1_f32=m1, desc2_f32=m2),
+        "fp8": dict(desc1=c1, desc2=c2, dtype="fp8", scale1=s1, scale2=s2, desc1_f32=m1,
+                    desc2_f32=m2),
+        "bin256": dict(desc1=n1, desc2=n2, dtype="bin256"),
+    }
+    res = {}
+    for name, kw in variants.items():
+        holder = {}
+
+        def step():
+            idx = E.Index(spec, kp2, eps=2.0, workspace=ws)
+            idx.query(kp1, row_offsets=offs, col_indices=cols, sync=False)
+            idx.match(offs, cols, out=out, **kw)
+            holder["idx"] = idx
+
+        sec = time_steps(torch, step, args.steps, args.warmup)
+        entry = {"value": round(p.m / sec, 1), "ms_per_step": round(sec * 1e3, 4)}
+        if name in ("bf16", "fp8"):
+            entry["match_stats"] = holder["idx"].match_stats()
+        res[name] = entry
+    line = {"metric": METRIC, "value": res["bf16"]["value"], "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": res["bf16"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64",
+            "data": "synthetic",
+            "config": {"workload": "precision: 1 pair 6048x4032, 60000 keypoints/image, "
+                                   "eps 2 px", "queries_per_step": p.m,
+                       "candidates_per_step": nnz, "kbar": round(nnz / p.m, 2)},
+            "paths": res,
+            "speedup_vs_plain": round(res["bf16"]["value"] / res["f32_plain"]["value"], 3)}
+    print(json.dumps(line), flush=True)
+
+
+def batch_workload(args):
+    """Uneven pairs (1920x1080 / 4032x3024 / 6048x4032, 500-30000 keypoints,
+    far, infinite, forward and general epipoles), BF16 descriptors with FP32
+    masters, eps = 2 px: one batched build/query/match against one plain
+    pipeline per pair."""
+    import torch
+
+    import paper_2603_18401_amd as E
+    import synth
+    dev = torch.device("cuda:0")
+    pairs = [synth.cfg3_pair(r) for r in range(args.pairs)]
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    b = synth.batch_pairs(pairs)
+    kp1, kp2, m1, m2 = g(b.kp1), g(b.kp2), g(b.desc1), g(b.desc2)
+    q1 = g(synth.f32_to_bf16(b.desc1).view(np.int16))
+    q2 = g(synth.f32_to_bf16(b.desc2).view(np.int16))
+    specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in pairs]
+    N1 = int(sum(p.m for p in pairs))
+    idx0 = E.Index(specs, kp2, eps=2.0)
+    ws = idx0.workspace
+    o, c = idx0.query(kp1)
+    nnz = int(o[-1].item())
+    offs = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(nnz, dtype=torch.int32, device=dev)
+    out = (torch.empty(N1, dtype=torch.int32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev))
+    holder = {}
+
+    def step():
+        idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+        idx.query(kp1, row_offsets=offs, col_indices=cols, sync=False)
+        idx.match(offs, cols, q1, q2, dtype="bf16", desc1_f32=m1, desc2_f32=m2, out=out)
+        holder["idx"] = idx
+
+    sec = time_steps(torch, step, args.steps, args.warmup)
+    qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
+    kb = np.concatenate([[0], np.cumsum([p.n for p in pairs])])
+    per = [(specs[i], kp1[qb[i]:qb[i + 1]], kp2[kb[i]:kb[i + 1]], m1[qb[i]:qb[i + 1]],
+            m2[kb[i]:kb[i + 1]]) for i in range(len(pairs))]
+
+    def plain_step():
+        for sp, a1, a2, d1, d2 in per:
+            idx = E.Index([sp], a2, eps=2.0)
+            o2, c2 = idx.query(a1)
+            idx.match(o2, c2, d1, d2, dtype="f32", algo="plain")
+
+    psec = time_steps(torch, plain_step, 1, 1)
+    line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16+f32+f64", "data": "synthetic",
+            "config": {"workload": f"batch: {len(pairs)} uneven pairs, eps 2 px, BF16 "
+                                   "descriptors with FP32 masters",
+                       "queries_per_step": N1, "candidates_per_step": nnz,
+                       "kbar": round(nnz / N1, 2)},
+            "match_stats": holder["idx"].match_stats(),
+            "query_stats": holder["idx"].stats(),
+            "plain_gpu": {"value": round(N1 / psec, 1), "ms_per_step": round(psec * 1e3, 2)},
+            "speedup_vs_plain": round(psec / sec, 3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +235,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): the "
               "matching path has no multi-GPU form in this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "precision":
+        return precision_workload(args)
+    if args.workload == "batch":
+        return batch_workload(args)
 
     import torch
 

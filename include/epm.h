@@ -218,9 +218,9 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out);
 /* Counters of the last reduced-precision (BF16 / FP8) epm_match on an index. */
 typedef struct {
   int64_t queries;        /* image-1 queries                                         */
-  int64_t reranked_rows;  /* rows of 1..64 candidates ranked on MFMA, top-4 re-ranked  */
+  int64_t reranked_rows;  /* non-empty rows ranked on MFMA with the top-4 re-ranked    */
   int64_t fallback_rows;  /* of those, not certified: every candidate evaluated exactly */
-  int64_t long_rows;      /* rows longer than 64: every candidate evaluated exactly    */
+  int64_t long_rows;      /* rows beyond a tile's 4096-entry list: evaluated exactly  */
 } epm_match_stats;
 
 /*

@@ -78,11 +78,11 @@ constexpr int kRowSortMax = 2048;
 
 // Stabbing tiles: kTileQ consecutive angle-sorted queries of one pair share
 // one window search per width class; the window's records are staged in LDS
-// kChunk at a time.  Rows of up to kStage candidates are finished inside the
-// tile kernel (sorted, parked in a staging buffer); longer rows are rebuilt
-// by the fill kernel.
+// kChunk at a time.  Rows of up to kStage candidates are parked in a staging
+// buffer by the tile kernel and sorted by the copy pass; longer rows are
+// rebuilt by the fill kernel.
 constexpr int kTileQ = 64;
-constexpr int kStage = 64;
+constexpr int kStage = 128;
 constexpr int kChunk = 512;
 
 // Per-tile record windows found by the window pass: up to two ranges of

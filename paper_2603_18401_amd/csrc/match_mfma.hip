@@ -15,8 +15,9 @@
 //      FP32 chains on the masters; when the smallest LB among the others
 //      exceeds the exact second distance (or the row has at most four
 //      candidates), best and second are certified exact;
-//   5. otherwise (and for rows longer than 64) every candidate is evaluated
-//      exactly -- the fallback, counted in the match statistics.
+//   5. otherwise (and for rows that do not fit the tile's dense list of 4096
+//      entries) every candidate is evaluated exactly -- counted in the match
+//      statistics.
 // Final outputs therefore equal the FP32 path bit for bit.
 #include "device_common.h"
 #include "launch.h"
@@ -29,9 +30,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kChunkRows = 64;
-constexpr int kMaxPairs = kTileQ * kStage;
+constexpr int kMaxPairs = 4096;  // dense (query, candidate) entries per tile
 constexpr uint32_t kPending = 0x80000000u;
-constexpr uint32_t kNoWindow = (1u << 19) - 1u;
+constexpr uint32_t kNoWindow = (1u << 25) - 1u;
 constexpr int kReRank = 4;
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
@@ -66,8 +67,8 @@ struct Fmt<1> {  // OCP E4M3FN with a per-row scale: 4 significant bits
 template <int FMT>
 constexpr int row_stride() { return Fmt<FMT>::kRowBytes + 16; }
 
-__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t t, uint32_t v) {
-  return kPending | (v << 12) | (t << 6) | q;
+__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t v) {
+  return kPending | (v << 6) | q;
 }
 
 __device__ __forceinline__ float exact_distance(const float4* __restrict__ a,
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint32_t ss_b[kSlots], ss_v[kSlots], ss_len[kSlots];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
-  __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1];
+  __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1], q_in[kTileQ];
   __shared__ float q_norm[kTileQ], q_scale[kTileQ], w_norm[kChunkRows], w_scale[kChunkRows];
   __shared__ int32_t row_j[kChunkRows];
   __shared__ uint32_t n_sorted_slots, n_fallback;
@@ -144,14 +145,27 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
     q_i[q] = i;
     q_o0[q] = o0;
     q_k[q] = (uint32_t)k;
-    const uint32_t kk = k <= kStage ? (uint32_t)k : 0u;
-    uint32_t incl = kk;
+    // rows enter the dense list in order while they fit; the rest are
+    // evaluated by gathers
+    uint32_t incl = (uint32_t)(k < kMaxPairs ? k : kMaxPairs);
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    const bool fits = incl <= (uint32_t)kMaxPairs;
+    const uint64_t fit_mask = ballot(fits);
+    // the fitting rows are a prefix: recompute the offsets over that prefix
+    const int nfit = __popcll(fit_mask);
+    uint32_t kk = lane < nfit ? (uint32_t)k : 0u;
+    incl = kk;
     #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const uint32_t o = __shfl_up(incl, off);
       if (lane >= off) incl += o;
     }
     q_off[q + 1] = incl;
+    q_in[q] = lane < nfit ? 1u : 0u;
     if (lane == 0) {
       q_off[0] = 0;
       n_fallback = 0;
@@ -204,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
     }
     if (v >= kNoWindow) v = kNoWindow;
-    ent[e] = pack_entry(q, t, v);
+    ent[e] = pack_entry(q, v);
     ent_j[e] = j;
   }
   __syncthreads();
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
     for (uint32_t e = tid; e < npairs; e += kThreads) {
       const uint32_t x = ent[e];
       if (!(x & kPending)) continue;
-      const uint32_t v = (x >> 12) & kNoWindow;
+      const uint32_t v = (x >> 6) & kNoWindow;
       if (v < c0 || v >= c0 + nr) continue;
       const uint32_t q = x & 63u, r = v - c0;
       const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
@@ -310,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   __syncthreads();
 
   // choose, per query, the four smallest bounds and the fifth bound
-  if (tid < T.count && q_k[tid] <= (uint32_t)kStage) {
+  if (tid < T.count && q_in[tid]) {
     const int q = tid;
     float bd[kReRank + 1];
     uint32_t be[kReRank + 1];
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   {
     const int q = tid >> 2, u = tid & 3;
     float d = __builtin_inff();
-    if (q < T.count && q_k[q] <= (uint32_t)kStage && pick[q][u] != 0xFFFFFFFFu) {
+    if (q < T.count && q_in[q] && pick[q][u] != 0xFFFFFFFFu) {
       const int32_t j = ent_j[pick[q][u]];
       d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
                          reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
@@ -351,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
     pick_d[q][u] = d;
   }
   __syncthreads();
-  if (tid < T.count && q_k[tid] <= (uint32_t)kStage) {
+  if (tid < T.count && q_in[tid]) {
     const int q = tid;
     Top2 t;
     #pragma unroll
@@ -371,8 +385,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   if (A.match_stats && tid == 0) {
     uint32_t longs = 0, reranked = 0;
     for (int q = 0; q < T.count; ++q) {
-      longs += q_k[q] > (uint32_t)kStage;
-      reranked += q_k[q] <= (uint32_t)kStage && q_k[q] > 0;
+      longs += !q_in[q] && q_k[q] > 0;
+      reranked += q_in[q] && q_k[q] > 0;
     }
     atomicAdd(&A.match_stats[0], (unsigned long long)reranked);
     atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
@@ -386,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       q = fallback_q[t0];
     } else {
       q = t0 - (int)nfb;
-      if (q_k[q] <= (uint32_t)kStage) continue;
+      if (q_in[q]) continue;
     }
     const int64_t i = q_i[q];
     if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1_f32)[i * 32 + lane];

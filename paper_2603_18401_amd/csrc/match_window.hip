@@ -12,8 +12,9 @@
 //   3. every thread evaluates whole canonical FP32 distances for list entries
 //      (query row from L1, candidate row from LDS, k ascending, fmaf);
 //   4. one thread per query selects (distance, j) best and second.
-// Rows longer than kStage, and candidates outside the window (a CSR that did
-// not come from this index's last query), use per-candidate gathers.  Every
+// Rows that do not fit the tile's dense list, and candidates outside the
+// window (a CSR that did not come from this index's last query), use
+// per-candidate gathers.  Every
 // distance is the canonical one, so results equal the plain kernel's bit for
 // bit.
 #include "device_common.h"
@@ -28,12 +29,12 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kRowStride = 132;  // floats
 constexpr int kWinRows = 64;     // rows staged per pass
-constexpr int kMaxPairs = kTileQ * kStage;
+constexpr int kMaxPairs = 4096;  // dense (query, candidate) entries per tile
 constexpr uint32_t kPending = 0x80000000u;
-constexpr uint32_t kNoWindow = (1u << 19) - 1u;
+constexpr uint32_t kNoWindow = (1u << 25) - 1u;
 
-__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t t, uint32_t v) {
-  return kPending | (v << 12) | (t << 6) | q;
+__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t v) {
+  return kPending | (v << 6) | q;
 }
 
 __device__ __forceinline__ float row_distance_global(const float4* __restrict__ qr,
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint32_t ss_b[kSlots], ss_v[kSlots], ss_len[kSlots];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
-  __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1];
+  __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1], q_in[kTileQ];
   __shared__ int32_t row_j[kWinRows];
   __shared__ uint32_t n_sorted_slots;
   __shared__ float4 qdesc[kWaves][32];
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
   const TileWindow* W = A.windows + tile;
 
   if (wave == 0) {
-    // rows of the tile's queries; rows longer than kStage go the gather way
+    // rows of the tile's queries
     const int q = lane;
     int64_t i = 0, o0 = 0, k = 0;
     if (q < T.count) {
@@ -74,14 +75,27 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
     q_i[q] = i;
     q_o0[q] = o0;
     q_k[q] = (uint32_t)k;
-    const uint32_t kk = k <= kStage ? (uint32_t)k : 0u;
-    uint32_t incl = kk;
+    // rows enter the dense list in order while they fit; the rest are
+    // evaluated by gathers
+    uint32_t incl = (uint32_t)(k < kMaxPairs ? k : kMaxPairs);
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    const bool fits = incl <= (uint32_t)kMaxPairs;
+    const uint64_t fit_mask = ballot(fits);
+    // the fitting rows are a prefix: recompute the offsets over that prefix
+    const int nfit = __popcll(fit_mask);
+    uint32_t kk = lane < nfit ? (uint32_t)k : 0u;
+    incl = kk;
     #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const uint32_t o = __shfl_up(incl, off);
       if (lane >= off) incl += o;
     }
     q_off[q + 1] = incl;
+    q_in[q] = lane < nfit ? 1u : 0u;
     if (lane == 0) q_off[0] = 0;
     // window slots, and the non-empty ones ordered by start position
     const uint32_t b = W->slot_b[lane];
@@ -125,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
       if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
     }
     if (v >= kNoWindow) v = kNoWindow;
-    ent[e] = pack_entry(q, t, v);
+    ent[e] = pack_entry(q, v);
     ent_j[e] = j;
   }
   __syncthreads();
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
     for (uint32_t e = tid; e < npairs; e += kThreads) {
       const uint32_t x = ent[e];
       if (!(x & kPending)) continue;
-      const uint32_t v = (x >> 12) & kNoWindow;
+      const uint32_t v = (x >> 6) & kNoWindow;
       if (v < c0 || v >= c0 + nr) continue;
       const uint32_t q = x & 63u;
       const float4* qr = reinterpret_cast<const float4*>(A.desc1) + q_i[q] * 32;
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
   __syncthreads();
 
   // 4. selection, one thread per query
-  if (tid < T.count && q_k[tid] <= (uint32_t)kStage) {
+  if (tid < T.count && q_in[tid]) {
     const int q = tid;
     Top2 best;
     for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) best.insert(__uint_as_float(ent[e]), ent_j[e]);
@@ -186,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
   }
   // long rows: one wavefront each, one lane per candidate (gathers)
   for (int q = wave; q < T.count; q += kWaves) {
-    if (q_k[q] <= (uint32_t)kStage) continue;
+    if (q_in[q]) continue;
     const int64_t i = q_i[q];
     if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1)[i * 32 + lane];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -207,7 +207,8 @@ __global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
 
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
-static_assert(kTileQ == 64 && kStage == 64, "pair and staging indexing use 6-bit fields");
+static_assert(kTileQ == 64, "pair indexing uses a 6-bit query field");
+static_assert(kStage == 2 * kWave, "the copy pass holds two staged entries per lane");
 
 __device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict__ keys,
                                                       int64_t lo, int64_t hi, uint32_t target) {
@@ -431,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   // row lengths, and short rows parked unsorted (the copy pass sorts them)
   if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
   for (int p = tid; p < T.count * kStage; p += kThreads) {
-    const int q = p >> 6, t = p & (kStage - 1);
+    const int q = p / kStage, t = p % kStage;
     const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
     if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
   }
@@ -446,12 +447,26 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len <= kStage) {
-    // rank sort of the parked row: the j are distinct, so each lane's rank
-    // is the number of smaller entries (readlane broadcasts, no LDS)
-    const int32_t v = lane < len ? A.staging[i * kStage + lane] : INT32_MAX;
-    uint32_t rank = 0;
-    for (int t = 0; t < (int)len; ++t) rank += __builtin_amdgcn_readlane(v, t) < v ? 1u : 0u;
-    if (lane < len && o0 + rank < A.capacity) A.cols[o0 + rank] = v;
+    // rank sort of the parked row (two entries per lane): the j are
+    // distinct, so an entry's rank is the number of smaller entries;
+    // readlane broadcasts them without an LDS round trip
+    const int n = (int)len;
+    const int32_t v0 = lane < n ? A.staging[i * kStage + lane] : INT32_MAX;
+    const int32_t v1 = lane + kWave < n ? A.staging[i * kStage + kWave + lane] : INT32_MAX;
+    uint32_t r0 = 0, r1 = 0;
+    const int n0 = n < kWave ? n : kWave;
+    for (int t = 0; t < n0; ++t) {
+      const int32_t x = __builtin_amdgcn_readlane(v0, t);
+      r0 += x < v0 ? 1u : 0u;
+      r1 += x < v1 ? 1u : 0u;
+    }
+    for (int t = kWave; t < n; ++t) {
+      const int32_t x = __builtin_amdgcn_readlane(v1, t - kWave);
+      r0 += x < v0 ? 1u : 0u;
+      r1 += x < v1 ? 1u : 0u;
+    }
+    if (lane < n && o0 + r0 < A.capacity) A.cols[o0 + r0] = v0;
+    if (lane + kWave < n && o0 + r1 < A.capacity) A.cols[o0 + r1] = v1;
   } else if (lane == 0) {
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
