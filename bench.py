@@ -47,6 +47,10 @@ def parse():
                     help="scale: six 20000-keypoint pairs (default); precision: one "
                          "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs")
     ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: EPM_TUNE_CACHE or ~/.cache/epm)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="scale workload: skip the recorded-graph figure")
     return ap.parse_args()
 
 
@@ -168,14 +172,24 @@ def precision_workload(args):
 def batch_workload(args):
     """Uneven pairs (1920x1080 / 4032x3024 / 6048x4032, 500-30000 keypoints,
     far, infinite, forward and general epipoles), BF16 descriptors with FP32
-    masters, eps = 2 px: one batched build/query/match against one plain
-    pipeline per pair."""
+    masters, eps = 2 px.  Timed: replays of the whole batch (build, query,
+    match) recorded as one HIP graph with the autotuned tile schedule.  Beside
+    it: the same batch through the eager calls, and the plain path (one
+    pipeline per pair, FP32 gathers)."""
     import torch
 
     import paper_2603_18401_amd as E
     import synth
+    from paper_2603_18401_amd import autotune
     dev = torch.device("cuda:0")
-    pairs = [synth.cfg3_pair(r) for r in range(args.pairs)]
+    t_gen = time.perf_counter()
+    pairs = []
+    for r in range(args.pairs):
+        pairs.append(synth.cfg3_pair(r))
+        if (r + 1) % 64 == 0:
+            print(f"batch: {r + 1} pairs generated", file=sys.stderr, flush=True)
+    print(f"batch: generated {len(pairs)} pairs in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     b = synth.batch_pairs(pairs)
     kp1, kp2, m1, m2 = g(b.kp1), g(b.kp2), g(b.desc1), g(b.desc2)
@@ -183,24 +197,45 @@ def batch_workload(args):
     q2 = g(synth.f32_to_bf16(b.desc2).view(np.int16))
     specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in pairs]
     N1 = int(sum(p.m for p in pairs))
+    N2 = int(sum(p.n for p in pairs))
     idx0 = E.Index(specs, kp2, eps=2.0)
     ws = idx0.workspace
     o, c = idx0.query(kp1)
     nnz = int(o[-1].item())
+    idx0.close()
+    del o, c
+    cap = nnz + 1024
+
+    # ---- autotuned schedule, then graph replays
+    sched, tinfo = autotune.tune(specs, kp1, kp2, q1, q2, cap, dtype="bf16", eps=2.0,
+                                 desc1_f32=m1, desc2_f32=m2, steps=3, warmup=1,
+                                 cache=args.tune_cache,
+                                 log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    bt = E.Batch(specs, kp1, kp2, q1, q2, cap, eps=2.0, dtype="bf16", desc1_f32=m1,
+                 desc2_f32=m2, sched=sched, workspace=ws)
+    sec = time_steps(torch, bt.launch, args.steps, args.warmup)
+    assert bt.nnz() == nnz
+    gstats, gmatch = bt.stats(), bt.match_stats()
+    res_graph = [x.clone() for x in bt.outputs()[2:]]
+    bt.close()
+
+    # ---- the same batch through the eager calls (default schedule)
     offs = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
-    cols = torch.empty(nnz, dtype=torch.int32, device=dev)
+    cols = torch.empty(cap, dtype=torch.int32, device=dev)
     out = (torch.empty(N1, dtype=torch.int32, device=dev),
            torch.empty(N1, dtype=torch.float32, device=dev),
            torch.empty(N1, dtype=torch.float32, device=dev))
-    holder = {}
 
-    def step():
+    def eager_step():
         idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
         idx.query(kp1, row_offsets=offs, col_indices=cols, sync=False)
         idx.match(offs, cols, q1, q2, dtype="bf16", desc1_f32=m1, desc2_f32=m2, out=out)
-        holder["idx"] = idx
+        idx.close()
 
-    sec = time_steps(torch, step, args.steps, args.warmup)
+    esec = time_steps(torch, eager_step, args.steps, args.warmup)
+    same = all(torch.equal(a, r) for a, r in zip(out, res_graph))
+
+    # ---- plain path: one pipeline per pair
     qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
     kb = np.concatenate([[0], np.cumsum([p.n for p in pairs])])
     per = [(specs[i], kp1[qb[i]:qb[i + 1]], kp2[kb[i]:kb[i + 1]], m1[qb[i]:qb[i + 1]],
@@ -211,18 +246,29 @@ def batch_workload(args):
             idx = E.Index([sp], a2, eps=2.0)
             o2, c2 = idx.query(a1)
             idx.match(o2, c2, d1, d2, dtype="f32", algo="plain")
+            idx.close()
 
     psec = time_steps(torch, plain_step, 1, 1)
+    # algorithmic bytes of the batch (BF16 rows, FP32 masters read for the re-rank)
+    alg_bytes = N1 * (8 + 256 + 8 + 12) + N2 * (8 + 4 + 256 + 24) + 4 * nnz + 512 * (N1 + N2)
     line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16+f32+f64", "data": "synthetic",
-            "config": {"workload": f"batch: {len(pairs)} uneven pairs, eps 2 px, BF16 "
-                                   "descriptors with FP32 masters",
-                       "queries_per_step": N1, "candidates_per_step": nnz,
-                       "kbar": round(nnz / N1, 2)},
-            "match_stats": holder["idx"].match_stats(),
-            "query_stats": holder["idx"].stats(),
+            "config": {"workload": f"batch: {len(pairs)} uneven pairs (cfg3 mix), eps 2 px, "
+                                   "BF16 descriptors with FP32 masters, one HIP graph replay "
+                                   "per step",
+                       "queries_per_step": N1, "keypoints2_per_step": N2,
+                       "candidates_per_step": nnz, "kbar": round(nnz / N1, 2)},
+            "sched": sched.as_dict(), "autotune": {k: tinfo[k] for k in ("key", "cached")},
+            "autotune_candidates_ms": [[c, round(t * 1e3, 4)]
+                                       for c, t in tinfo.get("candidates", [])],
+            "whole_step_hbm": {"algorithmic_bytes": int(alg_bytes),
+                               "achieved_GBps": round(alg_bytes / sec / 1e9, 1),
+                               "frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4)},
+            "match_stats": gmatch, "query_stats": gstats,
+            "eager_batched": {"value": round(N1 / esec, 1), "ms_per_step": round(esec * 1e3, 4),
+                              "identical_matches": bool(same)},
             "plain_gpu": {"value": round(N1 / psec, 1), "ms_per_step": round(psec * 1e3, 2)},
             "speedup_vs_plain": round(psec / sec, 3)}
     print(json.dumps(line), flush=True)
@@ -331,6 +377,24 @@ def main():
         plain = {"value": N1 * ksteps / pel, "unit": "queries/s",
                  "ms_per_step": 1e3 * pel / ksteps, "steps": ksteps}
 
+    # ---- the same step recorded once as a HIP graph (autotuned schedule)
+    graph = None
+    if not args.no_graph:
+        from paper_2603_18401_amd import autotune
+        sched, tinfo = autotune.tune(specs, g["kp1"], g["kp2"], g["d1"], g["d2"], nnz + 1024,
+                                     dtype="f32", eps2=g["eps2"], steps=5, warmup=2,
+                                     cache=args.tune_cache)
+        bt = E.Batch(specs, g["kp1"], g["kp2"], g["d1"], g["d2"], nnz + 1024, eps2=g["eps2"],
+                     sched=sched, workspace=ws)
+        gsec = time_steps(torch, bt.launch, args.steps, args.warmup)
+        same = all(torch.equal(a, r) for a, r in zip(bt.outputs()[2:], (best, bd, sd)))
+        graph = {"value": round(N1 / gsec, 1), "unit": "queries/s",
+                 "ms_per_step": round(gsec * 1e3, 4), "sched": sched.as_dict(),
+                 "identical_matches": bool(same),
+                 "autotune_candidates_ms": [[c, round(t * 1e3, 4)]
+                                            for c, t in tinfo.get("candidates", [])]}
+        bt.close()
+
     # ---- roofline of the dominant kernel (descriptor matching)
     match_avg_ms = float(np.mean(match_ms))
     b_desc = 512
@@ -395,6 +459,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_gpu": plain,
+        "graph": graph,
     }
     if plain:
         out["speedup_vs_plain"] = round(qps / plain["value"], 3)

@@ -145,10 +145,13 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
                                 hipStream_t stream);
 
 typedef struct {
-  epm_algo algo;   /* EPM_ALGO_AUTO by default                                   */
-  int32_t tile_q;  /* tiled path: queries per tile (16, 32 or 64; 0 = default)   */
-  int32_t window;  /* tiled path: LDS window chunk in records (0 = default)      */
-  int32_t reserved[5];
+  epm_algo algo;            /* EPM_ALGO_AUTO by default                           */
+  int32_t check_capacity;   /* 1: col_capacity is the length of col_indices, and
+                               the launch writes no output when row_offsets[N1]
+                               exceeds it (an incomplete CSR, see
+                               epm_query_candidates with nnz_host == NULL)      */
+  int64_t col_capacity;
+  int32_t reserved[4];      /* zero                                               */
 } epm_match_opts;
 
 /*
@@ -196,6 +199,96 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,
                                 hipStream_t stream);
+
+/*
+ * Work distribution of the angle-tile kernels (the stabbing pass of
+ * epm_query_candidates and the tiled paths of epm_match).  All zero (the
+ * default of a new index) launches one workgroup per tile of 64 angle-sorted
+ * queries.  A persistent launch starts `*_workgroups` workgroups that take
+ * tiles from a device queue until it is empty; with lpt = 1 the queue holds
+ * the tiles longest first (cost = queries x angle-window records of the
+ * tile, bucketed by powers of two), which keeps batches of very uneven pairs
+ * from ending on one long tile.  Results never depend on these settings.
+ */
+typedef struct {
+  int32_t stab_workgroups;   /* 0: one per tile; > 0: persistent launch        */
+  int32_t match_workgroups;  /* 0: one per tile; > 0: persistent launch        */
+  int32_t lpt;               /* persistent launches: 1 = longest tiles first   */
+  int32_t reserved[5];       /* zero                                           */
+} epm_sched;
+
+/* Sets the work distribution used by later calls on idx (host only).
+ * Errors: EPM_ERR_ARG (NULL, negative counts, lpt not 0/1, reserved != 0). */
+epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);
+
+/*
+ * Batched execution under a HIP graph (many image pairs per launch).
+ *
+ * epm_batch_create builds an index over `pairs` (as epm_build_intervals), then
+ * records the whole per-batch pipeline -- interval build, query sort,
+ * stabbing with the FP64 test, CSR compaction and descriptor matching
+ * (Algorithm 1, preprocessing and matching loop) -- for the buffers named in
+ * `desc` into one HIP graph: kernels only, no host synchronisation, no
+ * memset or memcpy nodes.  epm_batch_launch replays it on a stream; every
+ * replay recomputes every output from the current contents of the input
+ * buffers, so new keypoints and descriptors of the same sizes can be written
+ * between replays (the pairs' F and slices are fixed at creation).
+ *
+ * The CSR capacity cannot be checked on the host inside a graph: rows are
+ * written up to `capacity` and, when the total exceeds it, the match writes
+ * nothing; epm_batch_nnz reports it.  The buffers in `desc` and the
+ * workspace must stay alive, and must not be used by other work, while the
+ * batch exists.  Replays of one batch on different streams race.
+ */
+typedef struct {
+  const float* kp1_xy;       /* [N1][2]                                              */
+  const float* kp2_xy;       /* [N2][2]                                              */
+  const float* eps2;         /* [N2] or NULL                                         */
+  float eps_scalar;          /* used when eps2 == NULL                               */
+  int64_t* row_offsets;      /* [N1 + 1] output                                      */
+  int32_t* col_indices;      /* [capacity] output                                    */
+  int64_t capacity;
+  epm_dtype dtype;           /* matching, as in epm_match                            */
+  int32_t dim;
+  const void* desc1;
+  const void* desc2;
+  const float* scale1;
+  const float* scale2;
+  const float* desc1_f32;
+  const float* desc2_f32;
+  float ratio;
+  int32_t* best_idx;         /* [N1] outputs                                         */
+  float* best_dist;
+  float* second_dist;
+  epm_algo algo;             /* matching algorithm                                   */
+  epm_sched sched;           /* work distribution of the tile kernels                */
+} epm_batch_desc;
+
+typedef struct epm_batch epm_batch;
+
+/* Creates the batch (host setup and one upload of its tables on `stream`;
+ * the graph itself is recorded on a private stream and launches nothing).
+ * workspace: at least epm_workspace_bytes(pairs, num_pairs), 256-byte
+ * aligned.  Errors: as epm_build_intervals and epm_match, EPM_ERR_HIP when
+ * the graph cannot be recorded.  On error *out is NULL. */
+epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_batch_desc* desc,
+                            void* workspace, size_t workspace_bytes, epm_batch** out,
+                            hipStream_t stream);
+
+/* Replays the recorded pipeline on `stream` (asynchronous). */
+epm_status epm_batch_launch(epm_batch* batch, hipStream_t stream);
+
+/* Waits for `stream` and reads the total number of candidates of the last
+ * replay into *nnz; returns EPM_ERR_CAPACITY when it exceeded the capacity
+ * (the match outputs of that replay were not written). */
+epm_status epm_batch_nnz(epm_batch* batch, int64_t* nnz, hipStream_t stream);
+
+/* The batch's index, for epm_get_query_stats / epm_get_match_stats after a
+ * replay (they then read the counters of the last replay). */
+const epm_index* epm_batch_index(const epm_batch* batch);
+
+/* Releases the graph and the host objects (not the caller's buffers). */
+void epm_batch_destroy(epm_batch* batch);
 
 /* Counters of the last epm_query_candidates call on an index. */
 typedef struct {

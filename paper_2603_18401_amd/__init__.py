@@ -11,6 +11,11 @@ The three entry points mirror include/epm.h:
     idx = Index(pairs, kp2, eps2=None, eps=2.0)      # epm_build_intervals
     offs, cols = idx.query(kp1)                       # epm_query_candidates
     best, d1, d2 = idx.match(offs, cols, desc1, desc2)  # epm_match
+
+and a whole batch can be recorded once and replayed as one HIP graph:
+
+    b = Batch(pairs, kp1, kp2, desc1, desc2, capacity=..., eps=2.0)  # epm_batch_create
+    b.launch()                                                       # epm_batch_launch
 """
 
 import ctypes
@@ -18,8 +23,8 @@ import os
 
 import numpy as np
 
-__all__ = ["EpmError", "Index", "PairSpec", "load_library", "library_path", "point_line_terms",
-           "DTYPES", "ALGOS"]
+__all__ = ["EpmError", "Index", "Batch", "Sched", "PairSpec", "load_library", "library_path",
+           "point_line_terms", "DTYPES", "ALGOS"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libepm.so")
@@ -31,7 +36,9 @@ DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "bin256": 3}
 ALGOS = {"auto": 0, "plain": 1, "tiled": 2}
 EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates", "epm_match",
            "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms",
-           "epm_get_query_stats", "epm_get_match_stats"]
+           "epm_get_query_stats", "epm_get_match_stats", "epm_index_set_sched",
+           "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
+           "epm_batch_destroy"]
 
 
 class EpmError(RuntimeError):
@@ -58,8 +65,53 @@ class _MatchStats(ctypes.Structure):
 
 
 class _MatchOpts(ctypes.Structure):
-    _fields_ = [("algo", ctypes.c_int32), ("tile_q", ctypes.c_int32),
-                ("window", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+    _fields_ = [("algo", ctypes.c_int32), ("check_capacity", ctypes.c_int32),
+                ("col_capacity", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class _Sched(ctypes.Structure):
+    _fields_ = [("stab_workgroups", ctypes.c_int32), ("match_workgroups", ctypes.c_int32),
+                ("lpt", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+_V = ctypes.c_void_p
+
+
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [("kp1_xy", _V), ("kp2_xy", _V), ("eps2", _V), ("eps_scalar", ctypes.c_float),
+                ("row_offsets", _V), ("col_indices", _V), ("capacity", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("dim", ctypes.c_int32), ("desc1", _V), ("desc2", _V),
+                ("scale1", _V), ("scale2", _V), ("desc1_f32", _V), ("desc2_f32", _V),
+                ("ratio", ctypes.c_float), ("best_idx", _V), ("best_dist", _V),
+                ("second_dist", _V), ("algo", ctypes.c_int32), ("sched", _Sched)]
+
+
+class Sched:
+    """Work distribution of the tile kernels (epm_sched): 0 workgroups = one
+    workgroup per angle tile; n > 0 = persistent launch of n workgroups;
+    lpt = take tiles longest first (persistent launches)."""
+
+    def __init__(self, stab_workgroups=0, match_workgroups=0, lpt=0):
+        self.stab_workgroups = int(stab_workgroups)
+        self.match_workgroups = int(match_workgroups)
+        self.lpt = int(lpt)
+
+    def as_dict(self):
+        return {"stab_workgroups": self.stab_workgroups,
+                "match_workgroups": self.match_workgroups, "lpt": self.lpt}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(d.get("stab_workgroups", 0), d.get("match_workgroups", 0), d.get("lpt", 0))
+
+    def _c(self):
+        c = _Sched()
+        c.stab_workgroups, c.match_workgroups, c.lpt = (self.stab_workgroups,
+                                                        self.match_workgroups, self.lpt)
+        return c
+
+    def __repr__(self):
+        return f"Sched({self.stab_workgroups}, {self.match_workgroups}, lpt={self.lpt})"
 
 
 def library_path():
@@ -97,6 +149,19 @@ def load_library(path=None):
     lib.epm_get_query_stats.restype = ctypes.c_int
     lib.epm_get_match_stats.argtypes = [V, ctypes.POINTER(_MatchStats)]
     lib.epm_get_match_stats.restype = ctypes.c_int
+    lib.epm_index_set_sched.argtypes = [V, ctypes.POINTER(_Sched)]
+    lib.epm_index_set_sched.restype = ctypes.c_int
+    lib.epm_batch_create.argtypes = [P, i32, ctypes.POINTER(_BatchDesc), V, ctypes.c_size_t,
+                                     ctypes.POINTER(V), V]
+    lib.epm_batch_create.restype = ctypes.c_int
+    lib.epm_batch_launch.argtypes = [V, V]
+    lib.epm_batch_launch.restype = ctypes.c_int
+    lib.epm_batch_nnz.argtypes = [V, ctypes.POINTER(i64), V]
+    lib.epm_batch_nnz.restype = ctypes.c_int
+    lib.epm_batch_index.argtypes = [V]
+    lib.epm_batch_index.restype = V
+    lib.epm_batch_destroy.argtypes = [V]
+    lib.epm_batch_destroy.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -228,10 +293,18 @@ class Index:
         _check(self.lib.epm_get_match_stats(self.handle, ctypes.byref(st)), "epm_get_match_stats")
         return {k: int(getattr(st, k)) for k, _ in st._fields_}
 
+    def set_sched(self, sched):
+        """Work distribution of later query/match calls (a Sched)."""
+        c = sched._c()
+        _check(self.lib.epm_index_set_sched(self.handle, ctypes.byref(c)), "epm_index_set_sched")
+
     def match(self, row_offsets, col_indices, desc1, desc2, dtype="f32", scale1=None,
-              scale2=None, desc1_f32=None, desc2_f32=None, ratio=0.0, algo="auto", tile_q=0,
-              window=0, out=None):
-        """Nearest neighbour per query: (best_idx int32, best_dist f32, second_dist f32)."""
+              scale2=None, desc1_f32=None, desc2_f32=None, ratio=0.0, algo="auto", out=None,
+              check_capacity=False):
+        """Nearest neighbour per query: (best_idx int32, best_dist f32, second_dist f32).
+
+        check_capacity: the launch writes nothing when row_offsets[N1] exceeds
+        col_indices.numel() (a CSR from query(..., sync=False) that did not fit)."""
         torch = self._torch
         dim = 256 if dtype == "bin256" else 128
         if out is None:
@@ -242,8 +315,9 @@ class Index:
             best, bd, sd = out
         opts = _MatchOpts()
         opts.algo = ALGOS[algo]
-        opts.tile_q = int(tile_q)
-        opts.window = int(window)
+        if check_capacity:
+            opts.check_capacity = 1
+            opts.col_capacity = col_indices.numel()
         st = self.lib.epm_match(self.handle, _dptr(row_offsets), _dptr(col_indices), DTYPES[dtype],
                                 dim, _dptr(desc1), _dptr(desc2), _dptr(scale1), _dptr(scale2),
                                 _dptr(desc1_f32), _dptr(desc2_f32), float(ratio), _dptr(best),
@@ -251,6 +325,110 @@ class Index:
                                 _stream(torch, self.device, self.stream))
         _check(st, "epm_match")
         return best, bd, sd
+
+
+class Batch:
+    """epm_batch_create: the whole build / query / match pipeline over a batch
+    of pairs, recorded once as a HIP graph and replayed by launch().
+
+    Inputs and outputs are fixed device tensors (new contents of the same
+    sizes may be written between launches).  capacity: length of the CSR
+    column buffer; nnz() reports the total of the last launch and raises
+    EpmError(EPM_ERR_CAPACITY) when it did not fit."""
+
+    def __init__(self, pairs, kp1, kp2, desc1, desc2, capacity, eps2=None, eps=0.0,
+                 dtype="f32", scale1=None, scale2=None, desc1_f32=None, desc2_f32=None,
+                 ratio=0.0, algo="auto", sched=None, stream=None, workspace=None):
+        torch = _torch()
+        self._torch = torch
+        self.lib = load_library()
+        self.device = kp2.device
+        self.specs = list(pairs)
+        self._pairs, self.n1, self.n2 = _pair_array(self.specs)
+        for name, t, n in (("kp1", kp1, self.n1), ("kp2", kp2, self.n2)):
+            if tuple(t.shape) != (n, 2) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 [{n}, 2] device tensor")
+        nbytes = self.lib.epm_workspace_bytes(self._pairs, len(self.specs))
+        if nbytes == 0:
+            raise EpmError(1, "epm_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        dev = self.device
+        self.row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
+        self.col_indices = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
+        self.best_idx = torch.empty(self.n1, dtype=torch.int32, device=dev)
+        self.best_dist = torch.empty(self.n1, dtype=torch.float32, device=dev)
+        self.second_dist = torch.empty(self.n1, dtype=torch.float32, device=dev)
+        self.sched = sched or Sched()
+        d = _BatchDesc()
+        d.kp1_xy, d.kp2_xy, d.eps2 = kp1.data_ptr(), kp2.data_ptr(), (
+            eps2.data_ptr() if eps2 is not None else None)
+        d.eps_scalar = float(eps)
+        d.row_offsets, d.col_indices = self.row_offsets.data_ptr(), self.col_indices.data_ptr()
+        d.capacity = int(capacity)
+        d.dtype, d.dim = DTYPES[dtype], 256 if dtype == "bin256" else 128
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        d.desc1, d.desc2, d.scale1, d.scale2 = ptr(desc1), ptr(desc2), ptr(scale1), ptr(scale2)
+        d.desc1_f32, d.desc2_f32 = ptr(desc1_f32), ptr(desc2_f32)
+        d.ratio = float(ratio)
+        d.best_idx, d.best_dist, d.second_dist = (self.best_idx.data_ptr(),
+                                                  self.best_dist.data_ptr(),
+                                                  self.second_dist.data_ptr())
+        d.algo = ALGOS[algo]
+        d.sched = self.sched._c()
+        # the graph reads these buffers on every replay
+        self._keep = (kp1, kp2, eps2, desc1, desc2, scale1, scale2, desc1_f32, desc2_f32)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.epm_batch_create(self._pairs, len(self.specs), ctypes.byref(d),
+                                       _dptr(workspace), workspace.numel(), ctypes.byref(h),
+                                       _stream(torch, dev, stream))
+        _check(st, "epm_batch_create")
+        self.handle = h
+
+    def launch(self):
+        _check(self.lib.epm_batch_launch(self.handle, _stream(self._torch, self.device,
+                                                              self.stream)), "epm_batch_launch")
+
+    def nnz(self):
+        v = ctypes.c_int64(0)
+        st = self.lib.epm_batch_nnz(self.handle, ctypes.byref(v),
+                                    _stream(self._torch, self.device, self.stream))
+        _check(st, f"epm_batch_nnz ({v.value} candidates)")
+        return v.value
+
+    def outputs(self):
+        """(row_offsets, col_indices[:nnz], best_idx, best_dist, second_dist)."""
+        n = self.nnz()
+        return (self.row_offsets, self.col_indices[:n], self.best_idx, self.best_dist,
+                self.second_dist)
+
+    def _index_handle(self):
+        return ctypes.c_void_p(self.lib.epm_batch_index(self.handle))
+
+    def stats(self):
+        st = _QueryStats()
+        _check(self.lib.epm_get_query_stats(self._index_handle(), ctypes.byref(st)),
+               "epm_get_query_stats")
+        return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def match_stats(self):
+        st = _MatchStats()
+        _check(self.lib.epm_get_match_stats(self._index_handle(), ctypes.byref(st)),
+               "epm_get_match_stats")
+        return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.epm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def point_line_terms(F, kp1, kp2, qi, kj, eps2=None, eps=0.0, stream=None):

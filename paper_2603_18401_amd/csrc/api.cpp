@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows, match_stats;
+  size_t digit_base, windows, match_stats, sched, tile_cost, order;
   size_t total;
 };
 
@@ -74,6 +74,9 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.digit_base = take(sizeof(uint32_t) * 256 * P);
   L.windows = take(sizeof(TileWindow) * ts);
   L.match_stats = take(sizeof(unsigned long long) * kNumMatchStats);
+  L.sched = take(sizeof(uint32_t) * kSchedWords);
+  L.tile_cost = take(sizeof(uint32_t) * ts);
+  L.order = take(sizeof(uint32_t) * ts);
   L.total = off;
   return L;
 }
@@ -229,6 +232,8 @@ struct epm_index {
   bool have_stats = false;
   bool have_match_stats = false;
   hipStream_t match_stream = nullptr;
+  epm_sched sched{};         // work distribution of the tile kernels
+  bool have_order = false;  // the last query wrote the longest-first tile order
 
   template <typename T>
   T* at(size_t off) const {
@@ -241,31 +246,20 @@ struct epm_index {
     if ((call) != hipSuccess) return EPM_ERR_HIP; \
   } while (0)
 
-extern "C" {
+namespace {
 
-size_t epm_workspace_bytes(const epm_pair* pairs, int32_t num_pairs) {
-  int64_t n1, n2;
-  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return 0;
-  int64_t tr = 0, tq = 0, ts = 0;
-  for (int p = 0; p < num_pairs; ++p) {
-    tr += tiles_of(pairs[p].n);
-    tq += tiles_of(pairs[p].m);
-    ts += stab_tiles_of(pairs[p].m);
-  }
-  return make_layout(num_pairs, n1, n2, tr, tq, ts).total;
-}
+// ------------------------------------------------------------ host stages
+// Every stage below either does host work only or enqueues kernels only, so
+// the enqueue stages can be recorded into a HIP graph as they are.
 
-epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
-                               const float* eps2, float eps_scalar, void* workspace,
-                               size_t workspace_bytes, epm_index** out, hipStream_t stream) {
-  if (!out) return EPM_ERR_ARG;
+// Validation, FP64 pair setup, tiles, workspace layout and the host image of
+// the table region.  No device work.
+epm_status index_prepare(const epm_pair* pairs, int32_t num_pairs, void* workspace,
+                         size_t workspace_bytes, epm_index** out) {
   *out = nullptr;
   int64_t n1, n2;
   if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
-  if (n2 > 0 && !kp2_xy) return EPM_ERR_ARG;
-  if (!eps2 && !(eps_scalar > 0.0f && std::isfinite(eps_scalar))) return EPM_ERR_ARG;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1))) return EPM_ERR_WORKSPACE;
-
   epm_index* idx = new (std::nothrow) epm_index();
   if (!idx) return EPM_ERR_ARG;
   idx->P = num_pairs;
@@ -311,11 +305,6 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
   }
   idx->ws = static_cast<char*>(workspace);
   const Layout& L = idx->L;
-
-  auto fail = [&](epm_status s) {
-    delete idx;
-    return s;
-  };
   // every host table goes up in one copy: they sit at the head of the
   // workspace, in front of the histogram buffer
   idx->head.assign(L.hist, 0);
@@ -330,82 +319,64 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
   put(L.qtiles, idx->qtiles.data(), sizeof(SortTile) * idx->qtiles.size());
   put(L.qsegs, idx->qsegs.data(), sizeof(SortSeg) * num_pairs);
   put(L.stiles, idx->stiles.data(), sizeof(StabTile) * idx->stiles.size());
-  if (hipMemcpyAsync(idx->ws, idx->head.data(), L.hist, hipMemcpyHostToDevice, stream) !=
-      hipSuccess)
-    return fail(EPM_ERR_HIP);
-
-  const PairDev* dpairs = idx->at<PairDev>(L.pairs);
-  const int64_t* dkstart = idx->at<int64_t>(L.kstart);
-  if (launch_intervals(dpairs, dkstart, num_pairs, n2, kp2_xy, eps2, eps_scalar,
-                       idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
-                       idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH), stream) != hipSuccess)
-    return fail(EPM_ERR_HIP);
-  bool in1 = false;
-  if (segmented_radix_sort(idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
-                           idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
-                           idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
-                           idx->at<SortSeg>(L.rsegs), num_pairs, idx->at<uint32_t>(L.hist),
-                           kSortBits, &in1, stream, idx->at<uint32_t>(L.digit_base)) != hipSuccess)
-    return fail(EPM_ERR_HIP);
-  const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
-  const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
-  if (launch_gather_records(dkstart, num_pairs, n2, sval, kp2_xy, eps2, eps_scalar,
-                            idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH),
-                            idx->at<uint32_t>(L.rC), idx->at<uint32_t>(L.rH),
-                            idx->at<int32_t>(L.rj), idx->at<float2>(L.rxy),
-                            idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv), stream) != hipSuccess)
-    return fail(EPM_ERR_HIP);
-  idx->skey_off = in1 ? L.rk1 : L.rk0;
-  const hipError_t cb =
-      n2 > 0 ? launch_class_bounds_from_digits(dkstart, num_pairs, idx->at<uint32_t>(L.digit_base),
-                                               idx->at<int64_t>(L.class_begin), stream)
-             : launch_class_bounds(dkstart, num_pairs, skey, idx->at<int64_t>(L.class_begin),
-                                   stream);
-  if (cb != hipSuccess) return fail(EPM_ERR_HIP);
   *out = idx;
   return EPM_OK;
 }
 
-epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
-                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
-                                hipStream_t stream) {
-  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
-  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
-  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
-  const Layout& L = idx->L;
-  const int64_t n1 = idx->N1;
-  if (n1 == 0) {
-    static const int64_t zero = 0;
-    EPM_HIP(hipMemcpyAsync(row_offsets, &zero, sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    if (nnz_host) {
-      EPM_HIP(hipStreamSynchronize(stream));
-      *nnz_host = 0;
-    }
-    return EPM_OK;
-  }
-  const PairDev* dpairs = idx->at<PairDev>(L.pairs);
-  const int64_t* dqstart = idx->at<int64_t>(L.qstart);
-  EPM_HIP(launch_query_keys(dpairs, dqstart, idx->P, n1, kp1_xy, idx->at<uint32_t>(L.qkey),
-                            idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
-                            idx->at<uint32_t>(L.qv0), stream));
-  bool in1 = false;
-  EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
-                               idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
-                               idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
-                               idx->at<SortSeg>(L.qsegs), idx->P, idx->at<uint32_t>(L.hist), 16,
-                               &in1, stream));
-  idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
-  idx->have_qperm = true;
+epm_status index_upload(epm_index* idx, hipStream_t stream) {
+  EPM_HIP(hipMemcpyAsync(idx->ws, idx->head.data(), idx->L.hist, hipMemcpyHostToDevice, stream));
+  return EPM_OK;
+}
 
+bool build_args_ok(int64_t n2, const float* kp2_xy, const float* eps2, float eps_scalar) {
+  if (n2 > 0 && !kp2_xy) return false;
+  return eps2 || (eps_scalar > 0.0f && std::isfinite(eps_scalar));
+}
+
+// Interval records, their segmented sort by (width class, centre) and the
+// class bounds (Algorithm 1, preprocessing).
+epm_status enqueue_build(epm_index* idx, const float* kp2_xy, const float* eps2,
+                         float eps_scalar, hipStream_t stream) {
+  const Layout& L = idx->L;
+  const int P = idx->P;
+  const int64_t n2 = idx->N2;
+  const PairDev* dpairs = idx->at<PairDev>(L.pairs);
+  const int64_t* dkstart = idx->at<int64_t>(L.kstart);
+  EPM_HIP(launch_intervals(dpairs, dkstart, P, n2, kp2_xy, eps2, eps_scalar,
+                           idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
+                           idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH), stream));
+  bool in1 = false;
+  EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
+                               idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
+                               idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
+                               idx->at<SortSeg>(L.rsegs), P, idx->at<uint32_t>(L.hist), kSortBits,
+                               &in1, stream, idx->at<uint32_t>(L.digit_base)));
+  const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
+  const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
+  EPM_HIP(launch_gather_records(dkstart, P, n2, sval, kp2_xy, eps2, eps_scalar,
+                                idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH),
+                                idx->at<uint32_t>(L.rC), idx->at<uint32_t>(L.rH),
+                                idx->at<int32_t>(L.rj), idx->at<float2>(L.rxy),
+                                idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv), stream));
+  idx->skey_off = in1 ? L.rk1 : L.rk0;
+  EPM_HIP(n2 > 0 ? launch_class_bounds_from_digits(dkstart, P, idx->at<uint32_t>(L.digit_base),
+                                                   idx->at<int64_t>(L.class_begin), stream)
+                 : launch_class_bounds(dkstart, P, skey, idx->at<int64_t>(L.class_begin), stream));
+  return EPM_OK;
+}
+
+StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                   int32_t* col_indices, int64_t capacity) {
+  const Layout& L = idx->L;
   StabArgs A;
-  A.pairs = dpairs;
-  A.qstart = dqstart;
+  A.pairs = idx->at<PairDev>(L.pairs);
+  A.qstart = idx->at<int64_t>(L.qstart);
   A.num_pairs = idx->P;
-  A.n1 = n1;
+  A.n1 = idx->N1;
   A.kp1 = kp1_xy;
   A.qkey = idx->at<uint32_t>(L.qkey);
   A.qflag = idx->at<uint32_t>(L.qflag);
-  A.qperm = idx->qperm;
+  A.qperm = nullptr;
   A.class_begin = idx->at<int64_t>(L.class_begin);
   A.skey = idx->at<uint32_t>(idx->skey_off);
   A.rC = idx->at<uint32_t>(L.rC);
@@ -423,53 +394,107 @@ epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* ro
   A.staging = idx->at<int32_t>(L.staging);
   A.stats = idx->at<unsigned long long>(L.stats);
   A.long_rows = idx->at<uint32_t>(L.long_rows);
-  idx->last_stream = stream;
-  idx->last_offsets = row_offsets;
-  idx->have_stats = true;
   A.windows = idx->at<TileWindow>(L.windows);
-  EPM_HIP(launch_clear_stats(A.stats, stream));
-  EPM_HIP(launch_tile_windows(A, stream));
-  EPM_HIP(launch_stab_tiles(A, stream));
-  EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
-  if (nnz_host) {
-    int64_t nnz = 0;
-    EPM_HIP(hipMemcpyAsync(&nnz, row_offsets + n1, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-    EPM_HIP(hipStreamSynchronize(stream));
-    *nnz_host = nnz;
-    if (nnz > capacity) return EPM_ERR_CAPACITY;
+  A.tile_cost = nullptr;
+  A.order = nullptr;
+  A.queue = nullptr;
+  return A;
+}
+
+// Query keys and their sort, the tile windows, the stabbing pass and the
+// scan of the row lengths into row_offsets (Algorithm 1, matching loop).
+epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
+                         hipStream_t stream) {
+  const Layout& L = idx->L;
+  const int64_t n1 = idx->N1;
+  idx->have_order = false;
+  if (n1 == 0) {
+    // row_offsets[0] = 0 (two zero words, by kernel)
+    EPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(row_offsets), 2, 0u, stream));
+    return EPM_OK;
   }
+  EPM_HIP(launch_query_keys(A.pairs, A.qstart, idx->P, n1, A.kp1, idx->at<uint32_t>(L.qkey),
+                            idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
+                            idx->at<uint32_t>(L.qv0), stream));
+  bool in1 = false;
+  EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
+                               idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
+                               idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
+                               idx->at<SortSeg>(L.qsegs), idx->P, idx->at<uint32_t>(L.hist), 16,
+                               &in1, stream));
+  idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
+  idx->have_qperm = true;
+  A.qperm = idx->qperm;
+  const epm_sched& S = idx->sched;
+  const bool persistent = S.stab_workgroups > 0 || S.match_workgroups > 0;
+  const bool lpt = persistent && S.lpt == 1;
+  uint32_t* sched = idx->at<uint32_t>(L.sched);
+  EPM_HIP(launch_clear_stats(A.stats, stream));
+  if (persistent) EPM_HIP(launch_fill_u32(sched, kSchedWords, 0u, stream));
+  A.tile_cost = lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
+  EPM_HIP(launch_tile_windows(A, stream));
+  if (lpt) {
+    EPM_HIP(launch_lpt_order(A.tile_cost, A.num_tiles, sched, idx->at<uint32_t>(L.order), stream));
+    idx->have_order = true;
+  }
+  if (S.stab_workgroups > 0) {
+    A.queue = sched + kSchedStabQueue;
+    A.order = lpt ? idx->at<uint32_t>(L.order) : nullptr;
+  }
+  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, stream));
+  EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
+  return EPM_OK;
+}
+
+epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream) {
+  if (idx->N1 == 0) return EPM_OK;
   EPM_HIP(launch_fill_rows(A, stream));
   return EPM_OK;
 }
 
-epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
-                     const int32_t* col_indices, epm_dtype dtype, int32_t dim,
-                     const void* desc1, const void* desc2, const float* scale1,
-                     const float* scale2, const float* desc1_f32, const float* desc2_f32,
-                     float ratio, int32_t* best_idx, float* best_dist, float* second_dist,
-                     const epm_match_opts* opts, hipStream_t stream) {
-  if (!idx || !row_offsets) return EPM_ERR_ARG;
-  if (!(ratio >= 0.0f) || !std::isfinite(ratio)) return EPM_ERR_ARG;
+struct MatchCall {
+  const int64_t* row_offsets;
+  const int32_t* col_indices;
+  epm_dtype dtype;
+  int32_t dim;
+  const void *desc1, *desc2;
+  const float *scale1, *scale2, *desc1_f32, *desc2_f32;
+  float ratio;
+  int32_t* best_idx;
+  float *best_dist, *second_dist;
+  epm_algo algo;
+  int64_t capacity;  // < 0: trusted
+};
+
+epm_status validate_match(const epm_index* idx, const MatchCall& c) {
+  if (!idx || !c.row_offsets) return EPM_ERR_ARG;
+  if (!(c.ratio >= 0.0f) || !std::isfinite(c.ratio)) return EPM_ERR_ARG;
   const int64_t n1 = idx->N1;
-  if (n1 > 0 && (!best_idx || !best_dist || !second_dist || !desc1)) return EPM_ERR_ARG;
-  if (idx->N2 > 0 && !desc2) return EPM_ERR_ARG;
-  epm_algo algo = opts ? opts->algo : EPM_ALGO_AUTO;
-  if (algo != EPM_ALGO_AUTO && algo != EPM_ALGO_PLAIN && algo != EPM_ALGO_TILED) return EPM_ERR_ARG;
-  switch (dtype) {
+  if (n1 > 0 && (!c.best_idx || !c.best_dist || !c.second_dist || !c.desc1)) return EPM_ERR_ARG;
+  if (idx->N2 > 0 && !c.desc2) return EPM_ERR_ARG;
+  if (c.algo != EPM_ALGO_AUTO && c.algo != EPM_ALGO_PLAIN && c.algo != EPM_ALGO_TILED)
+    return EPM_ERR_ARG;
+  switch (c.dtype) {
     case EPM_F32:
     case EPM_BF16:
     case EPM_FP8_E4M3:
-      if (dim != 128) return EPM_ERR_ARG;
+      if (c.dim != 128) return EPM_ERR_ARG;
       break;
     case EPM_BIN256:
-      if (dim != 256) return EPM_ERR_ARG;
+      if (c.dim != 256) return EPM_ERR_ARG;
       break;
     default:
       return EPM_ERR_ARG;
   }
-  const bool reduced = dtype == EPM_BF16 || dtype == EPM_FP8_E4M3;
-  if (reduced && n1 > 0 && (!desc1_f32 || (idx->N2 > 0 && !desc2_f32))) return EPM_ERR_ARG;
-  if (dtype == EPM_FP8_E4M3 && n1 > 0 && (!scale1 || (idx->N2 > 0 && !scale2))) return EPM_ERR_ARG;
+  const bool reduced = c.dtype == EPM_BF16 || c.dtype == EPM_FP8_E4M3;
+  if (reduced && n1 > 0 && (!c.desc1_f32 || (idx->N2 > 0 && !c.desc2_f32))) return EPM_ERR_ARG;
+  if (c.dtype == EPM_FP8_E4M3 && n1 > 0 && (!c.scale1 || (idx->N2 > 0 && !c.scale2)))
+    return EPM_ERR_ARG;
+  return EPM_OK;
+}
+
+epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream) {
+  const int64_t n1 = idx->N1;
   if (n1 == 0) return EPM_OK;
   const Layout& L = idx->L;
   MatchArgs A;
@@ -478,45 +503,62 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   A.num_pairs = idx->P;
   A.n1 = n1;
   A.qperm = idx->have_qperm ? idx->qperm : nullptr;
-  A.row_offsets = row_offsets;
-  A.cols = col_indices;
-  A.desc1 = desc1;
-  A.desc2 = desc2;
-  A.ratio = ratio;
-  A.best_idx = best_idx;
-  A.best_dist = best_dist;
-  A.second_dist = second_dist;
+  A.row_offsets = c.row_offsets;
+  A.cols = c.col_indices;
+  A.desc1 = c.desc1;
+  A.desc2 = c.desc2;
+  A.ratio = c.ratio;
+  A.best_idx = c.best_idx;
+  A.best_dist = c.best_dist;
+  A.second_dist = c.second_dist;
   A.tiles = idx->at<StabTile>(L.stiles);
   A.num_tiles = (int)idx->stiles.size();
   A.windows = idx->at<TileWindow>(L.windows);
   A.rinv = idx->at<uint32_t>(L.rinv);
   A.rj = idx->at<int32_t>(L.rj);
   A.xcd_order = false;
-  A.scale1 = scale1;
-  A.scale2 = scale2;
-  A.desc1_f32 = desc1_f32;
-  A.desc2_f32 = desc2_f32;
+  A.scale1 = c.scale1;
+  A.scale2 = c.scale2;
+  A.desc1_f32 = c.desc1_f32;
+  A.desc2_f32 = c.desc2_f32;
   A.match_stats = idx->at<unsigned long long>(L.match_stats);
+  A.capacity = c.capacity;
+  A.order = nullptr;
+  A.queue = nullptr;
   // the window kernels walk the angle tiles and windows of the last query
-  const bool tiled = algo != EPM_ALGO_PLAIN && idx->have_qperm;
+  const bool tiled = c.algo != EPM_ALGO_PLAIN && idx->have_qperm;
+  const int grid = idx->sched.match_workgroups;
+  if (tiled && grid > 0) {
+    uint32_t* sched = idx->at<uint32_t>(L.sched);
+    A.queue = sched + kSchedMatchQueue;
+    A.order = idx->have_order ? idx->at<uint32_t>(L.order) : nullptr;
+  }
+  auto tiled_launch = [&](int fmt) -> hipError_t {
+    if (grid > 0) {
+      const hipError_t e = launch_fill_u32(A.queue, 1, 0u, stream);
+      if (e != hipSuccess) return e;
+    }
+    return fmt < 0 ? launch_match_window_f32(A, grid, stream)
+                   : launch_match_window_mfma(A, fmt, grid, stream);
+  };
+  const bool reduced = c.dtype == EPM_BF16 || c.dtype == EPM_FP8_E4M3;
   if (reduced) {
-    epm_index* mi = const_cast<epm_index*>(idx);
-    mi->have_match_stats = true;
-    mi->match_stream = stream;
+    idx->have_match_stats = true;
+    idx->match_stream = stream;
     EPM_HIP(launch_clear_stats(A.match_stats, stream));
     if (!tiled) {
       // no angle tiles to stage: exact FP32 evaluation on the masters
-      A.desc1 = desc1_f32;
-      A.desc2 = desc2_f32;
+      A.desc1 = c.desc1_f32;
+      A.desc2 = c.desc2_f32;
       EPM_HIP(launch_match_plain_f32(A, stream));
       return EPM_OK;
     }
-    EPM_HIP(launch_match_window_mfma(A, dtype == EPM_BF16 ? 0 : 1, stream));
+    EPM_HIP(tiled_launch(c.dtype == EPM_BF16 ? 0 : 1));
     return EPM_OK;
   }
-  switch (dtype) {
+  switch (c.dtype) {
     case EPM_F32:
-      EPM_HIP(tiled ? launch_match_window_f32(A, stream) : launch_match_plain_f32(A, stream));
+      EPM_HIP(tiled ? tiled_launch(-1) : launch_match_plain_f32(A, stream));
       return EPM_OK;
     case EPM_BIN256:
       // 32-byte rows: per-candidate gathers are already line-efficient
@@ -526,6 +568,233 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
       return EPM_ERR_UNSUPPORTED;
   }
 }
+
+}  // namespace
+
+// A recorded pipeline: the index it runs on and the instantiated graph.
+struct epm_batch {
+  epm_index* idx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t* row_offsets = nullptr;
+  int64_t capacity = 0;
+  ~epm_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    delete idx;
+  }
+};
+
+extern "C" {
+
+size_t epm_workspace_bytes(const epm_pair* pairs, int32_t num_pairs) {
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return 0;
+  int64_t tr = 0, tq = 0, ts = 0;
+  for (int p = 0; p < num_pairs; ++p) {
+    tr += tiles_of(pairs[p].n);
+    tq += tiles_of(pairs[p].m);
+    ts += stab_tiles_of(pairs[p].m);
+  }
+  return make_layout(num_pairs, n1, n2, tr, tq, ts).total;
+}
+
+epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
+                               const float* eps2, float eps_scalar, void* workspace,
+                               size_t workspace_bytes, epm_index** out, hipStream_t stream) {
+  if (!out) return EPM_ERR_ARG;
+  *out = nullptr;
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
+  if (!build_args_ok(n2, kp2_xy, eps2, eps_scalar)) return EPM_ERR_ARG;
+  epm_index* idx = nullptr;
+  const epm_status st = index_prepare(pairs, num_pairs, workspace, workspace_bytes, &idx);
+  if (st != EPM_OK) return st;
+  epm_status r = index_upload(idx, stream);
+  if (r == EPM_OK) r = enqueue_build(idx, kp2_xy, eps2, eps_scalar, stream);
+  if (r != EPM_OK) {
+    delete idx;
+    return r;
+  }
+  *out = idx;
+  return EPM_OK;
+}
+
+epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched) {
+  if (!idx || !sched) return EPM_ERR_ARG;
+  if (sched->stab_workgroups < 0 || sched->match_workgroups < 0) return EPM_ERR_ARG;
+  if (sched->lpt != 0 && sched->lpt != 1) return EPM_ERR_ARG;
+  for (int k = 0; k < 5; ++k)
+    if (sched->reserved[k] != 0) return EPM_ERR_ARG;
+  idx->sched = *sched;
+  return EPM_OK;
+}
+
+epm_status epm_query_candidates(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                                hipStream_t stream) {
+  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
+  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  const int64_t n1 = idx->N1;
+  StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
+  const epm_status st = enqueue_count(idx, A, row_offsets, stream);
+  if (st != EPM_OK) return st;
+  if (n1 > 0) {
+    idx->last_stream = stream;
+    idx->last_offsets = row_offsets;
+    idx->have_stats = true;
+  }
+  if (nnz_host) {
+    int64_t nnz = 0;
+    EPM_HIP(hipMemcpyAsync(&nnz, row_offsets + n1, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    EPM_HIP(hipStreamSynchronize(stream));
+    *nnz_host = nnz;
+    if (nnz > capacity) return EPM_ERR_CAPACITY;
+  }
+  return enqueue_fill(idx, A, stream);
+}
+
+epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
+                     const int32_t* col_indices, epm_dtype dtype, int32_t dim,
+                     const void* desc1, const void* desc2, const float* scale1,
+                     const float* scale2, const float* desc1_f32, const float* desc2_f32,
+                     float ratio, int32_t* best_idx, float* best_dist, float* second_dist,
+                     const epm_match_opts* opts, hipStream_t stream) {
+  MatchCall c;
+  c.row_offsets = row_offsets;
+  c.col_indices = col_indices;
+  c.dtype = dtype;
+  c.dim = dim;
+  c.desc1 = desc1;
+  c.desc2 = desc2;
+  c.scale1 = scale1;
+  c.scale2 = scale2;
+  c.desc1_f32 = desc1_f32;
+  c.desc2_f32 = desc2_f32;
+  c.ratio = ratio;
+  c.best_idx = best_idx;
+  c.best_dist = best_dist;
+  c.second_dist = second_dist;
+  c.algo = opts ? opts->algo : EPM_ALGO_AUTO;
+  c.capacity = -1;
+  if (opts) {
+    if (opts->check_capacity != 0 && opts->check_capacity != 1) return EPM_ERR_ARG;
+    for (int k = 0; k < 4; ++k)
+      if (opts->reserved[k] != 0) return EPM_ERR_ARG;
+    if (opts->check_capacity) {
+      if (opts->col_capacity < 0) return EPM_ERR_ARG;
+      c.capacity = opts->col_capacity;
+    }
+  }
+  const epm_status v = validate_match(idx, c);
+  if (v != EPM_OK) return v;
+  return enqueue_match(const_cast<epm_index*>(idx), c, stream);
+}
+
+epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_batch_desc* d,
+                            void* workspace, size_t workspace_bytes, epm_batch** out,
+                            hipStream_t stream) {
+  if (!out) return EPM_ERR_ARG;
+  *out = nullptr;
+  if (!d) return EPM_ERR_ARG;
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
+  if (!build_args_ok(n2, d->kp2_xy, d->eps2, d->eps_scalar)) return EPM_ERR_ARG;
+  if (!d->row_offsets || d->capacity < 0 || (n1 > 0 && !d->kp1_xy)) return EPM_ERR_ARG;
+  if (d->capacity > 0 && !d->col_indices) return EPM_ERR_ARG;
+  epm_batch* b = new (std::nothrow) epm_batch();
+  if (!b) return EPM_ERR_ARG;
+  epm_status st = index_prepare(pairs, num_pairs, workspace, workspace_bytes, &b->idx);
+  if (st != EPM_OK) {
+    delete b;
+    return st;
+  }
+  epm_index* idx = b->idx;
+  st = epm_index_set_sched(idx, &d->sched);
+  MatchCall c;
+  c.row_offsets = d->row_offsets;
+  c.col_indices = d->col_indices;
+  c.dtype = d->dtype;
+  c.dim = d->dim;
+  c.desc1 = d->desc1;
+  c.desc2 = d->desc2;
+  c.scale1 = d->scale1;
+  c.scale2 = d->scale2;
+  c.desc1_f32 = d->desc1_f32;
+  c.desc2_f32 = d->desc2_f32;
+  c.ratio = d->ratio;
+  c.best_idx = d->best_idx;
+  c.best_dist = d->best_dist;
+  c.second_dist = d->second_dist;
+  c.algo = d->algo;
+  c.capacity = d->capacity;
+  if (st == EPM_OK) st = validate_match(idx, c);
+  if (st == EPM_OK) st = index_upload(idx, stream);
+  if (st != EPM_OK) {
+    delete b;
+    return st;
+  }
+  b->row_offsets = d->row_offsets;
+  b->capacity = d->capacity;
+
+  // record on a private stream: kernels only
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return EPM_ERR_HIP;
+  }
+  st = EPM_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = EPM_ERR_HIP;
+  if (st == EPM_OK) {
+    epm_status r = enqueue_build(idx, d->kp2_xy, d->eps2, d->eps_scalar, cs);
+    // after the build: the stab arguments name the sorted key buffer it chose
+    StabArgs A = stab_args(idx, d->kp1_xy, d->row_offsets, d->col_indices, d->capacity);
+    if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs);
+    if (r == EPM_OK) r = enqueue_fill(idx, A, cs);
+    if (r == EPM_OK) r = enqueue_match(idx, c, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    b->graph = g;
+    if (r != EPM_OK) st = r;
+    else if (e != hipSuccess || !g) st = EPM_ERR_HIP;
+  }
+  if (st == EPM_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = EPM_ERR_HIP;
+  (void)hipStreamDestroy(cs);
+  if (st != EPM_OK) {
+    delete b;
+    return st;
+  }
+  idx->have_stats = idx->N1 > 0;
+  idx->last_offsets = d->row_offsets;
+  idx->last_stream = stream;
+  idx->match_stream = stream;
+  *out = b;
+  return EPM_OK;
+}
+
+epm_status epm_batch_launch(epm_batch* b, hipStream_t stream) {
+  if (!b || !b->exec) return EPM_ERR_ARG;
+  EPM_HIP(hipGraphLaunch(b->exec, stream));
+  b->idx->last_stream = stream;
+  b->idx->match_stream = stream;
+  return EPM_OK;
+}
+
+epm_status epm_batch_nnz(epm_batch* b, int64_t* nnz, hipStream_t stream) {
+  if (!b || !nnz) return EPM_ERR_ARG;
+  int64_t v = 0;
+  EPM_HIP(hipMemcpyAsync(&v, b->row_offsets + b->idx->N1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                         stream));
+  EPM_HIP(hipStreamSynchronize(stream));
+  *nnz = v;
+  return v > b->capacity ? EPM_ERR_CAPACITY : EPM_OK;
+}
+
+const epm_index* epm_batch_index(const epm_batch* b) { return b ? b->idx : nullptr; }
+
+void epm_batch_destroy(epm_batch* b) { delete b; }
 
 epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
                                 const float* eps2, float eps_scalar, const int64_t* qi,

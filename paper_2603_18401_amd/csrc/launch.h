@@ -69,7 +69,22 @@ struct StabArgs {
   unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
   uint32_t* long_rows;        // [n1] queue of rows longer than kStage
   TileWindow* windows;        // [num_tiles], written by launch_tile_windows
+  uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
+  const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
+  uint32_t* queue;            // persistent launch: next-tile counter, zero at launch
 };
+
+// Scheduling counters (u32 words of one workspace block).
+constexpr int kCostBuckets = 33;  // cost 0, then one bucket per power of two
+constexpr int kSchedHist = 0, kSchedCursor = kCostBuckets, kSchedStabQueue = 2 * kCostBuckets,
+              kSchedMatchQueue = 2 * kCostBuckets + 1;
+constexpr int kSchedWords = 2 * kCostBuckets + 2;
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// Longest-first order of the tiles from their costs; the histogram and cursor
+// words of `sched` must be zero.
+hipError_t launch_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
+                            uint32_t* order, hipStream_t s);
 
 // One wavefront per tile finds the tile's window in every width class.
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
@@ -81,8 +96,9 @@ hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
 
 hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
 hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s);
-// Tiled count pass (also parks rows of <= kStage candidates, sorted).
-hipError_t launch_stab_tiles(const StabArgs& a, hipStream_t s);
+// Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
+// workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, hipStream_t s);
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the rest.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
 
@@ -116,16 +132,21 @@ struct MatchArgs {
   const float* desc1_f32;     // FP32 masters (re-rank and exact fallback)
   const float* desc2_f32;
   unsigned long long* match_stats;  // [kNumMatchStats], cleared before the launch
+  int64_t capacity;            // size of cols; < 0: trusted.  Nothing is written
+                               // when row_offsets[n1] exceeds it.
+  const uint32_t* order;       // persistent tiled launch: tile order (NULL = angle order)
+  uint32_t* queue;             // persistent tiled launch: next-tile counter, zero at launch
 };
 
 constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallback), long rows
 // fmt 0: BF16, 1: FP8-E4M3 with row scales.
-hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, hipStream_t s);
+// grid as for launch_stab_tiles.
+hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, int grid, hipStream_t s);
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
 // One workgroup per stabbing tile, window descriptor rows staged in LDS.
-hipError_t launch_match_window_f32(const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_window_f32(const MatchArgs& a, int grid, hipStream_t s);
 
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,

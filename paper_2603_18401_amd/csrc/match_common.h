@@ -76,6 +76,12 @@ __device__ __forceinline__ Top2 wave_merge_top2(Top2 t) {
 
 // Output convention: empty row -> -1 / +inf / +inf; ratio rejection -> -1
 // with both distances kept.
+// A CSR that did not fit its buffer (row_offsets[n1] beyond the caller's
+// capacity) is incomplete: such a launch writes nothing.
+__device__ __forceinline__ bool csr_overflow(const MatchArgs& A) {
+  return A.capacity >= 0 && A.row_offsets[A.n1] > A.capacity;
+}
+
 __device__ __forceinline__ void write_match(const MatchArgs& A, int64_t i, const Top2& t,
                                             bool binary) {
   int32_t idx = t.bj == INT32_MAX ? -1 : t.bj;

@@ -102,7 +102,7 @@ __device__ __forceinline__ double lower_bound(double dt, double nq, double nw, d
   return (1.0 - 1e-5) * r * r;
 }
 
-template <int FMT>
+template <int FMT, bool PERSIST>
 __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   constexpr int RS = row_stride<FMT>();
   __shared__ __attribute__((aligned(16))) uint8_t qrows[kTileQ * RS];
@@ -125,312 +125,338 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   __shared__ float pick_d[kTileQ][kReRank];
   __shared__ float lb5[kTileQ];
 
-  const int tile = xcd_tile(blockIdx.x, A.num_tiles);
-  const StabTile T = A.tiles[tile];
-  const int64_t kb = A.kstart[T.pair];
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const TileWindow* W = A.windows + tile;
-  const uint8_t* d1 = reinterpret_cast<const uint8_t*>(A.desc1);
-  const uint8_t* d2 = reinterpret_cast<const uint8_t*>(A.desc2);
-  constexpr int RB = Fmt<FMT>::kRowBytes;
+  __shared__ int next_tile;
+  if (csr_overflow(A)) return;
+  // one tile per workgroup, or (persistent) tiles from the queue until it is
+  // exhausted; every workgroup leaves once the counter passes the last tile
+  for (int iter = 0;; ++iter) {
+    int tile;
+    if (PERSIST) {
+      if (threadIdx.x == 0) next_tile = (int)atomicAdd(A.queue, 1u);
+      __syncthreads();
+      const int t = next_tile;
+      if (t >= A.num_tiles) break;
+      tile = A.order ? (int)A.order[t] : t;
+    } else {
+      if (iter > 0) break;
+      tile = xcd_tile(blockIdx.x, A.num_tiles);
+    }
+    const StabTile T = A.tiles[tile];
+    const int64_t kb = A.kstart[T.pair];
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    const TileWindow* W = A.windows + tile;
+    const uint8_t* d1 = reinterpret_cast<const uint8_t*>(A.desc1);
+    const uint8_t* d2 = reinterpret_cast<const uint8_t*>(A.desc2);
+    constexpr int RB = Fmt<FMT>::kRowBytes;
 
-  if (wave == 0) {
-    const int q = lane;
-    int64_t i = 0, o0 = 0, k = 0;
-    if (q < T.count) {
-      i = (int64_t)A.qperm[T.begin + q];
-      o0 = A.row_offsets[i];
-      k = A.row_offsets[i + 1] - o0;
+    if (wave == 0) {
+      const int q = lane;
+      int64_t i = 0, o0 = 0, k = 0;
+      if (q < T.count) {
+        i = (int64_t)A.qperm[T.begin + q];
+        o0 = A.row_offsets[i];
+        k = A.row_offsets[i + 1] - o0;
+      }
+      q_i[q] = i;
+      q_o0[q] = o0;
+      q_k[q] = (uint32_t)k;
+      // rows enter the dense list in order while they fit; the rest are
+      // evaluated by gathers
+      uint32_t incl = (uint32_t)(k < kMaxPairs ? k : kMaxPairs);
+      #pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      const bool fits = incl <= (uint32_t)kMaxPairs;
+      const uint64_t fit_mask = ballot(fits);
+      // the fitting rows are a prefix: recompute the offsets over that prefix
+      const int nfit = __popcll(fit_mask);
+      uint32_t kk = lane < nfit ? (uint32_t)k : 0u;
+      incl = kk;
+      #pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      q_off[q + 1] = incl;
+      q_in[q] = lane < nfit ? 1u : 0u;
+      if (lane == 0) {
+        q_off[0] = 0;
+        n_fallback = 0;
+      }
+      const uint32_t b = W->slot_b[lane];
+      const uint32_t p0 = W->slot_pref[lane], p1 = W->slot_pref[lane + 1];
+      slot_b[lane] = b;
+      slot_pref[lane] = p0;
+      if (lane == 0) slot_pref[kSlots] = W->slot_pref[kSlots];
+      const bool nonempty = p1 > p0;
+      const uint64_t ne = ballot(nonempty);
+      uint32_t rank = 0;
+      for (int s = 0; s < kWave; ++s) {
+        const uint32_t bs = __builtin_amdgcn_readlane(b, s);
+        if (((ne >> s) & 1ull) && (bs < b || (bs == b && s < lane))) ++rank;
+      }
+      if (nonempty) {
+        ss_b[rank] = b;
+        ss_v[rank] = p0;
+        ss_len[rank] = p1 - p0;
+      }
+      if (lane == 0) n_sorted_slots = (uint32_t)__popcll(ne);
     }
-    q_i[q] = i;
-    q_o0[q] = o0;
-    q_k[q] = (uint32_t)k;
-    // rows enter the dense list in order while they fit; the rest are
-    // evaluated by gathers
-    uint32_t incl = (uint32_t)(k < kMaxPairs ? k : kMaxPairs);
-    #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t o = __shfl_up(incl, off);
-      if (lane >= off) incl += o;
-    }
-    const bool fits = incl <= (uint32_t)kMaxPairs;
-    const uint64_t fit_mask = ballot(fits);
-    // the fitting rows are a prefix: recompute the offsets over that prefix
-    const int nfit = __popcll(fit_mask);
-    uint32_t kk = lane < nfit ? (uint32_t)k : 0u;
-    incl = kk;
-    #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t o = __shfl_up(incl, off);
-      if (lane >= off) incl += o;
-    }
-    q_off[q + 1] = incl;
-    q_in[q] = lane < nfit ? 1u : 0u;
-    if (lane == 0) {
-      q_off[0] = 0;
-      n_fallback = 0;
-    }
-    const uint32_t b = W->slot_b[lane];
-    const uint32_t p0 = W->slot_pref[lane], p1 = W->slot_pref[lane + 1];
-    slot_b[lane] = b;
-    slot_pref[lane] = p0;
-    if (lane == 0) slot_pref[kSlots] = W->slot_pref[kSlots];
-    const bool nonempty = p1 > p0;
-    const uint64_t ne = ballot(nonempty);
-    uint32_t rank = 0;
-    for (int s = 0; s < kWave; ++s) {
-      const uint32_t bs = __builtin_amdgcn_readlane(b, s);
-      if (((ne >> s) & 1ull) && (bs < b || (bs == b && s < lane))) ++rank;
-    }
-    if (nonempty) {
-      ss_b[rank] = b;
-      ss_v[rank] = p0;
-      ss_len[rank] = p1 - p0;
-    }
-    if (lane == 0) n_sorted_slots = (uint32_t)__popcll(ne);
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // quantised query rows (zero rows past the tile end), their norms and scales
-  for (int f = tid; f < kTileQ * (RB / 16); f += kThreads) {
-    const int q = f / (RB / 16), c = f % (RB / 16);
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (q < T.count) v = reinterpret_cast<const uint4*>(d1 + q_i[q] * RB)[c];
-    *reinterpret_cast<uint4*>(qrows + q * RS + c * 16) = v;
-  }
-  // dense (query, candidate, window index) list
-  const uint32_t npairs = q_off[kTileQ];
-  const uint32_t nss = n_sorted_slots;
-  for (uint32_t e = tid; e < npairs; e += kThreads) {
-    uint32_t q = 0;
-    #pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-      if (q + step < kTileQ && q_off[q + step] <= e) q += step;
-    const uint32_t t = e - q_off[q];
-    const int32_t j = A.cols[q_o0[q] + t];
-    const uint32_t pos = A.rinv[kb + j];
-    uint32_t v = kNoWindow;
-    if (nss > 0) {
-      uint32_t s = 0;
+    // quantised query rows (zero rows past the tile end), their norms and scales
+    for (int f = tid; f < kTileQ * (RB / 16); f += kThreads) {
+      const int q = f / (RB / 16), c = f % (RB / 16);
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (q < T.count) v = reinterpret_cast<const uint4*>(d1 + q_i[q] * RB)[c];
+      *reinterpret_cast<uint4*>(qrows + q * RS + c * 16) = v;
+    }
+    // dense (query, candidate, window index) list
+    const uint32_t npairs = q_off[kTileQ];
+    const uint32_t nss = n_sorted_slots;
+    for (uint32_t e = tid; e < npairs; e += kThreads) {
+      uint32_t q = 0;
       #pragma unroll
       for (int step = 32; step > 0; step >>= 1)
-        if (s + step < nss && ss_b[s + step] <= pos) s += step;
-      if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
-    }
-    if (v >= kNoWindow) v = kNoWindow;
-    ent[e] = pack_entry(q, v);
-    ent_j[e] = j;
-  }
-  __syncthreads();
-  if (tid < kTileQ) {
-    float n = 0.0f;
-    for (int k = 0; k < 128; ++k) {
-      const float x = Fmt<FMT>::decode(qrows + tid * RS, k);
-      n = __builtin_fmaf(x, x, n);
-    }
-    const float s = (FMT == 1 && tid < T.count) ? A.scale1[q_i[tid]] : 1.0f;
-    q_scale[tid] = s;
-    q_norm[tid] = n * s * s;  // squared norm of the dequantised row
-  }
-
-  const uint32_t wlen = slot_pref[kSlots];
-  float* score = reinterpret_cast<float*>(wrows);  // reused after the MFMA reads
-  for (uint32_t c0 = 0; c0 < wlen; c0 += kChunkRows) {
-    const uint32_t nr = wlen - c0 < (uint32_t)kChunkRows ? wlen - c0 : (uint32_t)kChunkRows;
-    for (uint32_t r = tid; r < kChunkRows; r += kThreads) {
-      int32_t j = -1;
-      if (r < nr) {
-        const uint32_t v = c0 + r;
+        if (q + step < kTileQ && q_off[q + step] <= e) q += step;
+      const uint32_t t = e - q_off[q];
+      const int32_t j = A.cols[q_o0[q] + t];
+      const uint32_t pos = A.rinv[kb + j];
+      uint32_t v = kNoWindow;
+      if (nss > 0) {
         uint32_t s = 0;
         #pragma unroll
         for (int step = 32; step > 0; step >>= 1)
-          if (s + step <= kSlots && slot_pref[s + step] <= v) s += step;
-        j = A.rj[slot_b[s] + (v - slot_pref[s])];
+          if (s + step < nss && ss_b[s + step] <= pos) s += step;
+        if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
       }
-      row_j[r] = j;
+      if (v >= kNoWindow) v = kNoWindow;
+      ent[e] = pack_entry(q, v);
+      ent_j[e] = j;
     }
     __syncthreads();
-    for (int f = tid; f < kChunkRows * (RB / 16); f += kThreads) {
-      const int r = f / (RB / 16), c = f % (RB / 16);
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (row_j[r] >= 0) v = reinterpret_cast<const uint4*>(d2 + (kb + row_j[r]) * RB)[c];
-      *reinterpret_cast<uint4*>(wrows + r * RS + c * 16) = v;
-    }
-    __syncthreads();
-    if (tid < kChunkRows) {
+    if (tid < kTileQ) {
       float n = 0.0f;
       for (int k = 0; k < 128; ++k) {
-        const float x = Fmt<FMT>::decode(wrows + tid * RS, k);
+        const float x = Fmt<FMT>::decode(qrows + tid * RS, k);
         n = __builtin_fmaf(x, x, n);
       }
-      const float s = (FMT == 1 && row_j[tid] >= 0) ? A.scale2[kb + row_j[tid]] : 1.0f;
-      w_scale[tid] = s;
-      w_norm[tid] = n * s * s;
+      const float s = (FMT == 1 && tid < T.count) ? A.scale1[q_i[tid]] : 1.0f;
+      q_scale[tid] = s;
+      q_norm[tid] = n * s * s;  // squared norm of the dequantised row
     }
-    // S = Q W^T: wavefront w owns queries 16w..16w+15 against all 64 rows
-    f32x4 acc[4];
-    #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    const int arow = wave * 16 + (lane & 15);
-    #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
-      if (FMT == 0) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * RS + koff * 2);
-        #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(wrows + (cb * 16 + (lane & 15)) * RS + koff * 2);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
-        }
-      } else {
-        const long a = *reinterpret_cast<const long*>(qrows + arow * RS + koff);
-        #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const long b = *reinterpret_cast<const long*>(wrows + (cb * 16 + (lane & 15)) * RS + koff);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[cb], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();  // every wave has read wrows; the scores go there now
-    #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = wave * 16 + (lane >> 4) * 4 + i;
-        const int r = cb * 16 + (lane & 15);
-        score[q * (kChunkRows + 1) + r] = acc[cb][i];
-      }
-    }
-    __syncthreads();
-    for (uint32_t e = tid; e < npairs; e += kThreads) {
-      const uint32_t x = ent[e];
-      if (!(x & kPending)) continue;
-      const uint32_t v = (x >> 6) & kNoWindow;
-      if (v < c0 || v >= c0 + nr) continue;
-      const uint32_t q = x & 63u, r = v - c0;
-      const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
-      const double nq = sqrt((double)q_norm[q]) * (1.0 + 1e-5);
-      const double nw = sqrt((double)w_norm[r]) * (1.0 + 1e-5);
-      const double dt = (double)q_norm[q] + (double)w_norm[r] - 2.0 * s;
-      const double lb = lower_bound(dt, nq, nw, row_delta<FMT>(nq, q_scale[q]),
-                                    row_delta<FMT>(nw, w_scale[r]));
-      ent[e] = __float_as_uint((float)lb * (1.0f - 1e-6f));  // rounded down, >= 0
-    }
-    __syncthreads();
-  }
-  // candidates outside the window: bound 0 (always re-ranked or evaluated)
-  for (uint32_t e = tid; e < npairs; e += kThreads)
-    if (ent[e] & kPending) ent[e] = 0u;
-  __syncthreads();
 
-  // choose, per query, the four smallest bounds and the fifth bound
-  if (tid < T.count && q_in[tid]) {
-    const int q = tid;
-    float bd[kReRank + 1];
-    uint32_t be[kReRank + 1];
-    #pragma unroll
-    for (int u = 0; u <= kReRank; ++u) {
-      bd[u] = __builtin_inff();
-      be[u] = 0xFFFFFFFFu;
+    const uint32_t wlen = slot_pref[kSlots];
+    float* score = reinterpret_cast<float*>(wrows);  // reused after the MFMA reads
+    for (uint32_t c0 = 0; c0 < wlen; c0 += kChunkRows) {
+      const uint32_t nr = wlen - c0 < (uint32_t)kChunkRows ? wlen - c0 : (uint32_t)kChunkRows;
+      for (uint32_t r = tid; r < kChunkRows; r += kThreads) {
+        int32_t j = -1;
+        if (r < nr) {
+          const uint32_t v = c0 + r;
+          uint32_t s = 0;
+          #pragma unroll
+          for (int step = 32; step > 0; step >>= 1)
+            if (s + step <= kSlots && slot_pref[s + step] <= v) s += step;
+          j = A.rj[slot_b[s] + (v - slot_pref[s])];
+        }
+        row_j[r] = j;
+      }
+      __syncthreads();
+      for (int f = tid; f < kChunkRows * (RB / 16); f += kThreads) {
+        const int r = f / (RB / 16), c = f % (RB / 16);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row_j[r] >= 0) v = reinterpret_cast<const uint4*>(d2 + (kb + row_j[r]) * RB)[c];
+        *reinterpret_cast<uint4*>(wrows + r * RS + c * 16) = v;
+      }
+      __syncthreads();
+      if (tid < kChunkRows) {
+        float n = 0.0f;
+        for (int k = 0; k < 128; ++k) {
+          const float x = Fmt<FMT>::decode(wrows + tid * RS, k);
+          n = __builtin_fmaf(x, x, n);
+        }
+        const float s = (FMT == 1 && row_j[tid] >= 0) ? A.scale2[kb + row_j[tid]] : 1.0f;
+        w_scale[tid] = s;
+        w_norm[tid] = n * s * s;
+      }
+      // S = Q W^T: wavefront w owns queries 16w..16w+15 against all 64 rows
+      f32x4 acc[4];
+      #pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+      const int arow = wave * 16 + (lane & 15);
+      #pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
+        if (FMT == 0) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * RS + koff * 2);
+          #pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(wrows + (cb * 16 + (lane & 15)) * RS + koff * 2);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+          }
+        } else {
+          const long a = *reinterpret_cast<const long*>(qrows + arow * RS + koff);
+          #pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const long b = *reinterpret_cast<const long*>(wrows + (cb * 16 + (lane & 15)) * RS + koff);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[cb], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();  // every wave has read wrows; the scores go there now
+      #pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = wave * 16 + (lane >> 4) * 4 + i;
+          const int r = cb * 16 + (lane & 15);
+          score[q * (kChunkRows + 1) + r] = acc[cb][i];
+        }
+      }
+      __syncthreads();
+      for (uint32_t e = tid; e < npairs; e += kThreads) {
+        const uint32_t x = ent[e];
+        if (!(x & kPending)) continue;
+        const uint32_t v = (x >> 6) & kNoWindow;
+        if (v < c0 || v >= c0 + nr) continue;
+        const uint32_t q = x & 63u, r = v - c0;
+        const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
+        const double nq = sqrt((double)q_norm[q]) * (1.0 + 1e-5);
+        const double nw = sqrt((double)w_norm[r]) * (1.0 + 1e-5);
+        const double dt = (double)q_norm[q] + (double)w_norm[r] - 2.0 * s;
+        const double lb = lower_bound(dt, nq, nw, row_delta<FMT>(nq, q_scale[q]),
+                                      row_delta<FMT>(nw, w_scale[r]));
+        ent[e] = __float_as_uint((float)lb * (1.0f - 1e-6f));  // rounded down, >= 0
+      }
+      __syncthreads();
     }
-    for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) {
-      float d = __uint_as_float(ent[e]);
-      uint32_t ee = e;
+    // candidates outside the window: bound 0 (always re-ranked or evaluated)
+    for (uint32_t e = tid; e < npairs; e += kThreads)
+      if (ent[e] & kPending) ent[e] = 0u;
+    __syncthreads();
+
+    // choose, per query, the four smallest bounds and the fifth bound
+    if (tid < T.count && q_in[tid]) {
+      const int q = tid;
+      float bd[kReRank + 1];
+      uint32_t be[kReRank + 1];
       #pragma unroll
       for (int u = 0; u <= kReRank; ++u) {
-        if (d < bd[u]) {
-          const float td = bd[u];
-          const uint32_t te = be[u];
-          bd[u] = d;
-          be[u] = ee;
-          d = td;
-          ee = te;
+        bd[u] = __builtin_inff();
+        be[u] = 0xFFFFFFFFu;
+      }
+      for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) {
+        float d = __uint_as_float(ent[e]);
+        uint32_t ee = e;
+        #pragma unroll
+        for (int u = 0; u <= kReRank; ++u) {
+          if (d < bd[u]) {
+            const float td = bd[u];
+            const uint32_t te = be[u];
+            bd[u] = d;
+            be[u] = ee;
+            d = td;
+            ee = te;
+          }
         }
       }
+      #pragma unroll
+      for (int u = 0; u < kReRank; ++u) pick[q][u] = be[u];
+      lb5[q] = bd[kReRank];
     }
-    #pragma unroll
-    for (int u = 0; u < kReRank; ++u) pick[q][u] = be[u];
-    lb5[q] = bd[kReRank];
-  }
-  __syncthreads();
-  // exact canonical distances of the picks: thread = (query, pick)
-  {
-    const int q = tid >> 2, u = tid & 3;
-    float d = __builtin_inff();
-    if (q < T.count && q_in[q] && pick[q][u] != 0xFFFFFFFFu) {
-      const int32_t j = ent_j[pick[q][u]];
-      d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
-                         reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
+    __syncthreads();
+    // exact canonical distances of the picks: thread = (query, pick)
+    {
+      const int q = tid >> 2, u = tid & 3;
+      float d = __builtin_inff();
+      if (q < T.count && q_in[q] && pick[q][u] != 0xFFFFFFFFu) {
+        const int32_t j = ent_j[pick[q][u]];
+        d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
+                           reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
+      }
+      pick_d[q][u] = d;
     }
-    pick_d[q][u] = d;
-  }
-  __syncthreads();
-  if (tid < T.count && q_in[tid]) {
-    const int q = tid;
-    Top2 t;
-    #pragma unroll
-    for (int u = 0; u < kReRank; ++u)
-      if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], ent_j[pick[q][u]]);
-    const uint32_t k = q_k[q];
-    // certified when every candidate left out has a bound above the second
-    const bool ok = k <= (uint32_t)kReRank || lb5[q] > t.sd;
-    if (ok) {
-      write_match(A, q_i[q], t, false);
-    } else {
-      const uint32_t slot = atomicAdd(&n_fallback, 1u);
-      fallback_q[slot] = (uint16_t)q;
+    __syncthreads();
+    if (tid < T.count && q_in[tid]) {
+      const int q = tid;
+      Top2 t;
+      #pragma unroll
+      for (int u = 0; u < kReRank; ++u)
+        if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], ent_j[pick[q][u]]);
+      const uint32_t k = q_k[q];
+      // certified when every candidate left out has a bound above the second
+      const bool ok = k <= (uint32_t)kReRank || lb5[q] > t.sd;
+      if (ok) {
+        write_match(A, q_i[q], t, false);
+      } else {
+        const uint32_t slot = atomicAdd(&n_fallback, 1u);
+        fallback_q[slot] = (uint16_t)q;
+      }
     }
-  }
-  __syncthreads();
-  if (A.match_stats && tid == 0) {
-    uint32_t longs = 0, reranked = 0;
-    for (int q = 0; q < T.count; ++q) {
-      longs += !q_in[q] && q_k[q] > 0;
-      reranked += q_in[q] && q_k[q] > 0;
+    __syncthreads();
+    if (A.match_stats && tid == 0) {
+      uint32_t longs = 0, reranked = 0;
+      for (int q = 0; q < T.count; ++q) {
+        longs += !q_in[q] && q_k[q] > 0;
+        reranked += q_in[q] && q_k[q] > 0;
+      }
+      atomicAdd(&A.match_stats[0], (unsigned long long)reranked);
+      atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
+      atomicAdd(&A.match_stats[2], (unsigned long long)longs);
     }
-    atomicAdd(&A.match_stats[0], (unsigned long long)reranked);
-    atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
-    atomicAdd(&A.match_stats[2], (unsigned long long)longs);
-  }
-  // fallback and long rows: every candidate exactly, one wavefront per query
-  const uint32_t nfb = n_fallback;
-  for (int t0 = wave; t0 < T.count + (int)nfb; t0 += kWaves) {
-    int q;
-    if (t0 < (int)nfb) {
-      q = fallback_q[t0];
-    } else {
-      q = t0 - (int)nfb;
-      if (q_in[q]) continue;
+    // fallback and long rows: every candidate exactly, one wavefront per query
+    const uint32_t nfb = n_fallback;
+    for (int t0 = wave; t0 < T.count + (int)nfb; t0 += kWaves) {
+      int q;
+      if (t0 < (int)nfb) {
+        q = fallback_q[t0];
+      } else {
+        q = t0 - (int)nfb;
+        if (q_in[q]) continue;
+      }
+      const int64_t i = q_i[q];
+      if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1_f32)[i * 32 + lane];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      Top2 t;
+      for (int64_t e = q_o0[q] + lane; e < q_o0[q] + q_k[q]; e += kWave) {
+        const int32_t j = A.cols[e];
+        const float4* r2 = reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32;
+        float acc = 0.0f;
+        #pragma unroll 8
+        for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qdesc[wave][k], r2[k]);
+        t.insert(acc, j);
+      }
+      t = wave_merge_top2(t);
+      if (lane == 0) write_match(A, i, t, false);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    const int64_t i = q_i[q];
-    if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1_f32)[i * 32 + lane];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    Top2 t;
-    for (int64_t e = q_o0[q] + lane; e < q_o0[q] + q_k[q]; e += kWave) {
-      const int32_t j = A.cols[e];
-      const float4* r2 = reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32;
-      float acc = 0.0f;
-      #pragma unroll 8
-      for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qdesc[wave][k], r2[k]);
-      t.insert(acc, j);
-    }
-    t = wave_merge_top2(t);
-    if (lane == 0) write_match(A, i, t, false);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
 }
 
 }  // namespace
 
-hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, hipStream_t s) {
+hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, int grid, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
-  if (fmt == 0)
-    hipLaunchKernelGGL(k_match_window_mfma<0>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_match_window_mfma<1>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  if (grid > 0 && !a.queue) return hipErrorInvalidValue;
+  const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
+  if (fmt == 0) {
+    if (grid > 0)
+      hipLaunchKernelGGL((k_match_window_mfma<0, true>), g, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_match_window_mfma<0, false>), g, dim3(kThreads), 0, s, a);
+  } else {
+    if (grid > 0)
+      hipLaunchKernelGGL((k_match_window_mfma<1, true>), g, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_match_window_mfma<1, false>), g, dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ constexpr int kWaves = kThreads / kWave;
 
 __global__ __launch_bounds__(kThreads) void k_match_plain_f32(MatchArgs A) {
   __shared__ float4 qdesc[kWaves][32];
+  if (csr_overflow(A)) return;
   const int lane = lane_id(), wave = wave_id();
   const int64_t blk = A.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
   const int64_t qs = blk * kWaves + wave;
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_match_plain_f32(MatchArgs A) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_match_plain_bin256(MatchArgs A) {
+  if (csr_overflow(A)) return;
   const int lane = lane_id(), wave = wave_id();
   const int64_t qs = (int64_t)blockIdx.x * kWaves + wave;
   if (qs >= A.n1) return;

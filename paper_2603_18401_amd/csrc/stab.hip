@@ -245,11 +245,13 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
   const int lane = lane_id();
   const int t = blockIdx.x;
   const StabTile T = A.tiles[t];
-  bool normal = false;
+  bool normal = false, brute = false;
   uint32_t key = 0;
   if (lane < T.count) {
     const int64_t i = A.qperm[T.begin + lane];
-    normal = A.qflag[i] == kQueryNormal;
+    const uint32_t flag = A.qflag[i];
+    normal = flag == kQueryNormal;
+    brute = flag == kQueryBrute;
     key = A.qkey[i];
   }
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
@@ -300,6 +302,17 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
   w->slot_b[lane] = (uint32_t)myb;
   w->slot_pref[lane + 1] = (uint32_t)incl;
   if (lane == 0) w->slot_pref[0] = 0u;
+  if (A.tile_cost) {
+    // work estimate: (query, record) pairs of the window scan, brute-force
+    // scans, and one unit per query
+    const uint64_t wlen = (uint64_t)__shfl(incl, kWave - 1);
+    const uint64_t nn = (uint64_t)__popcll(ballot(normal));
+    const uint64_t nb = (uint64_t)__popcll(ballot(brute));
+    if (lane == 0) {
+      const uint64_t c = nn * wlen + nb * (uint64_t)A.pairs[T.pair].n + (uint64_t)T.count;
+      A.tile_cost[t] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+    }
+  }
 }
 
 // Counts every row of a tile of kTileQ angle-sorted queries and parks rows of
@@ -309,6 +322,7 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // threads on different queries of the same record (the record is an LDS
 // broadcast), angle test, FP64 test, and an LDS atomic slot in the query's
 // hit list.  No wavefront-wide dependency chains.
+template <bool PERSIST>
 __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   __shared__ uint32_t sC[kChunk], sH[kChunk];
   __shared__ float2 sXY[kChunk];
@@ -320,121 +334,138 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   __shared__ int64_t qidx[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ unsigned long long tile_stats[3];
+  __shared__ int next_tile;
 
-  const int tile = xcd_tile(blockIdx.x, A.num_tiles);
-  const StabTile T = A.tiles[tile];
-  const PairDev& pd = A.pairs[T.pair];
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-
-  if (wave == 0) {
-    const bool live = lane < T.count;
-    int64_t i = 0;
-    uint32_t flag = kQueryEmpty, key = 0;
-    double a = 0.0, b = 0.0, c = 0.0;
-    if (live) {
-      i = A.qperm[T.begin + lane];
-      flag = A.qflag[i];
-      key = A.qkey[i];
-      if (flag != kQueryEmpty) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
+  // one tile per workgroup, or (persistent) tiles from the queue until it is
+  // exhausted; every workgroup leaves the loop once the counter passes the
+  // last tile
+  for (int iter = 0;; ++iter) {
+    int tile;
+    if (PERSIST) {
+      if (threadIdx.x == 0) next_tile = (int)atomicAdd(A.queue, 1u);
+      __syncthreads();
+      const int t = next_tile;
+      if (t >= A.num_tiles) break;
+      tile = A.order ? (int)A.order[t] : t;
+    } else {
+      if (iter > 0) break;
+      tile = xcd_tile(blockIdx.x, A.num_tiles);
     }
-    qa[lane] = a;
-    qb[lane] = b;
-    qc[lane] = c;
-    qk[lane] = key;
-    qmode[lane] = live ? flag : kQueryEmpty;
-    qidx[lane] = i;
-    cnt[lane] = 0;
-    if (lane < 3) tile_stats[lane] = 0ull;
-  }
-  {
-    const TileWindow* w = A.windows + tile;
-    if (tid < kSlots) slot_b[tid] = w->slot_b[tid];
-    if (tid <= kSlots) slot_pref[tid] = w->slot_pref[tid];
-  }
-  __syncthreads();
+    const StabTile T = A.tiles[tile];
+    const PairDev& pd = A.pairs[T.pair];
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
 
-  const int64_t total_len = slot_pref[kSlots];
-  uint32_t scanned = 0, angle_hits = 0;
-  for (int64_t base = 0; base < total_len; base += kChunk) {
-    const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
-    for (int v = tid; v < clen; v += kThreads) {
-      const int64_t virt = base + v;
-      int s = 0;  // last slot with slot_pref[s] <= virt
-      #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (s + step <= kSlots && slot_pref[s + step] <= virt) s += step;
-      const int64_t pos = slot_b[s] + (virt - slot_pref[s]);
-      sC[v] = A.rC[pos];
-      sH[v] = A.rH[pos];
-      sXY[v] = A.rxy[pos];
-      sE[v] = A.reps[pos];
-      sJ[v] = A.rj[pos];
+    if (wave == 0) {
+      const bool live = lane < T.count;
+      int64_t i = 0;
+      uint32_t flag = kQueryEmpty, key = 0;
+      double a = 0.0, b = 0.0, c = 0.0;
+      if (live) {
+        i = A.qperm[T.begin + lane];
+        flag = A.qflag[i];
+        key = A.qkey[i];
+        if (flag != kQueryEmpty) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
+      }
+      qa[lane] = a;
+      qb[lane] = b;
+      qc[lane] = c;
+      qk[lane] = key;
+      qmode[lane] = live ? flag : kQueryEmpty;
+      qidx[lane] = i;
+      cnt[lane] = 0;
+      if (lane < 3) tile_stats[lane] = 0ull;
+    }
+    {
+      const TileWindow* w = A.windows + tile;
+      if (tid < kSlots) slot_b[tid] = w->slot_b[tid];
+      if (tid <= kSlots) slot_pref[tid] = w->slot_pref[tid];
     }
     __syncthreads();
-    const int npairs = clen * kTileQ;
-    for (int p = tid; p < npairs; p += kThreads) {
-      const int q = p & (kTileQ - 1);
-      const int r = p >> 6;
-      if (qmode[q] != kQueryNormal) continue;
-      ++scanned;
-      if (key_distance(qk[q], sC[r]) > sH[r]) continue;
-      ++angle_hits;
-      const float2 xy = sXY[r];
-      if (!within_tolerance(qa[q], qb[q], qc[q], xy.x, xy.y, sE[r])) continue;
-      const uint32_t slot = atomicAdd(&cnt[q], 1u);
-      if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
+
+    const int64_t total_len = slot_pref[kSlots];
+    uint32_t scanned = 0, angle_hits = 0;
+    for (int64_t base = 0; base < total_len; base += kChunk) {
+      const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
+      for (int v = tid; v < clen; v += kThreads) {
+        const int64_t virt = base + v;
+        int s = 0;  // last slot with slot_pref[s] <= virt
+        #pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (s + step <= kSlots && slot_pref[s + step] <= virt) s += step;
+        const int64_t pos = slot_b[s] + (virt - slot_pref[s]);
+        sC[v] = A.rC[pos];
+        sH[v] = A.rH[pos];
+        sXY[v] = A.rxy[pos];
+        sE[v] = A.reps[pos];
+        sJ[v] = A.rj[pos];
+      }
+      __syncthreads();
+      const int npairs = clen * kTileQ;
+      for (int p = tid; p < npairs; p += kThreads) {
+        const int q = p & (kTileQ - 1);
+        const int r = p >> 6;
+        if (qmode[q] != kQueryNormal) continue;
+        ++scanned;
+        if (key_distance(qk[q], sC[r]) > sH[r]) continue;
+        ++angle_hits;
+        const float2 xy = sXY[r];
+        if (!within_tolerance(qa[q], qb[q], qc[q], xy.x, xy.y, sE[r])) continue;
+        const uint32_t slot = atomicAdd(&cnt[q], 1u);
+        if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
+      }
+      __syncthreads();
+    }
+
+    // queries whose line misses the epipole too far: exact scan of the pair
+    uint32_t brute = 0;
+    for (int qq = 0; qq < kQPerWave; ++qq) {
+      const int q = wave * kQPerWave + qq;
+      if (qmode[q] != kQueryBrute) continue;
+      const double a = qa[q], b = qb[q], c = qc[q];
+      uint32_t c0 = 0;
+      brute += 1;
+      for (int64_t base = pd.k_begin; base < pd.k_begin + pd.n; base += kWave) {
+        const int64_t pos = base + lane;
+        bool hit = false;
+        if (pos < pd.k_begin + pd.n) {
+          const float2 xy = A.rxy[pos];
+          hit = within_tolerance(a, b, c, xy.x, xy.y, A.reps[pos]);
+        }
+        const uint64_t m = ballot(hit);
+        if (hit) {
+          const uint32_t slot = c0 + lanes_below(m);
+          if (slot < (uint32_t)kStage) hits[q][slot] = A.rj[pos];
+        }
+        c0 += (uint32_t)__popcll(m);
+      }
+      if (lane == 0) cnt[q] = c0;
+    }
+    if (A.stats) {
+      if (scanned) atomicAdd(&tile_stats[0], (unsigned long long)scanned);
+      if (angle_hits) atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
     }
     __syncthreads();
-  }
-
-  // queries whose line misses the epipole too far: exact scan of the pair
-  uint32_t brute = 0;
-  for (int qq = 0; qq < kQPerWave; ++qq) {
-    const int q = wave * kQPerWave + qq;
-    if (qmode[q] != kQueryBrute) continue;
-    const double a = qa[q], b = qb[q], c = qc[q];
-    uint32_t c0 = 0;
-    brute += 1;
-    for (int64_t base = pd.k_begin; base < pd.k_begin + pd.n; base += kWave) {
-      const int64_t pos = base + lane;
-      bool hit = false;
-      if (pos < pd.k_begin + pd.n) {
-        const float2 xy = A.rxy[pos];
-        hit = within_tolerance(a, b, c, xy.x, xy.y, A.reps[pos]);
+    if (A.stats && tid == 0) {
+      uint64_t empty = 0, nbrute = 0;
+      for (int q = 0; q < T.count; ++q) {
+        empty += qmode[q] == kQueryEmpty;
+        nbrute += qmode[q] == kQueryBrute;
       }
-      const uint64_t m = ballot(hit);
-      if (hit) {
-        const uint32_t slot = c0 + lanes_below(m);
-        if (slot < (uint32_t)kStage) hits[q][slot] = A.rj[pos];
-      }
-      c0 += (uint32_t)__popcll(m);
+      if (nbrute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nbrute);
+      atomicAdd(&A.stats[kStatRecords], tile_stats[0] + nbrute * (uint64_t)pd.n);
+      atomicAdd(&A.stats[kStatAngleHits], tile_stats[1] + nbrute * (uint64_t)pd.n);
+      if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
     }
-    if (lane == 0) cnt[q] = c0;
-  }
-  if (A.stats) {
-    if (scanned) atomicAdd(&tile_stats[0], (unsigned long long)scanned);
-    if (angle_hits) atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
-  }
-  __syncthreads();
-  if (A.stats && tid == 0) {
-    uint64_t empty = 0, nbrute = 0;
-    for (int q = 0; q < T.count; ++q) {
-      empty += qmode[q] == kQueryEmpty;
-      nbrute += qmode[q] == kQueryBrute;
-    }
-    if (nbrute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nbrute);
-    atomicAdd(&A.stats[kStatRecords], tile_stats[0] + nbrute * (uint64_t)pd.n);
-    atomicAdd(&A.stats[kStatAngleHits], tile_stats[1] + nbrute * (uint64_t)pd.n);
-    if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
-  }
-  (void)brute;
+    (void)brute;
 
-  // row lengths, and short rows parked unsorted (the copy pass sorts them)
-  if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
-  for (int p = tid; p < T.count * kStage; p += kThreads) {
-    const int q = p / kStage, t = p % kStage;
-    const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
-    if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
+    // row lengths, and short rows parked unsorted (the copy pass sorts them)
+    if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
+    for (int p = tid; p < T.count * kStage; p += kThreads) {
+      const int q = p / kStage, t = p % kStage;
+      const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
+      if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
+    }
+    if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
 }
 
@@ -589,9 +620,15 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stab_tiles(const StabArgs& a, hipStream_t s) {
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stab_tile, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  if (grid > 0) {
+    if (!a.queue) return hipErrorInvalidValue;
+    const int g = grid < a.num_tiles ? grid : a.num_tiles;
+    hipLaunchKernelGGL(k_stab_tile<true>, dim3(g), dim3(kThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_stab_tile<false>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -103,3 +103,88 @@ def test_query_and_match_argument_errors(lib):
     assert lib.epm_get_query_stats(None, None) == 1
     assert lib.epm_point_line_terms(None, None, None, None, 0.0, None, None, 5, None, None,
                                     None) == 1
+
+
+LAYOUT_PROGRAM = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "epm.h"
+#define S(t) printf(#t " size %zu\n", sizeof(t))
+#define O(t, f) printf(#t " " #f " %zu\n", offsetof(t, f))
+int main(void) {
+  S(epm_pair); O(epm_pair, w2); O(epm_pair, q_begin); O(epm_pair, n);
+  S(epm_match_opts); O(epm_match_opts, check_capacity); O(epm_match_opts, col_capacity);
+  S(epm_sched); O(epm_sched, lpt);
+  S(epm_query_stats); S(epm_match_stats);
+  S(epm_batch_desc);
+  O(epm_batch_desc, eps_scalar); O(epm_batch_desc, row_offsets); O(epm_batch_desc, capacity);
+  O(epm_batch_desc, dtype); O(epm_batch_desc, dim); O(epm_batch_desc, desc1);
+  O(epm_batch_desc, ratio); O(epm_batch_desc, best_idx); O(epm_batch_desc, algo);
+  O(epm_batch_desc, sched);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout."""
+    import shutil
+    import subprocess
+
+    import paper_2603_18401_amd as E
+    if shutil.which("gcc") is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("gcc or the ROCm headers are missing")
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text(LAYOUT_PROGRAM)
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__=1", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    c = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                               check=True).stdout.splitlines():
+        *name, v = line.split()
+        c[" ".join(name)] = int(v)
+    mirrors = {"epm_pair": E._Pair, "epm_match_opts": E._MatchOpts, "epm_sched": E._Sched,
+               "epm_query_stats": E._QueryStats, "epm_match_stats": E._MatchStats,
+               "epm_batch_desc": E._BatchDesc}
+    for key, v in c.items():
+        parts = key.split()
+        cls = mirrors[parts[0]]
+        if parts[1] == "size":
+            assert ctypes.sizeof(cls) == v, key
+        else:
+            assert getattr(cls, parts[1]).offset == v, key
+
+
+def test_batch_and_sched_argument_errors(lib):
+    import paper_2603_18401_amd as E
+    V = ctypes.c_void_p
+    pairs = (E._Pair * 1)()
+    pairs[0].F[:] = [0, 0, 0, 0, 0, -1, 0, 1, 0]
+    pairs[0].w2, pairs[0].h2, pairs[0].m, pairs[0].n = 640, 480, 10, 10
+    h = V()
+    d = E._BatchDesc()
+    lib.epm_batch_create.argtypes = [V, ctypes.c_int32, V, V, ctypes.c_size_t,
+                                     ctypes.POINTER(V), V]
+    # no descriptor, no output pointer
+    assert lib.epm_batch_create(pairs, 1, None, V(256), 1 << 20, ctypes.byref(h), None) == 1
+    assert lib.epm_batch_create(pairs, 1, ctypes.byref(d), V(256), 1 << 20, None, None) == 1
+    # missing inputs and outputs are caught before anything is enqueued
+    d.kp1_xy, d.kp2_xy, d.eps_scalar = 256, 256, 2.0
+    assert lib.epm_batch_create(pairs, 1, ctypes.byref(d), V(256), 1 << 20, ctypes.byref(h),
+                                None) == 1
+    d.row_offsets, d.col_indices, d.capacity = 256, 256, 100
+    d.dtype, d.dim = 0, 64  # float descriptors need dim 128
+    assert lib.epm_batch_create(pairs, 1, ctypes.byref(d), V(256), 1 << 20, ctypes.byref(h),
+                                None) == 1
+    d.dim = 128
+    d.sched.lpt = 2
+    assert lib.epm_batch_create(pairs, 1, ctypes.byref(d), V(256), 1 << 20, ctypes.byref(h),
+                                None) == 1
+    assert h.value is None
+    assert lib.epm_batch_launch(None, None) == 1
+    nnz = ctypes.c_int64(0)
+    assert lib.epm_batch_nnz(None, ctypes.byref(nnz), None) == 1
+    assert lib.epm_batch_index(None) is None
+    lib.epm_batch_destroy(None)
+    s = E._Sched()
+    assert lib.epm_index_set_sched(None, ctypes.byref(s)) == 1
