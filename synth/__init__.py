@@ -24,4 +24,5 @@ from .pairs import (  # noqa: F401
     rot_axis_angle,
     skew,
 )
+from .mlp_init import mlp_init  # noqa: F401
 from .quant import bf16_to_f32, f32_to_bf16, f32_to_fp8_e4m3, fp8_e4m3_to_f32  # noqa: F401
