@@ -290,6 +290,71 @@ const epm_index* epm_batch_index(const epm_batch* batch);
 /* Releases the graph and the host objects (not the caller's buffers). */
 void epm_batch_destroy(epm_batch* batch);
 
+/*
+ * Learned per-keypoint tolerance.  The candidate test (Eq. 3-4) takes one
+ * tolerance per image-2 keypoint; Sec. 6 leaves predicting it from keypoint
+ * attributes as future work.  These calls implement that predictor: a
+ * 6 -> 64 -> 64 -> 1 ReLU network
+ *     eps_j = clamp(softplus(z_j), 0.5, 8) px
+ * over the features
+ *     f_j = (scale, response, orientation, (x - W/2)/(W/2), (y - H/2)/(W/2),
+ *            log1p(min(|p_j - e2| / diag, 1000)))
+ * (W, H, diag: image-2 size and diagonal; e2: image-2 epipole, at infinity
+ * giving the clipped value), trained on the device with a pinball (quantile)
+ * loss of the unclamped softplus(z) against point-line residuals of matches
+ * the method accepted, and Adam.  The output feeds eps2 of
+ * epm_build_intervals; a fixed scalar tolerance remains the fallback.
+ *
+ * Parameters: EPM_EPS_NPARAM float32 values, W1 [64][6], b1 [64], W2 [64][64],
+ * b2 [64], w3 [64], b3 (row-major, one row per output unit).
+ */
+#define EPM_EPS_NPARAM 4673
+
+/* Workspace of epm_eps_features (num_pairs > 0) and epm_eps_grad: bytes,
+ * 256-byte aligned base. */
+size_t epm_eps_workspace_bytes(int32_t num_pairs);
+
+/* features [N2][6] float32 for the image-2 keypoints of `pairs` (slices as in
+ * epm_build_intervals).  attrs [N2][3] float32: scale (px), detector
+ * response, orientation (rad).  Synchronises the host with `stream` once
+ * (upload of the per-pair epipoles).  Errors: EPM_ERR_ARG,
+ * EPM_ERR_DEGENERATE_F, EPM_ERR_WORKSPACE, EPM_ERR_HIP. */
+epm_status epm_eps_features(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
+                            const float* attrs, float* features, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* eps2[j] for n feature rows: BF16 weights (round to nearest even from
+ * `params`), FP32 activations and accumulation.  Asynchronous. */
+epm_status epm_eps_infer(const float* features, int64_t n, const float* params, float* eps2,
+                         hipStream_t stream);
+
+/* Gradient of the mean pinball loss (level q in (0, 1)) of softplus(z) over a
+ * minibatch: sample t uses slot s = sample_idx[t], target[s] and feature row
+ * feat_index[s] (or s when feat_index is NULL).  features [num_rows][6];
+ * target and feat_index [num_slots].  A sample whose slot or row lies
+ * outside those arrays contributes nothing (the mean still divides by
+ * batch).  grad [EPM_EPS_NPARAM] and loss [1] are device outputs.  FP32,
+ * deterministic: the same inputs give the same bits.  batch >= 1.
+ * Asynchronous. */
+epm_status epm_eps_grad(const float* features, int64_t num_rows, const int64_t* feat_index,
+                        const float* target, int64_t num_slots, const int32_t* sample_idx,
+                        int32_t batch, float q, const float* params, float* grad, float* loss,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One Adam step (step number >= 1) on params with moments m, v (device,
+ * EPM_EPS_NPARAM each; start from zeros).  Asynchronous. */
+epm_status epm_eps_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                        float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
+/* Residual targets: for each query with best_idx[i] in [0, n) of its pair
+ * (a match of the last epm_match on idx), the point-line distance of Eq. 3 in
+ * FP64 (the same evaluation as the candidate test), rounded to float32, and
+ * the global image-2 row of the match in feat_index[i] (may be NULL); -1 in
+ * both for other queries.  Asynchronous. */
+epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const float* kp2_xy,
+                               const int32_t* best_idx, float* residual, int64_t* feat_index,
+                               hipStream_t stream);
+
 /* Counters of the last epm_query_candidates call on an index. */
 typedef struct {
   int64_t queries;          /* image-1 queries                                       */

@@ -38,7 +38,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_index_destroy", "epm_status_string", "epm_version", "epm_point_line_terms",
            "epm_get_query_stats", "epm_get_match_stats", "epm_index_set_sched",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
-           "epm_batch_destroy"]
+           "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
+           "epm_eps_grad", "epm_eps_adam", "epm_match_residuals"]
 
 
 class EpmError(RuntimeError):
@@ -162,6 +163,19 @@ def load_library(path=None):
     lib.epm_batch_index.restype = V
     lib.epm_batch_destroy.argtypes = [V]
     lib.epm_batch_destroy.restype = None
+    f32 = ctypes.c_float
+    lib.epm_eps_workspace_bytes.argtypes = [i32]
+    lib.epm_eps_workspace_bytes.restype = ctypes.c_size_t
+    lib.epm_eps_features.argtypes = [P, i32, V, V, V, V, ctypes.c_size_t, V]
+    lib.epm_eps_features.restype = ctypes.c_int
+    lib.epm_eps_infer.argtypes = [V, i64, V, V, V]
+    lib.epm_eps_infer.restype = ctypes.c_int
+    lib.epm_eps_grad.argtypes = [V, i64, V, V, i64, V, i32, f32, V, V, V, V, ctypes.c_size_t, V]
+    lib.epm_eps_grad.restype = ctypes.c_int
+    lib.epm_eps_adam.argtypes = [V, V, V, V, i32, f32, f32, f32, f32, V]
+    lib.epm_eps_adam.restype = ctypes.c_int
+    lib.epm_match_residuals.argtypes = [V, V, V, V, V, V, V]
+    lib.epm_match_residuals.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib

@@ -796,6 +796,116 @@ const epm_index* epm_batch_index(const epm_batch* b) { return b ? b->idx : nullp
 
 void epm_batch_destroy(epm_batch* b) { delete b; }
 
+size_t epm_eps_workspace_bytes(int32_t num_pairs) {
+  if (num_pairs < 0) return 0;
+  return align_up(sizeof(EpsPair) * (size_t)num_pairs) +
+         align_up(sizeof(int64_t) * ((size_t)num_pairs + 1)) +
+         align_up(sizeof(float) * (size_t)kEpsGradMaxBlocks * (kEpsParams + 1));
+}
+
+epm_status epm_eps_features(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
+                            const float* attrs, float* features, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
+  if (n2 > 0 && (!kp2_xy || !attrs || !features)) return EPM_ERR_ARG;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) ||
+      workspace_bytes < epm_eps_workspace_bytes(num_pairs))
+    return EPM_ERR_WORKSPACE;
+  // head: per-pair constants, then the image-2 slice starts
+  const size_t off_k = align_up(sizeof(EpsPair) * (size_t)num_pairs);
+  std::vector<char> head(off_k + sizeof(int64_t) * ((size_t)num_pairs + 1), 0);
+  EpsPair* ep = reinterpret_cast<EpsPair*>(head.data());
+  int64_t* ks = reinterpret_cast<int64_t*>(head.data() + off_k);
+  for (int p = 0; p < num_pairs; ++p) {
+    PairDev pd;
+    const epm_status st = setup_pair(pairs[p], pd);
+    if (st != EPM_OK) return st;
+    // e is the epipole in normalised image-2 coordinates p^ = s (p - c)
+    const double ew = pd.e[2];
+    EpsPair& E = ep[p];
+    E.w = pairs[p].w2;
+    E.h = pairs[p].h2;
+    E.diag = std::hypot(E.w, E.h);
+    E.finite = 0;
+    if (ew != 0.0) {
+      E.ex = pd.e[0] / (pd.s * ew) + pd.cx;
+      E.ey = pd.e[1] / (pd.s * ew) + pd.cy;
+      E.finite = std::isfinite(E.ex) && std::isfinite(E.ey) ? 1 : 0;
+    }
+    ks[p] = pairs[p].k_begin;
+  }
+  ks[num_pairs] = n2;
+  if (n2 == 0) return EPM_OK;
+  char* ws = static_cast<char*>(workspace);
+  EPM_HIP(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, stream));
+  EPM_HIP(launch_eps_features(reinterpret_cast<const EpsPair*>(ws),
+                              reinterpret_cast<const int64_t*>(ws + off_k), num_pairs, n2, kp2_xy,
+                              attrs, features, stream));
+  // the host table must outlive the copy
+  EPM_HIP(hipStreamSynchronize(stream));
+  return EPM_OK;
+}
+
+epm_status epm_eps_infer(const float* features, int64_t n, const float* params, float* eps2,
+                         hipStream_t stream) {
+  if (n < 0) return EPM_ERR_ARG;
+  if (n == 0) return EPM_OK;
+  if (!features || !params || !eps2) return EPM_ERR_ARG;
+  EPM_HIP(launch_eps_infer(features, n, params, eps2, stream));
+  return EPM_OK;
+}
+
+epm_status epm_eps_grad(const float* features, int64_t num_rows, const int64_t* feat_index,
+                        const float* target, int64_t num_slots, const int32_t* sample_idx,
+                        int32_t batch, float q, const float* params, float* grad, float* loss,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!features || !target || !sample_idx || !params || !grad || batch < 1) return EPM_ERR_ARG;
+  if (num_rows < 1 || num_slots < 1) return EPM_ERR_ARG;
+  if (!(q > 0.0f && q < 1.0f)) return EPM_ERR_ARG;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) ||
+      workspace_bytes < epm_eps_workspace_bytes(0))
+    return EPM_ERR_WORKSPACE;
+  EpsGradArgs a;
+  a.features = features;
+  a.num_rows = num_rows;
+  a.feat_index = feat_index;
+  a.target = target;
+  a.num_slots = num_slots;
+  a.sample_idx = sample_idx;
+  a.batch = batch;
+  a.q = q;
+  a.inv_batch = 1.0f / (float)batch;
+  a.params = params;
+  a.partials = static_cast<float*>(workspace);
+  EPM_HIP(launch_eps_grad(a, grad, loss, stream));
+  return EPM_OK;
+}
+
+epm_status epm_eps_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                        float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+  if (!params || !m || !v || !grad || step < 1) return EPM_ERR_ARG;
+  if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps >= 0.0f))
+    return EPM_ERR_ARG;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  EPM_HIP(launch_eps_adam(params, m, v, grad, lr, beta1, beta2, eps, c1, c2, stream));
+  return EPM_OK;
+}
+
+epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const float* kp2_xy,
+                               const int32_t* best_idx, float* residual, int64_t* feat_index,
+                               hipStream_t stream) {
+  if (!idx) return EPM_ERR_ARG;
+  if (idx->N1 == 0) return EPM_OK;
+  if (!kp1_xy || !kp2_xy || !best_idx || !residual) return EPM_ERR_ARG;
+  EPM_HIP(launch_residuals(idx->at<PairDev>(idx->L.pairs), idx->at<int64_t>(idx->L.qstart),
+                           idx->P, idx->N1, kp1_xy, kp2_xy, best_idx, residual, feat_index,
+                           stream));
+  return EPM_OK;
+}
+
 epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,

@@ -148,6 +148,46 @@ hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
 // One workgroup per stabbing tile, window descriptor rows staged in LDS.
 hipError_t launch_match_window_f32(const MatchArgs& a, int grid, hipStream_t s);
 
+// ------------------------------------------------ learned tolerance network
+constexpr int kEpsParams = 4673;       // 6-64-64-1 network, see mlp.hip
+constexpr int kEpsGradMaxBlocks = 256;  // workgroups (and partial gradients) per batch
+
+struct EpsPair {  // per-pair constants of the keypoint features
+  double ex, ey;   // image-2 epipole in pixels (when finite)
+  double diag;     // image-2 diagonal
+  double w, h;     // image-2 size
+  int32_t finite;  // 0: epipole at infinity
+  int32_t pad;
+};
+
+struct EpsGradArgs {
+  const float* features;    // [num_rows][6]
+  int64_t num_rows;
+  const int64_t* feat_index;  // [num_slots] sample slot -> feature row, or NULL (identity)
+  const float* target;      // [num_slots] residuals
+  int64_t num_slots;
+  const int32_t* sample_idx;  // [batch] slots of this minibatch
+  int64_t batch;
+  float q;                  // quantile level of the pinball loss
+  float inv_batch;
+  const float* params;
+  float* partials;          // [kEpsGradMaxBlocks][kEpsParams + 1]
+};
+
+hipError_t launch_eps_features(const EpsPair* pairs, const int64_t* kstart, int num_pairs,
+                               int64_t n2, const float* kp2, const float* attrs, float* out,
+                               hipStream_t s);
+hipError_t launch_eps_infer(const float* feat, int64_t n, const float* params, float* eps,
+                            hipStream_t s);
+int eps_grad_blocks(int64_t batch);
+hipError_t launch_eps_grad(const EpsGradArgs& a, float* grad, float* loss, hipStream_t s);
+hipError_t launch_eps_adam(float* theta, float* m, float* v, const float* grad, float lr,
+                           float beta1, float beta2, float eps, float c1, float c2,
+                           hipStream_t s);
+hipError_t launch_residuals(const PairDev* pairs, const int64_t* qstart, int num_pairs,
+                            int64_t n1, const float* kp1, const float* kp2, const int32_t* best,
+                            float* residual, int64_t* feat_index, hipStream_t s);
+
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,
                                   const int64_t* kj, int64_t count, double* num, double* rhs,

@@ -188,3 +188,45 @@ def test_batch_and_sched_argument_errors(lib):
     lib.epm_batch_destroy(None)
     s = E._Sched()
     assert lib.epm_index_set_sched(None, ctypes.byref(s)) == 1
+
+
+def test_learned_eps_argument_errors(lib):
+    import paper_2603_18401_amd as E
+    V = ctypes.c_void_p
+    assert lib.epm_eps_workspace_bytes(-1) == 0
+    assert lib.epm_eps_workspace_bytes(0) >= 256 * 4674 * 4
+    assert lib.epm_eps_infer(V(256), -1, V(256), V(256), None) == 1
+    assert lib.epm_eps_infer(None, 10, V(256), V(256), None) == 1
+    assert lib.epm_eps_infer(None, 0, None, None, None) == 0  # nothing to do
+    ws = lib.epm_eps_workspace_bytes(0)
+    args = [V(256), 100, None, V(256), 100, V(256), 64, 0.99, V(256), V(256), V(256), V(256),
+            ws, None]
+    bad = list(args)
+    bad[6] = 0  # empty batch
+    assert lib.epm_eps_grad(*bad) == 1
+    bad = list(args)
+    bad[1] = 0  # no feature rows
+    assert lib.epm_eps_grad(*bad) == 1
+    for q in (0.0, 1.0, float("nan")):
+        bad = list(args)
+        bad[7] = q
+        assert lib.epm_eps_grad(*bad) == 1
+    bad = list(args)
+    bad[12] = ws - 1
+    assert lib.epm_eps_grad(*bad) == 4
+    bad = list(args)
+    bad[11] = V(258)  # misaligned workspace
+    assert lib.epm_eps_grad(*bad) == 4
+    assert lib.epm_eps_adam(V(256), V(256), V(256), V(256), 0, 1e-3, 0.9, 0.999, 1e-8,
+                            None) == 1
+    assert lib.epm_eps_adam(V(256), V(256), V(256), V(256), 1, 1e-3, 1.0, 0.999, 1e-8,
+                            None) == 1
+    pairs = (E._Pair * 1)()
+    pairs[0].F[:] = [0, 0, 0, 0, 0, -1, 0, 1, 0]
+    pairs[0].w2, pairs[0].h2, pairs[0].m, pairs[0].n = 640, 480, 10, 10
+    wsp = lib.epm_eps_workspace_bytes(1)
+    assert lib.epm_eps_features(pairs, 1, None, V(256), V(256), V(256), wsp, None) == 1
+    assert lib.epm_eps_features(pairs, 1, V(256), V(256), V(256), V(256), wsp - 1, None) == 4
+    pairs[0].F[:] = [0] * 9
+    assert lib.epm_eps_features(pairs, 1, V(256), V(256), V(256), V(256), wsp, None) == 2
+    assert lib.epm_match_residuals(None, V(256), V(256), V(256), V(256), None, None) == 1
