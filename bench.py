@@ -43,10 +43,16 @@ def parse():
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="scale", choices=["scale", "precision", "batch"],
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "precision", "batch", "learned"],
                     help="scale: six 20000-keypoint pairs (default); precision: one "
                          "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs")
     ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
+    ap.add_argument("--train-pairs", type=int, default=2000,
+                    help="learned workload: training pairs")
+    ap.add_argument("--test-pairs", type=int, default=200,
+                    help="learned workload: held-out pairs")
+    ap.add_argument("--epochs", type=int, default=10, help="learned workload: epochs")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: EPM_TUNE_CACHE or ~/.cache/epm)")
     ap.add_argument("--no-graph", action="store_true",
@@ -274,6 +280,147 @@ def batch_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def _recall_kbar_batch(pairs, offs, cols):
+    """Candidate recall of the true matches and candidates per query of a
+    batch CSR (columns local to each pair)."""
+    hit = tot = 0
+    q0 = 0
+    for p in pairs:
+        o = offs[q0:q0 + p.m + 1]
+        c = cols[o[0]:o[-1]]
+        rows = np.repeat(np.arange(p.m), np.diff(o))
+        keys = rows.astype(np.int64) * (p.n + 1) + c
+        t = np.nonzero(p.gt12 >= 0)[0]
+        want = t.astype(np.int64) * (p.n + 1) + p.gt12[t]
+        pos = np.searchsorted(keys, want)
+        ok = (pos < len(keys)) & (keys[np.minimum(pos, max(len(keys) - 1, 0))] == want)
+        hit += int(ok.sum())
+        tot += len(t)
+        q0 += p.m
+    return hit / max(tot, 1), float(offs[-1]) / max(q0, 1)
+
+
+def learned_workload(args):
+    """Learned per-keypoint tolerance at full scale: 6048x4032 pairs with
+    10000 keypoints per image, heteroscedastic noise (sigma = 0.15 * scale,
+    scale log-uniform in [1, 12] px), poses as the batching mix.  Training data
+    are the residuals of the method's own matches (eps 8 px, ratio 0.8) on
+    --train-pairs pairs; the network is trained on the GPU (pinball q = 0.99,
+    Adam lr 1e-3, batch 65536) and judged on --test-pairs held-out pairs
+    against a sweep of fixed tolerances.  The timed step is the hot path with
+    the learned tolerance: features, BF16 inference, build, query and FP32
+    match of the whole held-out batch."""
+    import multiprocessing as mp
+
+    import torch
+
+    import paper_2603_18401_amd as E
+    import synth
+    from paper_2603_18401_amd import learned_eps as L
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    attrs = lambda ps: np.concatenate([np.stack([p.scale2, p.resp2, p.ori2], 1)  # noqa: E731
+                                       for p in ps]).astype(np.float32)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    Xs, Ys = [], []
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for c0 in range(0, args.train_pairs, 64):
+            pairs = pool.map(synth.cfg4_pair, range(c0, min(args.train_pairs, c0 + 64)))
+            b = synth.batch_pairs(pairs)
+            specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in pairs]
+            k2 = g(b.kp2)
+            res, fidx = L.residual_targets(specs, g(b.kp1), k2, g(b.desc1), g(b.desc2))
+            feat = L.features(specs, k2, g(attrs(pairs))).cpu().numpy()
+            res, fidx = res.cpu().numpy(), fidx.cpu().numpy()
+            ok = fidx >= 0
+            Xs.append(feat[fidx[ok]])
+            Ys.append(res[ok])
+            del pairs, b
+            print(f"learned: {min(args.train_pairs, c0 + 64)} training pairs "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+        test = pool.map(synth.cfg4_pair, range(10000, 10000 + args.test_pairs))
+    X = g(np.concatenate(Xs))
+    Y = g(np.concatenate(Ys))
+    del Xs, Ys
+    nsamp = int(Y.numel())
+    tr = L.Trainer(synth.mlp_init(0), dev, q=0.99, lr=1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = tr.fit(X, Y, args.epochs, batch=65536, seed=1,
+                  log=lambda m: print("learned: " + m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+
+    # held-out batch: learned tolerance vs fixed tolerances
+    bt = synth.batch_pairs(test)
+    specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in test]
+    k1, k2, d1, d2, at = g(bt.kp1), g(bt.kp2), g(bt.desc1), g(bt.desc2), g(attrs(test))
+    N1 = int(k1.shape[0])
+
+    def candidates(eps2=None, eps=0.0):
+        idx = E.Index(specs, k2, eps2=eps2, eps=eps)
+        o, c = idx.query(k1)
+        idx.close()
+        return o.cpu().numpy(), c.cpu().numpy()
+
+    feat = L.features(specs, k2, at)
+    eps_l = L.infer(feat, tr.params)
+    rl, kl = _recall_kbar_batch(test, *candidates(eps2=eps_l))
+    sweep = []
+    for e in (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 5.0, 6.0, 8.0):
+        r, k = _recall_kbar_batch(test, *candidates(eps=e))
+        sweep.append({"eps": e, "recall": round(r, 5), "kbar": round(k, 3)})
+    ks = np.array([f["kbar"] for f in sweep])
+    rs = np.array([f["recall"] for f in sweep])
+    r_at = float(np.interp(kl, ks, rs))
+    fx = {f["eps"]: f for f in sweep}
+
+    # timed: the hot path with the learned tolerance
+    o0, _ = candidates(eps2=eps_l)
+    cap = int(o0[-1]) + 1024
+    offs = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(cap, dtype=torch.int32, device=dev)
+    out = (torch.empty(N1, dtype=torch.int32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev))
+    ws = {}
+
+    def step():
+        e2 = L.infer(L.features(specs, k2, at), tr.params)
+        idx = E.Index(specs, k2, eps2=e2, workspace=ws.get("w"))
+        ws["w"] = idx.workspace
+        idx.query(k1, row_offsets=offs, col_indices=cols, sync=False)
+        idx.match(offs, cols, d1, d2, dtype="f32", out=out)
+        idx.close()
+
+    sec = time_steps(torch, step, args.steps, args.warmup)
+    line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16+f32+f64", "data": "synthetic",
+            "config": {"workload": f"learned eps: {len(test)} held-out 6048x4032 pairs, 10000 "
+                                   "keypoints/image, heteroscedastic noise; step = features + "
+                                   "BF16 eps inference + build + query + FP32 match",
+                       "queries_per_step": N1, "kbar": round(kl, 3)},
+            "training": {"pairs": args.train_pairs, "residual_samples": nsamp,
+                         "epochs": args.epochs, "batch": 65536, "q": 0.99,
+                         "seconds": round(train_s, 3),
+                         "samples_per_s": round(nsamp * args.epochs / train_s, 1),
+                         "loss_first_epoch": round(hist[0], 6),
+                         "loss_last_epoch": round(hist[-1], 6)},
+            "held_out": {"pairs": len(test), "learned": {"recall": round(rl, 5),
+                                                         "kbar": round(kl, 3),
+                                                         "mean_eps": round(float(
+                                                             eps_l.mean().item()), 4)},
+                         "fixed": sweep, "fixed_recall_at_learned_kbar": round(r_at, 5),
+                         "reaches_eps4_recall_with_fewer_candidates": bool(
+                             rl >= fx[4.0]["recall"] and kl < fx[4.0]["kbar"]),
+                         "beats_eps2_recall_within_its_kbar": bool(
+                             rl > fx[2.0]["recall"] and kl <= fx[2.0]["kbar"])}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -285,6 +432,8 @@ def main():
         return precision_workload(args)
     if args.workload == "batch":
         return batch_workload(args)
+    if args.workload == "learned":
+        return learned_workload(args)
 
     import torch
 

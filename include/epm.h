@@ -201,6 +201,23 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
                                 hipStream_t stream);
 
 /*
+ * epm_query_candidates followed by epm_match with FP32 descriptors (EPM_F32,
+ * dim 128, tiled path), in one pass over the candidates (Algorithm 1 matching
+ * loop with the selection of Sec. 4.3): every query's hits are ranked while
+ * they are still on chip, so the CSR is not read back for them.  Outputs are
+ * identical to the two calls: the CSR (with the same capacity and nnz_host
+ * contract as epm_query_candidates) and best_idx / best_dist / second_dist
+ * (as epm_match, ratio 0 = off).  When nnz_host is NULL and the candidates
+ * exceed `capacity`, the match outputs are incomplete (row_offsets[N1] tells);
+ * with nnz_host, EPM_ERR_CAPACITY is returned as in epm_query_candidates.
+ */
+epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                           int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                           const float* desc1, const float* desc2, float ratio,
+                           int32_t* best_idx, float* best_dist, float* second_dist,
+                           hipStream_t stream);
+
+/*
  * Work distribution of the angle-tile kernels (the stabbing pass of
  * epm_query_candidates and the tiled paths of epm_match).  All zero (the
  * default of a new index) launches one workgroup per tile of 64 angle-sorted
@@ -229,14 +246,16 @@ epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);
  * stabbing with the FP64 test, CSR compaction and descriptor matching
  * (Algorithm 1, preprocessing and matching loop) -- for the buffers named in
  * `desc` into one HIP graph: kernels only, no host synchronisation, no
- * memset or memcpy nodes.  epm_batch_launch replays it on a stream; every
+ * memset or memcpy nodes.  FP32 descriptors on the tiled path use the fused
+ * pass of epm_query_match.  epm_batch_launch replays it on a stream; every
  * replay recomputes every output from the current contents of the input
  * buffers, so new keypoints and descriptors of the same sizes can be written
  * between replays (the pairs' F and slices are fixed at creation).
  *
  * The CSR capacity cannot be checked on the host inside a graph: rows are
- * written up to `capacity` and, when the total exceeds it, the match writes
- * nothing; epm_batch_nnz reports it.  The buffers in `desc` and the
+ * written up to `capacity` and nothing is read past it; when the total
+ * exceeds it, the match outputs of that replay are incomplete and
+ * epm_batch_nnz reports EPM_ERR_CAPACITY.  The buffers in `desc` and the
  * workspace must stay alive, and must not be used by other work, while the
  * batch exists.  Replays of one batch on different streams race.
  */
@@ -280,7 +299,7 @@ epm_status epm_batch_launch(epm_batch* batch, hipStream_t stream);
 
 /* Waits for `stream` and reads the total number of candidates of the last
  * replay into *nnz; returns EPM_ERR_CAPACITY when it exceeded the capacity
- * (the match outputs of that replay were not written). */
+ * (the match outputs of that replay are then not valid). */
 epm_status epm_batch_nnz(epm_batch* batch, int64_t* nnz, hipStream_t stream);
 
 /* The batch's index, for epm_get_query_stats / epm_get_match_stats after a

@@ -39,7 +39,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_get_query_stats", "epm_get_match_stats", "epm_index_set_sched",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
-           "epm_eps_grad", "epm_eps_adam", "epm_match_residuals"]
+           "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match"]
 
 
 class EpmError(RuntimeError):
@@ -176,6 +176,8 @@ def load_library(path=None):
     lib.epm_eps_adam.restype = ctypes.c_int
     lib.epm_match_residuals.argtypes = [V, V, V, V, V, V, V]
     lib.epm_match_residuals.restype = ctypes.c_int
+    lib.epm_query_match.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, f32, V, V, V, V]
+    lib.epm_query_match.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -294,6 +296,44 @@ class Index:
                                                ctypes.byref(nnz), st_ptr)
         _check(st, "epm_query_candidates")
         return row_offsets, col_indices[: nnz.value]
+
+    def query_match(self, kp1, desc1, desc2, ratio=0.0, capacity=None, row_offsets=None,
+                    col_indices=None, out=None, sync=True):
+        """epm_query_match: the candidate CSR and the FP32 matches in one pass.
+        Returns (row_offsets, col_indices, best_idx, best_dist, second_dist);
+        capacity / sync as in query()."""
+        torch = self._torch
+        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
+            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
+        dev = self.device
+        if row_offsets is None:
+            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
+        if col_indices is None:
+            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
+            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if out is None:
+            out = (torch.empty(self.n1, dtype=torch.int32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev))
+        best, bd, sd = out
+        st_ptr = _stream(torch, dev, self.stream)
+
+        def call(cols, nnz_ref):
+            return self.lib.epm_query_match(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                            _dptr(cols), cols.numel(), nnz_ref, _dptr(desc1),
+                                            _dptr(desc2), float(ratio), _dptr(best), _dptr(bd),
+                                            _dptr(sd), st_ptr)
+
+        if not sync:
+            _check(call(col_indices, None), "epm_query_match")
+            return row_offsets, col_indices, best, bd, sd
+        nnz = ctypes.c_int64(0)
+        st = call(col_indices, ctypes.byref(nnz))
+        if st == 3:
+            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+            st = call(col_indices, ctypes.byref(nnz))
+        _check(st, "epm_query_match")
+        return row_offsets, col_indices[: nnz.value], best, bd, sd
 
     def stats(self):
         """Counters of the last query (dict; waits for its stream)."""

@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows, match_stats, sched, tile_cost, order;
+  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest;
   size_t total;
 };
 
@@ -77,6 +77,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.sched = take(sizeof(uint32_t) * kSchedWords);
   L.tile_cost = take(sizeof(uint32_t) * ts);
   L.order = take(sizeof(uint32_t) * ts);
+  L.rest = take(sizeof(uint32_t) * N1);
   L.total = off;
   return L;
 }
@@ -398,13 +399,20 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.tile_cost = nullptr;
   A.order = nullptr;
   A.queue = nullptr;
+  A.desc1 = nullptr;
+  A.desc2 = nullptr;
+  A.ratio = 0.0f;
+  A.best_idx = nullptr;
+  A.best_dist = nullptr;
+  A.second_dist = nullptr;
+  A.rest = idx->at<uint32_t>(L.rest);
   return A;
 }
 
 // Query keys and their sort, the tile windows, the stabbing pass and the
 // scan of the row lengths into row_offsets (Algorithm 1, matching loop).
 epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
-                         hipStream_t stream) {
+                         hipStream_t stream, bool fuse = false) {
   const Layout& L = idx->L;
   const int64_t n1 = idx->N1;
   idx->have_order = false;
@@ -441,7 +449,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
     A.queue = sched + kSchedStabQueue;
     A.order = lpt ? idx->at<uint32_t>(L.order) : nullptr;
   }
-  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, stream));
+  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, fuse, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
 }
@@ -493,15 +501,13 @@ epm_status validate_match(const epm_index* idx, const MatchCall& c) {
   return EPM_OK;
 }
 
-epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream) {
-  const int64_t n1 = idx->N1;
-  if (n1 == 0) return EPM_OK;
+MatchArgs match_args(epm_index* idx, const MatchCall& c) {
   const Layout& L = idx->L;
   MatchArgs A;
   A.qstart = idx->at<int64_t>(L.qstart);
   A.kstart = idx->at<int64_t>(L.kstart);
   A.num_pairs = idx->P;
-  A.n1 = n1;
+  A.n1 = idx->N1;
   A.qperm = idx->have_qperm ? idx->qperm : nullptr;
   A.row_offsets = c.row_offsets;
   A.cols = c.col_indices;
@@ -525,6 +531,14 @@ epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream)
   A.capacity = c.capacity;
   A.order = nullptr;
   A.queue = nullptr;
+  return A;
+}
+
+epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream) {
+  const int64_t n1 = idx->N1;
+  if (n1 == 0) return EPM_OK;
+  const Layout& L = idx->L;
+  MatchArgs A = match_args(idx, c);
   // the window kernels walk the angle tiles and windows of the last query
   const bool tiled = c.algo != EPM_ALGO_PLAIN && idx->have_qperm;
   const int grid = idx->sched.match_workgroups;
@@ -567,6 +581,38 @@ epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream)
     default:
       return EPM_ERR_UNSUPPORTED;
   }
+}
+
+// Stabbing with fused FP32 selection, then the CSR fill and the listed-query
+// match of the rows the fused pass left.  nnz_host as in
+// epm_query_candidates.
+epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets,
+                               int64_t* nnz_host, const MatchCall& c, hipStream_t stream) {
+  const int64_t n1 = idx->N1;
+  A.desc1 = static_cast<const float*>(c.desc1);
+  A.desc2 = static_cast<const float*>(c.desc2);
+  A.ratio = c.ratio;
+  A.best_idx = c.best_idx;
+  A.best_dist = c.best_dist;
+  A.second_dist = c.second_dist;
+  const epm_status st = enqueue_count(idx, A, row_offsets, stream, true);
+  if (st != EPM_OK) return st;
+  if (n1 == 0) return EPM_OK;
+  idx->last_stream = stream;
+  idx->last_offsets = row_offsets;
+  idx->have_stats = true;
+  if (nnz_host) {
+    int64_t nnz = 0;
+    EPM_HIP(hipMemcpyAsync(&nnz, row_offsets + n1, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    EPM_HIP(hipStreamSynchronize(stream));
+    *nnz_host = nnz;
+    if (nnz > A.capacity) return EPM_ERR_CAPACITY;
+  }
+  const epm_status fs = enqueue_fill(idx, A, stream);
+  if (fs != EPM_OK) return fs;
+  MatchArgs M = match_args(idx, c);
+  EPM_HIP(launch_match_listed_f32(M, A.rest, A.stats + kStatRest, n1, stream));
+  return EPM_OK;
 }
 
 }  // namespace
@@ -692,6 +738,35 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
   return enqueue_match(const_cast<epm_index*>(idx), c, stream);
 }
 
+epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                           int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                           const float* desc1, const float* desc2, float ratio,
+                           int32_t* best_idx, float* best_dist, float* second_dist,
+                           hipStream_t stream) {
+  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
+  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  MatchCall c;
+  c.row_offsets = row_offsets;
+  c.col_indices = col_indices;
+  c.dtype = EPM_F32;
+  c.dim = 128;
+  c.desc1 = desc1;
+  c.desc2 = desc2;
+  c.scale1 = c.scale2 = c.desc1_f32 = c.desc2_f32 = nullptr;
+  c.ratio = ratio;
+  c.best_idx = best_idx;
+  c.best_dist = best_dist;
+  c.second_dist = second_dist;
+  c.algo = EPM_ALGO_TILED;
+  // without a host check the leftover rows must not read past the buffer
+  c.capacity = nnz_host ? -1 : capacity;
+  const epm_status v = validate_match(idx, c);
+  if (v != EPM_OK) return v;
+  StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
+  return enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
+}
+
 epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_batch_desc* d,
                             void* workspace, size_t workspace_bytes, epm_batch** out,
                             hipStream_t stream) {
@@ -750,9 +825,15 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
     epm_status r = enqueue_build(idx, d->kp2_xy, d->eps2, d->eps_scalar, cs);
     // after the build: the stab arguments name the sorted key buffer it chose
     StabArgs A = stab_args(idx, d->kp1_xy, d->row_offsets, d->col_indices, d->capacity);
-    if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs);
-    if (r == EPM_OK) r = enqueue_fill(idx, A, cs);
-    if (r == EPM_OK) r = enqueue_match(idx, c, cs);
+    // FP32 on the tiled path: selection fused into the stabbing pass
+    const bool fused = c.dtype == EPM_F32 && c.algo != EPM_ALGO_PLAIN;
+    if (fused) {
+      if (r == EPM_OK) r = enqueue_query_match(idx, A, d->row_offsets, nullptr, c, cs);
+    } else {
+      if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs);
+      if (r == EPM_OK) r = enqueue_fill(idx, A, cs);
+      if (r == EPM_OK) r = enqueue_match(idx, c, cs);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
     b->graph = g;
@@ -923,7 +1004,7 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->queries = idx->N1;
   if (!idx->have_stats) return EPM_OK;
-  unsigned long long c[kNumStats] = {0, 0, 0, 0, 0};
+  unsigned long long c[kNumStats] = {};
   int64_t nnz = 0;
   EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.stats), sizeof(c),
                          hipMemcpyDeviceToHost, idx->last_stream));
@@ -943,7 +1024,7 @@ epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->queries = idx->N1;
   if (!idx->have_match_stats) return EPM_OK;
-  unsigned long long c[kNumStats] = {0, 0, 0, 0, 0};
+  unsigned long long c[kNumStats] = {};
   EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.match_stats),
                          sizeof(unsigned long long) * kNumMatchStats, hipMemcpyDeviceToHost,
                          idx->match_stream));

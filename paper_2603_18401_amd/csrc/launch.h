@@ -72,6 +72,14 @@ struct StabArgs {
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
   uint32_t* queue;            // persistent launch: next-tile counter, zero at launch
+  // fused matching (FP32 descriptors), see launch_stab_tiles
+  const float* desc1;
+  const float* desc2;
+  float ratio;
+  int32_t* best_idx;
+  float* best_dist;
+  float* second_dist;
+  uint32_t* rest;             // [n1] queries left to the listed-query match
 };
 
 // Scheduling counters (u32 words of one workspace block).
@@ -90,15 +98,18 @@ hipError_t launch_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
 
 constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
-              kStatLongRows = 4;
-constexpr int kNumStats = 5;
+              kStatLongRows = 4, kStatRest = 5;
+constexpr int kNumStats = 6;
 hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
 
 hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
 hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s);
 // Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
 // workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.
-hipError_t launch_stab_tiles(const StabArgs& a, int grid, hipStream_t s);
+// fuse: also selects the FP32 matches of the rows it can (desc1/desc2 and the
+// outputs in a); the other queries are appended to a.rest, counted in
+// stats[kStatRest], for launch_match_listed_f32 once the CSR is complete.
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t s);
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the rest.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
 
@@ -144,6 +155,11 @@ constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallbac
 hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, int grid, hipStream_t s);
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s);
+// FP32 matches of the queries list[0 .. *count) (count on the device, at most
+// max_count).
+hipError_t launch_match_listed_f32(const MatchArgs& a, const uint32_t* list,
+                                   const unsigned long long* count, int64_t max_count,
+                                   hipStream_t s);
 hipError_t launch_match_plain_bin256(const MatchArgs& a, hipStream_t s);
 // One workgroup per stabbing tile, window descriptor rows staged in LDS.
 hipError_t launch_match_window_f32(const MatchArgs& a, int grid, hipStream_t s);

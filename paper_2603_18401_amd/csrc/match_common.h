@@ -82,22 +82,29 @@ __device__ __forceinline__ bool csr_overflow(const MatchArgs& A) {
   return A.capacity >= 0 && A.row_offsets[A.n1] > A.capacity;
 }
 
-__device__ __forceinline__ void write_match(const MatchArgs& A, int64_t i, const Top2& t,
-                                            bool binary) {
+__device__ __forceinline__ void write_match_to(float ratio, int32_t* __restrict__ best_idx,
+                                               float* __restrict__ best_dist,
+                                               float* __restrict__ second_dist, int64_t i,
+                                               const Top2& t, bool binary) {
   int32_t idx = t.bj == INT32_MAX ? -1 : t.bj;
-  if (idx >= 0 && A.ratio > 0.0f) {
+  if (idx >= 0 && ratio > 0.0f) {
     bool accept;
     if (binary) {
-      accept = t.bd < A.ratio * t.sd;
+      accept = t.bd < ratio * t.sd;
     } else {
-      const float thr = A.ratio * A.ratio;
+      const float thr = ratio * ratio;
       accept = t.bd < thr * t.sd;
     }
     if (!accept) idx = -1;
   }
-  A.best_idx[i] = idx;
-  A.best_dist[i] = t.bd;
-  A.second_dist[i] = t.sd;
+  best_idx[i] = idx;
+  best_dist[i] = t.bd;
+  second_dist[i] = t.sd;
+}
+
+__device__ __forceinline__ void write_match(const MatchArgs& A, int64_t i, const Top2& t,
+                                            bool binary) {
+  write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, i, t, binary);
 }
 
 }  // namespace epm

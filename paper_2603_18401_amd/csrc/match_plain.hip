@@ -76,7 +76,54 @@ __global__ __launch_bounds__(kThreads) void k_match_plain_bin256(MatchArgs A) {
   if (lane == 0) write_match(A, i, t, true);
 }
 
+// Listed queries (the ones the fused stab + match pass left over): one
+// wavefront per listed query, grid-stride over a list whose length only the
+// device knows.
+__global__ __launch_bounds__(kThreads) void k_match_listed_f32(MatchArgs A,
+                                                               const uint32_t* __restrict__ list,
+                                                               const unsigned long long* __restrict__ count) {
+  __shared__ float4 qdesc[kWaves][32];
+  if (csr_overflow(A)) return;
+  const int lane = lane_id(), wave = wave_id();
+  const uint64_t n = *count;
+  for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wave; t < n;
+       t += (uint64_t)gridDim.x * kWaves) {
+    const int64_t i = (int64_t)list[t];
+    const int pair = find_pair(A.qstart, A.num_pairs, i);
+    const int64_t kb = A.kstart[pair];
+    if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1)[i * 32 + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t o0 = A.row_offsets[i], o1 = A.row_offsets[i + 1];
+    Top2 tp;
+    for (int64_t e = o0 + lane; e < o1; e += kWave) {
+      const int32_t j = A.cols[e];
+      const float4* d2 = reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32;
+      float acc = 0.0f;
+      #pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qdesc[wave][k], d2[k]);
+      tp.insert(acc, j);
+    }
+    tp = wave_merge_top2(tp);
+    if (lane == 0) write_match(A, i, tp, false);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_match_listed_f32(const MatchArgs& a, const uint32_t* list,
+                                   const unsigned long long* count, int64_t max_count,
+                                   hipStream_t s) {
+  if (max_count <= 0) return hipSuccess;
+  int64_t blocks = (max_count + kWaves - 1) / kWaves;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_match_listed_f32, dim3((unsigned)blocks), dim3(kThreads), 0, s, a, list,
+                     count);
+  return hipGetLastError();
+}
 
 hipError_t launch_match_plain_f32(const MatchArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;

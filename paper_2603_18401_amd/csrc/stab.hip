@@ -12,6 +12,7 @@
 // scan, gathers the hits in LDS, sorts them by j and writes the CSR row.
 #include "device_common.h"
 #include "launch.h"
+#include "match_common.h"
 
 namespace epm {
 
@@ -322,13 +323,71 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // threads on different queries of the same record (the record is an LDS
 // broadcast), angle test, FP64 test, and an LDS atomic slot in the query's
 // hit list.  No wavefront-wide dependency chains.
-template <bool PERSIST>
+//
+// FUSE: the same pass also selects every query's match (Sec. 4.3) from its
+// hit list while the list is still in LDS: the hits keep their window
+// positions, the window's descriptor rows are staged kFuseRows at a time
+// (over the record chunk buffers, dead by then), and four lanes per query
+// evaluate canonical FP32 distances of that query's hits in the chunk and
+// keep a top-2, merged across the four lanes at the end.  Queries this
+// cannot serve (brute-force rows, rows longer than kStage, windows longer
+// than 16-bit positions) are listed for the listed-query match after the
+// CSR is complete; empty rows get their (-1, inf, inf) here.
+constexpr int kFuseRows = 32;
+constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
+constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
+constexpr int kFuseBytes = kFuseRows * kFuseStride * 4;
+constexpr int64_t kFuseMaxWindow = 65535;
+
+// This thread's share of window chunk [c0, c0 + kFuseRows): row f >> 5,
+// 16-byte column f & 31, for f = tid + kThreads u (rows past the window end
+// repeat its last row).
+constexpr int kFusePer = kFuseRows * 32 / kThreads;
+struct FuseRows {
+  float4 v[kFusePer];
+};
+
+__device__ __forceinline__ FuseRows fuse_fetch(const StabArgs& A, int64_t c0, int64_t total_len,
+                                               int64_t kb, bool local_j, const int32_t* sJ,
+                                               const uint32_t* slot_b,
+                                               const uint32_t* slot_pref, int tid) {
+  const int64_t nr = total_len - c0 < kFuseRows ? total_len - c0 : kFuseRows;
+  FuseRows out;
+  #pragma unroll
+  for (int u = 0; u < kFusePer; ++u) {
+    const int f = tid + u * kThreads;
+    const int64_t r = (f >> 5) < nr ? (f >> 5) : nr - 1;
+    const int64_t virt = c0 + r;
+    int32_t j;
+    if (local_j) {
+      j = sJ[virt];
+    } else {
+      int sl = 0;  // last slot with slot_pref[sl] <= virt
+      #pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (sl + step <= kSlots && slot_pref[sl + step] <= virt) sl += step;
+      j = A.rj[slot_b[sl] + (virt - slot_pref[sl])];
+    }
+    out.v[u] = reinterpret_cast<const float4*>(A.desc2)[(kb + j) * 32 + (f & 31)];
+  }
+  return out;
+}
+
+template <bool PERSIST, bool FUSE>
 __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
-  __shared__ uint32_t sC[kChunk], sH[kChunk];
-  __shared__ float2 sXY[kChunk];
-  __shared__ float sE[kChunk];
-  __shared__ int32_t sJ[kChunk];
+  // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps it for the match
+  // phase), reused for descriptor rows in the match phase
+  constexpr int kRecRaw = FUSE ? kRecBytes - kChunk * 4 : kRecBytes;
+  constexpr int kRaw = FUSE && kFuseBytes > kRecRaw ? kFuseBytes : kRecRaw;
+  __shared__ __attribute__((aligned(16))) unsigned char raw[kRaw];
+  __shared__ int32_t sJ_keep[FUSE ? kChunk : 1];
+  uint32_t* sC = reinterpret_cast<uint32_t*>(raw);
+  uint32_t* sH = sC + kChunk;
+  float2* sXY = reinterpret_cast<float2*>(sH + kChunk);
+  float* sE = reinterpret_cast<float*>(sXY + kChunk);
+  int32_t* sJ = FUSE ? sJ_keep : reinterpret_cast<int32_t*>(sE + kChunk);
   __shared__ int32_t hits[kTileQ][kStage + 1];  // +1: rows start in different banks
+  __shared__ uint16_t hits_v[FUSE ? kTileQ : 1][FUSE ? kStage + 2 : 1];  // window positions
   __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ];
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
@@ -411,7 +470,10 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         const float2 xy = sXY[r];
         if (!within_tolerance(qa[q], qb[q], qc[q], xy.x, xy.y, sE[r])) continue;
         const uint32_t slot = atomicAdd(&cnt[q], 1u);
-        if (slot < (uint32_t)kStage) hits[q][slot] = sJ[r];
+        if (slot < (uint32_t)kStage) {
+          hits[q][slot] = sJ[r];
+          if (FUSE) hits_v[q][slot] = (uint16_t)(base + r);
+        }
       }
       __syncthreads();
     }
@@ -465,7 +527,75 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
       if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
     }
-    if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
+
+    if (FUSE) {
+      const bool fusable = total_len <= kFuseMaxWindow;
+      if (tid < T.count) {
+        const uint32_t mode = qmode[tid];
+        if (mode == kQueryEmpty) {
+          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[tid], Top2(),
+                         false);
+        } else if (mode != kQueryNormal || cnt[tid] > (uint32_t)kStage || !fusable) {
+          const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
+          A.rest[at] = (uint32_t)qidx[tid];
+        }
+      }
+      const int q = tid >> 2, part = tid & 3;
+      const bool mine = q < T.count && qmode[q] == kQueryNormal && cnt[q] <= (uint32_t)kStage &&
+                        fusable;
+      const int nq = mine ? (int)cnt[q] : 0;
+      const int64_t kb = pd.k_begin;
+      float4* rows4 = reinterpret_cast<float4*>(raw);
+      // a window of one record chunk still has every row's j in LDS
+      const bool local_j = total_len <= kChunk;
+      FuseRows pre;
+      // the query's row stays in registers for all its hits
+      float4 qreg[32];
+      {
+        const float4* qrow = reinterpret_cast<const float4*>(A.desc1) + qidx[q] * 32;
+        #pragma unroll
+        for (int k = 0; k < 32; ++k) qreg[k] = mine ? qrow[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      Top2 best;
+      if (fusable && total_len > 0) {
+        pre = fuse_fetch(A, 0, total_len, kb, local_j, sJ, slot_b, slot_pref, tid);
+        for (int64_t c0 = 0; c0 < total_len; c0 += kFuseRows) {
+          const int nr = (int)(total_len - c0 < kFuseRows ? total_len - c0 : kFuseRows);
+          __syncthreads();  // the previous rows (or the record chunk) are no longer read
+          #pragma unroll
+          for (int u = 0; u < kFusePer; ++u) {
+            const int f = tid + u * kThreads;
+            if ((f >> 5) < nr) rows4[(f >> 5) * (kFuseStride / 4) + (f & 31)] = pre.v[u];
+          }
+          __syncthreads();
+          if (c0 + kFuseRows < total_len)  // in flight during the distances below
+            pre = fuse_fetch(A, c0 + kFuseRows, total_len, kb, local_j, sJ, slot_b, slot_pref,
+                             tid);
+          for (int sl = part; sl < nq; sl += 4) {
+            const int64_t v = hits_v[q][sl];
+            if (v < c0 || v >= c0 + nr) continue;
+            const float4* wr = rows4 + (v - c0) * (kFuseStride / 4);
+            float acc = 0.0f;
+            #pragma unroll
+            for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qreg[k], wr[k]);
+            best.insert(acc, hits[q][sl]);
+          }
+        }
+      }
+      // the four parts of a query are adjacent lanes and hold distinct hits
+      #pragma unroll
+      for (int off = 1; off < 4; off <<= 1) {
+        Top2 o;
+        o.bd = __shfl_xor(best.bd, off);
+        o.bj = __shfl_xor(best.bj, off);
+        o.sd = __shfl_xor(best.sd, off);
+        o.sj = __shfl_xor(best.sj, off);
+        best = merge_top2(best, o);
+      }
+      if (mine && part == 0)
+        write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], best, false);
+    }
+    if (PERSIST || FUSE) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
 }
 
@@ -620,14 +750,22 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stab_tiles(const StabArgs& a, int grid, hipStream_t s) {
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
-  if (grid > 0) {
-    if (!a.queue) return hipErrorInvalidValue;
-    const int g = grid < a.num_tiles ? grid : a.num_tiles;
-    hipLaunchKernelGGL(k_stab_tile<true>, dim3(g), dim3(kThreads), 0, s, a);
+  if (grid > 0 && !a.queue) return hipErrorInvalidValue;
+  if (fuse && (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest))
+    return hipErrorInvalidValue;
+  const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
+  if (fuse) {
+    if (grid > 0)
+      hipLaunchKernelGGL((k_stab_tile<true, true>), g, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stab_tile<false, true>), g, dim3(kThreads), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_stab_tile<false>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+    if (grid > 0)
+      hipLaunchKernelGGL((k_stab_tile<true, false>), g, dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stab_tile<false, false>), g, dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
 }
