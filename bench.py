@@ -10,9 +10,13 @@ synthetic (seeded), resident in HBM before the timed region.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Prints one JSON line.  `value` is keypoint queries/s of the batched path;
-`plain_gpu` is the same work through the plain path (one pipeline per pair,
-host-synchronised CSR sizing, gather-based matching).
+Prints one JSON line.  `value` is keypoint queries/s of one step through
+epm_build_intervals + epm_query_match (the six pairs as one batch, selection
+fused into the stabbing pass); `separate_calls` is the same step through
+epm_query_candidates + epm_match, `graph` the step recorded as one HIP graph
+(autotuned tile schedule), and `plain_gpu` the plain path (one pipeline per
+pair, host-synchronised CSR sizing, gather-based matching).  Other workloads:
+--workload precision | batch | learned.
 """
 
 import argparse
@@ -38,9 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4000,
-                    help="queries per pair in the oracle sample")
-    ap.add_argument("--algo", default="auto")
+    ap.add_argument("--cpu-sample", type=int, default=20000,
+                    help="queries per pair in the oracle sample (default: all of them)")
+    ap.add_argument("--algo", default="fused", choices=["fused", "tiled", "auto", "plain"],
+                    help="fused: epm_query_match; otherwise query + match with this algo")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="scale",
@@ -55,14 +60,25 @@ def parse():
     ap.add_argument("--epochs", type=int, default=10, help="learned workload: epochs")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: EPM_TUNE_CACHE or ~/.cache/epm)")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="scale workload: skip the separate-calls figure")
     ap.add_argument("--no-graph", action="store_true",
                     help="scale workload: skip the recorded-graph figure")
     return ap.parse_args()
 
 
-KERNEL = "k_match_window_f32"
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_18401_amd", "csrc", "match_window.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_window_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2603_18401_amd", "csrc")
+# dominant kernel of the timed step per --algo: (name, source, committed traffic summary)
+KERNELS = {
+    "fused": ("k_stab_tile<false, true> (stabbing + FP32 selection)",
+              os.path.join(CSRC, "stab.hip"),
+              os.path.join(ROOT, "profiles", "stab_match_fused_traffic.md")),
+    "tiled": ("k_match_window_f32", os.path.join(CSRC, "match_window.hip"),
+              os.path.join(ROOT, "profiles", "match_window_traffic.md")),
+    "auto": ("k_match_window_f32", os.path.join(CSRC, "match_window.hip"),
+             os.path.join(ROOT, "profiles", "match_window_traffic.md")),
+    "plain": ("k_match_plain_f32", os.path.join(CSRC, "match_plain.hip"), None),
+}
 
 
 def source_hash(path):
@@ -71,16 +87,19 @@ def source_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(src, summary):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when there is none or the kernel source changed since
+    it was taken."""
+    if summary is None:
+        return None
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(summary).read()
     except OSError:
         return None
     vals = dict(line.split(":", 1) for line in text.splitlines()
                 if line.startswith(("source_sha256:", "traffic_bytes_per_launch:")))
-    if vals.get("source_sha256", "").strip() != source_hash(KERNEL_SRC):
+    if vals.get("source_sha256", "").strip() != source_hash(src):
         return None
     try:
         return int(vals["traffic_bytes_per_launch"].strip())
@@ -455,33 +474,40 @@ def main():
     specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in pairs]
     stream = torch.cuda.current_stream(dev)
 
-    # ---- batched path: one build/query/match over the six pairs
+    # ---- the timed step: build + query + match of the six pairs in one batch
     idx0 = E.Index(specs, g["kp2"], eps2=g["eps2"])
     ws = idx0.workspace
     offs, cols = idx0.query(g["kp1"])
     nnz = int(offs[-1].item())
-    cap = nnz
-    row_offsets = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
-    col_indices = torch.empty(cap, dtype=torch.int32, device=dev)
-    best = torch.empty(N1, dtype=torch.int32, device=dev)
-    bd = torch.empty(N1, dtype=torch.float32, device=dev)
-    sd = torch.empty(N1, dtype=torch.float32, device=dev)
     idx0.close()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    row_offsets = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    col_indices = torch.empty(nnz, dtype=torch.int32, device=dev)
+    outs = tuple(torch.empty(N1, dtype=t, device=dev)
+                 for t in (torch.int32, torch.float32, torch.float32))
+    fused = args.algo == "fused"
 
-    def step(ev=None):
-        idx = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
-        if ev:
-            ev[0].record(stream)
-        idx.query(g["kp1"], row_offsets=row_offsets, col_indices=col_indices, sync=False)
-        if ev:
-            ev[1].record(stream)
-        idx.match(row_offsets, col_indices, g["d1"], g["d2"], dtype="f32", algo=args.algo,
-                  out=(best, bd, sd))
-        if ev:
-            ev[2].record(stream)
-        idx.close()
+    def make_step(algo):
+        def step(ev=None):
+            idx = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
+            if ev is not None:
+                idx.set_timing_events(*ev)
+            if algo == "fused":
+                idx.query_match(g["kp1"], g["d1"], g["d2"], row_offsets=row_offsets,
+                                col_indices=col_indices, out=outs, sync=False)
+            else:
+                if ev is not None:  # time the match kernel, not the query's stabbing
+                    idx.set_timing_events(None, None)
+                idx.query(g["kp1"], row_offsets=row_offsets, col_indices=col_indices,
+                          sync=False)
+                if ev is not None:
+                    idx.set_timing_events(*ev)
+                idx.match(row_offsets, col_indices, g["d1"], g["d2"], dtype="f32", algo=algo,
+                          out=outs)
+            idx.close()
+        return step
 
+    step = make_step(args.algo)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -492,9 +518,17 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     qps = N1 * args.steps / elapsed
-    query_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    match_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    kernel_ms = [e[0].elapsed_time(e[1]) for e in evs]
     assert int(row_offsets[-1].item()) == nnz
+    ref_out = [x.clone() for x in outs]
+
+    # ---- the same work through the separate query and match calls
+    separate = None
+    if fused and not args.no_separate:
+        ssec = time_steps(torch, make_step("tiled"), args.steps, args.warmup)
+        same = all(torch.equal(a, r) for a, r in zip(outs, ref_out))
+        separate = {"value": round(N1 / ssec, 1), "unit": "queries/s",
+                    "ms_per_step": round(ssec * 1e3, 4), "identical_matches": bool(same)}
 
     # ---- plain path: one pipeline per pair, sized through the host
     plain = None
@@ -514,17 +548,10 @@ def main():
                 idx.match(o, c, q["d1"], q["d2"], dtype="f32", algo="plain")
                 idx.close()
 
-        for _ in range(max(1, args.warmup)):
-            plain_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         ksteps = max(1, args.steps // 2)
-        for _ in range(ksteps):
-            plain_step()
-        torch.cuda.synchronize()
-        pel = time.perf_counter() - t0
-        plain = {"value": N1 * ksteps / pel, "unit": "queries/s",
-                 "ms_per_step": 1e3 * pel / ksteps, "steps": ksteps}
+        pel = time_steps(torch, plain_step, ksteps, max(1, args.warmup))
+        plain = {"value": N1 / pel, "unit": "queries/s", "ms_per_step": 1e3 * pel,
+                 "steps": ksteps}
 
     # ---- the same step recorded once as a HIP graph (autotuned schedule)
     graph = None
@@ -536,7 +563,7 @@ def main():
         bt = E.Batch(specs, g["kp1"], g["kp2"], g["d1"], g["d2"], nnz + 1024, eps2=g["eps2"],
                      sched=sched, workspace=ws)
         gsec = time_steps(torch, bt.launch, args.steps, args.warmup)
-        same = all(torch.equal(a, r) for a, r in zip(bt.outputs()[2:], (best, bd, sd)))
+        same = all(torch.equal(a, r) for a, r in zip(bt.outputs()[2:], ref_out))
         graph = {"value": round(N1 / gsec, 1), "unit": "queries/s",
                  "ms_per_step": round(gsec * 1e3, 4), "sched": sched.as_dict(),
                  "identical_matches": bool(same),
@@ -544,24 +571,27 @@ def main():
                                             for c, t in tinfo.get("candidates", [])]}
         bt.close()
 
-    # ---- roofline of the dominant kernel (descriptor matching)
-    match_avg_ms = float(np.mean(match_ms))
-    b_desc = 512
-    match_bytes = N1 * (b_desc + 16 + 12) + nnz * 4 + N2 * b_desc
-    achieved = match_bytes / (match_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL if args.algo == "auto" else args.algo,
+    # ---- roofline of the dominant kernel
+    kern_ms = float(np.mean(kernel_ms))
+    if fused:
+        kernel_bytes = N1 * (8 + 512 + 4 + 12) + N2 * (24 + 512) + 4 * nnz
+    else:
+        kernel_bytes = N1 * (512 + 16 + 12) + nnz * 4 + N2 * 512
+    name, src, tfile = KERNELS[args.algo]
+    achieved = kernel_bytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": name,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic() if args.algo == "auto" else None,
-                "avg_launch_ms": round(match_avg_ms, 5),
-                "algorithmic_bytes_per_launch": int(match_bytes),
-                "kernel_source_sha256": source_hash(KERNEL_SRC)}
+                "traffic": measured_traffic(src, tfile),
+                "avg_launch_ms": round(kern_ms, 5),
+                "algorithmic_bytes_per_launch": int(kernel_bytes),
+                "kernel_source_sha256": source_hash(src)}
 
     if args.calibrate_copy:
-        src = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
+        src_b = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        dst_b = torch.empty_like(src_b)
         for _ in range(3):
-            dst.copy_(src)
+            dst_b.copy_(src_b)
         torch.cuda.synchronize()
 
     # ---- CPU oracle on a bounded sample of the same workload
@@ -580,9 +610,9 @@ def main():
         cel = time.perf_counter() - t0
         cpu = {"value": round(done / cel, 1), "unit": "queries/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"first {s} queries of each of the {P} pairs against all 20000 "
-                         f"keypoints ({done} queries, brute-force FP64 candidates + FP32 "
-                         f"matching, {cel:.1f} s)",
+               "sample": f"first {min(s, 20000)} queries of each of the {P} pairs against "
+                         f"all 20000 keypoints ({done} queries, brute-force FP64 candidates "
+                         f"+ FP32 matching, {cel:.1f} s)",
                "cpu": platform.processor() or platform.machine()}
 
     out = {
@@ -603,11 +633,11 @@ def main():
                                "FP32 descriptors",
                    "queries_per_step": N1, "candidates_per_step": nnz,
                    "kbar": round(nnz / N1, 2), "algo": args.algo,
-                   "query_ms_avg": round(float(np.mean(query_ms)), 4),
-                   "match_ms_avg": round(match_avg_ms, 4)},
+                   "dominant_kernel_ms_avg": round(kern_ms, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_gpu": plain,
+        "separate_calls": separate,
         "graph": graph,
     }
     if plain:

@@ -234,6 +234,14 @@ typedef struct {
   int32_t reserved[5];       /* zero                                           */
 } epm_sched;
 
+/* Profiling aid: with start and stop not NULL, later epm_query_candidates /
+ * epm_query_match calls on idx record `start` right before the stabbing-tile
+ * kernel and `stop` right after it, and epm_match calls record them around
+ * its matching kernel, on the call's stream, so a caller can time that kernel
+ * alone with hipEventElapsedTime.  NULL, NULL turns it off.  Errors:
+ * EPM_ERR_ARG (idx NULL, or only one event given). */
+epm_status epm_index_set_timing_events(epm_index* idx, hipEvent_t start, hipEvent_t stop);
+
 /* Sets the work distribution used by later calls on idx (host only).
  * Errors: EPM_ERR_ARG (NULL, negative counts, lpt not 0/1, reserved != 0). */
 epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);

@@ -39,7 +39,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_get_query_stats", "epm_get_match_stats", "epm_index_set_sched",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
-           "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match"]
+           "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
+           "epm_index_set_timing_events"]
 
 
 class EpmError(RuntimeError):
@@ -178,6 +179,8 @@ def load_library(path=None):
     lib.epm_match_residuals.restype = ctypes.c_int
     lib.epm_query_match.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, f32, V, V, V, V]
     lib.epm_query_match.restype = ctypes.c_int
+    lib.epm_index_set_timing_events.argtypes = [V, V, V]
+    lib.epm_index_set_timing_events.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -346,6 +349,22 @@ class Index:
         st = _MatchStats()
         _check(self.lib.epm_get_match_stats(self.handle, ctypes.byref(st)), "epm_get_match_stats")
         return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def set_timing_events(self, start=None, stop=None):
+        """Records two torch.cuda.Events (enable_timing=True) around the
+        dominant kernel of later query / query_match / match calls; None, None
+        turns it off."""
+        handles = []
+        for ev in (start, stop):
+            if ev is None:
+                handles.append(None)
+                continue
+            if not ev.cuda_event:  # created lazily by the first record
+                ev.record()
+            handles.append(ctypes.c_void_p(ev.cuda_event))
+        self._timing = (start, stop)
+        _check(self.lib.epm_index_set_timing_events(self.handle, *handles),
+               "epm_index_set_timing_events")
 
     def set_sched(self, sched):
         """Work distribution of later query/match calls (a Sched)."""

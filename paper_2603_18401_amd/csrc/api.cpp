@@ -234,6 +234,7 @@ struct epm_index {
   bool have_match_stats = false;
   hipStream_t match_stream = nullptr;
   epm_sched sched{};         // work distribution of the tile kernels
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // around the dominant kernel of a call
   bool have_order = false;  // the last query wrote the longest-first tile order
 
   template <typename T>
@@ -449,7 +450,9 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
     A.queue = sched + kSchedStabQueue;
     A.order = lpt ? idx->at<uint32_t>(L.order) : nullptr;
   }
+  if (idx->ev_start) EPM_HIP(hipEventRecord(idx->ev_start, stream));
   EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, fuse, stream));
+  if (idx->ev_stop) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
 }
@@ -534,9 +537,18 @@ MatchArgs match_args(epm_index* idx, const MatchCall& c) {
   return A;
 }
 
+epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t stream);
+
 epm_status enqueue_match(epm_index* idx, const MatchCall& c, hipStream_t stream) {
+  if (idx->N1 == 0) return EPM_OK;
+  if (idx->ev_start) EPM_HIP(hipEventRecord(idx->ev_start, stream));
+  const epm_status st = enqueue_match_kernels(idx, c, stream);
+  if (st == EPM_OK && idx->ev_stop) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
+  return st;
+}
+
+epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t stream) {
   const int64_t n1 = idx->N1;
-  if (n1 == 0) return EPM_OK;
   const Layout& L = idx->L;
   MatchArgs A = match_args(idx, c);
   // the window kernels walk the angle tiles and windows of the last query
@@ -663,6 +675,13 @@ epm_status epm_build_intervals(const epm_pair* pairs, int32_t num_pairs, const f
     return r;
   }
   *out = idx;
+  return EPM_OK;
+}
+
+epm_status epm_index_set_timing_events(epm_index* idx, hipEvent_t start, hipEvent_t stop) {
+  if (!idx || (start == nullptr) != (stop == nullptr)) return EPM_ERR_ARG;
+  idx->ev_start = start;
+  idx->ev_stop = stop;
   return EPM_OK;
 }
 
