@@ -185,6 +185,20 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
                      const epm_match_opts* opts, hipStream_t stream);
 
 /*
+ * Storage formats of the reduced-precision path (a helper for callers that
+ * hold FP32 descriptors): src [rows][dim] float32 ->
+ *   EPM_BF16:     dst [rows][dim] uint16 bfloat16 bit patterns, round to
+ *                 nearest even (scale unused, may be NULL);
+ *   EPM_FP8_E4M3: dst [rows][dim] uint8 OCP E4M3FN codes and scale [rows]
+ *                 float32 with scale = amax / 448 (1 for an all-zero row) and
+ *                 code = round-to-nearest-even(x / scale), saturated at 448.
+ * 1 <= dim <= 4096.  Errors: EPM_ERR_ARG (other dtypes, bad sizes, NULL).
+ * Asynchronous.
+ */
+epm_status epm_quantize(const float* src, int64_t rows, int32_t dim, epm_dtype dtype, void* dst,
+                        float* scale, hipStream_t stream);
+
+/*
  * The two sides of the point-line test of Eq. 3 (multiplied through by the
  * denominator) for listed (query, keypoint) pairs, exactly as the candidate
  * search evaluates them on the device:

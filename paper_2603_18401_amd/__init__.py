@@ -24,7 +24,7 @@ import os
 import numpy as np
 
 __all__ = ["EpmError", "Index", "Batch", "Sched", "PairSpec", "load_library", "library_path",
-           "point_line_terms", "DTYPES", "ALGOS"]
+           "point_line_terms", "quantize", "DTYPES", "ALGOS"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libepm.so")
@@ -40,7 +40,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
-           "epm_index_set_timing_events"]
+           "epm_index_set_timing_events", "epm_quantize"]
 
 
 class EpmError(RuntimeError):
@@ -181,6 +181,8 @@ def load_library(path=None):
     lib.epm_query_match.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
     lib.epm_index_set_timing_events.restype = ctypes.c_int
+    lib.epm_quantize.argtypes = [V, i64, i32, ctypes.c_int, V, V, V]
+    lib.epm_quantize.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -502,6 +504,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def quantize(desc, dtype, stream=None):
+    """epm_quantize on the device: FP32 rows [N, D] -> BF16 bit patterns
+    (int16 [N, D]), or FP8-E4M3 codes (uint8 [N, D]) and per-row scales."""
+    torch = _torch()
+    lib = load_library()
+    if desc.dtype != torch.float32 or desc.dim() != 2 or not desc.is_contiguous():
+        raise ValueError("desc must be a contiguous float32 [N, D] device tensor")
+    n, d = desc.shape
+    if dtype == "bf16":
+        out, scale = torch.empty((n, d), dtype=torch.int16, device=desc.device), None
+    elif dtype == "fp8":
+        out = torch.empty((n, d), dtype=torch.uint8, device=desc.device)
+        scale = torch.empty(n, dtype=torch.float32, device=desc.device)
+    else:
+        raise ValueError("dtype must be 'bf16' or 'fp8'")
+    st = lib.epm_quantize(_dptr(desc), n, d, DTYPES[dtype], _dptr(out), _dptr(scale),
+                          _stream(torch, desc.device, stream))
+    _check(st, "epm_quantize")
+    return (out, scale) if dtype == "fp8" else out
 
 
 def point_line_terms(F, kp1, kp2, qi, kj, eps2=None, eps=0.0, stream=None):

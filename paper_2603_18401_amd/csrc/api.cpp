@@ -1006,6 +1006,16 @@ epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const 
   return EPM_OK;
 }
 
+epm_status epm_quantize(const float* src, int64_t rows, int32_t dim, epm_dtype dtype, void* dst,
+                        float* scale, hipStream_t stream) {
+  if (rows < 0 || dim < 1 || dim > 4096) return EPM_ERR_ARG;
+  if (dtype != EPM_BF16 && dtype != EPM_FP8_E4M3) return EPM_ERR_ARG;
+  if (rows == 0) return EPM_OK;
+  if (!src || !dst || (dtype == EPM_FP8_E4M3 && !scale)) return EPM_ERR_ARG;
+  EPM_HIP(launch_quantize(src, rows, dim, dtype == EPM_BF16 ? 0 : 1, dst, scale, stream));
+  return EPM_OK;
+}
+
 epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,

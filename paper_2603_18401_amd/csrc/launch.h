@@ -204,6 +204,10 @@ hipError_t launch_residuals(const PairDev* pairs, const int64_t* qstart, int num
                             int64_t n1, const float* kp1, const float* kp2, const int32_t* best,
                             float* residual, int64_t* feat_index, hipStream_t s);
 
+// fmt 0: BF16 codes [rows][dim]; 1: E4M3 codes [rows][dim] and scales [rows].
+hipError_t launch_quantize(const float* src, int64_t rows, int dim, int fmt, void* dst,
+                           float* scale, hipStream_t s);
+
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,
                                   const int64_t* kj, int64_t count, double* num, double* rhs,
