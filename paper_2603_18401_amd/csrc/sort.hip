@@ -40,8 +40,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __
   __shared__ uint32_t sc[kRadix];
   const SortSeg sg = segs[blockIdx.x];
   const int d = threadIdx.x;
+  constexpr int kBatch = 8;  // tiles whose counts are in flight at once
+  const uint32_t* hd = hist + (int64_t)sg.tile_begin * kRadix + d;
   uint32_t total = 0;
-  for (int t = 0; t < sg.tile_count; ++t) total += hist[(int64_t)(sg.tile_begin + t) * kRadix + d];
+  for (int t0 = 0; t0 < sg.tile_count; t0 += kBatch) {
+    uint32_t c[kBatch];
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      c[u] = t0 + u < sg.tile_count ? hd[(int64_t)(t0 + u) * kRadix] : 0u;
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u) total += c[u];
+  }
   // exclusive scan over the 256 digits (Hillis-Steele in LDS)
   sc[d] = total;
   __syncthreads();
@@ -55,11 +64,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __
   // start of every digit inside the segment (after the last pass: the sorted
   // order's bucket boundaries)
   if (seg_base) seg_base[(int64_t)blockIdx.x * kRadix + d] = run;
-  for (int t = 0; t < sg.tile_count; ++t) {
-    const int64_t h = (int64_t)(sg.tile_begin + t) * kRadix + d;
-    const uint32_t c = hist[h];
-    hist[h] = run;
-    run += c;
+  uint32_t* hw = hist + (int64_t)sg.tile_begin * kRadix + d;
+  for (int t0 = 0; t0 < sg.tile_count; t0 += kBatch) {
+    uint32_t c[kBatch];
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      c[u] = t0 + u < sg.tile_count ? hw[(int64_t)(t0 + u) * kRadix] : 0u;
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (t0 + u < sg.tile_count) hw[(int64_t)(t0 + u) * kRadix] = run;
+      run += c[u];
+    }
   }
 }
 
