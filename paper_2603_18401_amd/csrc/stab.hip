@@ -520,12 +520,22 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
     }
     (void)brute;
 
-    // row lengths, and short rows parked unsorted (the copy pass sorts them)
+    // row lengths, and short rows parked in ascending j: four threads per
+    // row, each placing a quarter of its hits by rank (the j of a row are
+    // distinct, so a hit's place is the number of smaller hits)
     if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
-    for (int p = tid; p < T.count * kStage; p += kThreads) {
-      const int q = p / kStage, t = p % kStage;
-      const uint32_t n = qmode[q] == kQueryEmpty ? 0u : cnt[q];
-      if (n <= (uint32_t)kStage && (uint32_t)t < n) A.staging[qidx[q] * kStage + t] = hits[q][t];
+    {
+      const int q = tid >> 2, part = tid & 3;
+      const uint32_t n = q < T.count && qmode[q] != kQueryEmpty ? cnt[q] : 0u;
+      if (n <= (uint32_t)kStage) {
+        int32_t* dst = A.staging + qidx[q] * kStage;
+        for (uint32_t t = part; t < n; t += 4) {
+          const int32_t v = hits[q][t];
+          uint32_t r = 0;
+          for (uint32_t u = 0; u < n; ++u) r += hits[q][u] < v ? 1u : 0u;
+          dst[r] = v;
+        }
+      }
     }
 
     if (FUSE) {
@@ -600,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
 }
 
 // Fill pass, part 1: one wavefront per query in natural order copies the
-// parked short rows; longer rows are queued for part 2.
+// parked (already sorted) short rows; longer rows are queued for part 2.
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int lane = lane_id(), wave = wave_id();
   const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
@@ -608,26 +618,10 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len <= kStage) {
-    // rank sort of the parked row (two entries per lane): the j are
-    // distinct, so an entry's rank is the number of smaller entries;
-    // readlane broadcasts them without an LDS round trip
     const int n = (int)len;
-    const int32_t v0 = lane < n ? A.staging[i * kStage + lane] : INT32_MAX;
-    const int32_t v1 = lane + kWave < n ? A.staging[i * kStage + kWave + lane] : INT32_MAX;
-    uint32_t r0 = 0, r1 = 0;
-    const int n0 = n < kWave ? n : kWave;
-    for (int t = 0; t < n0; ++t) {
-      const int32_t x = __builtin_amdgcn_readlane(v0, t);
-      r0 += x < v0 ? 1u : 0u;
-      r1 += x < v1 ? 1u : 0u;
-    }
-    for (int t = kWave; t < n; ++t) {
-      const int32_t x = __builtin_amdgcn_readlane(v1, t - kWave);
-      r0 += x < v0 ? 1u : 0u;
-      r1 += x < v1 ? 1u : 0u;
-    }
-    if (lane < n && o0 + r0 < A.capacity) A.cols[o0 + r0] = v0;
-    if (lane + kWave < n && o0 + r1 < A.capacity) A.cols[o0 + r1] = v1;
+    if (lane < n && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
+    if (lane + kWave < n && o0 + kWave + lane < A.capacity)
+      A.cols[o0 + kWave + lane] = A.staging[i * kStage + kWave + lane];
   } else if (lane == 0) {
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
