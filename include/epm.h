@@ -419,7 +419,7 @@ typedef struct {
   int64_t queries;        /* image-1 queries                                         */
   int64_t reranked_rows;  /* non-empty rows ranked on MFMA with the top-4 re-ranked    */
   int64_t fallback_rows;  /* of those, not certified: every candidate evaluated exactly */
-  int64_t long_rows;      /* rows beyond a tile's 4096-entry list: evaluated exactly  */
+  int64_t long_rows;      /* rows beyond a tile's 8192-entry list: evaluated exactly  */
 } epm_match_stats;
 
 /*

@@ -15,7 +15,7 @@
 //      FP32 chains on the masters; when the smallest LB among the others
 //      exceeds the exact second distance (or the row has at most four
 //      candidates), best and second are certified exact;
-//   5. otherwise (and for rows that do not fit the tile's dense list of 4096
+//   5. otherwise (and for rows that do not fit the tile's dense list of 8192
 //      entries) every candidate is evaluated exactly -- counted in the match
 //      statistics.
 // Final outputs therefore equal the FP32 path bit for bit.
@@ -30,7 +30,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kChunkRows = 64;
-constexpr int kMaxPairs = 4096;  // dense (query, candidate) entries per tile
+constexpr int kMaxPairs = 8192;  // dense (query, candidate) entries per tile
 constexpr uint32_t kPending = 0x80000000u;
 constexpr uint32_t kNoWindow = (1u << 25) - 1u;
 constexpr int kReRank = 4;
@@ -110,7 +110,6 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   constexpr int kWBytes = kChunkRows * RS > kScoreBytes ? kChunkRows * RS : kScoreBytes;
   __shared__ __attribute__((aligned(16))) uint8_t wrows[kWBytes];
   __shared__ uint32_t ent[kMaxPairs];
-  __shared__ int32_t ent_j[kMaxPairs];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint32_t ss_b[kSlots], ss_v[kSlots], ss_len[kSlots];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
@@ -122,6 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   __shared__ float4 qdesc[kWaves][32];
   // re-rank scratch: per query the four chosen entries and the fifth bound
   __shared__ uint32_t pick[kTileQ][kReRank];
+  __shared__ int32_t pick_j[kTileQ][kReRank];  // image-2 index of each pick (from the CSR)
   __shared__ float pick_d[kTileQ][kReRank];
   __shared__ float lb5[kTileQ];
 
@@ -234,7 +234,6 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       }
       if (v >= kNoWindow) v = kNoWindow;
       ent[e] = pack_entry(q, v);
-      ent_j[e] = j;
     }
     __syncthreads();
     if (tid < kTileQ) {
@@ -373,7 +372,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       const int q = tid >> 2, u = tid & 3;
       float d = __builtin_inff();
       if (q < T.count && q_in[q] && pick[q][u] != 0xFFFFFFFFu) {
-        const int32_t j = ent_j[pick[q][u]];
+        const int32_t j = A.cols[q_o0[q] + (pick[q][u] - q_off[q])];
+        pick_j[q][u] = j;
         d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
                            reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
       }
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       Top2 t;
       #pragma unroll
       for (int u = 0; u < kReRank; ++u)
-        if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], ent_j[pick[q][u]]);
+        if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], pick_j[q][u]);
       const uint32_t k = q_k[q];
       // certified when every candidate left out has a bound above the second
       const bool ok = k <= (uint32_t)kReRank || lb5[q] > t.sd;
