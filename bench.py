@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=10, help="learned workload: epochs")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: EPM_TUNE_CACHE or ~/.cache/epm)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload: default tile schedule instead of the autotuner")
     ap.add_argument("--no-separate", action="store_true",
                     help="scale workload: skip the separate-calls figure")
     ap.add_argument("--no-graph", action="store_true",
@@ -232,10 +234,13 @@ def batch_workload(args):
     cap = nnz + 1024
 
     # ---- autotuned schedule, then graph replays
-    sched, tinfo = autotune.tune(specs, kp1, kp2, q1, q2, cap, dtype="bf16", eps=2.0,
-                                 desc1_f32=m1, desc2_f32=m2, steps=3, warmup=1,
-                                 cache=args.tune_cache,
-                                 log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    if args.no_tune:
+        sched, tinfo = E.Sched(), {"key": None, "cached": None}
+    else:
+        sched, tinfo = autotune.tune(specs, kp1, kp2, q1, q2, cap, dtype="bf16", eps=2.0,
+                                     desc1_f32=m1, desc2_f32=m2, steps=3, warmup=1,
+                                     cache=args.tune_cache,
+                                     log=lambda msg: print(msg, file=sys.stderr, flush=True))
     bt = E.Batch(specs, kp1, kp2, q1, q2, cap, eps=2.0, dtype="bf16", desc1_f32=m1,
                  desc2_f32=m2, sched=sched, workspace=ws)
     sec = time_steps(torch, bt.launch, args.steps, args.warmup)
@@ -273,7 +278,7 @@ def batch_workload(args):
             idx.match(o2, c2, d1, d2, dtype="f32", algo="plain")
             idx.close()
 
-    psec = time_steps(torch, plain_step, 1, 1)
+    psec = time_steps(torch, plain_step, 1, 1) if not args.no_plain else float("nan")
     # algorithmic bytes of the batch (BF16 rows, FP32 masters read for the re-rank)
     alg_bytes = N1 * (8 + 256 + 8 + 12) + N2 * (8 + 4 + 256 + 24) + 4 * nnz + 512 * (N1 + N2)
     line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
@@ -294,8 +299,9 @@ def batch_workload(args):
             "match_stats": gmatch, "query_stats": gstats,
             "eager_batched": {"value": round(N1 / esec, 1), "ms_per_step": round(esec * 1e3, 4),
                               "identical_matches": bool(same)},
-            "plain_gpu": {"value": round(N1 / psec, 1), "ms_per_step": round(psec * 1e3, 2)},
-            "speedup_vs_plain": round(psec / sec, 3)}
+            "plain_gpu": None if args.no_plain else {"value": round(N1 / psec, 1),
+                                                     "ms_per_step": round(psec * 1e3, 2)},
+            "speedup_vs_plain": None if args.no_plain else round(psec / sec, 3)}
     print(json.dumps(line), flush=True)
 
 
