@@ -79,6 +79,34 @@ __device__ __forceinline__ float exact_distance(const float4* __restrict__ a,
   return acc;
 }
 
+// Squared norm of a quantised row in LDS, k ascending, read 16 bytes at a time.
+template <int FMT>
+__device__ __forceinline__ float row_sqnorm(const uint8_t* row) {
+  constexpr int kElemBytes = Fmt<FMT>::kRowBytes / 128;  // 2 (BF16) or 1 (FP8)
+  constexpr int kPer = 16 / kElemBytes;                    // elements per 16 bytes
+  static_assert(kPer * kElemBytes == 16 && 128 % kPer == 0, "row layout");
+  float n = 0.0f;
+  #pragma unroll 1
+  for (int c = 0; c < 128 / kPer; ++c) {
+    const uint4 w = reinterpret_cast<const uint4*>(row)[c];
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    #pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int byte = k * kElemBytes;
+      const uint32_t bits = words[byte >> 2] >> ((byte & 3) * 8);
+      float x;
+      if (FMT == 0) {
+        x = __uint_as_float((bits & 0xFFFFu) << 16);
+      } else {
+        const uint8_t code = (uint8_t)(bits & 0xFFu);
+        x = Fmt<FMT>::decode(&code, 0);
+      }
+      n = __builtin_fmaf(x, x, n);
+    }
+  }
+  return n;
+}
+
 // Quantisation error bound of a row from its quantised norm:
 // |x^ - x|_2 <= (u |x^| + a s sqrt(128)) / (1 - u), slightly inflated.
 template <int FMT>
@@ -115,6 +143,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
   __shared__ uint32_t q_k[kTileQ], q_off[kTileQ + 1], q_in[kTileQ];
   __shared__ float q_norm[kTileQ], q_scale[kTileQ], w_norm[kChunkRows], w_scale[kChunkRows];
+  // per-row terms of the bound: inflated norm and quantisation error bound
+  __shared__ double q_nb[kTileQ], q_db[kTileQ], w_nb[kChunkRows], w_db[kChunkRows];
   __shared__ int32_t row_j[kChunkRows];
   __shared__ uint32_t n_sorted_slots, n_fallback;
   __shared__ uint16_t fallback_q[kTileQ];
@@ -237,14 +267,13 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
     }
     __syncthreads();
     if (tid < kTileQ) {
-      float n = 0.0f;
-      for (int k = 0; k < 128; ++k) {
-        const float x = Fmt<FMT>::decode(qrows + tid * RS, k);
-        n = __builtin_fmaf(x, x, n);
-      }
+      const float n = row_sqnorm<FMT>(qrows + tid * RS);
       const float s = (FMT == 1 && tid < T.count) ? A.scale1[q_i[tid]] : 1.0f;
       q_scale[tid] = s;
       q_norm[tid] = n * s * s;  // squared norm of the dequantised row
+      const double nb = sqrt((double)q_norm[tid]) * (1.0 + 1e-5);
+      q_nb[tid] = nb;
+      q_db[tid] = row_delta<FMT>(nb, s);
     }
 
     const uint32_t wlen = slot_pref[kSlots];
@@ -272,14 +301,13 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       }
       __syncthreads();
       if (tid < kChunkRows) {
-        float n = 0.0f;
-        for (int k = 0; k < 128; ++k) {
-          const float x = Fmt<FMT>::decode(wrows + tid * RS, k);
-          n = __builtin_fmaf(x, x, n);
-        }
+        const float n = row_sqnorm<FMT>(wrows + tid * RS);
         const float s = (FMT == 1 && row_j[tid] >= 0) ? A.scale2[kb + row_j[tid]] : 1.0f;
         w_scale[tid] = s;
         w_norm[tid] = n * s * s;
+        const double nb = sqrt((double)w_norm[tid]) * (1.0 + 1e-5);
+        w_nb[tid] = nb;
+        w_db[tid] = row_delta<FMT>(nb, s);
       }
       // S = Q W^T: wavefront w owns queries 16w..16w+15 against all 64 rows
       f32x4 acc[4];
@@ -323,11 +351,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
         if (v < c0 || v >= c0 + nr) continue;
         const uint32_t q = x & 63u, r = v - c0;
         const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
-        const double nq = sqrt((double)q_norm[q]) * (1.0 + 1e-5);
-        const double nw = sqrt((double)w_norm[r]) * (1.0 + 1e-5);
         const double dt = (double)q_norm[q] + (double)w_norm[r] - 2.0 * s;
-        const double lb = lower_bound(dt, nq, nw, row_delta<FMT>(nq, q_scale[q]),
-                                      row_delta<FMT>(nw, w_scale[r]));
+        const double lb = lower_bound(dt, q_nb[q], w_nb[r], q_db[q], w_db[r]);
         ent[e] = __float_as_uint((float)lb * (1.0f - 1e-6f));  // rounded down, >= 0
       }
       __syncthreads();
