@@ -74,6 +74,66 @@ __device__ __forceinline__ Top2 wave_merge_top2(Top2 t) {
   return t;
 }
 
+// Dense (query, candidate) lists of the window kernels: entry e of query q is
+// its t-th candidate, e = q_off[q] + t; an entry packs (pending bit, window
+// position v, query q) as kEntPending | v << 6 | q, v = kEntNoWindow when the
+// candidate lies outside the tile's window.
+constexpr uint32_t kEntPending = 0x80000000u;
+constexpr uint32_t kEntNoWindow = (1u << 25) - 1u;
+
+__device__ __forceinline__ uint32_t entry_query(const uint32_t* q_off, uint32_t e) {
+  uint32_t q = 0;  // last query with q_off[q] <= e
+  #pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (q + step < kTileQ && q_off[q + step] <= e) q += step;
+  return q;
+}
+
+// Builds ent[0 .. npairs) (and ent_j, the candidates' image-2 indices, when
+// not NULL) for one tile.  Every thread handles entries tid, tid + NT, ...,
+// kBatch of them at a time so that their CSR and inverse-permutation loads are
+// in flight together; the caller synchronises afterwards.  The window is
+// given by its non-empty slots sorted by start position (ss_*, nss of them).
+template <int NT>
+__device__ __forceinline__ void build_dense_list(const MatchArgs& A, int64_t kb, uint32_t npairs,
+                                                 const uint32_t* q_off, const int64_t* q_o0,
+                                                 const uint32_t* ss_b, const uint32_t* ss_v,
+                                                 const uint32_t* ss_len, uint32_t nss,
+                                                 uint32_t* ent, int32_t* ent_j, int tid) {
+  constexpr int kBatch = 4;
+  for (uint32_t e0 = tid; e0 < npairs; e0 += NT * kBatch) {
+    int32_t j[kBatch];
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t e = e0 + u * NT;
+      if (e < npairs) {
+        const uint32_t q = entry_query(q_off, e);
+        j[u] = A.cols[q_o0[q] + (e - q_off[q])];
+      }
+    }
+    uint32_t pos[kBatch];
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (e0 + u * NT < npairs) pos[u] = A.rinv[kb + j[u]];
+    #pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t e = e0 + u * NT;
+      if (e >= npairs) continue;
+      uint32_t v = kEntNoWindow;
+      if (nss > 0) {
+        uint32_t s = 0;  // last sorted slot with ss_b[s] <= pos
+        #pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (s + step < nss && ss_b[s + step] <= pos[u]) s += step;
+        if (ss_b[s] <= pos[u] && pos[u] - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos[u] - ss_b[s]);
+      }
+      if (v >= kEntNoWindow) v = kEntNoWindow;
+      ent[e] = kEntPending | (v << 6) | entry_query(q_off, e);
+      if (ent_j) ent_j[e] = j[u];
+    }
+  }
+}
+
 // Output convention: empty row -> -1 / +inf / +inf; ratio rejection -> -1
 // with both distances kept.
 // A CSR that did not fit its buffer (row_offsets[n1] beyond the caller's

@@ -31,8 +31,8 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kChunkRows = 64;
 constexpr int kMaxPairs = 8192;  // dense (query, candidate) entries per tile
-constexpr uint32_t kPending = 0x80000000u;
-constexpr uint32_t kNoWindow = (1u << 25) - 1u;
+constexpr uint32_t kPending = kEntPending;
+constexpr uint32_t kNoWindow = kEntNoWindow;
 constexpr int kReRank = 4;
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
@@ -66,10 +66,6 @@ struct Fmt<1> {  // OCP E4M3FN with a per-row scale: 4 significant bits
 // 16-byte (BF16) or 8-byte (FP8) fragment reads of 16 rows are conflict free.
 template <int FMT>
 constexpr int row_stride() { return Fmt<FMT>::kRowBytes + 16; }
-
-__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t v) {
-  return kPending | (v << 6) | q;
-}
 
 __device__ __forceinline__ float exact_distance(const float4* __restrict__ a,
                                                 const float4* __restrict__ b) {
@@ -246,25 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
     // dense (query, candidate, window index) list
     const uint32_t npairs = q_off[kTileQ];
     const uint32_t nss = n_sorted_slots;
-    for (uint32_t e = tid; e < npairs; e += kThreads) {
-      uint32_t q = 0;
-      #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (q + step < kTileQ && q_off[q + step] <= e) q += step;
-      const uint32_t t = e - q_off[q];
-      const int32_t j = A.cols[q_o0[q] + t];
-      const uint32_t pos = A.rinv[kb + j];
-      uint32_t v = kNoWindow;
-      if (nss > 0) {
-        uint32_t s = 0;
-        #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-          if (s + step < nss && ss_b[s + step] <= pos) s += step;
-        if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
-      }
-      if (v >= kNoWindow) v = kNoWindow;
-      ent[e] = pack_entry(q, v);
-    }
+    build_dense_list<kThreads>(A, kb, npairs, q_off, q_o0, ss_b, ss_v, ss_len, nss, ent, nullptr,
+                               tid);
     __syncthreads();
     if (tid < kTileQ) {
       const float n = row_sqnorm<FMT>(qrows + tid * RS);

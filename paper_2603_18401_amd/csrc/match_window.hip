@@ -30,12 +30,8 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kRowStride = 132;  // floats
 constexpr int kWinRows = 64;     // rows staged per pass
 constexpr int kMaxPairs = 4096;  // dense (query, candidate) entries per tile
-constexpr uint32_t kPending = 0x80000000u;
-constexpr uint32_t kNoWindow = (1u << 25) - 1u;
-
-__device__ __forceinline__ uint32_t pack_entry(uint32_t q, uint32_t v) {
-  return kPending | (v << 6) | q;
-}
+constexpr uint32_t kPending = kEntPending;
+constexpr uint32_t kNoWindow = kEntNoWindow;
 
 __device__ __forceinline__ float row_distance_global(const float4* __restrict__ qr,
                                                      const float4* __restrict__ wr) {
@@ -138,26 +134,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
     // 1. dense (query, candidate, window index) list
     const uint32_t npairs = q_off[kTileQ];
     const uint32_t nss = n_sorted_slots;
-    for (uint32_t e = tid; e < npairs; e += kThreads) {
-      uint32_t q = 0;  // last query with q_off[q] <= e
-      #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (q + step < kTileQ && q_off[q + step] <= e) q += step;
-      const uint32_t t = e - q_off[q];
-      const int32_t j = A.cols[q_o0[q] + t];
-      const uint32_t pos = A.rinv[kb + j];
-      uint32_t v = kNoWindow;
-      if (nss > 0) {
-        uint32_t s = 0;  // last sorted slot with ss_b[s] <= pos
-        #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-          if (s + step < nss && ss_b[s + step] <= pos) s += step;
-        if (ss_b[s] <= pos && pos - ss_b[s] < ss_len[s]) v = ss_v[s] + (pos - ss_b[s]);
-      }
-      if (v >= kNoWindow) v = kNoWindow;
-      ent[e] = pack_entry(q, v);
-      ent_j[e] = j;
-    }
+    build_dense_list<kThreads>(A, kb, npairs, q_off, q_o0, ss_b, ss_v, ss_len, nss, ent, ent_j,
+                               tid);
     __syncthreads();
 
     // 2-3. stage window rows and evaluate the entries that fall in them
