@@ -1,0 +1,59 @@
+"""Every bench.py workload emits one JSON line with the required fields
+(small settings; the numbers themselves are not checked)."""
+
+import json
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+REQUIRED = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")
+
+
+def _run(monkeypatch, capsys, argv):
+    import bench
+    monkeypatch.setattr(sys, "argv", ["bench.py"] + argv)
+    print(f"bench {' '.join(argv)}", file=sys.stderr, flush=True)
+    bench.main()
+    lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1
+    line = json.loads(lines[-1])
+    for k in REQUIRED:
+        assert k in line, k
+    assert line["n_gpus"] == 1 and line["value"] > 0 and "workload" in line["config"]
+    return line
+
+
+def test_scale_workload_line(monkeypatch, capsys):
+    line = _run(monkeypatch, capsys, ["--steps", "2", "--warmup", "1", "--no-plain",
+                                      "--no-graph", "--cpu-sample", "200"])
+    r = line["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r, k
+    assert r["peak"] == 8000.0 and 0 < r["frac"] < 1
+    c = line["cpu_baseline"]
+    for k in ("value", "unit", "cores", "kind", "sample"):
+        assert k in c, k
+    assert c["kind"] == "oracle"
+    assert line["separate_calls"]["identical_matches"]
+
+
+def test_batch_workload_line(monkeypatch, capsys):
+    line = _run(monkeypatch, capsys, ["--workload", "batch", "--pairs", "8", "--steps", "1",
+                                      "--warmup", "0", "--no-plain", "--no-tune"])
+    assert line["eager_batched"]["identical_matches"]
+
+
+def test_precision_workload_line(monkeypatch, capsys):
+    line = _run(monkeypatch, capsys, ["--workload", "precision", "--steps", "1", "--warmup", "0"])
+    assert set(line["paths"]) == {"f32", "f32_plain", "bf16", "fp8", "bin256"}
+
+
+def test_learned_workload_line(monkeypatch, capsys):
+    line = _run(monkeypatch, capsys, ["--workload", "learned", "--train-pairs", "8",
+                                      "--test-pairs", "2", "--epochs", "1", "--steps", "1",
+                                      "--warmup", "0"])
+    assert line["training"]["residual_samples"] > 0
+    assert len(line["held_out"]["fixed"]) > 3

@@ -160,3 +160,45 @@ def test_tolerance_covering_the_image_is_brute_force_matching():
     for path, got in out.items():
         assert np.all(np.diff(got[0]) == p.n), path
     _check(out, _oracle([p], 2000.0), "full rows")
+
+
+def test_tiny_tolerance_keeps_noiseless_true_matches():
+    """eps = 1e-3 px on noiseless keypoints: every true match is still a
+    candidate (the FP32 storage error is far below 1e-3 px at 640 px)."""
+    import copy
+    p0 = synth.cfg0_pair(2)
+    p = copy.copy(p0)
+    p.kp1, p.kp2 = p0.clean1.copy(), p0.clean2.copy()
+    log("eps 1e-3 on noiseless keypoints")
+    out = _run_all([p], 1e-3)
+    o, c = out["fused"][0], out["fused"][1]
+    t = np.nonzero(p.gt12 >= 0)[0]
+    for i in t:
+        assert p.gt12[i] in c[o[i]:o[i + 1]]
+    _check(out, _oracle([p], 1e-3), "tiny eps")
+
+
+def test_single_keypoint_and_keypoints_outside_the_image():
+    p = _cut(synth.cfg0_pair(3), 600, 1)
+    log("one image-2 keypoint")
+    _check(_run_all([p], 50.0), _oracle([p], 50.0), "n = 1")
+    import copy
+    q = copy.copy(synth.cfg0_pair(4))
+    rng = np.random.default_rng(8)
+    q.kp1 = q.kp1 + rng.uniform(-900, 900, q.kp1.shape).astype(np.float32)
+    q.kp2 = q.kp2 + rng.uniform(-900, 900, q.kp2.shape).astype(np.float32)
+    log("keypoints outside the image")
+    _check(_run_all([q], 4.0), _oracle([q], 4.0), "outside")
+
+
+def test_epipole_on_the_image_border():
+    """Translation towards a point on the right border of image 2."""
+    W, H, f = 640, 480, 500.0
+    # camera 2 centre along the ray of the border pixel (W, H/2)
+    ray = np.array([(W - W / 2) / f, 0.0, 1.0])
+    C2 = ray / np.linalg.norm(ray)
+    p = synth.make_pair(W, H, f, np.eye(3), C2, 800, 200, 200, 77)
+    e = p.e2 / p.e2[2]
+    assert abs(e[0] - W) < 1e-6 and abs(e[1] - H / 2) < 1e-6
+    log("epipole on the border")
+    _check(_run_all([p], 2.0), _oracle([p], 2.0), "border epipole")
