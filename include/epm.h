@@ -423,8 +423,10 @@ typedef struct {
 } epm_match_stats;
 
 /*
- * Reads the counters of the last BF16/FP8 epm_match on idx (waits for the
- * stream that call used).  fallback_rows / reranked_rows is the rate at which
+ * Reads the counters of the last BF16/FP8 epm_match on idx, or of the rows
+ * with more than 128 candidates of the last epm_query_match on idx (ranked on
+ * MFMA with BF16 copies of the FP32 rows; long_rows is then 0), and waits for
+ * the stream that call used.  fallback_rows / reranked_rows is the rate at which
  * the four re-ranked candidates could not be certified to contain the exact
  * best and second; those rows are then evaluated exactly, so results never
  * depend on it.

@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest;
+  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest, tile_wide;
   size_t total;
 };
 
@@ -78,6 +78,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.tile_cost = take(sizeof(uint32_t) * ts);
   L.order = take(sizeof(uint32_t) * ts);
   L.rest = take(sizeof(uint32_t) * N1);
+  L.tile_wide = take(sizeof(uint32_t) * ts);
   L.total = off;
   return L;
 }
@@ -407,6 +408,8 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.best_dist = nullptr;
   A.second_dist = nullptr;
   A.rest = idx->at<uint32_t>(L.rest);
+  A.tile_wide = idx->at<uint32_t>(L.tile_wide);
+  A.match_stats = nullptr;
   return A;
 }
 
@@ -457,9 +460,13 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   return EPM_OK;
 }
 
-epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream) {
+// CSR fill after the scan: parked short rows, brute-force long rows, then the
+// wide-row pass (match: with its FP32 selection, see launch_wide_tiles).
+epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream,
+                        bool match = false) {
   if (idx->N1 == 0) return EPM_OK;
   EPM_HIP(launch_fill_rows(A, stream));
+  EPM_HIP(launch_wide_tiles(A, match, stream));
   return EPM_OK;
 }
 
@@ -595,9 +602,9 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
   }
 }
 
-// Stabbing with fused FP32 selection, then the CSR fill and the listed-query
-// match of the rows the fused pass left.  nnz_host as in
-// epm_query_candidates.
+// Stabbing with fused FP32 selection, then the CSR fill with the wide-row
+// selection, and the listed-query match of the rows the two passes left.
+// nnz_host as in epm_query_candidates.
 epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets,
                                int64_t* nnz_host, const MatchCall& c, hipStream_t stream) {
   const int64_t n1 = idx->N1;
@@ -607,6 +614,11 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   A.best_idx = c.best_idx;
   A.best_dist = c.best_dist;
   A.second_dist = c.second_dist;
+  // counters of the wide-row selection (certified / listed rows)
+  A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);
+  EPM_HIP(launch_clear_stats(A.match_stats, stream));
+  idx->have_match_stats = true;
+  idx->match_stream = stream;
   const epm_status st = enqueue_count(idx, A, row_offsets, stream, true);
   if (st != EPM_OK) return st;
   if (n1 == 0) return EPM_OK;
@@ -620,7 +632,7 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
     *nnz_host = nnz;
     if (nnz > A.capacity) return EPM_ERR_CAPACITY;
   }
-  const epm_status fs = enqueue_fill(idx, A, stream);
+  const epm_status fs = enqueue_fill(idx, A, stream, true);
   if (fs != EPM_OK) return fs;
   MatchArgs M = match_args(idx, c);
   EPM_HIP(launch_match_listed_f32(M, A.rest, A.stats + kStatRest, n1, stream));

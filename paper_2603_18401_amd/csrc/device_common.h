@@ -59,15 +59,24 @@ __device__ __forceinline__ void epipolar_line(const double* __restrict__ F, floa
   c = __dadd_rn(__dadd_rn(__dmul_rn(F[6], x), __dmul_rn(F[7], y)), F[8]);
 }
 
+// sqrt(a^2 + b^2) of a line, correctly rounded (the denominator of Eq. 3).
+__device__ __forceinline__ double line_norm(double a, double b) {
+  return __dsqrt_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)));
+}
+
 // Eq. 3-4 multiplied through by sqrt(a^2 + b^2): the only FP64 step of the
-// per-candidate path.  Closed boundary.
-__device__ __forceinline__ bool within_tolerance(double a, double b, double c, float xf,
-                                                 float yf, float ef) {
+// per-candidate path.  Closed boundary.  nrm = line_norm(a, b), computed once
+// per query; the decision is the same bit for bit as with the norm inline.
+__device__ __forceinline__ bool within_tolerance_n(double a, double b, double c, double nrm,
+                                                   float xf, float yf, float ef) {
   const double num =
       fabs(__dadd_rn(__dadd_rn(__dmul_rn(a, (double)xf), __dmul_rn(b, (double)yf)), c));
-  const double rhs =
-      __dmul_rn((double)ef, __dsqrt_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b))));
-  return num <= rhs;
+  return num <= __dmul_rn((double)ef, nrm);
+}
+
+__device__ __forceinline__ bool within_tolerance(double a, double b, double c, float xf,
+                                                 float yf, float ef) {
+  return within_tolerance_n(a, b, c, line_norm(a, b), xf, yf, ef);
 }
 
 // Circular distance between two angle keys (mod 2^32 == mod pi).

@@ -67,7 +67,8 @@ struct StabArgs {
   int num_tiles;
   int32_t* staging;  // [n1][kStage], indexed by the original query index
   unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
-  uint32_t* long_rows;        // [n1] queue of rows longer than kStage
+  uint32_t* long_rows;        // [n1] queue of brute-force rows longer than kStage
+  uint32_t* tile_wide;        // [num_tiles] 1: the tile has a normal row longer than kStage
   TileWindow* windows;        // [num_tiles], written by launch_tile_windows
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
@@ -80,6 +81,7 @@ struct StabArgs {
   float* best_dist;
   float* second_dist;
   uint32_t* rest;             // [n1] queries left to the listed-query match
+  unsigned long long* match_stats;  // wide-row matching counters (kNumMatchStats), or NULL
 };
 
 // Scheduling counters (u32 words of one workspace block).
@@ -102,16 +104,21 @@ constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kSt
 constexpr int kNumStats = 6;
 hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
 
-hipError_t launch_stab_count(const StabArgs& a, hipStream_t s);
-hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s);
 // Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
 // workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.
 // fuse: also selects the FP32 matches of the rows it can (desc1/desc2 and the
 // outputs in a); the other queries are appended to a.rest, counted in
 // stats[kStatRest], for launch_match_listed_f32 once the CSR is complete.
 hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t s);
-// Fill pass after launch_stab_tiles: copies parked rows, rebuilds the rest.
+// Fill pass after launch_stab_tiles: copies parked rows, rebuilds the
+// brute-force long rows.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
+// Wide-row pass after the scan: writes the rows longer than kStage of normal
+// queries, tile by tile (tiles flagged in a.tile_wide).  match: also selects
+// their FP32 matches (desc1/desc2 and the outputs in a) through a BF16 MFMA
+// bound with a certified FP32 re-rank; uncertified queries are appended to
+// a.rest like those of the fused stabbing pass.
+hipError_t launch_wide_tiles(const StabArgs& a, bool match, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,

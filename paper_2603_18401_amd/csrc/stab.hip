@@ -3,13 +3,14 @@
 // is confirmed by the FP64 point-line test (Eq. 3), so the rows are exactly
 // the candidate sets of Eq. 4.
 //
-// One wavefront per query, queries taken in angle order so that neighbouring
-// wavefronts read neighbouring windows.  For width class c the only centres
-// that can hold the key lie within 2^c - 1 key units of it; the window is
-// found with a cooperative 64-way search and scanned 64 records at a time,
-// one lane per record.  Hits are compacted with a ballot and a lane prefix
-// count.  The count pass writes the row lengths; the fill pass repeats the
-// scan, gathers the hits in LDS, sorts them by j and writes the CSR row.
+// Queries are taken in tiles of kTileQ angle-sorted queries of one pair.  For
+// width class c the only centres that can hold a key lie within 2^c - 1 key
+// units of it, so the window pass finds each tile's record window in every
+// class; the tile pass tests every (query, record) pair of the window, writes
+// the row lengths and parks short rows.  After the scan of the lengths the
+// fill pass copies the parked rows and rebuilds the long rows of brute-force
+// queries one wavefront per query (scan, LDS sort by j); long rows of normal
+// queries are written tile by tile by the wide-row pass.
 #include "device_common.h"
 #include "launch.h"
 #include "match_common.h"
@@ -181,31 +182,6 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
   wave_sync_lds();
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(kThreads) void k_stab(StabArgs A) {
-  __shared__ int32_t rowbuf[FILL ? kWaves : 1][FILL ? kRowSortMax : 1];
-  const int lane = lane_id(), wave = wave_id();
-  const int64_t qs = (int64_t)blockIdx.x * kWaves + wave;
-  if (qs >= A.n1) return;
-  const int64_t i = A.qperm ? (int64_t)A.qperm[qs] : qs;
-  if (FILL) {
-    fill_row(A, i, rowbuf[wave]);
-    return;
-  }
-  const int pair = find_pair(A.qstart, A.num_pairs, i);
-  const PairDev& pd = A.pairs[pair];
-  const uint32_t flag = A.qflag[i];
-  uint32_t total = 0;
-  if (flag != kQueryEmpty) {
-    QueryCtx q;
-    epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], q.a, q.b, q.c);
-    q.key = A.qkey[i];
-    q.brute = flag == kQueryBrute;
-    total = stab_query<false>(A, pd, pair, q, nullptr);
-  }
-  if (lane == 0) A.counts[i] = total;
-}
-
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
 static_assert(kTileQ == 64, "pair indexing uses a 6-bit query field");
@@ -329,10 +305,11 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // positions, the window's descriptor rows are staged kFuseRows at a time
 // (over the record chunk buffers, dead by then), and four lanes per query
 // evaluate canonical FP32 distances of that query's hits in the chunk and
-// keep a top-2, merged across the four lanes at the end.  Queries this
-// cannot serve (brute-force rows, rows longer than kStage, windows longer
-// than 16-bit positions) are listed for the listed-query match after the
-// CSR is complete; empty rows get their (-1, inf, inf) here.
+// keep a top-2, merged across the four lanes at the end.  Rows longer than
+// kStage are matched by the wide-row pass; the other queries this cannot
+// serve (brute-force rows, windows longer than 16-bit positions) are listed
+// for the listed-query match after the CSR is complete; empty rows get their
+// (-1, inf, inf) here.
 constexpr int kFuseRows = 32;
 constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
 constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
@@ -388,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   int32_t* sJ = FUSE ? sJ_keep : reinterpret_cast<int32_t*>(sE + kChunk);
   __shared__ int32_t hits[kTileQ][kStage + 1];  // +1: rows start in different banks
   __shared__ uint16_t hits_v[FUSE ? kTileQ : 1][FUSE ? kStage + 2 : 1];  // window positions
-  __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ];
+  __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ], qn[kTileQ];
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
@@ -428,6 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       qa[lane] = a;
       qb[lane] = b;
       qc[lane] = c;
+      qn[lane] = line_norm(a, b);
       qk[lane] = key;
       qmode[lane] = live ? flag : kQueryEmpty;
       qidx[lane] = i;
@@ -468,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         if (key_distance(qk[q], sC[r]) > sH[r]) continue;
         ++angle_hits;
         const float2 xy = sXY[r];
-        if (!within_tolerance(qa[q], qb[q], qc[q], xy.x, xy.y, sE[r])) continue;
+        if (!within_tolerance_n(qa[q], qb[q], qc[q], qn[q], xy.x, xy.y, sE[r])) continue;
         const uint32_t slot = atomicAdd(&cnt[q], 1u);
         if (slot < (uint32_t)kStage) {
           hits[q][slot] = sJ[r];
@@ -483,7 +461,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
     for (int qq = 0; qq < kQPerWave; ++qq) {
       const int q = wave * kQPerWave + qq;
       if (qmode[q] != kQueryBrute) continue;
-      const double a = qa[q], b = qb[q], c = qc[q];
+      const double a = qa[q], b = qb[q], c = qc[q], nrm = qn[q];
       uint32_t c0 = 0;
       brute += 1;
       for (int64_t base = pd.k_begin; base < pd.k_begin + pd.n; base += kWave) {
@@ -491,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         bool hit = false;
         if (pos < pd.k_begin + pd.n) {
           const float2 xy = A.rxy[pos];
-          hit = within_tolerance(a, b, c, xy.x, xy.y, A.reps[pos]);
+          hit = within_tolerance_n(a, b, c, nrm, xy.x, xy.y, A.reps[pos]);
         }
         const uint64_t m = ballot(hit);
         if (hit) {
@@ -519,6 +497,13 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
     }
     (void)brute;
+    // rows longer than kStage of normal queries are written (and, fused,
+    // matched) by the wide-row pass over the tile
+    if (wave == 0) {
+      const bool wide = lane < T.count && qmode[lane] == kQueryNormal && cnt[lane] > (uint32_t)kStage;
+      const uint64_t wm = ballot(wide);
+      if (lane == 0) A.tile_wide[tile] = wm != 0 ? 1u : 0u;
+    }
 
     // row lengths, and short rows parked in ascending j: four threads per
     // row, each placing a quarter of its hits by rank (the j of a row are
@@ -545,7 +530,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         if (mode == kQueryEmpty) {
           write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[tid], Top2(),
                          false);
-        } else if (mode != kQueryNormal || cnt[tid] > (uint32_t)kStage || !fusable) {
+        } else if (mode != kQueryNormal || (cnt[tid] <= (uint32_t)kStage && !fusable)) {
           const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
           A.rest[at] = (uint32_t)qidx[tid];
         }
@@ -610,7 +595,8 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
 }
 
 // Fill pass, part 1: one wavefront per query in natural order copies the
-// parked (already sorted) short rows; longer rows are queued for part 2.
+// parked (already sorted) short rows; longer rows of brute-force queries are
+// queued for part 2 (those of normal queries go to the wide-row pass).
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   const int lane = lane_id(), wave = wave_id();
   const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
@@ -622,7 +608,8 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
     if (lane < n && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
     if (lane + kWave < n && o0 + kWave + lane < A.capacity)
       A.cols[o0 + kWave + lane] = A.staging[i * kStage + kWave + lane];
-  } else if (lane == 0) {
+  } else if (lane == 0 && A.qflag[i] != kQueryNormal) {
+    // long rows of normal queries belong to the wide-row pass of their tile
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
   }
@@ -714,20 +701,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __r
 }
 
 }  // namespace
-
-hipError_t launch_stab_count(const StabArgs& a, hipStream_t s) {
-  if (a.n1 == 0) return hipSuccess;
-  const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_stab<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_stab_fill(const StabArgs& a, hipStream_t s) {
-  if (a.n1 == 0) return hipSuccess;
-  const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_stab<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
-}
 
 __global__ void k_clear_stats(unsigned long long* stats) {
   if (threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;

@@ -71,9 +71,9 @@ def test_cfg1_fused_equals_oracle(motion, eps):
     assert idx.stats()["candidates"] == int(got[0][-1])
 
 
-def test_long_rows_take_the_listed_path():
+def test_long_rows_take_the_wide_row_pass():
     """A wide tolerance gives rows beyond the on-chip list (more than 128
-    candidates); they are matched after the CSR is complete."""
+    candidates); the wide-row pass writes and matches them."""
     p = synth.cfg0_pair(1)
     log("fused cfg0 with eps 30")
     got, _ = _fused([p], 30.0)
