@@ -67,11 +67,16 @@ __device__ __forceinline__ double line_norm(double a, double b) {
 // Eq. 3-4 multiplied through by sqrt(a^2 + b^2): the only FP64 step of the
 // per-candidate path.  Closed boundary.  nrm = line_norm(a, b), computed once
 // per query; the decision is the same bit for bit as with the norm inline.
+__device__ __forceinline__ bool within_tolerance_d(double a, double b, double c, double nrm,
+                                                   double x, double y, double e) {
+  const double num = fabs(__dadd_rn(__dadd_rn(__dmul_rn(a, x), __dmul_rn(b, y)), c));
+  return num <= __dmul_rn(e, nrm);
+}
+
+// (x, y, eps) are FP32 inputs widened exactly.
 __device__ __forceinline__ bool within_tolerance_n(double a, double b, double c, double nrm,
                                                    float xf, float yf, float ef) {
-  const double num =
-      fabs(__dadd_rn(__dadd_rn(__dmul_rn(a, (double)xf), __dmul_rn(b, (double)yf)), c));
-  return num <= __dmul_rn((double)ef, nrm);
+  return within_tolerance_d(a, b, c, nrm, (double)xf, (double)yf, (double)ef);
 }
 
 __device__ __forceinline__ bool within_tolerance(double a, double b, double c, float xf,

@@ -552,7 +552,9 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         for (int k = 0; k < 32; ++k) qreg[k] = mine ? qrow[k] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       Top2 best;
-      if (fusable && total_len > 0) {
+      // tiles whose rows are all long (or empty) stage no descriptor rows
+      const bool any_mine = __syncthreads_or(mine) != 0;
+      if (fusable && total_len > 0 && any_mine) {
         pre = fuse_fetch(A, 0, total_len, kb, local_j, sJ, slot_b, slot_pref, tid);
         for (int64_t c0 = 0; c0 < total_len; c0 += kFuseRows) {
           const int nr = (int)(total_len - c0 < kFuseRows ? total_len - c0 : kFuseRows);

@@ -37,24 +37,30 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kSlabWords = 1024;                         // bitmap words per slab
 constexpr int64_t kSlabBits = (int64_t)kSlabWords * 64;  // j values per slab
-constexpr int kL = 64;                                   // window entries per chunk
+constexpr int kSC = kThreads;                            // window entries per super-chunk
+constexpr int kL = 64;                                   // rows per block
+constexpr int kSub = kSC / kL;                           // blocks per super-chunk
 constexpr int kRS = 256 + 16;  // LDS bytes per BF16 row: fragment reads of 16 rows hit distinct banks
-constexpr int kPicks = 4;
+constexpr int kQS = 132;       // floats per FP32 query row of the re-rank (rows start 4 banks apart)
+constexpr int kScoreS = kL + 1;
+constexpr int kPicks = 8;      // exactly re-ranked candidates per query
 constexpr int kQPerWave = kTileQ / kWaves;
-static_assert(kL == kWave, "one chunk entry per lane in the CSR step");
+constexpr int kRowPer = kL * 32 / kThreads;  // 16-byte pieces of a block's rows per thread
+constexpr int kScoreBytes = kWaves * kQPerWave * kScoreS * 4;
+static_assert(kL == kWave, "one block row per lane");
+static_assert(kRowPer == 8 && kThreads == 256, "row sums: eight rows per half-wavefront");
+static_assert(kPicks + 1 <= 16, "a query's kept keys are lanes 0 .. kPicks of the first DPP row");
 static_assert(kThreads * 4 == kSlabWords, "four bitmap words per thread in the prefix count");
+static_assert(kTileQ * kQS * 4 <= kL * kRS + kScoreBytes, "FP32 query rows fit the row area");
+static_assert(kTileQ * kPicks * 4 <= kSlabWords * 12, "exact distances fit the bitmap area");
 
-// FP32 -> BF16, round to nearest even (finite inputs).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void store_bf16x4(uint8_t* dst, const float4& v) {
-  uint2 w;
-  w.x = bf16_bits(v.x) | (bf16_bits(v.y) << 16);
-  w.y = bf16_bits(v.z) | (bf16_bits(v.w) << 16);
-  *reinterpret_cast<uint2*>(dst) = w;
+// Two FP32 values rounded to BF16 (round to nearest even), packed low first.
+__device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) {
+  const bf16x2_t b = __builtin_convertvector((float2_t){lo, hi}, bf16x2_t);
+  return __builtin_bit_cast(uint32_t, b);
 }
 
 // Position of the k-th set bit (k from 0) of w, which has more than k bits set.
@@ -74,66 +80,156 @@ __device__ __forceinline__ int select_bit(uint64_t w, uint32_t k) {
   return pos;
 }
 
-__device__ __forceinline__ double wave_max_f64(double v) {
-  #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Five smallest keys (ascending) with their image-2 indices.
-struct Top5 {
-  float k[kPicks + 1];
-  int32_t j[kPicks + 1];
-  __device__ __forceinline__ void init() {
-    #pragma unroll
-    for (int u = 0; u <= kPicks; ++u) {
-      k[u] = __builtin_inff();
-      j[u] = -1;
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Value of the next lower lane within each row of 16 lanes (DPP row_shr:1;
+// lane 0 of a row keeps its own value).
+__device__ __forceinline__ int32_t row_shift_up(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float row_shift_up(float v) {
+  return __int_as_float(row_shift_up(__float_as_int(v)));
+}
+
+// 64 FP32 rows (row r = piece f >> 5 of this thread, f = tid + kThreads u),
+// loaded ahead of their use.
+struct Rows {
+  float4 v[kRowPer];
+};
+
+__device__ __forceinline__ Rows fetch_rows(const float* __restrict__ desc, const int64_t* row_of,
+                                           int tid) {
+  Rows R;
+  #pragma unroll
+  for (int u = 0; u < kRowPer; ++u) {
+    const int f = tid + u * kThreads;
+    const int64_t row = row_of[f >> 5];
+    R.v[u] = row >= 0 ? reinterpret_cast<const float4*>(desc)[row * 32 + (f & 31)]
+                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  return R;
+}
+
+// The same for the tile's queries: rows q_i[q] of the queries set in mask.
+__device__ __forceinline__ Rows fetch_query_rows(const float* __restrict__ desc,
+                                                 const int64_t* q_i, uint64_t mask, int tid) {
+  Rows R;
+  #pragma unroll
+  for (int u = 0; u < kRowPer; ++u) {
+    const int f = tid + u * kThreads, q = f >> 5;
+    R.v[u] = (mask >> q) & 1ull ? reinterpret_cast<const float4*>(desc)[q_i[q] * 32 + (f & 31)]
+                                : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  return R;
+}
+
+// Stores the BF16 copies of 64 rows (stride kRS) and, per row, the squared
+// norm of the BF16 row and the squared norm of its rounding error, summed
+// over the 32 lanes that hold the row's pieces by a transposing butterfly
+// (each step halves the rows a lane keeps); optionally the running maxima of
+// the bound terms sqrt(norm) and sqrt(error), slightly inflated, as float bits.
+__device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* nrm, float* err,
+                                           uint32_t* max_nb, uint32_t* max_db, int tid) {
+  float sn[kRowPer], se[kRowPer];
+  #pragma unroll
+  for (int u = 0; u < kRowPer; ++u) {
+    const int f = tid + u * kThreads, r = f >> 5, c = f & 31;
+    const float4 x = R.v[u];
+    uint2 w;
+    w.x = bf16_pack(x.x, x.y);
+    w.y = bf16_pack(x.z, x.w);
+    *reinterpret_cast<uint2*>(dst + r * kRS + c * 8) = w;
+    const float y0 = __uint_as_float(w.x << 16), y1 = __uint_as_float(w.x & 0xFFFF0000u),
+                y2 = __uint_as_float(w.y << 16), y3 = __uint_as_float(w.y & 0xFFFF0000u);
+    // x - y is exact in FP32 (y is x rounded to fewer bits)
+    const float e0 = x.x - y0, e1 = x.y - y1, e2 = x.z - y2, e3 = x.w - y3;
+    sn[u] = y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3;
+    se[u] = e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+  }
+  const int lane = lane_id();
+  const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  float tn[4], te[4];
+  #pragma unroll
+  for (int v = 0; v < 4; ++v) {  // keep rows 4 b4 + v
+    tn[v] = (b4 ? sn[4 + v] : sn[v]) + __shfl_xor(b4 ? sn[v] : sn[4 + v], 16);
+    te[v] = (b4 ? se[4 + v] : se[v]) + __shfl_xor(b4 ? se[v] : se[4 + v], 16);
+  }
+  float un[2], ue[2];
+  #pragma unroll
+  for (int v = 0; v < 2; ++v) {  // keep rows 4 b4 + 2 b3 + v
+    un[v] = (b3 ? tn[2 + v] : tn[v]) + __shfl_xor(b3 ? tn[v] : tn[2 + v], 8);
+    ue[v] = (b3 ? te[2 + v] : te[v]) + __shfl_xor(b3 ? te[v] : te[2 + v], 8);
+  }
+  float vn = (b2 ? un[1] : un[0]) + __shfl_xor(b2 ? un[0] : un[1], 4);
+  float ve = (b2 ? ue[1] : ue[0]) + __shfl_xor(b2 ? ue[0] : ue[1], 4);
+  vn += __shfl_xor(vn, 2);
+  ve += __shfl_xor(ve, 2);
+  vn += __shfl_xor(vn, 1);
+  ve += __shfl_xor(ve, 1);
+  if ((lane & 3) == 0) {
+    const int r = (tid >> 5) + 8 * (4 * b4 + 2 * b3 + b2);
+    nrm[r] = vn;
+    if (err) err[r] = ve;
+    if (max_nb) {
+      // relative slack 2e-5 covers the FP32 sums (at most 2^-24 per term)
+      const float nb = (float)(sqrt((double)vn) * (1.0 + 2e-5));
+      const float db = (float)(sqrt((double)ve) * (1.0 + 2e-5) + 1e-30);
+      atomicMax(max_nb, __float_as_uint(nb));
+      atomicMax(max_db, __float_as_uint(db));
     }
   }
-  __device__ __forceinline__ void insert(float d, int32_t jj) {
-    if (!(d < k[kPicks])) return;
-    #pragma unroll
-    for (int u = 0; u <= kPicks; ++u) {
-      if (d < k[u]) {
-        const float td = k[u];
-        const int32_t tj = j[u];
-        k[u] = d;
-        j[u] = jj;
-        d = td;
-        jj = tj;
-      }
-    }
-  }
+}
+
+// One window entry in ascending j: its image-2 index and record.
+struct Entry {
+  int32_t j;
+  uint32_t C, H;
+  float2 xy;
+  float e;
 };
 
 template <bool MATCH>
 __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
-  __shared__ unsigned long long bits[kSlabWords];
-  __shared__ uint32_t wpref[kSlabWords];
+  // bitmap slab and word prefix; after the window sweep the picks live here
+  __shared__ __attribute__((aligned(16))) unsigned char slab_raw[kSlabWords * 12];
+  unsigned long long* bits = reinterpret_cast<unsigned long long*>(slab_raw);
+  uint32_t* wpref = reinterpret_cast<uint32_t*>(slab_raw + kSlabWords * 8);
   __shared__ uint32_t wsum[kWaves], n_entries;
-  __shared__ int32_t lj[kL];
-  __shared__ uint32_t lC[kL], lH[kL];
-  __shared__ float2 lXY[kL];
-  __shared__ float lE[kL];
-  __shared__ uint64_t lmask[kL];
+  // one super-chunk of window entries
+  __shared__ int32_t lj[kSC];
+  __shared__ uint32_t lC[kSC], lH[kSC];
+  __shared__ float2 lXY[kSC];
+  __shared__ float lE[kSC];
   __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ], qn[kTileQ];
-  __shared__ uint32_t qk[kTileQ], q_run[kTileQ];
+  __shared__ uint32_t qk[kTileQ];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint64_t wide_mask_s;
   // matching only
   constexpr int kQ = MATCH ? kTileQ : 1;
-  constexpr int kW = MATCH ? kL : 1;
+  constexpr int kRaw = MATCH ? kL * kRS + kScoreBytes : 16;
   __shared__ __attribute__((aligned(16))) uint8_t qrows[kQ * kRS];
-  __shared__ __attribute__((aligned(16))) uint8_t wrows[kW * kRS];
-  __shared__ float w_norm[kW], q_norm[kQ];
-  __shared__ double q_nb[kQ], q_db[kQ];
-  __shared__ double w_nbmax, w_dbmax;  // largest row terms of the bound over the window
-  __shared__ float pk[kQ][kPicks + 1];
-  __shared__ int32_t pj[kQ][kPicks];
-  __shared__ float pdist[kQ][kPicks];
+  // block rows and per-wavefront scores, then the FP32 query rows
+  __shared__ __attribute__((aligned(16))) uint8_t raw[kRaw];
+  __shared__ int64_t row_of[MATCH ? kSC : 1];  // global image-2 row of each entry, -1 past the end
+  __shared__ float w_norm[MATCH ? kL : 1];
+  __shared__ float q_norm[kQ], q_err[kQ];
+  __shared__ uint32_t q_run[kTileQ];  // CSR write position of every query
+  __shared__ float q_thr[kQ];         // largest kept key: the admission threshold of the list
+  __shared__ uint32_t max_nb, max_db;  // float bits of the largest window row terms
   __shared__ uint32_t n_cert, n_fallback;
+  // per query the kPicks + 1 smallest keys so far, ascending, with their j
+  constexpr int kK = kPicks + 1;
+  __shared__ float tkl[kQ * kK];
+  __shared__ int32_t tjl[kQ * kK];
 
   const int tile = xcd_tile(blockIdx.x, A.num_tiles);
   if (A.tile_wide[tile] == 0u) return;
@@ -164,6 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     q_i[lane] = i;
     q_o0[lane] = o0;
     q_run[lane] = 0u;
+    if (MATCH) q_thr[lane] = __builtin_inff();
     const uint64_t wm = ballot(wide);
     const TileWindow* W = A.windows + tile;
     slot_b[lane] = W->slot_b[lane];
@@ -172,8 +269,8 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
       slot_pref[kSlots] = W->slot_pref[kSlots];
       wide_mask_s = wm;
       if (MATCH) {
-        w_nbmax = 0.0;
-        w_dbmax = 0.0;
+        max_nb = 0u;
+        max_db = 0u;
         n_cert = 0u;
         n_fallback = 0u;
       }
@@ -181,30 +278,21 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   }
   __syncthreads();
   const uint64_t wide_mask = wide_mask_s;
-  // lane = query in the entry tests
-  const double my_a = qa[lane], my_b = qb[lane], my_c = qc[lane], my_n = qn[lane];
-  const uint32_t my_k = qk[lane];
-  const bool my_wide = (wide_mask >> lane) & 1ull;
+  const int q0 = wave * kQPerWave;  // this wavefront's queries
+  const uint32_t wmask = (uint32_t)(wide_mask >> q0) & 0xFFFFu;
 
-  Top5 best[4];  // this lane's four queries of the MFMA layout
   if (MATCH) {
-    #pragma unroll
-    for (int i = 0; i < 4; ++i) best[i].init();
+    for (int t = tid; t < kTileQ * kK; t += kThreads) {
+      tkl[t] = __builtin_inff();
+      tjl[t] = -1;
+    }
+  }
+  uint8_t* wrows = raw;
+  float* score = reinterpret_cast<float*>(raw + kL * kRS) + wave * kQPerWave * kScoreS;
+  if (MATCH) {
     // BF16 query rows (zero rows for the queries that are not wide)
-    for (int f = tid; f < kTileQ * 32; f += kThreads) {
-      const int q = f >> 5, c = f & 31;
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if ((wide_mask >> q) & 1ull) v = reinterpret_cast<const float4*>(A.desc1)[q_i[q] * 32 + c];
-      store_bf16x4(qrows + q * kRS + c * 8, v);
-    }
-    __syncthreads();
-    if (tid < kTileQ) {
-      const float n = row_sqnorm<0>(qrows + tid * kRS);
-      q_norm[tid] = n;
-      const double nb = sqrt((double)n) * (1.0 + 1e-5);
-      q_nb[tid] = nb;
-      q_db[tid] = row_delta<0>(nb, 1.0);
-    }
+    stage_bf16(fetch_query_rows(A.desc1, q_i, wide_mask, tid), qrows, q_norm, q_err, nullptr,
+               nullptr, tid);
   }
 
   const int64_t total_len = slot_pref[kSlots];
@@ -215,14 +303,24 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     const int nwords = (int)((jn + 63) >> 6);
     for (int w = tid; w < kSlabWords; w += kThreads) bits[w] = 0ull;
     __syncthreads();
-    // mark the window's j that fall in this slab
-    for (int64_t v = tid; v < total_len; v += kThreads) {
-      int s = 0;  // last slot with slot_pref[s] <= v
+    // mark the window's j that fall in this slab (four loads in flight per thread)
+    for (int64_t v0 = tid; v0 < total_len; v0 += 4 * kThreads) {
+      int64_t jj[4];
       #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (s + step <= kSlots && slot_pref[s + step] <= v) s += step;
-      const int64_t j = (int64_t)A.rj[slot_b[s] + (v - slot_pref[s])] - j0;
-      if (j >= 0 && j < jn) atomicOr(&bits[j >> 6], 1ull << (j & 63));
+      for (int u = 0; u < 4; ++u) {
+        const int64_t v = v0 + u * kThreads;
+        jj[u] = -1;
+        if (v < total_len) {
+          int s = 0;  // last slot with slot_pref[s] <= v
+          #pragma unroll
+          for (int step = 32; step > 0; step >>= 1)
+            if (s + step <= kSlots && slot_pref[s + step] <= v) s += step;
+          jj[u] = (int64_t)A.rj[slot_b[s] + (v - slot_pref[s])] - j0;
+        }
+      }
+      #pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (jj[u] >= 0 && jj[u] < jn) atomicOr(&bits[jj[u] >> 6], 1ull << (jj[u] & 63));
     }
     __syncthreads();
     // exclusive prefix count of the words: thread t owns words 4t .. 4t + 3
@@ -247,162 +345,190 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
         base += w < wave ? wsum[w] : 0u;
         all += wsum[w];
       }
-      uint32_t run = base + incl - tot;
+      uint32_t r = base + incl - tot;
       #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        wpref[tid * 4 + u] = run;
-        run += c[u];
+        wpref[tid * 4 + u] = r;
+        r += c[u];
       }
       if (tid == 0) n_entries = all;
     }
     __syncthreads();
     const uint32_t E = n_entries;
 
-    for (uint32_t e0 = 0; e0 < E; e0 += kL) {
-      // the chunk's entries in ascending j, with their records
-      if (tid < kL) {
-        const uint32_t e = e0 + tid;
-        int32_t j = -1;
-        if (e < E) {
-          int w = 0;  // last word with wpref[w] <= e (it holds entry e)
+    // entry e of the slab: its j, then its record (the loads stay in flight
+    // until the entry is stored)
+    auto entry_j = [&](uint32_t e) -> int32_t {
+      if (e >= E) return -1;
+      int w = 0;  // last word with wpref[w] <= e (it holds entry e)
+      #pragma unroll
+      for (int step = kSlabWords / 2; step > 0; step >>= 1)
+        if (w + step < nwords && wpref[w + step] <= e) w += step;
+      return (int32_t)(j0 + ((int64_t)w << 6) + select_bit(bits[w], e - wpref[w]));
+    };
+    auto load_entry = [&](int32_t j) -> Entry {
+      Entry en;
+      en.j = j;
+      if (j >= 0) {
+        const uint32_t pos = A.rinv[kb + j];
+        en.C = A.rC[pos];
+        en.H = A.rH[pos];
+        en.xy = A.rxy[pos];
+        en.e = A.reps[pos];
+      }
+      return en;
+    };
+    auto store_entry = [&](const Entry& en) {
+      lj[tid] = en.j;
+      lC[tid] = en.C;
+      lH[tid] = en.H;
+      lXY[tid] = en.xy;
+      lE[tid] = en.e;
+      if (MATCH) row_of[tid] = en.j >= 0 ? kb + en.j : -1;
+    };
+    if (E > 0) store_entry(load_entry(entry_j(tid)));
+    __syncthreads();
+
+    for (uint32_t e0 = 0; e0 < E; e0 += kSC) {
+      Rows pre;
+      if (MATCH) pre = fetch_rows(A.desc2, row_of, tid);  // block 0
+      // the next super-chunk's entry: j now, its record during the blocks
+      const int32_t nj = e0 + kSC < E ? entry_j(e0 + kSC + tid) : -1;
+      Entry nxt;
+      #pragma unroll 1
+      for (int sub = 0; sub < kSub; ++sub) {
+        const int base = sub * kL;
+        if (e0 + base >= E) break;  // uniform
+        float wn = 0.0f;
+        if (MATCH) {
+          stage_bf16(pre, wrows, w_norm, nullptr, &max_nb, &max_db, tid);
+          __syncthreads();  // block rows and norms complete
+          wn = w_norm[lane];
+          if (sub + 1 < kSub && e0 + base + kL < E) pre = fetch_rows(A.desc2, row_of + base + kL, tid);
+          // S = Q W^T: wavefront w owns queries 16w .. 16w + 15 against the 64 rows
+          f32x4 acc[4];
           #pragma unroll
-          for (int step = kSlabWords / 2; step > 0; step >>= 1)
-            if (w + step < nwords && wpref[w + step] <= e) w += step;
-          j = (int32_t)(j0 + ((int64_t)w << 6) + select_bit(bits[w], e - wpref[w]));
-          const uint32_t pos = A.rinv[kb + j];
-          lC[tid] = A.rC[pos];
-          lH[tid] = A.rH[pos];
-          lXY[tid] = A.rxy[pos];
-          lE[tid] = A.reps[pos];
-        }
-        lj[tid] = j;
-      }
-      __syncthreads();
-      if (MATCH) {
-        // BF16 copies of the entries' FP32 rows (zero rows past the end)
-        for (int f = tid; f < kL * 32; f += kThreads) {
-          const int r = f >> 5, c = f & 31;
-          const int32_t j = lj[r];
-          float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          if (j >= 0) v = reinterpret_cast<const float4*>(A.desc2)[(kb + j) * 32 + c];
-          store_bf16x4(wrows + r * kRS + c * 8, v);
-        }
-      }
-      // 1. entry masks: wavefront w tests entries w, w + 4, ... (lane = query)
-      for (int r = wave; r < kL; r += kWaves) {
-        bool hit = false;
-        if (my_wide && lj[r] >= 0 && key_distance(my_k, lC[r]) <= lH[r]) {
-          const float2 xy = lXY[r];
-          hit = within_tolerance_n(my_a, my_b, my_c, my_n, xy.x, xy.y, lE[r]);
-        }
-        const uint64_t m = ballot(hit);
-        if (lane == 0) lmask[r] = m;
-      }
-      __syncthreads();
-      // 2. CSR rows: wavefront w appends the hits of its queries (lane = entry)
-      {
-        const uint64_t em = lmask[lane];
-        const int32_t ej = lj[lane];
-        for (int qq = 0; qq < kQPerWave; ++qq) {
-          const int q = wave * kQPerWave + qq;
-          if (!((wide_mask >> q) & 1ull)) continue;
-          const bool hit = (em >> q) & 1ull;
-          const uint64_t b = ballot(hit);
-          const uint32_t run = q_run[q];
-          if (hit) {
-            const int64_t dst = q_o0[q] + run + lanes_below(b);
-            if (dst < A.capacity) A.cols[dst] = ej;
+          for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+          const int arow = q0 + (lane & 15);
+          #pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * kRS + koff * 2);
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                  wrows + (cb * 16 + (lane & 15)) * kRS + koff * 2);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+            }
           }
-          if (lane == 0) q_run[q] = run + (uint32_t)__popcll(b);
-        }
-      }
-      if (MATCH) {
-        if (tid < kL) {
-          // norms of the staged rows; running maxima of their bound terms
-          float n = 0.0f;
-          double nb = 0.0, db = 0.0;
-          if (lj[tid] >= 0) {
-            n = row_sqnorm<0>(wrows + tid * kRS);
-            nb = sqrt((double)n) * (1.0 + 1e-5);
-            db = row_delta<0>(nb, 1.0);
-          }
-          w_norm[tid] = n;
-          nb = wave_max_f64(nb);
-          db = wave_max_f64(db);
-          if (tid == 0) {
-            w_nbmax = fmax(w_nbmax, nb);
-            w_dbmax = fmax(w_dbmax, db);
-          }
-        }
-        // 3. S = Q W^T: wavefront w owns queries 16w .. 16w + 15 against all 64 rows
-        f32x4 acc[4];
-        #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-        const int arow = wave * 16 + (lane & 15);
-        #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * kRS + koff * 2);
           #pragma unroll
           for (int cb = 0; cb < 4; ++cb) {
-            const bf16x8 b =
-                *reinterpret_cast<const bf16x8*>(wrows + (cb * 16 + (lane & 15)) * kRS + koff * 2);
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+            #pragma unroll
+            for (int i = 0; i < 4; ++i)
+              score[((lane >> 4) * 4 + i) * kScoreS + cb * 16 + (lane & 15)] = acc[cb][i];
           }
+          __syncthreads();  // every wavefront has read the block rows
         }
-        __syncthreads();  // w_norm complete
-        #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const int r = cb * 16 + (lane & 15);
-          const uint64_t m = lmask[r];
-          const float wn = w_norm[r];
-          const int32_t j = lj[r];
-          #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int q = wave * 16 + (lane >> 4) * 4 + i;
-            if ((m >> q) & 1ull) best[i].insert(__builtin_fmaf(-2.0f, acc[cb][i], wn), j);
+        if (sub == 0 && nj >= 0) nxt = load_entry(nj);
+        // this lane's row of the block
+        const int32_t ej = lj[base + lane];
+        const uint32_t eC = lC[base + lane], eH = lH[base + lane];
+        const float2 exy = lXY[base + lane];
+        const double ex = (double)exy.x, ey = (double)exy.y, ee = (double)lE[base + lane];
+        // every query of the wavefront against the block: one ballot gives
+        // the query's hits, which extend its CSR row and feed its selection
+        #pragma unroll 1
+        for (int qq = 0; qq < kQPerWave; ++qq) {
+          if (!((wmask >> qq) & 1u)) continue;
+          const int q = q0 + qq;
+          bool hit = false;
+          if (ej >= 0 && key_distance(qk[q], eC) <= eH)
+            hit = within_tolerance_d(qa[q], qb[q], qc[q], qn[q], ex, ey, ee);
+          const uint64_t m = ballot(hit);
+          const uint32_t run = q_run[q];
+          if (hit) {
+            const int64_t dst = q_o0[q] + run + lanes_below(m);
+            if (dst < A.capacity) A.cols[dst] = ej;
           }
+          if (lane == 0) q_run[q] = run + (uint32_t)__popcll(m);
+          if (MATCH) {
+            // keys |w^|^2 - 2 q^.w^; only hits below the kept (kPicks+1)-th key enter
+            const float kf = __builtin_fmaf(-2.0f, score[qq * kScoreS + lane], wn);
+            const float th0 = q_thr[q];
+            uint64_t surv = ballot(hit && kf < th0);
+            if (surv) {
+              // the list in lanes 0 .. kPicks while the survivors enter it
+              const bool in = lane < kK;
+              float lk = in ? tkl[q * kK + lane] : __builtin_inff();
+              int32_t lji = in ? tjl[q * kK + lane] : -1;
+              float th = th0;
+              do {
+                const int sl = __builtin_ctzll(surv);
+                surv &= surv - 1;
+                const float ks = readlane_f(kf, sl);
+                if (!(ks < th)) continue;
+                const int32_t js = __builtin_amdgcn_readlane(ej, sl);
+                // the new key goes after the kept keys that are <= it; the
+                // ones above move up one lane
+                const int pos = __popcll(ballot(in && lk <= ks));
+                const float up_k = row_shift_up(lk);
+                const int32_t up_j = row_shift_up(lji);
+                if (lane == pos) {
+                  lk = ks;
+                  lji = js;
+                } else if (lane > pos) {
+                  lk = up_k;
+                  lji = up_j;
+                }
+                th = readlane_f(lk, kPicks);
+              } while (surv);
+              if (in) {
+                tkl[q * kK + lane] = lk;
+                tjl[q * kK + lane] = lji;
+              }
+              if (lane == 0) q_thr[q] = th;
+            }
+          }
+          wave_lds_sync();
         }
       }
-      __syncthreads();  // the chunk's LDS is dead
+      __syncthreads();  // the super-chunk's entries are dead
+      if (nj >= 0 || e0 + kSC < E) {
+        if (nj < 0) nxt.j = -1;
+        store_entry(nxt);
+      }
+      __syncthreads();
     }
   }
 
   if (!MATCH) return;
-  // merge the five smallest keys over the 16 lanes that share each query
-  #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  // the picks are the first kPicks of every list; the row area holds the
+  // FP32 query rows now, the bitmap area the exact distances
+  const float* pk = tkl;
+  const int32_t* pj = tjl;
+  float* pdist = reinterpret_cast<float*>(slab_raw);  // [kTileQ][kPicks]
+  float* qf = reinterpret_cast<float*>(raw);          // [kTileQ][kQS]
+  {
+    const Rows R = fetch_query_rows(A.desc1, q_i, wide_mask, tid);
     #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      float ok[kPicks + 1];
-      int32_t oj[kPicks + 1];
-      #pragma unroll
-      for (int u = 0; u <= kPicks; ++u) {
-        ok[u] = __shfl_xor(best[i].k[u], off);
-        oj[u] = __shfl_xor(best[i].j[u], off);
-      }
-      #pragma unroll
-      for (int u = 0; u <= kPicks; ++u) best[i].insert(ok[u], oj[u]);
-    }
-    if ((lane & 15) == 0) {
-      const int q = wave * 16 + (lane >> 4) * 4 + i;
-      #pragma unroll
-      for (int u = 0; u < kPicks; ++u) {
-        pk[q][u] = best[i].k[u];
-        pj[q][u] = best[i].j[u];
-      }
-      pk[q][kPicks] = best[i].k[kPicks];
+    for (int u = 0; u < kRowPer; ++u) {
+      const int f = tid + u * kThreads;
+      reinterpret_cast<float4*>(qf + (f >> 5) * kQS)[f & 31] = R.v[u];
     }
   }
   __syncthreads();
-  // exact canonical distances of the picks: thread = (query, pick)
+  // exact canonical distances of the picks: thread = (query, picks sp, sp + 4, ...)
   {
-    const int q = tid >> 2, u = tid & 3;
-    float d = __builtin_inff();
-    if (((wide_mask >> q) & 1ull) && pj[q][u] >= 0)
-      d = exact_distance(reinterpret_cast<const float4*>(A.desc1) + q_i[q] * 32,
-                         reinterpret_cast<const float4*>(A.desc2) + (kb + pj[q][u]) * 32);
-    pdist[q][u] = d;
+    const int sq = tid >> 2, sp = tid & 3;
+    #pragma unroll
+    for (int u = sp; u < kPicks; u += 4) {
+      float d = __builtin_inff();
+      const int32_t j = pj[sq * kK + u];
+      if (((wide_mask >> sq) & 1ull) && j >= 0)
+        d = exact_distance(reinterpret_cast<const float4*>(qf + sq * kQS),
+                           reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32);
+      pdist[sq * kPicks + u] = d;
+    }
   }
   __syncthreads();
   if (tid < kTileQ && ((wide_mask >> tid) & 1ull)) {
@@ -410,13 +536,16 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     Top2 t;
     #pragma unroll
     for (int u = 0; u < kPicks; ++u)
-      if (pj[q][u] >= 0) t.insert(pdist[q][u], pj[q][u]);
-    // every other hit has a key >= the fifth key: its exact distance is at
-    // least the bound of the smallest such approximate distance, taken with
+      if (pj[q * kK + u] >= 0) t.insert(pdist[q * kPicks + u], pj[q * kK + u]);
+    // every other hit has a key >= the (kPicks+1)-th key: its exact distance
+    // is at least the bound of the smallest such approximate distance, with
     // the largest row terms of the window and a slack for the key's rounding
-    const double nw = w_nbmax, s = q_nb[q] + nw;
-    const double dt = (double)q_norm[q] + (double)pk[q][kPicks] - 1e-6 * s * s;
-    const double lb = lower_bound(dt, q_nb[q], nw, q_db[q], w_dbmax);
+    const double qnb = sqrt((double)q_norm[q]) * (1.0 + 2e-5);
+    const double qdb = sqrt((double)q_err[q]) * (1.0 + 2e-5) + 1e-30;
+    const double nw = (double)__uint_as_float(max_nb), dw = (double)__uint_as_float(max_db);
+    const double s = qnb + nw;
+    const double dt = (double)q_norm[q] + (double)pk[q * kK + kPicks] - 1e-6 * s * s;
+    const double lb = lower_bound(dt, qnb, nw, qdb, dw);
     if (lb > (double)t.sd) {
       write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, q_i[q], t, false);
       atomicAdd(&n_cert, 1u);
@@ -428,9 +557,8 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   }
   if (A.match_stats) {
     __syncthreads();
-    if (tid == 0) {
-      if (n_cert + n_fallback)
-        atomicAdd(&A.match_stats[0], (unsigned long long)(n_cert + n_fallback));
+    if (tid == 0 && n_cert + n_fallback) {
+      atomicAdd(&A.match_stats[0], (unsigned long long)(n_cert + n_fallback));
       if (n_fallback) atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
     }
   }
