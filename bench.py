@@ -16,7 +16,8 @@ fused into the stabbing pass); `separate_calls` is the same step through
 epm_query_candidates + epm_match, `graph` the step recorded as one HIP graph
 (autotuned tile schedule), and `plain_gpu` the plain path (one pipeline per
 pair, host-synchronised CSR sizing, gather-based matching).  Other workloads:
---workload precision | batch | learned.
+--workload precision | batch | learned | paper (the tolerances of the paper's
+experiments: 50000 keypoints per image, eps 25 / 50 / 100 px).
 """
 
 import argparse
@@ -49,9 +50,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "precision", "batch", "learned"],
+                    choices=["scale", "precision", "batch", "learned", "paper"],
                     help="scale: six 20000-keypoint pairs (default); precision: one "
-                         "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs")
+                         "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs; "
+                         "paper: six 50000-keypoint pairs at eps 25/50/100 px")
     ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
     ap.add_argument("--train-pairs", type=int, default=2000,
                     help="learned workload: training pairs")
@@ -446,6 +448,154 @@ def learned_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def paper_workload(args):
+    """The tolerances of the paper's experiments (tens of pixels, so every
+    query keeps hundreds to thousands of candidates): 6048x4032 pairs with
+    50000 keypoints per image, sideways and forward motion, each at eps = 25,
+    50 and 100 px, one batch of six pairs per step (300000 queries) through
+    epm_build_intervals + epm_query_match.  The dominant kernel is the
+    wide-row pass (rows of more than 128 candidates: CSR written in ascending
+    j from a bitmap of the tile window, FP32 matches through a BF16 MFMA bound
+    with a certified re-rank)."""
+    import torch
+
+    import oracle
+    import paper_2603_18401_amd as E
+    import synth
+
+    dev = torch.device("cuda:0")
+    pairs, eps_list = [], []
+    for motion in ("sideways", "forward"):
+        base = synth.cfg1_pair(motion, n_kp=50000)
+        for eps in (25.0, 50.0, 100.0):
+            pairs.append(base)
+            eps_list.append(eps)
+    P = len(pairs)
+    m = np.array([p.m for p in pairs])
+    n = np.array([p.n for p in pairs])
+    N1, N2 = int(m.sum()), int(n.sum())
+    host = dict(kp1=np.concatenate([p.kp1 for p in pairs]),
+                kp2=np.concatenate([p.kp2 for p in pairs]),
+                eps2=np.concatenate([np.full(p.n, e, np.float32) for p, e in zip(pairs, eps_list)]),
+                d1=np.concatenate([p.desc1 for p in pairs]),
+                d2=np.concatenate([p.desc2 for p in pairs]))
+    g = {k: torch.from_numpy(v).to(dev) for k, v in host.items()}
+    specs = [E.PairSpec(p.F, p.W, p.H, p.m, p.n) for p in pairs]
+    idx0 = E.Index(specs, g["kp2"], eps2=g["eps2"])
+    ws = idx0.workspace
+    offs, _ = idx0.query(g["kp1"])
+    nnz = int(offs[-1].item())
+    idx0.close()
+    row_offsets = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    col_indices = torch.empty(nnz, dtype=torch.int32, device=dev)
+    outs = tuple(torch.empty(N1, dtype=t, device=dev)
+                 for t in (torch.int32, torch.float32, torch.float32))
+    holder = {}
+
+    def step(ev=None):
+        idx = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
+        if ev is not None:
+            idx.set_timing_events(*ev, kernel="wide")
+        idx.query_match(g["kp1"], g["d1"], g["d2"], row_offsets=row_offsets,
+                        col_indices=col_indices, out=outs, sync=False)
+        holder["idx"] = idx
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    kern_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    mstats = holder["idx"].match_stats()
+    ref_out = [x.clone() for x in outs]
+    assert int(row_offsets[-1].item()) == nnz
+
+    # the same step through epm_query_candidates + epm_match (window kernel)
+    separate = None
+    if not args.no_separate:
+        def sep_step():
+            idx = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
+            idx.query(g["kp1"], row_offsets=row_offsets, col_indices=col_indices, sync=False)
+            idx.match(row_offsets, col_indices, g["d1"], g["d2"], dtype="f32", algo="tiled",
+                      out=outs)
+        ssec = time_steps(torch, sep_step, max(1, args.steps // 4), 1)
+        same = all(torch.equal(a, r) for a, r in zip(outs, ref_out))
+        separate = {"value": round(N1 / ssec, 1), "ms_per_step": round(ssec * 1e3, 4),
+                    "identical_matches": bool(same)}
+
+    plain = None
+    if not args.no_plain:
+        per = []
+        for p_i in range(P):
+            sl1 = slice(int(m[:p_i].sum()), int(m[:p_i + 1].sum()))
+            sl2 = slice(int(n[:p_i].sum()), int(n[:p_i + 1].sum()))
+            per.append(dict(spec=[specs[p_i]], kp1=g["kp1"][sl1].contiguous(),
+                            kp2=g["kp2"][sl2].contiguous(), d1=g["d1"][sl1].contiguous(),
+                            d2=g["d2"][sl2].contiguous(), eps=eps_list[p_i]))
+
+        def plain_step():
+            for q in per:
+                idx = E.Index(q["spec"], q["kp2"], eps=q["eps"])
+                o, c = idx.query(q["kp1"])
+                idx.match(o, c, q["d1"], q["d2"], dtype="f32", algo="plain")
+                idx.close()
+
+        psec = time_steps(torch, plain_step, max(1, args.steps // 4), 1)
+        plain = {"value": round(N1 / psec, 1), "ms_per_step": round(psec * 1e3, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        s = min(args.cpu_sample, 50000)
+        t0 = time.perf_counter()
+        done = 0
+        for p_i, p in enumerate(pairs):
+            ro, rc, _ = oracle.candidates(p.F, p.kp1[:s], p.kp2, eps_list[p_i], nthreads=threads)
+            oracle.match(p.desc1[:s], p.desc2, ro, rc, nthreads=threads)
+            done += min(s, p.m)
+        cel = time.perf_counter() - t0
+        cpu = {"value": round(done / cel, 1), "unit": "queries/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {s} queries of each of the {P} pairs against all 50000 "
+                         f"keypoints ({done} queries, brute-force FP64 candidates + FP32 "
+                         f"matching, {cel:.1f} s)"}
+
+    # wide-row kernel: algorithmic bytes of one launch = the wide queries'
+    # keypoints, descriptors, row lengths and matches, the image-2 keypoints,
+    # tolerances, descriptors and records, and the CSR columns it writes
+    nw = int(mstats["reranked_rows"])
+    kernel_bytes = nw * (8 + 512 + 8 + 12) + N2 * (8 + 4 + 512 + 24) + 4 * nnz
+    achieved = kernel_bytes / (kern_ms * 1e-3) / 1e9
+    src = os.path.join(CSRC, "wide.hip")
+    line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64+f32+bf16", "data": "synthetic",
+            "config": {"workload": "paper regime: 6 pairs 6048x4032, 50000 keypoints/image, "
+                                   "sideways+forward motion x eps {25,50,100} px (300000 "
+                                   "queries per step), FP32 descriptors",
+                       "queries_per_step": N1, "candidates_per_step": nnz,
+                       "kbar": round(nnz / N1, 2), "wide_rows": nw},
+            "roofline": {"bound": "hbm", "kernel": "k_wide_tile<true> (wide rows: CSR + "
+                                                   "FP32 selection)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(src, os.path.join(
+                             ROOT, "profiles", "wide_tile_traffic.md")),
+                         "avg_launch_ms": round(kern_ms, 5),
+                         "algorithmic_bytes_per_launch": int(kernel_bytes),
+                         "kernel_source_sha256": source_hash(src)},
+            "match_stats": mstats,
+            "cpu_baseline": cpu, "plain_gpu": plain, "separate_calls": separate}
+    if plain:
+        line["speedup_vs_plain"] = round(plain["ms_per_step"] / (sec * 1e3), 3)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -459,6 +609,8 @@ def main():
         return batch_workload(args)
     if args.workload == "learned":
         return learned_workload(args)
+    if args.workload == "paper":
+        return paper_workload(args)
 
     import torch
 

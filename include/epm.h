@@ -256,6 +256,14 @@ typedef struct {
  * EPM_ERR_ARG (idx NULL, or only one event given). */
 epm_status epm_index_set_timing_events(epm_index* idx, hipEvent_t start, hipEvent_t stop);
 
+/* Which kernel of epm_query_candidates / epm_query_match the timing events
+ * bracket: the stabbing-tile kernel (the default) or the wide-row kernel
+ * that writes (and, in epm_query_match, matches) the rows with more than 128
+ * candidates -- the dominant kernel at tolerances of tens of pixels.
+ * Host only.  Errors: EPM_ERR_ARG (idx NULL, unknown kernel). */
+typedef enum { EPM_TIMED_STAB = 0, EPM_TIMED_WIDE = 1 } epm_timed_kernel;
+epm_status epm_index_set_timing_kernel(epm_index* idx, epm_timed_kernel kernel);
+
 /* Sets the work distribution used by later calls on idx (host only).
  * Errors: EPM_ERR_ARG (NULL, negative counts, lpt not 0/1, reserved != 0). */
 epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);

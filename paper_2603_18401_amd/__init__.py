@@ -40,7 +40,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
-           "epm_index_set_timing_events", "epm_quantize"]
+           "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize"]
 
 
 class EpmError(RuntimeError):
@@ -181,6 +181,8 @@ def load_library(path=None):
     lib.epm_query_match.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
     lib.epm_index_set_timing_events.restype = ctypes.c_int
+    lib.epm_index_set_timing_kernel.argtypes = [V, i32]
+    lib.epm_index_set_timing_kernel.restype = ctypes.c_int
     lib.epm_quantize.argtypes = [V, i64, i32, ctypes.c_int, V, V, V]
     lib.epm_quantize.restype = ctypes.c_int
     if path is None:
@@ -352,10 +354,15 @@ class Index:
         _check(self.lib.epm_get_match_stats(self.handle, ctypes.byref(st)), "epm_get_match_stats")
         return {k: int(getattr(st, k)) for k, _ in st._fields_}
 
-    def set_timing_events(self, start=None, stop=None):
+    def set_timing_events(self, start=None, stop=None, kernel=None):
         """Records two torch.cuda.Events (enable_timing=True) around the
         dominant kernel of later query / query_match / match calls; None, None
-        turns it off."""
+        turns it off.  kernel: "stab" (the stabbing-tile kernel of the query
+        calls, the default) or "wide" (their wide-row kernel)."""
+        if kernel is not None:
+            k = {"stab": 0, "wide": 1}[kernel]
+            _check(self.lib.epm_index_set_timing_kernel(self.handle, k),
+                   "epm_index_set_timing_kernel")
         handles = []
         for ev in (start, stop):
             if ev is None:

@@ -236,6 +236,7 @@ struct epm_index {
   hipStream_t match_stream = nullptr;
   epm_sched sched{};         // work distribution of the tile kernels
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // around the dominant kernel of a call
+  epm_timed_kernel timed = EPM_TIMED_STAB;           // which kernel of the query calls
   bool have_order = false;  // the last query wrote the longest-first tile order
 
   template <typename T>
@@ -453,9 +454,10 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
     A.queue = sched + kSchedStabQueue;
     A.order = lpt ? idx->at<uint32_t>(L.order) : nullptr;
   }
-  if (idx->ev_start) EPM_HIP(hipEventRecord(idx->ev_start, stream));
+  const bool timed = idx->ev_start && idx->timed == EPM_TIMED_STAB;
+  if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
   EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, fuse, stream));
-  if (idx->ev_stop) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
+  if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
 }
@@ -466,7 +468,10 @@ epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream,
                         bool match = false) {
   if (idx->N1 == 0) return EPM_OK;
   EPM_HIP(launch_fill_rows(A, stream));
+  const bool timed = idx->ev_start && idx->timed == EPM_TIMED_WIDE;
+  if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
   EPM_HIP(launch_wide_tiles(A, match, stream));
+  if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   return EPM_OK;
 }
 
@@ -694,6 +699,12 @@ epm_status epm_index_set_timing_events(epm_index* idx, hipEvent_t start, hipEven
   if (!idx || (start == nullptr) != (stop == nullptr)) return EPM_ERR_ARG;
   idx->ev_start = start;
   idx->ev_stop = stop;
+  return EPM_OK;
+}
+
+epm_status epm_index_set_timing_kernel(epm_index* idx, epm_timed_kernel kernel) {
+  if (!idx || (kernel != EPM_TIMED_STAB && kernel != EPM_TIMED_WIDE)) return EPM_ERR_ARG;
+  idx->timed = kernel;
   return EPM_OK;
 }
 

@@ -230,3 +230,8 @@ def test_learned_eps_argument_errors(lib):
     pairs[0].F[:] = [0] * 9
     assert lib.epm_eps_features(pairs, 1, V(256), V(256), V(256), V(256), wsp, None) == 2
     assert lib.epm_match_residuals(None, V(256), V(256), V(256), V(256), None, None) == 1
+
+
+def test_timing_kernel_argument_errors(lib):
+    assert lib.epm_index_set_timing_kernel(None, 0) == 1
+    assert lib.epm_index_set_timing_kernel(None, 1) == 1

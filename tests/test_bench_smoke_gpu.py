@@ -57,3 +57,11 @@ def test_learned_workload_line(monkeypatch, capsys):
                                       "--warmup", "0"])
     assert line["training"]["residual_samples"] > 0
     assert len(line["held_out"]["fixed"]) > 3
+
+
+def test_paper_workload_line(monkeypatch, capsys):
+    line = _run(monkeypatch, capsys, ["--workload", "paper", "--steps", "1", "--warmup", "0",
+                                      "--no-plain", "--no-separate", "--cpu-sample", "20"])
+    assert line["roofline"]["kernel"].startswith("k_wide_tile")
+    assert line["config"]["wide_rows"] > 0.9 * line["config"]["queries_per_step"]
+    assert line["cpu_baseline"]["kind"] == "oracle"
