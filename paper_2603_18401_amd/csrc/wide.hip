@@ -90,6 +90,16 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(v), l));
+}
+
 // Value of the next lower lane within each row of 16 lanes (DPP row_shr:1;
 // lane 0 of a row keeps its own value).
 __device__ __forceinline__ int32_t row_shift_up(int32_t v) {
@@ -222,8 +232,6 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   __shared__ int64_t row_of[MATCH ? kSC : 1];  // global image-2 row of each entry, -1 past the end
   __shared__ float w_norm[MATCH ? kL : 1];
   __shared__ float q_norm[kQ], q_err[kQ];
-  __shared__ uint32_t q_run[kTileQ];  // CSR write position of every query
-  __shared__ float q_thr[kQ];         // largest kept key: the admission threshold of the list
   __shared__ uint32_t max_nb, max_db;  // float bits of the largest window row terms
   __shared__ uint32_t n_cert, n_fallback;
   // per query the kPicks + 1 smallest keys so far, ascending, with their j
@@ -259,8 +267,6 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     qk[lane] = key;
     q_i[lane] = i;
     q_o0[lane] = o0;
-    q_run[lane] = 0u;
-    if (MATCH) q_thr[lane] = __builtin_inff();
     const uint64_t wm = ballot(wide);
     const TileWindow* W = A.windows + tile;
     slot_b[lane] = W->slot_b[lane];
@@ -280,6 +286,15 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   const uint64_t wide_mask = wide_mask_s;
   const int q0 = wave * kQPerWave;  // this wavefront's queries
   const uint32_t wmask = (uint32_t)(wide_mask >> q0) & 0xFFFFu;
+  // lane l holds query q0 + (l & 15): its line, key and row start, its CSR
+  // write position and (match) the largest kept key of its list -- read
+  // through readlane, off the LDS
+  const int ql = q0 + (lane & (kQPerWave - 1));
+  const uint32_t qp_k = qk[ql];
+  const double qp_a = qa[ql], qp_b = qb[ql], qp_c = qc[ql], qp_n = qn[ql];
+  const int64_t qp_o0 = q_o0[ql];
+  uint32_t qp_run = 0u;
+  float qp_thr = __builtin_inff();
 
   if (MATCH) {
     for (int t = tid; t < kTileQ * kK; t += kThreads) {
@@ -435,29 +450,37 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
         const uint32_t eC = lC[base + lane], eH = lH[base + lane];
         const float2 exy = lXY[base + lane];
         const double ex = (double)exy.x, ey = (double)exy.y, ee = (double)lE[base + lane];
+        // keys |w^|^2 - 2 q^.w^ of the row for the wavefront's queries
+        float kf[kQPerWave];
+        if (MATCH) {
+          #pragma unroll
+          for (int qq = 0; qq < kQPerWave; ++qq)
+            kf[qq] = __builtin_fmaf(-2.0f, score[qq * kScoreS + lane], wn);
+        }
         // every query of the wavefront against the block: one ballot gives
         // the query's hits, which extend its CSR row and feed its selection
-        #pragma unroll 1
+        #pragma unroll
         for (int qq = 0; qq < kQPerWave; ++qq) {
           if (!((wmask >> qq) & 1u)) continue;
-          const int q = q0 + qq;
           bool hit = false;
-          if (ej >= 0 && key_distance(qk[q], eC) <= eH)
-            hit = within_tolerance_d(qa[q], qb[q], qc[q], qn[q], ex, ey, ee);
+          if (ej >= 0 && key_distance((uint32_t)__builtin_amdgcn_readlane((int)qp_k, qq), eC) <= eH)
+            hit = within_tolerance_d(readlane_d(qp_a, qq), readlane_d(qp_b, qq),
+                                     readlane_d(qp_c, qq), readlane_d(qp_n, qq), ex, ey, ee);
           const uint64_t m = ballot(hit);
-          const uint32_t run = q_run[q];
+          const uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)qp_run, qq);
           if (hit) {
-            const int64_t dst = q_o0[q] + run + lanes_below(m);
+            const int64_t dst =
+                (int64_t)readlane_u64((uint64_t)qp_o0, qq) + run + lanes_below(m);
             if (dst < A.capacity) A.cols[dst] = ej;
           }
-          if (lane == 0) q_run[q] = run + (uint32_t)__popcll(m);
+          if ((lane & (kQPerWave - 1)) == qq) qp_run = run + (uint32_t)__popcll(m);
           if (MATCH) {
-            // keys |w^|^2 - 2 q^.w^; only hits below the kept (kPicks+1)-th key enter
-            const float kf = __builtin_fmaf(-2.0f, score[qq * kScoreS + lane], wn);
-            const float th0 = q_thr[q];
-            uint64_t surv = ballot(hit && kf < th0);
+            // only hits below the kept (kPicks+1)-th key enter the list
+            const float th0 = readlane_f(qp_thr, qq);
+            uint64_t surv = ballot(hit && kf[qq] < th0);
             if (surv) {
               // the list in lanes 0 .. kPicks while the survivors enter it
+              const int q = q0 + qq;
               const bool in = lane < kK;
               float lk = in ? tkl[q * kK + lane] : __builtin_inff();
               int32_t lji = in ? tjl[q * kK + lane] : -1;
@@ -465,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
               do {
                 const int sl = __builtin_ctzll(surv);
                 surv &= surv - 1;
-                const float ks = readlane_f(kf, sl);
+                const float ks = readlane_f(kf[qq], sl);
                 if (!(ks < th)) continue;
                 const int32_t js = __builtin_amdgcn_readlane(ej, sl);
                 // the new key goes after the kept keys that are <= it; the
@@ -486,10 +509,9 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
                 tkl[q * kK + lane] = lk;
                 tjl[q * kK + lane] = lji;
               }
-              if (lane == 0) q_thr[q] = th;
+              if ((lane & (kQPerWave - 1)) == qq) qp_thr = th;
             }
           }
-          wave_lds_sync();
         }
       }
       __syncthreads();  // the super-chunk's entries are dead
