@@ -25,7 +25,7 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest, tile_wide;
+  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest, tile_wide, qline;
   size_t total;
 };
 
@@ -79,6 +79,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.order = take(sizeof(uint32_t) * ts);
   L.rest = take(sizeof(uint32_t) * N1);
   L.tile_wide = take(sizeof(uint32_t) * ts);
+  L.qline = take(sizeof(double4) * N1);
   L.total = off;
   return L;
 }
@@ -411,6 +412,10 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.rest = idx->at<uint32_t>(L.rest);
   A.tile_wide = idx->at<uint32_t>(L.tile_wide);
   A.match_stats = nullptr;
+  A.qline = idx->at<double4>(L.qline);
+  A.codes1 = nullptr;
+  A.codes2 = nullptr;
+  A.rest_count = A.stats + kStatRest;
   return A;
 }
 
@@ -470,7 +475,7 @@ epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream,
   EPM_HIP(launch_fill_rows(A, stream));
   const bool timed = idx->ev_start && idx->timed == EPM_TIMED_WIDE;
   if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
-  EPM_HIP(launch_wide_tiles(A, match, stream));
+  EPM_HIP(launch_wide_tiles(A, match ? kWideFused : kWideFill, stream));
   if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   return EPM_OK;
 }
@@ -546,6 +551,7 @@ MatchArgs match_args(epm_index* idx, const MatchCall& c) {
   A.capacity = c.capacity;
   A.order = nullptr;
   A.queue = nullptr;
+  A.skip_tiles = nullptr;
   return A;
 }
 
@@ -580,10 +586,42 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
                    : launch_match_window_mfma(A, fmt, grid, stream);
   };
   const bool reduced = c.dtype == EPM_BF16 || c.dtype == EPM_FP8_E4M3;
-  if (reduced) {
+  // FP32 and BF16 on angle tiles: the tiles the last query flagged for rows
+  // longer than kStage are matched by the wide-row pass, the rest by the
+  // window kernels
+  const bool wide = tiled && (c.dtype == EPM_F32 || c.dtype == EPM_BF16);
+  if (reduced || wide) {
     idx->have_match_stats = true;
     idx->match_stream = stream;
     EPM_HIP(launch_clear_stats(A.match_stats, stream));
+  }
+  if (wide) A.skip_tiles = idx->at<uint32_t>(L.tile_wide);
+  auto wide_launch = [&]() -> hipError_t {
+    const bool bf = c.dtype == EPM_BF16;
+    StabArgs W = stab_args(idx, nullptr, const_cast<int64_t*>(c.row_offsets),
+                           const_cast<int32_t*>(c.col_indices),
+                           c.capacity >= 0 ? c.capacity : INT64_MAX);
+    W.qperm = idx->qperm;
+    W.desc1 = bf ? c.desc1_f32 : static_cast<const float*>(c.desc1);
+    W.desc2 = bf ? c.desc2_f32 : static_cast<const float*>(c.desc2);
+    W.codes1 = bf ? static_cast<const uint16_t*>(c.desc1) : nullptr;
+    W.codes2 = bf ? static_cast<const uint16_t*>(c.desc2) : nullptr;
+    W.ratio = c.ratio;
+    W.best_idx = c.best_idx;
+    W.best_dist = c.best_dist;
+    W.second_dist = c.second_dist;
+    W.match_stats = A.match_stats;
+    W.rest_count = A.match_stats + kMatchStatRest;
+    hipError_t e = launch_wide_tiles(W, bf ? kWideMatchBF16 : kWideMatchF32, stream);
+    if (e != hipSuccess) return e;
+    // the rows the pass could not certify or trust, exactly on the FP32 rows
+    MatchArgs M = A;
+    M.desc1 = W.desc1;
+    M.desc2 = W.desc2;
+    M.skip_tiles = nullptr;
+    return launch_match_listed_f32(M, W.rest, W.rest_count, n1, stream);
+  };
+  if (reduced) {
     if (!tiled) {
       // no angle tiles to stage: exact FP32 evaluation on the masters
       A.desc1 = c.desc1_f32;
@@ -592,11 +630,17 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
       return EPM_OK;
     }
     EPM_HIP(tiled_launch(c.dtype == EPM_BF16 ? 0 : 1));
+    if (wide) EPM_HIP(wide_launch());
     return EPM_OK;
   }
   switch (c.dtype) {
     case EPM_F32:
-      EPM_HIP(tiled ? tiled_launch(-1) : launch_match_plain_f32(A, stream));
+      if (!tiled) {
+        EPM_HIP(launch_match_plain_f32(A, stream));
+        return EPM_OK;
+      }
+      EPM_HIP(tiled_launch(-1));
+      EPM_HIP(wide_launch());
       return EPM_OK;
     case EPM_BIN256:
       // 32-byte rows: per-candidate gathers are already line-efficient

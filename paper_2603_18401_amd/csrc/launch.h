@@ -82,6 +82,11 @@ struct StabArgs {
   float* second_dist;
   uint32_t* rest;             // [n1] queries left to the listed-query match
   unsigned long long* match_stats;  // wide-row matching counters (kNumMatchStats), or NULL
+  double4* qline;             // [n1] (a, b, c, sqrt(a^2 + b^2)) of every query, by the tile pass
+  // wide-row matching of a caller's CSR (epm_match)
+  const uint16_t* codes1;     // BF16 descriptor codes (desc1 / desc2 are then the FP32 masters)
+  const uint16_t* codes2;
+  unsigned long long* rest_count;  // length of the rest list the wide-row pass appends to
 };
 
 // Scheduling counters (u32 words of one workspace block).
@@ -113,12 +118,21 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the
 // brute-force long rows.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
-// Wide-row pass after the scan: writes the rows longer than kStage of normal
-// queries, tile by tile (tiles flagged in a.tile_wide).  match: also selects
-// their FP32 matches (desc1/desc2 and the outputs in a) through a BF16 MFMA
-// bound with a certified FP32 re-rank; uncertified queries are appended to
-// a.rest like those of the fused stabbing pass.
-hipError_t launch_wide_tiles(const StabArgs& a, bool match, hipStream_t s);
+// Wide-row pass over the tiles flagged in a.tile_wide.
+//   kWideFill:  writes the rows longer than kStage of normal queries (after
+//               the scan of the row lengths);
+//   kWideFused: also selects their FP32 matches (desc1/desc2 and the outputs
+//               in a) through a BF16 MFMA bound with a certified FP32 re-rank;
+//   kWideMatchF32 / kWideMatchBF16: matches every query of the flagged tiles
+//               over the caller's CSR (a.cols, trusted up to a.capacity),
+//               FP32 rows rounded to BF16 on chip or the caller's BF16 codes
+//               (codes1/codes2, FP32 masters in desc1/desc2); rows that differ
+//               from the tile's candidate sets are not trusted to the bound.
+// Queries it cannot certify (and, when matching, rows of brute-force queries
+// or foreign rows) are appended to a.rest, counted in *a.rest_count, for the
+// listed-query match.
+constexpr int kWideFill = 0, kWideFused = 1, kWideMatchF32 = 2, kWideMatchBF16 = 3;
+hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,
@@ -154,9 +168,11 @@ struct MatchArgs {
                                // when row_offsets[n1] exceeds it.
   const uint32_t* order;       // persistent tiled launch: tile order (NULL = angle order)
   uint32_t* queue;             // persistent tiled launch: next-tile counter, zero at launch
+  const uint32_t* skip_tiles;  // tiled kernels: tiles left to the wide-row pass, or NULL
 };
 
 constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallback), long rows
+constexpr int kMatchStatRest = 3;  // internal: rest-list length of the wide-row match
 // fmt 0: BF16, 1: FP8-E4M3 with row scales.
 // grid as for launch_stab_tiles.
 hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, int grid, hipStream_t s);

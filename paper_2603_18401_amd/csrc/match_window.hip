@@ -70,6 +70,10 @@ __global__ __launch_bounds__(kThreads) void k_match_window_f32(MatchArgs A) {
       if (iter > 0) break;
       tile = xcd_tile(blockIdx.x, A.num_tiles);
     }
+    if (A.skip_tiles && A.skip_tiles[tile]) {  // matched by the wide-row pass
+      if (PERSIST) __syncthreads();            // next_tile is read before it is rewritten
+      continue;
+    }
     const StabTile T = A.tiles[tile];
     const int64_t kb = A.kstart[T.pair];
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();

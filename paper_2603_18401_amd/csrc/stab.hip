@@ -402,12 +402,14 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         key = A.qkey[i];
         if (flag != kQueryEmpty) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
       }
+      const double nrm = line_norm(a, b);
       qa[lane] = a;
       qb[lane] = b;
       qc[lane] = c;
-      qn[lane] = line_norm(a, b);
+      qn[lane] = nrm;
       qk[lane] = key;
       qmode[lane] = live ? flag : kQueryEmpty;
+      if (live) A.qline[i] = make_double4(a, b, c, nrm);
       qidx[lane] = i;
       cnt[lane] = 0;
       if (lane < 3) tile_stats[lane] = 0ull;

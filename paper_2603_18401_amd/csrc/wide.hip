@@ -24,6 +24,13 @@
 // exceeds the exact second distance the match is certified, otherwise the
 // query is listed for the exact listed-query match.  Final outputs therefore
 // equal the FP32 canonical selection bit for bit.
+//
+// epm_match on a caller's CSR uses the same pass over the flagged tiles
+// (every query of such a tile): the tile's candidate decisions are compared
+// with the caller's rows instead of written, and a row that differs is left
+// to the exact listed-query match.  BF16 descriptors given by the caller are
+// staged as they are, with the format's worst-case rounding bound, and the
+// picks re-ranked on the FP32 masters.
 #include "device_common.h"
 #include "launch.h"
 #include "match_common.h"
@@ -198,6 +205,79 @@ __device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* n
   }
 }
 
+// 64 BF16 rows of 256 bytes given as codes (row r = piece f >> 4 of this
+// thread, f = tid + kThreads u).
+constexpr int kCodePer = kL * 16 / kThreads;
+static_assert(kCodePer == 4, "row sums: four rows per 16-lane group");
+struct Codes {
+  uint4 v[kCodePer];
+};
+
+__device__ __forceinline__ Codes fetch_codes(const uint16_t* __restrict__ codes,
+                                             const int64_t* row_of, int tid) {
+  Codes C;
+  #pragma unroll
+  for (int u = 0; u < kCodePer; ++u) {
+    const int f = tid + u * kThreads;
+    const int64_t row = row_of[f >> 4];
+    C.v[u] = row >= 0 ? reinterpret_cast<const uint4*>(codes)[row * 16 + (f & 15)]
+                      : make_uint4(0u, 0u, 0u, 0u);
+  }
+  return C;
+}
+
+__device__ __forceinline__ Codes fetch_query_codes(const uint16_t* __restrict__ codes,
+                                                   const int64_t* q_i, uint64_t mask, int tid) {
+  Codes C;
+  #pragma unroll
+  for (int u = 0; u < kCodePer; ++u) {
+    const int f = tid + u * kThreads, q = f >> 4;
+    C.v[u] = (mask >> q) & 1ull ? reinterpret_cast<const uint4*>(codes)[q_i[q] * 16 + (f & 15)]
+                                : make_uint4(0u, 0u, 0u, 0u);
+  }
+  return C;
+}
+
+__device__ __forceinline__ float bf16_sq4(uint32_t w0, uint32_t w1) {
+  const float y0 = __uint_as_float(w0 << 16), y1 = __uint_as_float(w0 & 0xFFFF0000u),
+              y2 = __uint_as_float(w1 << 16), y3 = __uint_as_float(w1 & 0xFFFF0000u);
+  return y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3;
+}
+
+// Stores 64 BF16 rows (stride kRS) and their squared norms (sums over the 16
+// lanes of each row's pieces, transposing butterfly as in stage_bf16);
+// optionally the running maxima of sqrt(norm) and of the format's worst-case
+// rounding bound, slightly inflated, as float bits.
+__device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float* nrm,
+                                            uint32_t* max_nb, uint32_t* max_db, int tid) {
+  float sn[kCodePer];
+  #pragma unroll
+  for (int u = 0; u < kCodePer; ++u) {
+    const int f = tid + u * kThreads, r = f >> 4, c = f & 15;
+    const uint4 w = C.v[u];
+    *reinterpret_cast<uint4*>(dst + r * kRS + c * 16) = w;
+    sn[u] = bf16_sq4(w.x, w.y) + bf16_sq4(w.z, w.w);
+  }
+  const int lane = lane_id();
+  const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  float t[2];
+  #pragma unroll
+  for (int v = 0; v < 2; ++v)  // keep rows 2 b3 + v of the group's four
+    t[v] = (b3 ? sn[2 + v] : sn[v]) + __shfl_xor(b3 ? sn[v] : sn[2 + v], 8);
+  float x = (b2 ? t[1] : t[0]) + __shfl_xor(b2 ? t[0] : t[1], 4);
+  x += __shfl_xor(x, 2);
+  x += __shfl_xor(x, 1);
+  if ((lane & 3) == 0) {
+    const int r = (tid >> 4) + 16 * (2 * b3 + b2);
+    nrm[r] = x;
+    if (max_nb) {
+      const double nb = sqrt((double)x) * (1.0 + 2e-5);
+      atomicMax(max_nb, __float_as_uint((float)nb));
+      atomicMax(max_db, __float_as_uint((float)(row_delta<0>(nb, 1.0) * (1.0 + 1e-6))));
+    }
+  }
+}
+
 // One window entry in ascending j: its image-2 index and record.
 struct Entry {
   int32_t j;
@@ -206,8 +286,11 @@ struct Entry {
   float e;
 };
 
-template <bool MATCH>
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
+  constexpr bool MATCH = MODE != kWideFill;
+  constexpr bool WRITE = MODE == kWideFill || MODE == kWideFused;  // writes the CSR
+  constexpr bool CODES = MODE == kWideMatchBF16;                     // caller's BF16 codes
   // bitmap slab and word prefix; after the window sweep the picks live here
   __shared__ __attribute__((aligned(16))) unsigned char slab_raw[kSlabWords * 12];
   unsigned long long* bits = reinterpret_cast<unsigned long long*>(slab_raw);
@@ -219,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   __shared__ float2 lXY[kSC];
   __shared__ float lE[kSC];
   __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ], qn[kTileQ];
-  __shared__ uint32_t qk[kTileQ];
+  __shared__ uint32_t qk[kTileQ], q_len[kTileQ], q_bad[kTileQ];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint64_t wide_mask_s;
@@ -241,6 +324,8 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
 
   const int tile = xcd_tile(blockIdx.x, A.num_tiles);
   if (A.tile_wide[tile] == 0u) return;
+  // a caller's CSR that did not fit its buffer is incomplete: nothing is written
+  if (!WRITE && A.row_offsets[A.n1] > A.capacity) return;
   const StabTile T = A.tiles[tile];
   const PairDev& pd = A.pairs[T.pair];
   const int64_t kb = pd.k_begin, n2 = pd.n;
@@ -251,22 +336,41 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     int64_t i = 0, o0 = 0, len = 0;
     uint32_t flag = kQueryEmpty, key = 0;
     double a = 0.0, b = 0.0, c = 0.0;
+    double nrm = 0.0;
     if (live) {
       i = A.qperm[T.begin + lane];
       flag = A.qflag[i];
       key = A.qkey[i];
       o0 = A.row_offsets[i];
       len = A.row_offsets[i + 1] - o0;
-      if (flag == kQueryNormal) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
+      if (flag == kQueryNormal) {
+        const double4 L = A.qline[i];
+        a = L.x;
+        b = L.y;
+        c = L.z;
+        nrm = L.w;
+      }
     }
-    const bool wide = live && flag == kQueryNormal && len > kStage;
+    // writing: the long rows of normal queries; matching a caller's CSR:
+    // every normal query of the tile
+    const bool wide = live && flag == kQueryNormal && (WRITE ? len > kStage : len > 0);
+    if (!WRITE && live && !wide) {
+      if (len == 0) {
+        write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, i, Top2(), false);
+      } else {  // a brute-force query: exact listed match
+        const unsigned long long at = atomicAdd(A.rest_count, 1ull);
+        A.rest[at] = (uint32_t)i;
+        if (A.match_stats) atomicAdd(&A.match_stats[2], 1ull);
+      }
+    }
     qa[lane] = a;
     qb[lane] = b;
     qc[lane] = c;
-    qn[lane] = line_norm(a, b);
+    qn[lane] = nrm;
     qk[lane] = key;
     q_i[lane] = i;
     q_o0[lane] = o0;
+    q_len[lane] = (uint32_t)len;
     const uint64_t wm = ballot(wide);
     const TileWindow* W = A.windows + tile;
     slot_b[lane] = W->slot_b[lane];
@@ -293,8 +397,10 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   const uint32_t qp_k = qk[ql];
   const double qp_a = qa[ql], qp_b = qb[ql], qp_c = qc[ql], qp_n = qn[ql];
   const int64_t qp_o0 = q_o0[ql];
+  const uint32_t qp_len = q_len[ql];
   uint32_t qp_run = 0u;
   float qp_thr = __builtin_inff();
+  uint32_t badbits = 0u;  // matching a caller's CSR: queries whose row differs here
 
   if (MATCH) {
     for (int t = tid; t < kTileQ * kK; t += kThreads) {
@@ -304,8 +410,11 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   }
   uint8_t* wrows = raw;
   float* score = reinterpret_cast<float*>(raw + kL * kRS) + wave * kQPerWave * kScoreS;
-  if (MATCH) {
+  if (CODES) {
     // BF16 query rows (zero rows for the queries that are not wide)
+    stage_codes(fetch_query_codes(A.codes1, q_i, wide_mask, tid), qrows, q_norm, nullptr,
+                nullptr, tid);
+  } else if (MATCH) {
     stage_bf16(fetch_query_rows(A.desc1, q_i, wide_mask, tid), qrows, q_norm, q_err, nullptr,
                nullptr, tid);
   }
@@ -406,7 +515,9 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
 
     for (uint32_t e0 = 0; e0 < E; e0 += kSC) {
       Rows pre;
-      if (MATCH) pre = fetch_rows(A.desc2, row_of, tid);  // block 0
+      Codes prc;
+      if (CODES) prc = fetch_codes(A.codes2, row_of, tid);  // block 0
+      else if (MATCH) pre = fetch_rows(A.desc2, row_of, tid);
       // the next super-chunk's entry: j now, its record during the blocks
       const int32_t nj = e0 + kSC < E ? entry_j(e0 + kSC + tid) : -1;
       Entry nxt;
@@ -416,10 +527,14 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
         if (e0 + base >= E) break;  // uniform
         float wn = 0.0f;
         if (MATCH) {
-          stage_bf16(pre, wrows, w_norm, nullptr, &max_nb, &max_db, tid);
+          if (CODES) stage_codes(prc, wrows, w_norm, &max_nb, &max_db, tid);
+          else stage_bf16(pre, wrows, w_norm, nullptr, &max_nb, &max_db, tid);
           __syncthreads();  // block rows and norms complete
           wn = w_norm[lane];
-          if (sub + 1 < kSub && e0 + base + kL < E) pre = fetch_rows(A.desc2, row_of + base + kL, tid);
+          if (sub + 1 < kSub && e0 + base + kL < E) {
+            if (CODES) prc = fetch_codes(A.codes2, row_of + base + kL, tid);
+            else pre = fetch_rows(A.desc2, row_of + base + kL, tid);
+          }
           // S = Q W^T: wavefront w owns queries 16w .. 16w + 15 against the 64 rows
           f32x4 acc[4];
           #pragma unroll
@@ -458,9 +573,12 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
             kf[qq] = __builtin_fmaf(-2.0f, score[qq * kScoreS + lane], wn);
         }
         // every query of the wavefront against the block: one ballot gives
-        // the query's hits, which extend its CSR row and feed its selection
+        // the query's hits, which extend (or are checked against) its CSR row
+        // and feed its selection
+        int32_t got[kQPerWave];
         #pragma unroll
         for (int qq = 0; qq < kQPerWave; ++qq) {
+          got[qq] = ej;
           if (!((wmask >> qq) & 1u)) continue;
           bool hit = false;
           if (ej >= 0 && key_distance((uint32_t)__builtin_amdgcn_readlane((int)qp_k, qq), eC) <= eH)
@@ -469,9 +587,14 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
           const uint64_t m = ballot(hit);
           const uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)qp_run, qq);
           if (hit) {
-            const int64_t dst =
-                (int64_t)readlane_u64((uint64_t)qp_o0, qq) + run + lanes_below(m);
-            if (dst < A.capacity) A.cols[dst] = ej;
+            const uint32_t k = run + lanes_below(m);
+            const int64_t dst = (int64_t)readlane_u64((uint64_t)qp_o0, qq) + k;
+            if (WRITE) {
+              if (dst < A.capacity) A.cols[dst] = ej;
+            } else {
+              // the caller's row must hold this hit at this place
+              got[qq] = k < (uint32_t)__builtin_amdgcn_readlane((int)qp_len, qq) ? A.cols[dst] : -2;
+            }
           }
           if ((lane & (kQPerWave - 1)) == qq) qp_run = run + (uint32_t)__popcll(m);
           if (MATCH) {
@@ -513,6 +636,11 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
             }
           }
         }
+        if (!WRITE) {
+          #pragma unroll
+          for (int qq = 0; qq < kQPerWave; ++qq)
+            if (got[qq] != ej) badbits |= 1u << qq;
+        }
       }
       __syncthreads();  // the super-chunk's entries are dead
       if (nj >= 0 || e0 + kSC < E) {
@@ -524,6 +652,15 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   }
 
   if (!MATCH) return;
+  if (!WRITE) {
+    // rows that differ from the tile's candidate sets (a hit missing or out
+    // of place, or a different length) are evaluated exactly
+    #pragma unroll
+    for (int qq = 0; qq < kQPerWave; ++qq) {
+      const bool bad = ballot((badbits >> qq) & 1u) != 0ull;
+      if (lane == qq) q_bad[q0 + qq] = bad || qp_run != qp_len ? 1u : 0u;
+    }
+  }
   // the picks are the first kPicks of every list; the row area holds the
   // FP32 query rows now, the bitmap area the exact distances
   const float* pk = tkl;
@@ -563,16 +700,17 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
     // is at least the bound of the smallest such approximate distance, with
     // the largest row terms of the window and a slack for the key's rounding
     const double qnb = sqrt((double)q_norm[q]) * (1.0 + 2e-5);
-    const double qdb = sqrt((double)q_err[q]) * (1.0 + 2e-5) + 1e-30;
+    const double qdb = CODES ? row_delta<0>(qnb, 1.0) * (1.0 + 1e-6)
+                             : sqrt((double)q_err[q]) * (1.0 + 2e-5) + 1e-30;
     const double nw = (double)__uint_as_float(max_nb), dw = (double)__uint_as_float(max_db);
     const double s = qnb + nw;
     const double dt = (double)q_norm[q] + (double)pk[q * kK + kPicks] - 1e-6 * s * s;
     const double lb = lower_bound(dt, qnb, nw, qdb, dw);
-    if (lb > (double)t.sd) {
+    if (lb > (double)t.sd && (WRITE || q_bad[q] == 0u)) {
       write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, q_i[q], t, false);
       atomicAdd(&n_cert, 1u);
     } else {
-      const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
+      const unsigned long long at = atomicAdd(A.rest_count, 1ull);
       A.rest[at] = (uint32_t)q_i[q];
       atomicAdd(&n_fallback, 1u);
     }
@@ -588,15 +726,22 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
 
 }  // namespace
 
-hipError_t launch_wide_tiles(const StabArgs& a, bool match, hipStream_t s) {
+hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
-  if (!a.tile_wide) return hipErrorInvalidValue;
-  if (match && (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest))
+  if (!a.tile_wide || !a.qline) return hipErrorInvalidValue;
+  if (mode != kWideFill &&
+      (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest ||
+       !a.rest_count))
     return hipErrorInvalidValue;
-  if (match)
-    hipLaunchKernelGGL(k_wide_tile<true>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_wide_tile<false>, dim3(a.num_tiles), dim3(kThreads), 0, s, a);
+  if (mode == kWideMatchBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
+  const dim3 g(a.num_tiles), b(kThreads);
+  switch (mode) {
+    case kWideFill: hipLaunchKernelGGL(k_wide_tile<kWideFill>, g, b, 0, s, a); break;
+    case kWideFused: hipLaunchKernelGGL(k_wide_tile<kWideFused>, g, b, 0, s, a); break;
+    case kWideMatchF32: hipLaunchKernelGGL(k_wide_tile<kWideMatchF32>, g, b, 0, s, a); break;
+    case kWideMatchBF16: hipLaunchKernelGGL(k_wide_tile<kWideMatchBF16>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -147,3 +147,60 @@ def test_wide_rows_capacity_without_host_check():
     torch.cuda.synchronize()
     assert np.array_equal(offs.cpu().numpy(), ref[0])
     assert np.array_equal(cols.cpu().numpy(), ref[1][:cap])
+
+
+def _match_inputs(torch, p, dtype):
+    d1, d2 = _dev(torch, p.desc1), _dev(torch, p.desc2)
+    if dtype == "f32":
+        return dict(desc1=d1, desc2=d2, dtype="f32")
+    if dtype == "bf16":
+        return dict(desc1=_dev(torch, synth.f32_to_bf16(p.desc1).view(np.int16)),
+                    desc2=_dev(torch, synth.f32_to_bf16(p.desc2).view(np.int16)), dtype="bf16",
+                    desc1_f32=d1, desc2_f32=d2)
+    c1, s1 = synth.f32_to_fp8_e4m3(p.desc1)
+    c2, s2 = synth.f32_to_fp8_e4m3(p.desc2)
+    return dict(desc1=_dev(torch, c1), desc2=_dev(torch, c2), dtype="fp8",
+                scale1=_dev(torch, s1), scale2=_dev(torch, s2), desc1_f32=d1, desc2_f32=d2)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_separate_match_on_wide_rows(dtype):
+    """epm_match over the query's CSR at eps 50 px: the flagged tiles go to
+    the wide-row pass (FP32 and BF16), FP8 stays on the window kernel."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    p = synth.cfg1_pair("forward", n_kp=25000)
+    log(f"separate match on wide rows, {dtype}")
+    ref = _oracle(p, 50.0, ratio=0.8)
+    idx = E.Index(specs_of([p]), _dev(torch, p.kp2), eps=50.0)
+    o, c = idx.query(_dev(torch, p.kp1))
+    got = [x.cpu().numpy() for x in idx.match(o, c, ratio=0.8, algo="tiled",
+                                              **_match_inputs(torch, p, dtype))]
+    _same_matches(got, ref[2:], dtype)
+    if dtype != "fp8":
+        st = idx.match_stats()
+        assert st["reranked_rows"] > 0.9 * p.m
+        assert st["fallback_rows"] < 0.1 * st["reranked_rows"]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_foreign_csr_on_wide_tiles(dtype):
+    """A CSR from a different tolerance on an index whose last query flagged
+    its tiles as wide: rows that differ from the tile's candidate sets are
+    matched exactly, so the result is the oracle's over the given CSR."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    p = synth.cfg0_pair(3)
+    ro, rc, _ = oracle.candidates(p.F, p.kp1, p.kp2, 45.0)
+    rows = np.repeat(np.arange(p.m), np.diff(ro))
+    keep = (rows % 3 != 0) | (np.arange(len(rc)) % 5 != 0)  # and thin some rows out
+    ro2 = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=p.m))]).astype(np.int64)
+    rc2 = rc[keep]
+    ref = oracle.match(p.desc1, p.desc2, ro2, rc2, ratio=0.0)
+    log(f"foreign CSR on wide tiles, {dtype}")
+    idx = E.Index(specs_of([p]), _dev(torch, p.kp2), eps=50.0)
+    o, _ = idx.query(_dev(torch, p.kp1))
+    assert (np.diff(o.cpu().numpy()) > 128).sum() > 0
+    got = [x.cpu().numpy() for x in idx.match(_dev(torch, ro2), _dev(torch, rc2), algo="tiled",
+                                              **_match_inputs(torch, p, dtype))]
+    _same_matches(got, ref, "foreign")
