@@ -175,6 +175,12 @@ typedef struct {
  *              Ties are broken by the lower image-2 index.
  * opts         may be NULL (defaults).
  *
+ * On angle tiles (EPM_ALGO_AUTO / TILED after a query on idx), FP32 and BF16
+ * rows of the tiles whose last query had rows of more than 128 candidates
+ * are ranked on MFMA against BF16 rows with a certified FP32 re-rank; a row
+ * of the given CSR that differs from the tile's candidate set is evaluated
+ * exactly.  Results are the same either way.
+ *
  * Errors: EPM_ERR_ARG, EPM_ERR_HIP.  Asynchronous.
  */
 epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
@@ -431,10 +437,10 @@ typedef struct {
 } epm_match_stats;
 
 /*
- * Reads the counters of the last BF16/FP8 epm_match on idx, or of the rows
- * with more than 128 candidates of the last epm_query_match on idx (ranked on
- * MFMA with BF16 copies of the FP32 rows; long_rows is then 0), and waits for
- * the stream that call used.  fallback_rows / reranked_rows is the rate at which
+ * Reads the counters of the last BF16/FP8 (or FP32 on angle tiles) epm_match
+ * on idx, or of the rows with more than 128 candidates of the last
+ * epm_query_match on idx (ranked on MFMA with BF16 copies of the FP32 rows;
+ * long_rows is then 0), and waits for the stream that call used.  fallback_rows / reranked_rows is the rate at which
  * the four re-ranked candidates could not be certified to contain the exact
  * best and second; those rows are then evaluated exactly, so results never
  * depend on it.
