@@ -68,6 +68,8 @@ def parse():
                     help="scale workload: skip the separate-calls figure")
     ap.add_argument("--no-graph", action="store_true",
                     help="scale workload: skip the recorded-graph figure")
+    ap.add_argument("--no-mutual", action="store_true",
+                    help="scale workload: skip the mutual-matching figure")
     return ap.parse_args()
 
 
@@ -729,6 +731,40 @@ def main():
                                             for c, t in tinfo.get("candidates", [])]}
         bt.close()
 
+    # ---- mutual matching: both directions (F and its transpose) + cross-check
+    mutual = None
+    if not args.no_mutual:
+        rspecs = E.reversed_specs(specs, [(p.W, p.H) for p in pairs])
+        eps1 = torch.from_numpy(np.concatenate(
+            [np.full(p.m, e, np.float32) for p, e in zip(pairs, eps_list)])).to(dev)
+        ridx0 = E.Index(rspecs, g["kp1"], eps2=eps1)
+        rws = ridx0.workspace
+        roffs, _ = ridx0.query(g["kp2"])
+        rnnz = int(roffs[-1].item())
+        ridx0.close()
+        r_offsets = torch.empty(N2 + 1, dtype=torch.int64, device=dev)
+        r_cols = torch.empty(rnnz, dtype=torch.int32, device=dev)
+        r_outs = tuple(torch.empty(N2, dtype=t, device=dev)
+                       for t in (torch.int32, torch.float32, torch.float32))
+        mut = torch.empty(N1, dtype=torch.int32, device=dev)
+
+        def mutual_step():
+            fwd = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
+            fwd.query_match(g["kp1"], g["d1"], g["d2"], row_offsets=row_offsets,
+                            col_indices=col_indices, out=outs, sync=False)
+            rev = E.Index(rspecs, g["kp1"], eps2=eps1, workspace=rws)
+            rev.query_match(g["kp2"], g["d2"], g["d1"], row_offsets=r_offsets,
+                            col_indices=r_cols, out=r_outs, sync=False)
+            fwd.mutual(outs[0], r_outs[0], out=mut)
+            fwd.close()
+            rev.close()
+
+        msec = time_steps(torch, mutual_step, args.steps, args.warmup)
+        mutual = {"value": round(N1 / msec, 1), "unit": "queries/s",
+                  "ms_per_step": round(msec * 1e3, 4), "reverse_candidates": rnnz,
+                  "mutual_matches": int((mut >= 0).sum().item()),
+                  "forward_matches": int((outs[0] >= 0).sum().item())}
+
     # ---- roofline of the dominant kernel
     kern_ms = float(np.mean(kernel_ms))
     if fused:
@@ -797,6 +833,7 @@ def main():
         "plain_gpu": plain,
         "separate_calls": separate,
         "graph": graph,
+        "mutual": mutual,
     }
     if plain:
         out["speedup_vs_plain"] = round(qps / plain["value"], 3)

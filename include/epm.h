@@ -447,6 +447,22 @@ typedef struct {
  */
 epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out);
 
+/*
+ * Mutual guided matching (Sec. 4.3 with the classical cross-check): the
+ * caller matches image 1 against image 2 on idx (F, pairs as built) and
+ * image 2 against image 1 on a second index built with the transposed
+ * matrices and the roles of the images swapped (image-1 sizes, m and n
+ * exchanged).  This keeps a match only when it is mutual:
+ *   mutual[i] = best12[i]  if best21[k_begin + best12[i]] == i - q_begin
+ *               -1         otherwise (no match, rejected, or not mutual)
+ * best12 [N1] and mutual [N1] are indexed like the queries of idx; best21
+ * [N2] by the global image-2 row, holding image-1 indices local to the pair
+ * (as epm_match writes them on the reversed index).  Device pointers, no
+ * host synchronisation.  Errors: EPM_ERR_ARG, EPM_ERR_HIP.
+ */
+epm_status epm_mutual_check(const epm_index* idx, const int32_t* best12, const int32_t* best21,
+                            int32_t* mutual, hipStream_t stream);
+
 /* Releases the host object; the device workspace stays owned by the caller. */
 void epm_index_destroy(epm_index* idx);
 

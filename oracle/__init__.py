@@ -17,6 +17,8 @@ Parity status of each function (pins are the tests in tests/test_oracle*.py):
   match (binary)    pinned: Hamming vs numpy bit counts.
   paper_angle_*     pinned against the brute-force candidates (agreement
                     outside a 1e-6 px boundary band).
+  mutual.*          pinned: both directions keep noiseless true matches only
+                    with the transposed matrix; the cross-check on a hand case.
 """
 
 import ctypes

@@ -40,7 +40,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_create", "epm_batch_launch", "epm_batch_nnz", "epm_batch_index",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
-           "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize"]
+           "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
+           "epm_mutual_check"]
 
 
 class EpmError(RuntimeError):
@@ -177,6 +178,8 @@ def load_library(path=None):
     lib.epm_eps_adam.restype = ctypes.c_int
     lib.epm_match_residuals.argtypes = [V, V, V, V, V, V, V]
     lib.epm_match_residuals.restype = ctypes.c_int
+    lib.epm_mutual_check.argtypes = [V, V, V, V, V]
+    lib.epm_mutual_check.restype = ctypes.c_int
     lib.epm_query_match.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, f32, V, V, V, V]
     lib.epm_query_match.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
@@ -375,6 +378,18 @@ class Index:
         _check(self.lib.epm_index_set_timing_events(self.handle, *handles),
                "epm_index_set_timing_events")
 
+    def mutual(self, best12, best21, out=None):
+        """epm_mutual_check: best12 [N1] from this index, best21 [N2] from the
+        reversed index (image 2 against image 1 with the transposed F);
+        returns the mutual matches [N1] (-1 where not mutual)."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.n1, dtype=torch.int32, device=self.device)
+        _check(self.lib.epm_mutual_check(self.handle, _dptr(best12), _dptr(best21), _dptr(out),
+                                         _stream(torch, self.device, self.stream)),
+               "epm_mutual_check")
+        return out
+
     def set_sched(self, sched):
         """Work distribution of later query/match calls (a Sched)."""
         c = sched._c()
@@ -407,6 +422,28 @@ class Index:
                                 _stream(torch, self.device, self.stream))
         _check(st, "epm_match")
         return best, bd, sd
+
+
+def reversed_specs(specs, sizes1):
+    """PairSpecs of the other direction (image 2 against image 1): the
+    transposed F, the image-1 sizes [(w1, h1), ...], m and n exchanged."""
+    return [PairSpec(np.asarray(s.F, dtype=np.float64).reshape(3, 3).T, w, h, s.n, s.m)
+            for s, (w, h) in zip(specs, sizes1)]
+
+
+def mutual_match(specs, sizes1, kp1, kp2, desc1, desc2, eps=0.0, eps2=None, eps1=None,
+                 ratio=0.0):
+    """Mutual guided matching over a batch (FP32 descriptors): the
+    candidates and matches of image 1 against image 2 (tolerances eps2 per
+    image-2 keypoint, or eps), of image 2 against image 1 (eps1 per image-1
+    keypoint, or eps), and the cross-check.  Returns (best12, best21, mutual);
+    every step runs in the library."""
+    fwd = Index(specs, kp2, eps2=eps2, eps=eps)
+    rev = Index(reversed_specs(specs, sizes1), kp1, eps2=eps1, eps=eps)
+    _, _, best12, _, _ = fwd.query_match(kp1, desc1, desc2, ratio=ratio)
+    _, _, best21, _, _ = rev.query_match(kp2, desc2, desc1, ratio=ratio)
+    mutual = fwd.mutual(best12, best21)
+    return best12, best21, mutual
 
 
 class Batch:

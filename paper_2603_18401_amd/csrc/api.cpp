@@ -1061,6 +1061,16 @@ epm_status epm_eps_adam(float* params, float* m, float* v, const float* grad, in
   return EPM_OK;
 }
 
+epm_status epm_mutual_check(const epm_index* idx, const int32_t* best12, const int32_t* best21,
+                             int32_t* mutual, hipStream_t stream) {
+  if (!idx) return EPM_ERR_ARG;
+  if (idx->N1 == 0) return EPM_OK;
+  if (!best12 || !mutual || (idx->N2 > 0 && !best21)) return EPM_ERR_ARG;
+  EPM_HIP(launch_mutual(idx->at<int64_t>(idx->L.qstart), idx->at<int64_t>(idx->L.kstart), idx->P,
+                        idx->N1, best12, best21, mutual, stream));
+  return EPM_OK;
+}
+
 epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const float* kp2_xy,
                                const int32_t* best_idx, float* residual, int64_t* feat_index,
                                hipStream_t stream) {

@@ -227,6 +227,12 @@ hipError_t launch_residuals(const PairDev* pairs, const int64_t* qstart, int num
                             int64_t n1, const float* kp1, const float* kp2, const int32_t* best,
                             float* residual, int64_t* feat_index, hipStream_t s);
 
+// mutual[i] = best12[i] when best21 (indexed by the global image-2 row) maps
+// that keypoint back to query i of the same pair, else -1.
+hipError_t launch_mutual(const int64_t* qstart, const int64_t* kstart, int num_pairs, int64_t n1,
+                         const int32_t* best12, const int32_t* best21, int32_t* mutual,
+                         hipStream_t s);
+
 // fmt 0: BF16 codes [rows][dim]; 1: E4M3 codes [rows][dim] and scales [rows].
 hipError_t launch_quantize(const float* src, int64_t rows, int dim, int fmt, void* dst,
                            float* scale, hipStream_t s);

@@ -235,3 +235,7 @@ def test_learned_eps_argument_errors(lib):
 def test_timing_kernel_argument_errors(lib):
     assert lib.epm_index_set_timing_kernel(None, 0) == 1
     assert lib.epm_index_set_timing_kernel(None, 1) == 1
+
+
+def test_mutual_check_argument_errors(lib):
+    assert lib.epm_mutual_check(None, None, None, None, None) == 1

@@ -38,6 +38,7 @@ def test_scale_workload_line(monkeypatch, capsys):
         assert k in c, k
     assert c["kind"] == "oracle"
     assert line["separate_calls"]["identical_matches"]
+    assert 0 < line["mutual"]["mutual_matches"] <= line["mutual"]["forward_matches"]
 
 
 def test_batch_workload_line(monkeypatch, capsys):
