@@ -19,6 +19,8 @@ Parity status of each function (pins are the tests in tests/test_oracle*.py):
                     outside a 1e-6 px boundary band).
   mutual.*          pinned: both directions keep noiseless true matches only
                     with the transposed matrix; the cross-check on a hand case.
+  gms.*             pinned: hand-built motions, the threshold boundary, the
+                    tie rule, invariance under the query order.
 """
 
 import ctypes
