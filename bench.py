@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true",
                     help="scale workload: skip the recorded-graph figure")
     ap.add_argument("--no-mutual", action="store_true",
-                    help="scale workload: skip the mutual-matching figure")
+                    help="scale workload: skip the mutual-matching and GMS figures")
     return ap.parse_args()
 
 
@@ -765,6 +765,20 @@ def main():
                   "mutual_matches": int((mut >= 0).sum().item()),
                   "forward_matches": int((outs[0] >= 0).sum().item())}
 
+    # ---- GMS validation of the step's matches (grid 20, alpha 6)
+    gms = None
+    if not args.no_mutual:
+        gidx = E.Index(specs, g["kp2"], eps2=g["eps2"], workspace=ws)
+        gidx.query_match(g["kp1"], g["d1"], g["d2"], row_offsets=row_offsets,
+                         col_indices=col_indices, out=outs, sync=False)
+        sizes1 = [(p.W, p.H) for p in pairs]
+        kept = torch.empty(N1, dtype=torch.int32, device=dev)
+        gsec = time_steps(torch, lambda: gidx.gms(sizes1, g["kp1"], g["kp2"], outs[0], out=kept),
+                          args.steps, args.warmup)
+        gms = {"ms_per_call": round(gsec * 1e3, 4), "kept": int((kept >= 0).sum().item()),
+               "matches": int((outs[0] >= 0).sum().item()), "grid": 20, "alpha": 6.0}
+        gidx.close()
+
     # ---- roofline of the dominant kernel
     kern_ms = float(np.mean(kernel_ms))
     if fused:
@@ -834,6 +848,7 @@ def main():
         "separate_calls": separate,
         "graph": graph,
         "mutual": mutual,
+        "gms": gms,
     }
     if plain:
         out["speedup_vs_plain"] = round(qps / plain["value"], 3)

@@ -463,6 +463,35 @@ epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out);
 epm_status epm_mutual_check(const epm_index* idx, const int32_t* best12, const int32_t* best21,
                             int32_t* mutual, hipStream_t stream);
 
+/*
+ * GMS validation of the matches of idx (grid-based motion statistics, the
+ * filter the paper's experiments apply with the threshold set to 6; Sec. 4.3
+ * cites the method).  Single-grid form: both images are cut into grid x grid
+ * cells (cell of a point: floor(x grid / W), clamped); every image-1 cell's
+ * motion is the image-2 cell receiving most of its matches (ties to the
+ * lowest row-major index); the cell passes when the matches from its 3 x 3
+ * neighbourhood to the neighbourhood of its motion (same offsets) number S
+ * with S^2 * cells > alpha^2 * total, total the matches of the neighbourhood
+ * cells and cells their count (cells outside a grid are left out).  A match
+ * is kept when it follows its cell's motion and the cell passes.
+ *
+ * size1       host [P][2] int32: image-1 width and height of every pair
+ *             (image-2 sizes are those given to epm_build_intervals).
+ * grid        1 .. 32 (20 in GMS); alpha > 0 (6 in the paper).
+ * kp1_xy, kp2_xy  the keypoints of the batch, as for the query and the index.
+ * best_idx    [N1] matches (local image-2 index or -1), e.g. from epm_match.
+ * out_idx     [N1] the kept matches, -1 elsewhere (may not alias best_idx).
+ * workspace   caller-owned device memory of epm_gms_workspace_bytes(idx,
+ *             grid) bytes, 256-byte aligned.
+ * Host synchronisation: the pair-table upload.  Errors: EPM_ERR_ARG,
+ * EPM_ERR_WORKSPACE, EPM_ERR_HIP.
+ */
+size_t epm_gms_workspace_bytes(const epm_index* idx, int32_t grid);
+epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, float alpha,
+                   const float* kp1_xy, const float* kp2_xy, const int32_t* best_idx,
+                   int32_t* out_idx, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream);
+
 /* Releases the host object; the device workspace stays owned by the caller. */
 void epm_index_destroy(epm_index* idx);
 

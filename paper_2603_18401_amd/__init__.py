@@ -41,7 +41,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
-           "epm_mutual_check"]
+           "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms"]
 
 
 class EpmError(RuntimeError):
@@ -180,6 +180,10 @@ def load_library(path=None):
     lib.epm_match_residuals.restype = ctypes.c_int
     lib.epm_mutual_check.argtypes = [V, V, V, V, V]
     lib.epm_mutual_check.restype = ctypes.c_int
+    lib.epm_gms_workspace_bytes.argtypes = [V, i32]
+    lib.epm_gms_workspace_bytes.restype = ctypes.c_size_t
+    lib.epm_gms.argtypes = [V, P, i32, ctypes.c_float, V, V, V, V, V, ctypes.c_size_t, V]
+    lib.epm_gms.restype = ctypes.c_int
     lib.epm_query_match.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, f32, V, V, V, V]
     lib.epm_query_match.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
@@ -388,6 +392,25 @@ class Index:
         _check(self.lib.epm_mutual_check(self.handle, _dptr(best12), _dptr(best21), _dptr(out),
                                          _stream(torch, self.device, self.stream)),
                "epm_mutual_check")
+        return out
+
+    def gms(self, sizes1, kp1, kp2, best, grid=20, alpha=6.0, out=None):
+        """epm_gms: GMS validation of the matches `best` of this index.
+        sizes1: image-1 (width, height) of every pair.  Returns the kept
+        matches (-1 elsewhere)."""
+        torch = self._torch
+        if len(sizes1) != len(self.specs):
+            raise ValueError("one image-1 size per pair")
+        size1 = (ctypes.c_int32 * (2 * len(sizes1)))(*[int(v) for wh in sizes1 for v in wh])
+        nbytes = self.lib.epm_gms_workspace_bytes(self.handle, int(grid))
+        if nbytes == 0:
+            raise EpmError(1, "epm_gms_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty(self.n1, dtype=torch.int32, device=self.device)
+        _check(self.lib.epm_gms(self.handle, size1, int(grid), float(alpha), _dptr(kp1),
+                                _dptr(kp2), _dptr(best), _dptr(out), _dptr(ws), ws.numel(),
+                                _stream(torch, self.device, self.stream)), "epm_gms")
         return out
 
     def set_sched(self, sched):

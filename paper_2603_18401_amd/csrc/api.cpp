@@ -1061,6 +1061,90 @@ epm_status epm_eps_adam(float* params, float* m, float* v, const float* grad, in
   return EPM_OK;
 }
 
+namespace {
+
+struct GmsLayout {
+  size_t pairs, count, cursor, offsets, partials, key, rcell, list, total;
+};
+
+GmsLayout gms_layout(const epm_index* idx, int32_t grid) {
+  GmsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  const size_t cells = (size_t)idx->P * (size_t)grid * (size_t)grid;
+  const size_t n1 = (size_t)idx->N1;
+  L.pairs = take(sizeof(GmsPair) * (size_t)idx->P);
+  L.count = take(4 * cells);
+  L.cursor = take(4 * cells);
+  L.offsets = take(8 * (cells + 1));
+  L.partials = take(8 * (size_t)scan_partials_count((int64_t)cells));
+  L.key = take(4 * n1);
+  L.rcell = take(4 * n1);
+  L.list = take(4 * n1);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+size_t epm_gms_workspace_bytes(const epm_index* idx, int32_t grid) {
+  if (!idx || grid < 1 || grid > kGmsMaxGrid) return 0;
+  return gms_layout(idx, grid).total;
+}
+
+epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, float alpha,
+                   const float* kp1_xy, const float* kp2_xy, const int32_t* best_idx,
+                   int32_t* out_idx, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream) {
+  if (!idx || !size1 || grid < 1 || grid > kGmsMaxGrid || !(alpha > 0.0f) ||
+      !std::isfinite(alpha))
+    return EPM_ERR_ARG;
+  for (int p = 0; p < idx->P; ++p)
+    if (size1[2 * p] <= 0 || size1[2 * p + 1] <= 0) return EPM_ERR_ARG;
+  if (idx->N1 == 0) return EPM_OK;
+  if (!kp1_xy || !best_idx || !out_idx || (idx->N2 > 0 && !kp2_xy)) return EPM_ERR_ARG;
+  const GmsLayout L = gms_layout(idx, grid);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) ||
+      workspace_bytes < L.total)
+    return EPM_ERR_WORKSPACE;
+  std::vector<GmsPair> table((size_t)idx->P);
+  for (int p = 0; p < idx->P; ++p) {
+    table[p].w1 = size1[2 * p];
+    table[p].h1 = size1[2 * p + 1];
+    table[p].w2 = 2.0 * idx->pairs[p].cx;  // cx = w2 / 2 exactly
+    table[p].h2 = 2.0 * idx->pairs[p].cy;
+  }
+  char* ws = static_cast<char*>(workspace);
+  EPM_HIP(hipMemcpyAsync(ws + L.pairs, table.data(), sizeof(GmsPair) * table.size(),
+                         hipMemcpyHostToDevice, stream));
+  GmsArgs A;
+  A.pairs = reinterpret_cast<const GmsPair*>(ws + L.pairs);
+  A.qstart = idx->at<int64_t>(idx->L.qstart);
+  A.kstart = idx->at<int64_t>(idx->L.kstart);
+  A.num_pairs = idx->P;
+  A.n1 = idx->N1;
+  A.grid = grid;
+  A.alpha = alpha;
+  A.kp1 = kp1_xy;
+  A.kp2 = kp2_xy;
+  A.best = best_idx;
+  A.out = out_idx;
+  A.key = reinterpret_cast<int32_t*>(ws + L.key);
+  A.rcell = reinterpret_cast<int32_t*>(ws + L.rcell);
+  A.count = reinterpret_cast<uint32_t*>(ws + L.count);
+  A.cursor = reinterpret_cast<uint32_t*>(ws + L.cursor);
+  A.offsets = reinterpret_cast<const int64_t*>(ws + L.offsets);
+  A.list = reinterpret_cast<uint32_t*>(ws + L.list);
+  EPM_HIP(launch_gms(A, reinterpret_cast<int64_t*>(ws + L.partials), stream));
+  // the host table must outlive the copy
+  EPM_HIP(hipStreamSynchronize(stream));
+  return EPM_OK;
+}
+
 epm_status epm_mutual_check(const epm_index* idx, const int32_t* best12, const int32_t* best21,
                              int32_t* mutual, hipStream_t stream) {
   if (!idx) return EPM_ERR_ARG;

@@ -227,6 +227,33 @@ hipError_t launch_residuals(const PairDev* pairs, const int64_t* qstart, int num
                             int64_t n1, const float* kp1, const float* kp2, const int32_t* best,
                             float* residual, int64_t* feat_index, hipStream_t s);
 
+// GMS validation (see gms.hip).
+constexpr int kGmsMaxGrid = 32;
+constexpr int kGmsMaxCells = kGmsMaxGrid * kGmsMaxGrid;
+struct GmsPair {
+  double w1, h1, w2, h2;  // image sizes of the pair
+};
+struct GmsArgs {
+  const GmsPair* pairs;
+  const int64_t* qstart;
+  const int64_t* kstart;
+  int num_pairs;
+  int64_t n1;
+  int grid;
+  float alpha;
+  const float* kp1;
+  const float* kp2;
+  const int32_t* best;
+  int32_t* out;
+  int32_t* key;           // [n1] (pair, image-1 cell) of each match, -1 without one
+  int32_t* rcell;         // [n1] image-2 cell of each match
+  uint32_t* count;        // [pairs * grid^2] matches per (pair, cell)
+  uint32_t* cursor;       // [pairs * grid^2]
+  const int64_t* offsets; // [pairs * grid^2 + 1] exclusive scan of count
+  uint32_t* list;         // [n1] matches listed by (pair, cell)
+};
+hipError_t launch_gms(const GmsArgs& a, int64_t* partials, hipStream_t s);
+
 // mutual[i] = best12[i] when best21 (indexed by the global image-2 row) maps
 // that keypoint back to query i of the same pair, else -1.
 hipError_t launch_mutual(const int64_t* qstart, const int64_t* kstart, int num_pairs, int64_t n1,

@@ -239,3 +239,10 @@ def test_timing_kernel_argument_errors(lib):
 
 def test_mutual_check_argument_errors(lib):
     assert lib.epm_mutual_check(None, None, None, None, None) == 1
+
+
+def test_gms_argument_errors(lib):
+    import ctypes
+    size1 = (ctypes.c_int32 * 2)(640, 480)
+    assert lib.epm_gms_workspace_bytes(None, 20) == 0
+    assert lib.epm_gms(None, size1, 20, 6.0, None, None, None, None, None, 0, None) == 1
