@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "precision", "batch", "learned", "paper"],
+                    choices=["scale", "precision", "batch", "learned", "paper", "noise"],
                     help="scale: six 20000-keypoint pairs (default); precision: one "
                          "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs; "
-                         "paper: six 50000-keypoint pairs at eps 25/50/100 px")
+                         "paper: six 50000-keypoint pairs at eps 25/50/100 px; noise: "
+                         "pose-noise sweep at eps 200 px")
     ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
     ap.add_argument("--train-pairs", type=int, default=2000,
                     help="learned workload: training pairs")
@@ -598,6 +599,81 @@ def paper_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def noise_workload(args):
+    """The paper's noise-sensitivity setting: the relative pose behind F is
+    perturbed at noise levels 0, 1, 2, 3.3 and 4 (level 1: U(-1, 1) deg per
+    rotation axis, U(-0.25, 0.25) m per translation component; two draws per
+    level) while the keypoints keep the true geometry, and the tolerance is
+    raised to 200 px.  One step = build + query + FP32 match of the 20 pairs
+    (6048x4032, 20000 keypoints, sideways and forward motion) as one batch;
+    candidate and match recall of the true correspondences per level."""
+    import torch
+
+    import paper_2603_18401_amd as E
+    import synth
+
+    dev = torch.device("cuda:0")
+    levels = (0.0, 1.0, 2.0, 3.3, 4.0)
+    bases = [synth.cfg1_pair("sideways"), synth.cfg1_pair("forward")]
+    pairs, Fs, lv = [], [], []
+    for b_i, base in enumerate(bases):
+        for L in levels:
+            for d in range(2):
+                pairs.append(base)
+                Fs.append(synth.perturbed_F(base, L, 9000 + 100 * b_i + 10 * int(L * 10) + d))
+                lv.append(L)
+    eps = 200.0
+    specs = [E.PairSpec(F, p.W, p.H, p.m, p.n) for p, F in zip(pairs, Fs)]
+    N1 = sum(p.m for p in pairs)
+    g = {k: torch.from_numpy(np.ascontiguousarray(np.concatenate(v))).to(dev) for k, v in dict(
+        kp1=[p.kp1 for p in pairs], kp2=[p.kp2 for p in pairs], d1=[p.desc1 for p in pairs],
+        d2=[p.desc2 for p in pairs]).items()}
+    idx0 = E.Index(specs, g["kp2"], eps=eps)
+    ws = idx0.workspace
+    offs, cols = idx0.query(g["kp1"])
+    nnz = int(offs[-1].item())
+    idx0.close()
+    row_offsets = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    col_indices = torch.empty(nnz, dtype=torch.int32, device=dev)
+    outs = tuple(torch.empty(N1, dtype=t, device=dev)
+                 for t in (torch.int32, torch.float32, torch.float32))
+
+    def step():
+        idx = E.Index(specs, g["kp2"], eps=eps, workspace=ws)
+        idx.query_match(g["kp1"], g["d1"], g["d2"], row_offsets=row_offsets,
+                        col_indices=col_indices, out=outs, sync=False)
+        idx.close()
+
+    sec = time_steps(torch, step, args.steps, args.warmup)
+    # recall of the true correspondences, per noise level
+    n2 = pairs[0].n
+    rows = torch.repeat_interleave(torch.arange(N1, device=dev),
+                                   (row_offsets[1:] - row_offsets[:-1]))
+    keys = rows * (n2 + 1) + col_indices.to(torch.int64)
+    gt = torch.from_numpy(np.concatenate([p.gt12 for p in pairs]).astype(np.int64)).to(dev)
+    true = torch.nonzero(gt >= 0).flatten()
+    want = true * (n2 + 1) + gt[true]
+    pos = torch.searchsorted(keys, want).clamp(max=max(nnz - 1, 0))
+    cand_hit = (keys[pos] == want).cpu().numpy()
+    match_hit = (outs[0][true].to(torch.int64) == gt[true]).cpu().numpy()
+    qpair = np.repeat(np.arange(len(pairs)), [p.m for p in pairs])[true.cpu().numpy()]
+    per = []
+    for L in levels:
+        sel = np.isin(qpair, [k for k, v in enumerate(lv) if v == L])
+        per.append({"level": L, "candidate_recall": round(float(cand_hit[sel].mean()), 5),
+                    "match_recall": round(float(match_hit[sel].mean()), 5)})
+    line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64+f32+bf16", "data": "synthetic",
+            "config": {"workload": "pose-noise sweep: 20 pairs 6048x4032, 20000 keypoints, "
+                                   "sideways+forward x noise levels {0,1,2,3.3,4} x 2 draws, "
+                                   "eps 200 px", "queries_per_step": N1,
+                       "candidates_per_step": nnz, "kbar": round(nnz / N1, 2)},
+            "recall_by_level": per}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -613,6 +689,8 @@ def main():
         return learned_workload(args)
     if args.workload == "paper":
         return paper_workload(args)
+    if args.workload == "noise":
+        return noise_workload(args)
 
     import torch
 

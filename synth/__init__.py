@@ -21,6 +21,7 @@ from .pairs import (  # noqa: F401
     fundamental_from_cameras,
     intrinsics,
     make_pair,
+    perturbed_F,
     rot_axis_angle,
     skew,
 )

@@ -356,3 +356,18 @@ def batch_pairs(pairs):
         b.bin1 = np.ascontiguousarray(np.concatenate([p.bin1 for p in pairs]))
         b.bin2 = np.ascontiguousarray(np.concatenate([p.bin2 for p in pairs]))
     return b
+
+
+def perturbed_F(pair, level, seed):
+    """F from a relative pose perturbed at a noise level (the paper's noise
+    sensitivity experiment, Sec. 5): level 1 rotates by angles U(-1, 1) deg
+    about each axis and moves the translation by U(-0.25, 0.25) m per
+    component; level L scales both ranges by L.  The keypoints keep the true
+    geometry."""
+    rng = _rng(seed)
+    ang = np.deg2rad(rng.uniform(-1.0, 1.0, 3) * level)
+    Rn = (rot_axis_angle([1.0, 0.0, 0.0], ang[0]) @ rot_axis_angle([0.0, 1.0, 0.0], ang[1])
+          @ rot_axis_angle([0.0, 0.0, 1.0], ang[2]))
+    R = Rn @ pair.R
+    t = pair.t + rng.uniform(-0.25, 0.25, 3) * level
+    return fundamental_from_cameras(pair.K1, pair.K2, R, t)
