@@ -46,7 +46,9 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.qtiles = take(sizeof(SortTile) * tq);
   L.qsegs = take(sizeof(SortSeg) * P);
   L.stiles = take(sizeof(StabTile) * ts);
-  L.hist = take(sizeof(uint32_t) * 256 * (size_t)(tr > tq ? tr : tq));
+  // per-tile digit counts of every pass of the record (3) or query (2) sort
+  L.hist = take(sizeof(uint32_t) * 256 * (size_t)sort_passes(kSortBits) *
+                (size_t)(tr > tq ? tr : tq));
   L.rk0 = take(4 * N2);
   L.rv0 = take(4 * N2);
   L.rk1 = take(4 * N2);
@@ -85,6 +87,12 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
 }
 
 int64_t tiles_of(int64_t count) { return (count + kSortTile - 1) / kSortTile; }
+
+int max_tiles(const std::vector<SortSeg>& segs) {
+  int m = 0;
+  for (const SortSeg& g : segs) m = g.tile_count > m ? g.tile_count : m;
+  return m;
+}
 int64_t stab_tiles_of(int64_t m) { return (m + kTileQ - 1) / kTileQ; }
 
 bool validate_pairs(const epm_pair* pairs, int32_t num_pairs, int64_t* n1, int64_t* n2) {
@@ -354,8 +362,9 @@ epm_status enqueue_build(epm_index* idx, const float* kp2_xy, const float* eps2,
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
                                idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
                                idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
-                               idx->at<SortSeg>(L.rsegs), P, idx->at<uint32_t>(L.hist), kSortBits,
-                               &in1, stream, idx->at<uint32_t>(L.digit_base)));
+                               idx->at<SortSeg>(L.rsegs), P, max_tiles(idx->rsegs),
+                               idx->at<uint32_t>(L.hist), kSortBits, &in1, stream,
+                               idx->at<uint32_t>(L.digit_base)));
   const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
   const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
   EPM_HIP(launch_gather_records(dkstart, P, n2, sval, kp2_xy, eps2, eps_scalar,
@@ -438,8 +447,8 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
                                idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
                                idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
-                               idx->at<SortSeg>(L.qsegs), idx->P, idx->at<uint32_t>(L.hist), 16,
-                               &in1, stream));
+                               idx->at<SortSeg>(L.qsegs), idx->P, max_tiles(idx->qsegs),
+                               idx->at<uint32_t>(L.hist), 16, &in1, stream));
   idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
   idx->have_qperm = true;
   A.qperm = idx->qperm;

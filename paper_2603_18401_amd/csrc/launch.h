@@ -37,10 +37,14 @@ hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
 // ended in (k1, v1).
 // last_digit_base (optional, [num_segs][256]): global start of every digit
 // value of the last pass inside each segment.
+// hist: [sort_passes(bits)][num_tiles][256] words; max_seg_tiles: the most
+// tiles of one segment (up to 64 a pass is a single launch).
+int sort_passes(int bits);
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
-                                int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
-                                hipStream_t s, uint32_t* last_digit_base = nullptr);
+                                int num_segs, int max_seg_tiles, uint32_t* hist, int bits,
+                                bool* sorted_in_1, hipStream_t s,
+                                uint32_t* last_digit_base = nullptr);
 
 struct StabArgs {
   const PairDev* pairs;

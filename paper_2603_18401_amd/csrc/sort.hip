@@ -9,6 +9,10 @@
 // Per 8-bit pass: k_sort_hist (per-tile digit counts), k_sort_offsets (one
 // workgroup per segment turns the counts into global start offsets, in place)
 // and k_sort_scatter (stable ranking with wavefront ballots, then the write).
+// When no segment has more than kFusedTiles tiles, a pass is one launch:
+// k_sort_pass finds its tile's offsets from the per-tile counts of its
+// segment itself and, while writing, counts the next pass's digits into the
+// tiles the elements land in, so only the first pass needs k_sort_hist.
 #include "device_common.h"
 #include "launch.h"
 
@@ -19,13 +23,18 @@ namespace {
 constexpr int kRadix = 256;
 constexpr int kWavesPerBlock = kSortThreads / kWave;
 
+// zero_passes > 0: also clears this tile's counts of the next zero_passes
+// passes (the fused sort accumulates them with atomics).
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys,
                                                             const SortTile* __restrict__ tiles,
                                                             int shift,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            int zero_passes) {
   __shared__ uint32_t h[kRadix];
   const int tid = threadIdx.x;
   h[tid] = 0;
+  for (int p = 1; p <= zero_passes; ++p)
+    hist[((int64_t)p * gridDim.x + blockIdx.x) * kRadix + tid] = 0u;
   __syncthreads();
   const SortTile t = tiles[blockIdx.x];
   for (int k = tid; k < t.count; k += kSortThreads)
@@ -122,18 +131,151 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
 }
 
+constexpr int kFusedTiles = 64;
+
+// One pass of the fused sort.  hist: this pass's per-tile digit counts;
+// hist_next: the next pass's (zero on entry), or NULL on the last pass.
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const SortTile* __restrict__ tiles,
+    const SortSeg* __restrict__ segs, int num_segs, int shift, const uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ hist_next, uint32_t* __restrict__ seg_base) {
+  __shared__ uint32_t run[kRadix];
+  __shared__ uint32_t wsum[kWavesPerBlock];
+  __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const SortTile t = tiles[blockIdx.x];
+  const SortSeg sg = segs[t.seg];
+  static_assert(kSortThreads == kRadix, "one digit per thread");
+  // the tile's keys and values, loaded while the offsets are worked out
+  constexpr int kRounds = kSortTile / kSortThreads;
+  uint32_t rk[kRounds], rv[kRounds];
+  #pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int idx = r * kSortThreads + tid;
+    rk[r] = idx < t.count ? kin[t.begin + idx] : 0u;
+    rv[r] = idx < t.count ? vin[t.begin + idx] : 0u;
+  }
+  const int mine = (int)blockIdx.x - sg.tile_begin;
+  // digit d = tid: count in the segment's earlier tiles, and in all of them
+  {
+    uint32_t before = 0, total = 0;
+    const uint32_t* hd = hist + (int64_t)sg.tile_begin * kRadix + tid;
+    constexpr int kBatch = 16;  // tiles whose counts are in flight at once
+    for (int t0 = 0; t0 < sg.tile_count; t0 += kBatch) {
+      uint32_t c[kBatch];
+      #pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        c[u] = t0 + u < sg.tile_count ? hd[(int64_t)(t0 + u) * kRadix] : 0u;
+      #pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        total += c[u];
+        before += t0 + u < mine ? c[u] : 0u;
+      }
+    }
+    // exclusive scan of the totals over the digits: wavefront scans, then
+    // the wavefront totals
+    uint32_t incl = total;
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    #pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) incl += w < wave ? wsum[w] : 0u;
+    const uint32_t start = (uint32_t)sg.begin + incl - total;
+    run[tid] = start + before;
+    if (seg_base && mine == 0) seg_base[(int64_t)t.seg * kRadix + tid] = start;
+    // segments without elements have no tile: the first workgroup writes
+    // their (empty) digit starts
+    if (seg_base && blockIdx.x == 0) {
+      for (int g = tid; g < num_segs; g += kSortThreads) {
+        const SortSeg e = segs[g];
+        if (e.count == 0)
+          for (int dd = 0; dd < kRadix; ++dd) seg_base[(int64_t)g * kRadix + dd] = (uint32_t)e.begin;
+      }
+    }
+  }
+  const int nshift = shift + 8;
+  #pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int base = r * kSortThreads;
+    if (base >= t.count) break;  // uniform
+    const int idx = base + tid;
+    const bool valid = idx < t.count;
+    const uint32_t key = rk[r];
+    const uint32_t val = rv[r];
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    uint64_t same = ballot(valid);
+    #pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = ballot(valid && bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t rank = lanes_below(same);
+    #pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+      if (hist_next) {
+        // the tile of the segment that position pos belongs to next pass
+        const int64_t nt = sg.tile_begin + ((int64_t)pos - sg.begin) / kSortTile;
+        atomicAdd(&hist_next[nt * kRadix + ((key >> nshift) & (kRadix - 1))], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    #pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+int sort_passes(int bits) { return (bits + 7) / 8; }
 
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
-                                int num_segs, uint32_t* hist, int bits, bool* sorted_in_1,
-                                hipStream_t s, uint32_t* last_digit_base) {
+                                int num_segs, int max_seg_tiles, uint32_t* hist, int bits,
+                                bool* sorted_in_1, hipStream_t s, uint32_t* last_digit_base) {
   *sorted_in_1 = false;
   if (num_tiles == 0) return hipSuccess;
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  if (max_seg_tiles <= kFusedTiles) {
+    const int npass = sort_passes(bits);
+    // counts of passes 1 .. npass-1 are accumulated by the previous pass
+    // into rows this launch clears
+    hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, 0,
+                       hist, npass - 1);
+    for (int p = 0; p < npass; ++p) {
+      const bool last = p + 1 == npass;
+      uint32_t* h = hist + (int64_t)p * num_tiles * kRadix;
+      hipLaunchKernelGGL(k_sort_pass, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
+                         tiles, segs, num_segs, 8 * p, h,
+                         last ? nullptr : h + (int64_t)num_tiles * kRadix,
+                         last ? last_digit_base : nullptr);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      uint32_t* tk = ki; ki = ko; ko = tk;
+      uint32_t* tv = vi; vi = vo; vo = tv;
+      *sorted_in_1 = !*sorted_in_1;
+    }
+    return hipSuccess;
+  }
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, shift,
-                       hist);
+                       hist, 0);
     const bool last = shift + 8 >= bits;
     hipLaunchKernelGGL(k_sort_offsets, dim3(num_segs), dim3(kSortThreads), 0, s, segs, hist,
                        last ? last_digit_base : nullptr);
