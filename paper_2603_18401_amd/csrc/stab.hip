@@ -185,7 +185,6 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
 static_assert(kTileQ == 64, "pair indexing uses a 6-bit query field");
-static_assert(kStage == 2 * kWave, "the copy pass holds two staged entries per lane");
 
 __device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict__ keys,
                                                       int64_t lo, int64_t hi, uint32_t target) {
@@ -598,21 +597,22 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
   }
 }
 
-// Fill pass, part 1: one wavefront per query in natural order copies the
-// parked (already sorted) short rows; longer rows of brute-force queries are
-// queued for part 2 (those of normal queries go to the wide-row pass).
+// Fill pass, part 1: sixteen lanes per query, queries in natural order, copy
+// the parked (already sorted) short rows; longer rows of brute-force queries
+// are queued for part 2 (those of normal queries go to the wide-row pass).
+constexpr int kCopyLanes = 16;
+constexpr int kCopyQueries = kThreads / kCopyLanes;
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
-  const int lane = lane_id(), wave = wave_id();
-  const int64_t i = (int64_t)blockIdx.x * kWaves + wave;
+  const int sub = (int)(threadIdx.x & (kCopyLanes - 1));
+  const int64_t i = (int64_t)blockIdx.x * kCopyQueries + (threadIdx.x / kCopyLanes);
   if (i >= A.n1) return;
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
   if (len <= kStage) {
-    const int n = (int)len;
-    if (lane < n && o0 + lane < A.capacity) A.cols[o0 + lane] = A.staging[i * kStage + lane];
-    if (lane + kWave < n && o0 + kWave + lane < A.capacity)
-      A.cols[o0 + kWave + lane] = A.staging[i * kStage + kWave + lane];
-  } else if (lane == 0 && A.qflag[i] != kQueryNormal) {
+    const int32_t* src = A.staging + i * kStage;
+    for (int k = sub; k < (int)len; k += kCopyLanes)
+      if (o0 + k < A.capacity) A.cols[o0 + k] = src[k];
+  } else if (sub == 0 && A.qflag[i] != kQueryNormal) {
     // long rows of normal queries belong to the wide-row pass of their tile
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
@@ -744,7 +744,8 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  const int64_t cblocks = (a.n1 + kCopyQueries - 1) / kCopyQueries;
+  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)cblocks), dim3(kThreads), 0, s, a);
   const int64_t lblocks = blocks < 512 ? blocks : 512;
   hipLaunchKernelGGL(k_fill_long, dim3((unsigned)lblocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
