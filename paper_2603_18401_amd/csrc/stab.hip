@@ -186,13 +186,28 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
 constexpr int kQPerWave = kTileQ / kWaves;
 static_assert(kTileQ == 64, "pair indexing uses a 6-bit query field");
 
+// First index in [lo, hi) whose key is >= target (keys ascending), by one
+// lane: seven probes in flight per step cut the range to an eighth.
 __device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict__ keys,
                                                       int64_t lo, int64_t hi, uint32_t target) {
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < target) lo = mid + 1; else hi = mid;
+  // the answer lies in [lo, hi]
+  while (hi - lo > 8) {
+    const int64_t step = (hi - lo) / 8;
+    uint32_t k[7];
+    #pragma unroll
+    for (int m = 0; m < 7; ++m) k[m] = keys[lo + (m + 1) * step];
+    int c = 0;  // the probes below the target are a prefix
+    #pragma unroll
+    for (int m = 0; m < 7; ++m) c += k[m] < target ? 1 : 0;
+    const int64_t nlo = c == 0 ? lo : lo + c * step + 1;
+    const int64_t nhi = c == 7 ? hi : lo + (c + 1) * step;
+    lo = nlo;
+    hi = nhi;
   }
-  return lo;
+  int c = 0;
+  #pragma unroll
+  for (int m = 0; m < 8; ++m) c += lo + m < hi && keys[lo + m] < target ? 1 : 0;
+  return lo + c;
 }
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
