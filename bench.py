@@ -583,7 +583,7 @@ def paper_workload(args):
                                    "queries per step), FP32 descriptors",
                        "queries_per_step": N1, "candidates_per_step": nnz,
                        "kbar": round(nnz / N1, 2), "wide_rows": nw},
-            "roofline": {"bound": "hbm", "kernel": "k_wide_tile<true> (wide rows: CSR + "
+            "roofline": {"bound": "hbm", "kernel": "k_wide_tile<1> (wide rows: CSR + "
                                                    "FP32 selection)",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4),
