@@ -25,7 +25,8 @@ struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
-  size_t digit_base, windows, match_stats, sched, tile_cost, order, rest, tile_wide, qline;
+  size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
+      qline;
   size_t total;
 };
 
@@ -79,6 +80,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.sched = take(sizeof(uint32_t) * kSchedWords);
   L.tile_cost = take(sizeof(uint32_t) * ts);
   L.order = take(sizeof(uint32_t) * ts);
+  L.block_tile = take(sizeof(uint32_t) * ts);
   L.rest = take(sizeof(uint32_t) * N1);
   L.tile_wide = take(sizeof(uint32_t) * ts);
   L.qline = take(sizeof(double4) * N1);
@@ -412,6 +414,8 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.tile_cost = nullptr;
   A.order = nullptr;
   A.queue = nullptr;
+  A.xcd_hist = nullptr;
+  A.block_tile = nullptr;
   A.desc1 = nullptr;
   A.desc2 = nullptr;
   A.ratio = 0.0f;
@@ -455,14 +459,21 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   const epm_sched& S = idx->sched;
   const bool persistent = S.stab_workgroups > 0 || S.match_workgroups > 0;
   const bool lpt = persistent && S.lpt == 1;
+  // one workgroup per tile: the tiles of every XCD run longest first
+  const bool xcd_lpt = S.stab_workgroups == 0;
   uint32_t* sched = idx->at<uint32_t>(L.sched);
-  EPM_HIP(launch_clear_stats(A.stats, stream));
-  if (persistent) EPM_HIP(launch_fill_u32(sched, kSchedWords, 0u, stream));
-  A.tile_cost = lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
+  EPM_HIP(launch_clear_stats(A.stats, stream, sched));
+  A.tile_cost = lpt || xcd_lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
+  A.xcd_hist = xcd_lpt ? sched + kSchedXHist : nullptr;
   EPM_HIP(launch_tile_windows(A, stream));
   if (lpt) {
     EPM_HIP(launch_lpt_order(A.tile_cost, A.num_tiles, sched, idx->at<uint32_t>(L.order), stream));
     idx->have_order = true;
+  }
+  if (xcd_lpt) {
+    EPM_HIP(launch_xcd_lpt_order(A.tile_cost, A.num_tiles, sched,
+                                 idx->at<uint32_t>(L.block_tile), stream));
+    A.block_tile = idx->at<uint32_t>(L.block_tile);
   }
   if (S.stab_workgroups > 0) {
     A.queue = sched + kSchedStabQueue;

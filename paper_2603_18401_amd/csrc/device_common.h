@@ -30,6 +30,22 @@ __device__ __forceinline__ int xcd_tile(int block, int n) {
   return (g * kNumXcd + x) * kXcdGroup + o;
 }
 
+// XCD that xcd_tile gives tile t: the inverse of the mapping above, mod 8.
+__device__ __forceinline__ int xcd_of_tile(int t, int n) {
+  constexpr int round = kNumXcd * kXcdGroup;
+  const int full = (n / round) * round;
+  return t >= full ? t % kNumXcd : (t / kXcdGroup) % kNumXcd;
+}
+
+// Cost bucket of the longest-first orders: 0 for no work, else two buckets
+// per power of two (the bit below the leading one splits an octave).
+__device__ __forceinline__ int cost_bucket(uint32_t c) {
+  if (c == 0) return 0;
+  const int msb = 31 - __clz(c);
+  const int half = msb > 0 ? (int)((c >> (msb - 1)) & 1u) : 0;
+  return 1 + 2 * msb + half;
+}
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

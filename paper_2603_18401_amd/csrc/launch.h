@@ -77,6 +77,8 @@ struct StabArgs {
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
   uint32_t* queue;            // persistent launch: next-tile counter, zero at launch
+  uint32_t* xcd_hist;         // [kLptXcd][kCostBuckets] tile costs per XCD, or NULL
+  const uint32_t* block_tile;  // one workgroup per tile: tile of each workgroup, or NULL
   // fused matching (FP32 descriptors), see launch_stab_tiles
   const float* desc1;
   const float* desc2;
@@ -94,16 +96,25 @@ struct StabArgs {
 };
 
 // Scheduling counters (u32 words of one workspace block).
-constexpr int kCostBuckets = 33;  // cost 0, then one bucket per power of two
+constexpr int kCostBuckets = 65;  // cost 0, then two buckets per power of two
+constexpr int kLptXcd = 8;        // XCDs the workgroups of a launch are dealt to in turn
 constexpr int kSchedHist = 0, kSchedCursor = kCostBuckets, kSchedStabQueue = 2 * kCostBuckets,
-              kSchedMatchQueue = 2 * kCostBuckets + 1;
-constexpr int kSchedWords = 2 * kCostBuckets + 2;
+              kSchedMatchQueue = 2 * kCostBuckets + 1, kSchedXHist = 2 * kCostBuckets + 2,
+              kSchedXCursor = kSchedXHist + kLptXcd * kCostBuckets;
+constexpr int kSchedWords = kSchedXCursor + kLptXcd * kCostBuckets;
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // Longest-first order of the tiles from their costs; the histogram and cursor
 // words of `sched` must be zero.
 hipError_t launch_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
                             uint32_t* order, hipStream_t s);
+// One workgroup per tile, longest first on every XCD: block_tile[b] for the
+// workgroups b = x, x + 8, ... of XCD x lists the tiles that the XCD-grouped
+// angle order gives that XCD, by decreasing cost.  The per-XCD histogram
+// (sched + kSchedXHist, filled by launch_tile_windows through xcd_hist) must
+// be complete and the cursor words zero.
+hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
+                                uint32_t* block_tile, hipStream_t s);
 
 // One wavefront per tile finds the tile's window in every width class.
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
@@ -111,7 +122,8 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
 constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
               kStatLongRows = 4, kStatRest = 5;
 constexpr int kNumStats = 6;
-hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s);
+// Clears the counters, and the kSchedWords scheduling words unless sched is NULL.
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched = nullptr);
 
 // Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
 // workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.

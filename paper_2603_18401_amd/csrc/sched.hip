@@ -16,8 +16,8 @@ namespace epm {
 namespace {
 
 constexpr int kThreads = 256;
-
-__device__ __forceinline__ int cost_bucket(uint32_t c) { return c ? 32 - __clz(c) : 0; }
+static_assert(kLptXcd == kNumXcd, "the XCD order follows xcd_tile");
+static_assert(kCostBuckets == 65, "cost_bucket: 1 + 2 x 31 + 1 is the largest bucket");
 
 __global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t* __restrict__ p, int64_t n,
                                                        uint32_t v) {
@@ -68,7 +68,51 @@ __global__ __launch_bounds__(kThreads) void k_lpt_scatter(const uint32_t* __rest
   if (t < n) order[base[b] + rank] = (uint32_t)t;
 }
 
+// Per-XCD longest-first layout: tile t of XCD x and bucket b goes to rank
+// k = (tiles of XCD x in buckets above b) + its place in (x, b), i.e. to the
+// workgroup k * 8 + x.
+__global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __restrict__ cost,
+                                                              int n,
+                                                              const uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ cursor,
+                                                              uint32_t* __restrict__ block_tile) {
+  constexpr int kBins = kNumXcd * kCostBuckets;
+  __shared__ uint32_t h[kBins], base[kBins];
+  const int tid = (int)threadIdx.x;
+  for (int k = tid; k < kBins; k += kThreads) h[k] = 0u;
+  __syncthreads();
+  const int t = (int)blockIdx.x * kThreads + tid;
+  int bin = 0;
+  uint32_t rank = 0;
+  if (t < n) {
+    bin = xcd_of_tile(t, n) * kCostBuckets + cost_bucket(cost[t]);
+    rank = atomicAdd(&h[bin], 1u);
+  }
+  __syncthreads();
+  for (int k = tid; k < kBins; k += kThreads) {
+    if (!h[k]) continue;
+    const int x = k / kCostBuckets, b = k % kCostBuckets;
+    uint32_t start = 0;
+    for (int c = kCostBuckets - 1; c > b; --c) start += hist[x * kCostBuckets + c];
+    base[k] = start + atomicAdd(&cursor[k], h[k]);
+  }
+  __syncthreads();
+  if (t < n) {
+    const uint32_t k = base[bin] + rank;
+    block_tile[k * kNumXcd + (uint32_t)(bin / kCostBuckets)] = (uint32_t)t;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
+                                uint32_t* block_tile, hipStream_t s) {
+  if (num_tiles == 0) return hipSuccess;
+  const int blocks = (num_tiles + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_xcd_lpt_scatter, dim3(blocks), dim3(kThreads), 0, s, cost, num_tiles,
+                     sched + kSchedXHist, sched + kSchedXCursor, block_tile);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -184,6 +184,7 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
 
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
+static_assert(kQPerWave == 16, "the pair test packs four records of 16 queries per wavefront");
 static_assert(kTileQ == 64, "pair indexing uses a 6-bit query field");
 
 // First index in [lo, hi) whose key is >= target (keys ascending), by one
@@ -208,6 +209,12 @@ __device__ __forceinline__ int64_t lower_bound_scalar(const uint32_t* __restrict
   #pragma unroll
   for (int m = 0; m < 8; ++m) c += lo + m < hi && keys[lo + m] < target ? 1 : 0;
   return lo + c;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  #pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
@@ -301,84 +308,101 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
     const uint64_t nb = (uint64_t)__popcll(ballot(brute));
     if (lane == 0) {
       const uint64_t c = nn * wlen + nb * (uint64_t)A.pairs[T.pair].n + (uint64_t)T.count;
-      A.tile_cost[t] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+      const uint32_t c32 = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+      A.tile_cost[t] = c32;
+      if (A.xcd_hist)
+        atomicAdd(&A.xcd_hist[xcd_of_tile(t, A.num_tiles) * kCostBuckets + cost_bucket(c32)], 1u);
     }
   }
 }
 
 // Counts every row of a tile of kTileQ angle-sorted queries and parks rows of
-// up to kStage candidates (in any order) in the staging buffer.  The window
-// records of the tile are staged in LDS, and every (query, record) pair of
-// the tile is an independent work item: thread -> pair with consecutive
-// threads on different queries of the same record (the record is an LDS
-// broadcast), angle test, FP64 test, and an LDS atomic slot in the query's
-// hit list.  No wavefront-wide dependency chains.
+// up to kStage candidates in ascending j in the staging buffer.  The window
+// records of the tile are staged in LDS; wavefront w owns queries 16w..16w+15
+// (lane & 15), whose lines stay in registers, and tests them against four
+// records per step (lane >> 4, LDS broadcasts): angle test, FP64 test, and the
+// hit's slot from a ballot over the query's four lanes, so no atomics are
+// needed and every row lists its hits in ascending window position.
 //
 // FUSE: the same pass also selects every query's match (Sec. 4.3) from its
-// hit list while the list is still in LDS: the hits keep their window
-// positions, the window's descriptor rows are staged kFuseRows at a time
-// (over the record chunk buffers, dead by then), and four lanes per query
-// evaluate canonical FP32 distances of that query's hits in the chunk and
-// keep a top-2, merged across the four lanes at the end.  Rows longer than
-// kStage are matched by the wide-row pass; the other queries this cannot
-// serve (brute-force rows, windows longer than 16-bit positions) are listed
-// for the listed-query match after the CSR is complete; empty rows get their
-// (-1, inf, inf) here.
+// hit list while the list is still in LDS.  The hits are kept as 16-bit
+// window positions (their j from the window's j, kept in LDS for windows of
+// up to kKeepJ records); the window's descriptor rows are copied to LDS
+// kFuseRows at a time (over the record chunk buffers, dead by then), and four
+// lanes per query evaluate canonical FP32 distances of that query's hits in
+// the chunk, each lane resuming where the last chunk left it, and keep a
+// top-2, merged across the four lanes at the end.  Rows longer than kStage are
+// matched by the wide-row pass; the rows this pass does not keep (brute-force
+// queries, windows longer than kKeepJ) are marked for the fill pass to
+// rebuild, and those queries are listed for the listed-query match after the
+// CSR is complete; empty rows get their (-1, inf, inf) here.  The LDS and
+// register budget allows three workgroups per CU.
 constexpr int kFuseRows = 32;
 constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
 constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
-constexpr int kFuseBytes = kFuseRows * kFuseStride * 4;
-constexpr int64_t kFuseMaxWindow = 65535;
+// The staged rows are copied straight from global memory to LDS (lane l of a
+// wavefront copy writes 16-byte chunk l of it): kFuseCopies wavefront copies
+// cover the rows with their padding, and the tail of the last one is slack.
+constexpr int kFuseChunks = kFuseRows * (kFuseStride / 4);
+constexpr int kFuseCopies = (kFuseChunks + kWave - 1) / kWave;
+constexpr int kFuseBytes = kFuseCopies * kWave * 16;
+// First entry of a parked row that was not parked: the fill pass rebuilds it.
+constexpr int32_t kRowNotParked = -1;
 
-// This thread's share of window chunk [c0, c0 + kFuseRows): row f >> 5,
-// 16-byte column f & 31, for f = tid + kThreads u (rows past the window end
-// repeat its last row).
-constexpr int kFusePer = kFuseRows * 32 / kThreads;
-struct FuseRows {
-  float4 v[kFusePer];
-};
+// FUSE: the j of the first kKeepJ window positions stay in LDS; the hits
+// are kept as 16-bit window positions, and tiles with longer windows are not
+// fused (their rows are rebuilt by the fill pass and matched from the list)
+constexpr int kKeepJ = 2048;
+constexpr int64_t kFuseMaxWindow = kKeepJ;
 
-__device__ __forceinline__ FuseRows fuse_fetch(const StabArgs& A, int64_t c0, int64_t total_len,
-                                               int64_t kb, bool local_j, const int32_t* sJ,
-                                               const uint32_t* slot_b,
-                                               const uint32_t* slot_pref, int tid) {
-  const int64_t nr = total_len - c0 < kFuseRows ? total_len - c0 : kFuseRows;
-  FuseRows out;
-  #pragma unroll
-  for (int u = 0; u < kFusePer; ++u) {
-    const int f = tid + u * kThreads;
-    const int64_t r = (f >> 5) < nr ? (f >> 5) : nr - 1;
-    const int64_t virt = c0 + r;
-    int32_t j;
-    if (local_j) {
-      j = sJ[virt];
-    } else {
-      int sl = 0;  // last slot with slot_pref[sl] <= virt
-      #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (sl + step <= kSlots && slot_pref[sl + step] <= virt) sl += step;
-      j = A.rj[slot_b[sl] + (virt - slot_pref[sl])];
-    }
-    out.v[u] = reinterpret_cast<const float4*>(A.desc2)[(kb + j) * 32 + (f & 31)];
+// Starts the copy of rows [c0, c0 + nr) of the window (0 < nr <= kFuseRows)
+// to LDS at a stride of kFuseStride floats.  Chunk p of the image is column
+// p % 33 of row p / 33; the padding column and the rows past nr repeat real
+// data.  The copies complete asynchronously: wait for them (vmcnt) before the
+// barrier that publishes the rows.
+__device__ __forceinline__ void fuse_stage(const StabArgs& A, int c0, int nr, int64_t kb,
+                                           const int32_t* sJ, float4* rows4, int wave, int lane) {
+  constexpr int kRowChunks = kFuseStride / 4;
+  for (int g = wave; g < kFuseCopies; g += kWaves) {
+    const int p = g * kWave + lane;
+    int r = p / kRowChunks;
+    int c = p - r * kRowChunks;
+    r = r < nr ? r : nr - 1;
+    c = c < 32 ? c : 31;
+    const float4* src = reinterpret_cast<const float4*>(A.desc2) + (kb + sJ[c0 + r]) * 32 + c;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)(rows4 + g * kWave),
+                                     16, 0, 0);
   }
-  return out;
 }
 
+// s_waitcnt vmcnt(0): this wavefront's copies to LDS have landed.
+__device__ __forceinline__ void wait_lds_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// FUSE: three workgroups per CU (LDS and registers are sized for it)
 template <bool PERSIST, bool FUSE>
-__global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
-  // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps it for the match
-  // phase), reused for descriptor rows in the match phase
+__global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A) {
+  // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps the window's j
+  // in sJ_keep), reused for descriptor rows in the match phase
   constexpr int kRecRaw = FUSE ? kRecBytes - kChunk * 4 : kRecBytes;
   constexpr int kRaw = FUSE && kFuseBytes > kRecRaw ? kFuseBytes : kRecRaw;
   __shared__ __attribute__((aligned(16))) unsigned char raw[kRaw];
-  __shared__ int32_t sJ_keep[FUSE ? kChunk : 1];
+  __shared__ int32_t sJ_keep[FUSE ? kKeepJ : 1];
   uint32_t* sC = reinterpret_cast<uint32_t*>(raw);
   uint32_t* sH = sC + kChunk;
   float2* sXY = reinterpret_cast<float2*>(sH + kChunk);
   float* sE = reinterpret_cast<float*>(sXY + kChunk);
-  int32_t* sJ = FUSE ? sJ_keep : reinterpret_cast<int32_t*>(sE + kChunk);
-  __shared__ int32_t hits[kTileQ][kStage + 1];  // +1: rows start in different banks
-  __shared__ uint16_t hits_v[FUSE ? kTileQ : 1][FUSE ? kStage + 2 : 1];  // window positions
+  int32_t* sJ = reinterpret_cast<int32_t*>(sE + kChunk);  // not FUSE
+  // hit lists: image-2 indices, or (FUSE) 16-bit window positions
+  __shared__ int32_t hits[FUSE ? 1 : kTileQ][FUSE ? 1 : kStage + 1];  // +1: rows in different banks
+  __shared__ uint16_t hits_v[FUSE ? kTileQ : 1][FUSE ? kStage + 2 : 1];
+  // image-2 index of hit u of query q
+  const auto hit_j = [&](int q, uint32_t u) -> int32_t {
+    if constexpr (FUSE)
+      return sJ_keep[hits_v[q][u]];
+    else
+      return hits[q][u];
+  };
   __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ], qn[kTileQ];
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
@@ -399,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       tile = A.order ? (int)A.order[t] : t;
     } else {
       if (iter > 0) break;
-      tile = xcd_tile(blockIdx.x, A.num_tiles);
+      tile = A.block_tile ? (int)A.block_tile[blockIdx.x] : xcd_tile(blockIdx.x, A.num_tiles);
     }
     const StabTile T = A.tiles[tile];
     const PairDev& pd = A.pairs[T.pair];
@@ -437,6 +461,14 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
 
     const int64_t total_len = slot_pref[kSlots];
     uint32_t scanned = 0, angle_hits = 0;
+    // this lane's query of the pair test: its line stays in registers
+    const int lq = wave * kQPerWave + (lane & (kQPerWave - 1));
+    const bool line_live = qmode[lq] == kQueryNormal;
+    const bool any_live = ballot(line_live) != 0;
+    const uint32_t lkey = qk[lq];
+    const double la = qa[lq], lb = qb[lq], lc = qc[lq], ln = qn[lq];
+    const uint64_t same_query = 0x0001000100010001ull << (lane & (kQPerWave - 1));
+    uint32_t lcnt = 0;
     for (int64_t base = 0; base < total_len; base += kChunk) {
       const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
       for (int v = tid; v < clen; v += kThreads) {
@@ -450,27 +482,45 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         sH[v] = A.rH[pos];
         sXY[v] = A.rxy[pos];
         sE[v] = A.reps[pos];
-        sJ[v] = A.rj[pos];
+        if (!FUSE)
+          sJ[v] = A.rj[pos];
+        else if (virt < kKeepJ)
+          sJ_keep[virt] = A.rj[pos];
       }
       __syncthreads();
-      const int npairs = clen * kTileQ;
-      for (int p = tid; p < npairs; p += kThreads) {
-        const int q = p & (kTileQ - 1);
-        const int r = p >> 6;
-        if (qmode[q] != kQueryNormal) continue;
-        ++scanned;
-        if (key_distance(qk[q], sC[r]) > sH[r]) continue;
-        ++angle_hits;
-        const float2 xy = sXY[r];
-        if (!within_tolerance_n(qa[q], qb[q], qc[q], qn[q], xy.x, xy.y, sE[r])) continue;
-        const uint32_t slot = atomicAdd(&cnt[q], 1u);
-        if (slot < (uint32_t)kStage) {
-          hits[q][slot] = sJ[r];
-          if (FUSE) hits_v[q][slot] = (uint16_t)(base + r);
+      if (any_live) {
+        // this wave's 16 queries (lane & 15) against four records per step
+        // (lane >> 4); a hit's slot is the query's count plus its rank among
+        // the query's lanes of the step, so every row lists its hits in
+        // ascending window position
+        if (line_live && lane < kQPerWave) scanned += (uint32_t)clen;
+        for (int r0 = 0; r0 < clen; r0 += 4) {
+          const int r = r0 + (lane >> 4);
+          bool hit = false;
+          if (line_live && r < clen) {
+            const uint32_t C = sC[r], H = sH[r];
+            const float2 xy = sXY[r];
+            const float e = sE[r];
+            const bool ang = key_distance(lkey, C) <= H;
+            angle_hits += ang ? 1u : 0u;
+            hit = ang && within_tolerance_n(la, lb, lc, ln, xy.x, xy.y, e);
+          }
+          const uint64_t m = ballot(hit) & same_query;
+          if (hit) {
+            const uint32_t slot = lcnt + lanes_below(m);
+            if (slot < (uint32_t)kStage) {
+              if (FUSE)
+                hits_v[lq][slot] = (uint16_t)(base + r);
+              else
+                hits[lq][slot] = sJ[r];
+            }
+          }
+          lcnt += (uint32_t)__popcll(m);
         }
       }
       __syncthreads();
     }
+    if (line_live && lane < kQPerWave) cnt[lq] = lcnt;
 
     // queries whose line misses the epipole too far: exact scan of the pair
     uint32_t brute = 0;
@@ -488,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
           hit = within_tolerance_n(a, b, c, nrm, xy.x, xy.y, A.reps[pos]);
         }
         const uint64_t m = ballot(hit);
-        if (hit) {
+        if (!FUSE && hit) {  // FUSE: counted only, the row is rebuilt by the fill pass
           const uint32_t slot = c0 + lanes_below(m);
           if (slot < (uint32_t)kStage) hits[q][slot] = A.rj[pos];
         }
@@ -497,8 +547,12 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       if (lane == 0) cnt[q] = c0;
     }
     if (A.stats) {
-      if (scanned) atomicAdd(&tile_stats[0], (unsigned long long)scanned);
-      if (angle_hits) atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
+      scanned = wave_sum_u32(scanned);
+      angle_hits = wave_sum_u32(angle_hits);
+      if (lane == 0) {
+        atomicAdd(&tile_stats[0], (unsigned long long)scanned);
+        atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
+      }
     }
     __syncthreads();
     if (A.stats && tid == 0) {
@@ -521,26 +575,48 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
       if (lane == 0) A.tile_wide[tile] = wm != 0 ? 1u : 0u;
     }
 
+    // FUSE: four threads per query select its match
+    const int q = tid >> 2, part = tid & 3;
+    const bool fusable = total_len <= kFuseMaxWindow;
+    const bool mine = FUSE && q < T.count && qmode[q] == kQueryNormal &&
+                      cnt[q] <= (uint32_t)kStage && fusable;
+
     // row lengths, and short rows parked in ascending j: four threads per
     // row, each placing a quarter of its hits by rank (the j of a row are
-    // distinct, so a hit's place is the number of smaller hits)
+    // distinct, so a hit's place is the number of smaller hits); a thread
+    // ranks up to four of its hits in one pass over the row
     if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
     {
-      const int q = tid >> 2, part = tid & 3;
       const uint32_t n = q < T.count && qmode[q] != kQueryEmpty ? cnt[q] : 0u;
-      if (n <= (uint32_t)kStage) {
-        int32_t* dst = A.staging + qidx[q] * kStage;
-        for (uint32_t t = part; t < n; t += 4) {
-          const int32_t v = hits[q][t];
-          uint32_t r = 0;
-          for (uint32_t u = 0; u < n; ++u) r += hits[q][u] < v ? 1u : 0u;
-          dst[r] = v;
+      // FUSE keeps only the hits of normal queries in fused windows; other
+      // short rows are marked (first entry -1) for the fill pass to rebuild
+      const bool here = !FUSE || (fusable && qmode[q] == kQueryNormal);
+      int32_t* dst = A.staging + qidx[q] * kStage;
+      if (n <= (uint32_t)kStage && here) {
+        for (uint32_t t0 = part; t0 < n; t0 += 16) {
+          int32_t v[4];
+          uint32_t r[4];
+          #pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            v[m] = t0 + 4 * m < n ? hit_j(q, t0 + 4 * m) : INT32_MIN;
+            r[m] = 0;
+          }
+          #pragma unroll 4
+          for (uint32_t u = 0; u < n; ++u) {
+            const int32_t h = hit_j(q, u);
+            #pragma unroll
+            for (int m = 0; m < 4; ++m) r[m] += h < v[m] ? 1u : 0u;
+          }
+          #pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (t0 + 4 * m < n) dst[r[m]] = v[m];
         }
+      } else if (n > 0 && n <= (uint32_t)kStage && part == 0) {
+        dst[0] = kRowNotParked;
       }
     }
 
     if (FUSE) {
-      const bool fusable = total_len <= kFuseMaxWindow;
       if (tid < T.count) {
         const uint32_t mode = qmode[tid];
         if (mode == kQueryEmpty) {
@@ -551,16 +627,10 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
           A.rest[at] = (uint32_t)qidx[tid];
         }
       }
-      const int q = tid >> 2, part = tid & 3;
-      const bool mine = q < T.count && qmode[q] == kQueryNormal && cnt[q] <= (uint32_t)kStage &&
-                        fusable;
       const int nq = mine ? (int)cnt[q] : 0;
       const int64_t kb = pd.k_begin;
       float4* rows4 = reinterpret_cast<float4*>(raw);
-      // a window of one record chunk still has every row's j in LDS
-      const bool local_j = total_len <= kChunk;
-      FuseRows pre;
-      // the query's row stays in registers for all its hits
+      // the query row stays in registers for all its hits
       float4 qreg[32];
       {
         const float4* qrow = reinterpret_cast<const float4*>(A.desc1) + qidx[q] * 32;
@@ -568,30 +638,27 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
         for (int k = 0; k < 32; ++k) qreg[k] = mine ? qrow[k] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       Top2 best;
+      int cur = part;
       // tiles whose rows are all long (or empty) stage no descriptor rows
       const bool any_mine = __syncthreads_or(mine) != 0;
       if (fusable && total_len > 0 && any_mine) {
-        pre = fuse_fetch(A, 0, total_len, kb, local_j, sJ, slot_b, slot_pref, tid);
-        for (int64_t c0 = 0; c0 < total_len; c0 += kFuseRows) {
-          const int nr = (int)(total_len - c0 < kFuseRows ? total_len - c0 : kFuseRows);
+        const int wlen = (int)total_len;
+        for (int c0 = 0; c0 < wlen; c0 += kFuseRows) {
+          const int nr = wlen - c0 < kFuseRows ? wlen - c0 : kFuseRows;
           __syncthreads();  // the previous rows (or the record chunk) are no longer read
-          #pragma unroll
-          for (int u = 0; u < kFusePer; ++u) {
-            const int f = tid + u * kThreads;
-            if ((f >> 5) < nr) rows4[(f >> 5) * (kFuseStride / 4) + (f & 31)] = pre.v[u];
-          }
+          fuse_stage(A, c0, nr, kb, sJ_keep, rows4, wave, lane);
+          wait_lds_copies();
           __syncthreads();
-          if (c0 + kFuseRows < total_len)  // in flight during the distances below
-            pre = fuse_fetch(A, c0 + kFuseRows, total_len, kb, local_j, sJ, slot_b, slot_pref,
-                             tid);
-          for (int sl = part; sl < nq; sl += 4) {
-            const int64_t v = hits_v[q][sl];
-            if (v < c0 || v >= c0 + nr) continue;
+          // the row's hits are in ascending window position: this lane's
+          // hits in the chunk continue from where the previous chunk stopped
+          for (; cur < nq; cur += 4) {
+            const int v = hits_v[q][cur];
+            if (v >= c0 + nr) break;
             const float4* wr = rows4 + (v - c0) * (kFuseStride / 4);
             float acc = 0.0f;
             #pragma unroll
             for (int k = 0; k < 32; ++k) acc = canonical_step4(acc, qreg[k], wr[k]);
-            best.insert(acc, hits[q][sl]);
+            best.insert(acc, sJ_keep[v]);
           }
         }
       }
@@ -613,8 +680,9 @@ __global__ __launch_bounds__(kThreads) void k_stab_tile(StabArgs A) {
 }
 
 // Fill pass, part 1: sixteen lanes per query, queries in natural order, copy
-// the parked (already sorted) short rows; longer rows of brute-force queries
-// are queued for part 2 (those of normal queries go to the wide-row pass).
+// the parked (already sorted) short rows; short rows marked as not parked and
+// longer rows of brute-force queries are queued for part 2 (long rows of
+// normal queries go to the wide-row pass).
 constexpr int kCopyLanes = 16;
 constexpr int kCopyQueries = kThreads / kCopyLanes;
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
@@ -623,11 +691,11 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   if (i >= A.n1) return;
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
-  if (len <= kStage) {
-    const int32_t* src = A.staging + i * kStage;
+  const int32_t* src = A.staging + i * kStage;
+  if (len <= kStage && (len == 0 || src[0] != kRowNotParked)) {
     for (int k = sub; k < (int)len; k += kCopyLanes)
       if (o0 + k < A.capacity) A.cols[o0 + k] = src[k];
-  } else if (sub == 0 && A.qflag[i] != kQueryNormal) {
+  } else if (sub == 0 && (len <= kStage || A.qflag[i] != kQueryNormal)) {
     // long rows of normal queries belong to the wide-row pass of their tile
     const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
     A.long_rows[slot] = (uint32_t)i;
@@ -721,12 +789,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __r
 
 }  // namespace
 
-__global__ void k_clear_stats(unsigned long long* stats) {
+__global__ __launch_bounds__(256) void k_clear_stats(unsigned long long* stats, uint32_t* sched) {
   if (threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
+  if (sched)
+    for (int k = (int)threadIdx.x; k < kSchedWords; k += 256) sched[k] = 0u;
 }
 
-hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(64), 0, s, stats);
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched) {
+  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(256), 0, s, stats, sched);
   return hipGetLastError();
 }
 

@@ -82,6 +82,23 @@ def test_long_rows_take_the_wide_row_pass():
     _same(got, _oracle([p], 30.0), "wide rows")
 
 
+@pytest.mark.parametrize("eps", [1.5, 4.0])
+def test_sparse_queries_over_a_dense_image(eps):
+    """100 queries against 8040 image-2 keypoints: each tile spans a wide
+    angle range, its window holds thousands of records (more than the pass
+    keeps the j of), so its short rows are rebuilt by the fill pass and
+    matched from the list."""
+    yaw = synth.pairs.rot_axis_angle([0.0, 1.0, 0.0], np.deg2rad(8.0))
+    p = synth.make_pair(6048, 4032, 3400.0, yaw, [1.0, 0.0, 0.0], 40, 60, 8000, 777)
+    log(f"fused, sparse queries over {p.n} keypoints, eps {eps}")
+    got, idx = _fused([p], eps, 0.8)
+    lens = np.diff(got[0])
+    assert lens.max() <= 128
+    st = idx.stats()
+    assert st["records_scanned"] > 2048 * (st["queries"] - st["empty_queries"])
+    _same(got, _oracle([p], eps, 0.8), f"sparse queries eps {eps}")
+
+
 def test_mixed_batch_fused_equals_oracle():
     pairs = [synth.cfg3_pair(r, max_kp=4000) for r in range(24)]
     log("fused cfg3 mixed batch of 24")
