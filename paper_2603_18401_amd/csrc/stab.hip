@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // rebuild, and those queries are listed for the listed-query match after the
 // CSR is complete; empty rows get their (-1, inf, inf) here.  The LDS and
 // register budget allows three workgroups per CU.
-constexpr int kFuseRows = 32;
+constexpr int kFuseRows = 48;
 constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
 constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
 // The staged rows are copied straight from global memory to LDS (lane l of a
@@ -352,7 +352,7 @@ constexpr int32_t kRowNotParked = -1;
 // FUSE: the j of the first kKeepJ window positions stay in LDS; the hits
 // are kept as 16-bit window positions, and tiles with longer windows are not
 // fused (their rows are rebuilt by the fill pass and matched from the list)
-constexpr int kKeepJ = 2048;
+constexpr int kKeepJ = 1024;
 constexpr int64_t kFuseMaxWindow = kKeepJ;
 
 // Starts the copy of rows [c0, c0 + nr) of the window (0 < nr <= kFuseRows)

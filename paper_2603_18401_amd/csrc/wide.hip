@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   __shared__ float tkl[kQ * kK];
   __shared__ int32_t tjl[kQ * kK];
 
-  const int tile = xcd_tile(blockIdx.x, A.num_tiles);
+  const int tile = A.block_tile ? (int)A.block_tile[blockIdx.x] : xcd_tile(blockIdx.x, A.num_tiles);
   if (A.tile_wide[tile] == 0u) return;
   // a caller's CSR that did not fit its buffer is incomplete: nothing is written
   if (!WRITE && A.row_offsets[A.n1] > A.capacity) return;
