@@ -26,7 +26,7 @@ struct Layout {
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
-      qline;
+      qline, tile_q;
   size_t total;
 };
 
@@ -84,6 +84,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.rest = take(sizeof(uint32_t) * N1);
   L.tile_wide = take(sizeof(uint32_t) * ts);
   L.qline = take(sizeof(double4) * N1);
+  L.tile_q = take(sizeof(TileQuery) * kTileQ * (size_t)ts);
   L.total = off;
   return L;
 }
@@ -414,6 +415,7 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.tile_cost = nullptr;
   A.order = nullptr;
   A.queue = nullptr;
+  A.tile_q = idx->at<TileQuery>(L.tile_q);
   A.xcd_hist = nullptr;
   A.block_tile = nullptr;
   A.desc1 = nullptr;

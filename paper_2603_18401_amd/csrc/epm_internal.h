@@ -100,4 +100,13 @@ struct StabTile {
   int32_t pair;
 };
 
+// One query of a stabbing tile as the window pass leaves it for the tile
+// pass: the epipolar line (a, b, c), sqrt(a^2 + b^2), the query's index, flag
+// and key (slots past the tile's count: empty, index 0).
+struct TileQuery {
+  double a, b, c, n;
+  int64_t i;
+  uint32_t flag, key;
+};
+
 }  // namespace epm

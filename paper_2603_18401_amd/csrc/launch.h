@@ -77,6 +77,7 @@ struct StabArgs {
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
   uint32_t* queue;            // persistent launch: next-tile counter, zero at launch
+  TileQuery* tile_q;          // [num_tiles][kTileQ], written by launch_tile_windows
   uint32_t* xcd_hist;         // [kLptXcd][kCostBuckets] tile costs per XCD, or NULL
   const uint32_t* block_tile;  // one workgroup per tile: tile of each workgroup, or NULL
   // fused matching (FP32 descriptors), see launch_stab_tiles

@@ -245,13 +245,28 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
   const StabTile T = A.tiles[t];
   bool normal = false, brute = false;
   uint32_t key = 0;
+  TileQuery tq;
+  tq.a = tq.b = tq.c = tq.n = 0.0;
+  tq.i = 0;
+  tq.flag = kQueryEmpty;
+  tq.key = 0;
   if (lane < T.count) {
     const int64_t i = A.qperm[T.begin + lane];
     const uint32_t flag = A.qflag[i];
     normal = flag == kQueryNormal;
     brute = flag == kQueryBrute;
     key = A.qkey[i];
+    tq.i = i;
+    tq.flag = flag;
+    tq.key = key;
+    if (flag != kQueryEmpty) {
+      // the line of Eq. 2 and its norm, once per query for the tile passes
+      epipolar_line(A.pairs[T.pair].F, A.kp1[2 * i], A.kp1[2 * i + 1], tq.a, tq.b, tq.c);
+      tq.n = line_norm(tq.a, tq.b);
+    }
+    A.qline[i] = make_double4(tq.a, tq.b, tq.c, tq.n);
   }
+  A.tile_q[(int64_t)t * kTileQ + lane] = tq;
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
   const uint32_t kmax = wave_max_u32(normal ? key : 0u);
   const bool any = ballot(normal) != 0;
@@ -430,25 +445,15 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
 
     if (wave == 0) {
-      const bool live = lane < T.count;
-      int64_t i = 0;
-      uint32_t flag = kQueryEmpty, key = 0;
-      double a = 0.0, b = 0.0, c = 0.0;
-      if (live) {
-        i = A.qperm[T.begin + lane];
-        flag = A.qflag[i];
-        key = A.qkey[i];
-        if (flag != kQueryEmpty) epipolar_line(pd.F, A.kp1[2 * i], A.kp1[2 * i + 1], a, b, c);
-      }
-      const double nrm = line_norm(a, b);
-      qa[lane] = a;
-      qb[lane] = b;
-      qc[lane] = c;
-      qn[lane] = nrm;
-      qk[lane] = key;
-      qmode[lane] = live ? flag : kQueryEmpty;
-      if (live) A.qline[i] = make_double4(a, b, c, nrm);
-      qidx[lane] = i;
+      // the tile's queries with their lines, from the window pass
+      const TileQuery tq = A.tile_q[(int64_t)tile * kTileQ + lane];
+      qa[lane] = tq.a;
+      qb[lane] = tq.b;
+      qc[lane] = tq.c;
+      qn[lane] = tq.n;
+      qk[lane] = tq.key;
+      qmode[lane] = tq.flag;
+      qidx[lane] = tq.i;
       cnt[lane] = 0;
       if (lane < 3) tile_stats[lane] = 0ull;
     }
