@@ -76,7 +76,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.long_rows = take(sizeof(uint32_t) * N1);
   L.digit_base = take(sizeof(uint32_t) * 256 * P);
   L.windows = take(sizeof(TileWindow) * ts);
-  L.match_stats = take(sizeof(unsigned long long) * kNumMatchStats);
+  L.match_stats = take(sizeof(unsigned long long) * kMatchStatWords);
   L.sched = take(sizeof(uint32_t) * kSchedWords);
   L.tile_cost = take(sizeof(uint32_t) * ts);
   L.order = take(sizeof(uint32_t) * ts);
@@ -250,6 +250,7 @@ struct epm_index {
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // around the dominant kernel of a call
   epm_timed_kernel timed = EPM_TIMED_STAB;           // which kernel of the query calls
   bool have_order = false;  // the last query wrote the longest-first tile order
+  bool have_block_tile = false;  // ... or the per-XCD longest-first workgroup order
 
   template <typename T>
   T* at(size_t off) const {
@@ -441,9 +442,11 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   const Layout& L = idx->L;
   const int64_t n1 = idx->N1;
   idx->have_order = false;
+  idx->have_block_tile = false;
   if (n1 == 0) {
-    // row_offsets[0] = 0 (two zero words, by kernel)
+    // row_offsets[0] = 0 (two zero words, by kernel); the counters read zero
     EPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(row_offsets), 2, 0u, stream));
+    if (A.match_stats) EPM_HIP(launch_clear_stats(nullptr, stream, nullptr, A.match_stats));
     return EPM_OK;
   }
   EPM_HIP(launch_query_keys(A.pairs, A.qstart, idx->P, n1, A.kp1, idx->at<uint32_t>(L.qkey),
@@ -464,7 +467,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   // one workgroup per tile: the tiles of every XCD run longest first
   const bool xcd_lpt = S.stab_workgroups == 0;
   uint32_t* sched = idx->at<uint32_t>(L.sched);
-  EPM_HIP(launch_clear_stats(A.stats, stream, sched));
+  EPM_HIP(launch_clear_stats(A.stats, stream, sched, A.match_stats));
   A.tile_cost = lpt || xcd_lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
   A.xcd_hist = xcd_lpt ? sched + kSchedXHist : nullptr;
   EPM_HIP(launch_tile_windows(A, stream));
@@ -476,6 +479,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
     EPM_HIP(launch_xcd_lpt_order(A.tile_cost, A.num_tiles, sched,
                                  idx->at<uint32_t>(L.block_tile), stream));
     A.block_tile = idx->at<uint32_t>(L.block_tile);
+    idx->have_block_tile = true;
   }
   if (S.stab_workgroups > 0) {
     A.queue = sched + kSchedStabQueue;
@@ -574,6 +578,7 @@ MatchArgs match_args(epm_index* idx, const MatchCall& c) {
   A.order = nullptr;
   A.queue = nullptr;
   A.skip_tiles = nullptr;
+  A.block_tile = nullptr;
   return A;
 }
 
@@ -599,6 +604,7 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
     A.queue = sched + kSchedMatchQueue;
     A.order = idx->have_order ? idx->at<uint32_t>(L.order) : nullptr;
   }
+  if (tiled && grid == 0 && idx->have_block_tile) A.block_tile = idx->at<uint32_t>(L.block_tile);
   auto tiled_launch = [&](int fmt) -> hipError_t {
     if (grid > 0) {
       const hipError_t e = launch_fill_u32(A.queue, 1, 0u, stream);
@@ -615,7 +621,7 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
   if (reduced || wide) {
     idx->have_match_stats = true;
     idx->match_stream = stream;
-    EPM_HIP(launch_clear_stats(A.match_stats, stream));
+    EPM_HIP(launch_clear_stats(nullptr, stream, nullptr, A.match_stats));
   }
   if (wide) A.skip_tiles = idx->at<uint32_t>(L.tile_wide);
   auto wide_launch = [&]() -> hipError_t {
@@ -634,6 +640,7 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
     W.second_dist = c.second_dist;
     W.match_stats = A.match_stats;
     W.rest_count = A.match_stats + kMatchStatRest;
+    W.block_tile = A.block_tile;
     hipError_t e = launch_wide_tiles(W, bf ? kWideMatchBF16 : kWideMatchF32, stream);
     if (e != hipSuccess) return e;
     // the rows the pass could not certify or trust, exactly on the FP32 rows
@@ -686,8 +693,7 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   A.best_dist = c.best_dist;
   A.second_dist = c.second_dist;
   // counters of the wide-row selection (certified / listed rows)
-  A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);
-  EPM_HIP(launch_clear_stats(A.match_stats, stream));
+  A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);  // cleared with the counters
   idx->have_match_stats = true;
   idx->match_stream = stream;
   const epm_status st = enqueue_count(idx, A, row_offsets, stream, true);

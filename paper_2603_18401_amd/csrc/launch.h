@@ -123,8 +123,11 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
 constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
               kStatLongRows = 4, kStatRest = 5;
 constexpr int kNumStats = 6;
-// Clears the counters, and the kSchedWords scheduling words unless sched is NULL.
-hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched = nullptr);
+// Clears the kNumStats counters unless stats is NULL, the kSchedWords
+// scheduling words unless sched is NULL and the kMatchStatWords match counters
+// unless match_stats is NULL.
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched = nullptr,
+                              unsigned long long* match_stats = nullptr);
 
 // Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
 // workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.
@@ -186,10 +189,12 @@ struct MatchArgs {
   const uint32_t* order;       // persistent tiled launch: tile order (NULL = angle order)
   uint32_t* queue;             // persistent tiled launch: next-tile counter, zero at launch
   const uint32_t* skip_tiles;  // tiled kernels: tiles left to the wide-row pass, or NULL
+  const uint32_t* block_tile;  // one workgroup per tile: tile of each workgroup, or NULL
 };
 
 constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallback), long rows
 constexpr int kMatchStatRest = 3;  // internal: rest-list length of the wide-row match
+constexpr int kMatchStatWords = kMatchStatRest + 1;
 // fmt 0: BF16, 1: FP8-E4M3 with row scales.
 // grid as for launch_stab_tiles.
 hipError_t launch_match_window_mfma(const MatchArgs& a, int fmt, int grid, hipStream_t s);

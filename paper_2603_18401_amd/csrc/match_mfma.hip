@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       tile = A.order ? (int)A.order[t] : t;
     } else {
       if (iter > 0) break;
-      tile = xcd_tile(blockIdx.x, A.num_tiles);
+      tile = A.block_tile ? (int)A.block_tile[blockIdx.x] : xcd_tile(blockIdx.x, A.num_tiles);
     }
     if (A.skip_tiles && A.skip_tiles[tile]) {  // matched by the wide-row pass
       if (PERSIST) __syncthreads();            // next_tile is read before it is rewritten

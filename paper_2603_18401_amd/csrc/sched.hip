@@ -77,9 +77,12 @@ __global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __
                                                               uint32_t* __restrict__ cursor,
                                                               uint32_t* __restrict__ block_tile) {
   constexpr int kBins = kNumXcd * kCostBuckets;
-  __shared__ uint32_t h[kBins], base[kBins];
+  __shared__ uint32_t h[kBins], base[kBins], total[kBins];
   const int tid = (int)threadIdx.x;
-  for (int k = tid; k < kBins; k += kThreads) h[k] = 0u;
+  for (int k = tid; k < kBins; k += kThreads) {
+    h[k] = 0u;
+    total[k] = hist[k];
+  }
   __syncthreads();
   const int t = (int)blockIdx.x * kThreads + tid;
   int bin = 0;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __
     if (!h[k]) continue;
     const int x = k / kCostBuckets, b = k % kCostBuckets;
     uint32_t start = 0;
-    for (int c = kCostBuckets - 1; c > b; --c) start += hist[x * kCostBuckets + c];
+    for (int c = kCostBuckets - 1; c > b; --c) start += total[x * kCostBuckets + c];
     base[k] = start + atomicAdd(&cursor[k], h[k]);
   }
   __syncthreads();

@@ -794,14 +794,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __r
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_clear_stats(unsigned long long* stats, uint32_t* sched) {
-  if (threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
+__global__ __launch_bounds__(256) void k_clear_stats(unsigned long long* stats, uint32_t* sched,
+                                                     unsigned long long* match_stats) {
+  if (stats && threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
+  if (match_stats && threadIdx.x < kMatchStatWords) match_stats[threadIdx.x] = 0ull;
   if (sched)
     for (int k = (int)threadIdx.x; k < kSchedWords; k += 256) sched[k] = 0u;
 }
 
-hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched) {
-  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(256), 0, s, stats, sched);
+hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t* sched,
+                              unsigned long long* match_stats) {
+  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(256), 0, s, stats, sched, match_stats);
   return hipGetLastError();
 }
 
