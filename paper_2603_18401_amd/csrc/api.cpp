@@ -417,7 +417,6 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.order = nullptr;
   A.queue = nullptr;
   A.tile_q = idx->at<TileQuery>(L.tile_q);
-  A.xcd_hist = nullptr;
   A.block_tile = nullptr;
   A.desc1 = nullptr;
   A.desc2 = nullptr;
@@ -451,7 +450,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   }
   EPM_HIP(launch_query_keys(A.pairs, A.qstart, idx->P, n1, A.kp1, idx->at<uint32_t>(L.qkey),
                             idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
-                            idx->at<uint32_t>(L.qv0), stream));
+                            idx->at<uint32_t>(L.qv0), A.qline, stream));
   bool in1 = false;
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
                                idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
@@ -469,15 +468,14 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   uint32_t* sched = idx->at<uint32_t>(L.sched);
   EPM_HIP(launch_clear_stats(A.stats, stream, sched, A.match_stats));
   A.tile_cost = lpt || xcd_lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
-  A.xcd_hist = xcd_lpt ? sched + kSchedXHist : nullptr;
   EPM_HIP(launch_tile_windows(A, stream));
   if (lpt) {
     EPM_HIP(launch_lpt_order(A.tile_cost, A.num_tiles, sched, idx->at<uint32_t>(L.order), stream));
     idx->have_order = true;
   }
   if (xcd_lpt) {
-    EPM_HIP(launch_xcd_lpt_order(A.tile_cost, A.num_tiles, sched,
-                                 idx->at<uint32_t>(L.block_tile), stream));
+    EPM_HIP(launch_xcd_lpt_order(A.tile_cost, A.num_tiles, idx->at<uint32_t>(L.block_tile),
+                                 stream));
     A.block_tile = idx->at<uint32_t>(L.block_tile);
     idx->have_block_tile = true;
   }

@@ -112,7 +112,8 @@ __global__ __launch_bounds__(256) void k_intervals(
 __global__ __launch_bounds__(256) void k_query_keys(
     const PairDev* __restrict__ pairs, const int64_t* __restrict__ qstart, int num_pairs,
     int64_t n1, const float* __restrict__ kp1, uint32_t* __restrict__ qkey,
-    uint32_t* __restrict__ qflag, uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val) {
+    uint32_t* __restrict__ qflag, uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val,
+    double4* __restrict__ qline) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n1) return;
   const int p = find_pair(qstart, num_pairs, i);
@@ -146,6 +147,9 @@ __global__ __launch_bounds__(256) void k_query_keys(
   qflag[i] = flag;
   sort_key[i] = key >> 16;
   sort_val[i] = (uint32_t)i;
+  // the line and its norm for the tile passes (the denominator of Eq. 3)
+  qline[i] = flag == kQueryEmpty ? make_double4(0.0, 0.0, 0.0, 0.0)
+                                 : make_double4(a, b, c, line_norm(a, b));
 }
 
 // Sorted layout: structure-of-arrays in angle order, plus the inverse
@@ -217,11 +221,12 @@ hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num
 
 hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
                              int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
-                             uint32_t* sort_key, uint32_t* sort_val, hipStream_t s) {
+                             uint32_t* sort_key, uint32_t* sort_val, double4* qline,
+                             hipStream_t s) {
   if (n1 == 0) return hipSuccess;
   const int64_t blocks = (n1 + 255) / 256;
   hipLaunchKernelGGL(k_query_keys, dim3((unsigned)blocks), dim3(256), 0, s, pairs, qstart,
-                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val);
+                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val, qline);
   return hipGetLastError();
 }
 

@@ -13,9 +13,12 @@ hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num
                             uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,
                             uint32_t* recH, hipStream_t s);
 
+// Also writes every query's line (a, b, c, sqrt(a^2 + b^2)) to qline (zero for
+// a query without a line).
 hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
                              int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
-                             uint32_t* sort_key, uint32_t* sort_val, hipStream_t s);
+                             uint32_t* sort_key, uint32_t* sort_val, double4* qline,
+                             hipStream_t s);
 
 hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n2,
                                  const uint32_t* sorted_val, const float* kp2, const float* eps2,
@@ -78,7 +81,6 @@ struct StabArgs {
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
   uint32_t* queue;            // persistent launch: next-tile counter, zero at launch
   TileQuery* tile_q;          // [num_tiles][kTileQ], written by launch_tile_windows
-  uint32_t* xcd_hist;         // [kLptXcd][kCostBuckets] tile costs per XCD, or NULL
   const uint32_t* block_tile;  // one workgroup per tile: tile of each workgroup, or NULL
   // fused matching (FP32 descriptors), see launch_stab_tiles
   const float* desc1;
@@ -100,9 +102,8 @@ struct StabArgs {
 constexpr int kCostBuckets = 65;  // cost 0, then two buckets per power of two
 constexpr int kLptXcd = 8;        // XCDs the workgroups of a launch are dealt to in turn
 constexpr int kSchedHist = 0, kSchedCursor = kCostBuckets, kSchedStabQueue = 2 * kCostBuckets,
-              kSchedMatchQueue = 2 * kCostBuckets + 1, kSchedXHist = 2 * kCostBuckets + 2,
-              kSchedXCursor = kSchedXHist + kLptXcd * kCostBuckets;
-constexpr int kSchedWords = kSchedXCursor + kLptXcd * kCostBuckets;
+              kSchedMatchQueue = 2 * kCostBuckets + 1;
+constexpr int kSchedWords = 2 * kCostBuckets + 2;
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // Longest-first order of the tiles from their costs; the histogram and cursor
@@ -111,11 +112,10 @@ hipError_t launch_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched
                             uint32_t* order, hipStream_t s);
 // One workgroup per tile, longest first on every XCD: block_tile[b] for the
 // workgroups b = x, x + 8, ... of XCD x lists the tiles that the XCD-grouped
-// angle order gives that XCD, by decreasing cost.  The per-XCD histogram
-// (sched + kSchedXHist, filled by launch_tile_windows through xcd_hist) must
-// be complete and the cursor words zero.
-hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
-                                uint32_t* block_tile, hipStream_t s);
+// angle order gives that XCD, by decreasing cost bucket (cost from
+// launch_tile_windows).
+hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* block_tile,
+                                hipStream_t s);
 
 // One wavefront per tile finds the tile's window in every width class.
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);

@@ -69,51 +69,47 @@ __global__ __launch_bounds__(kThreads) void k_lpt_scatter(const uint32_t* __rest
 }
 
 // Per-XCD longest-first layout: tile t of XCD x and bucket b goes to rank
-// k = (tiles of XCD x in buckets above b) + its place in (x, b), i.e. to the
-// workgroup k * 8 + x.
+// k = (tiles of XCD x in buckets above b) + (tiles of (x, b) in earlier
+// workgroups of this kernel) + its place among this workgroup's tiles of
+// (x, b), i.e. to the workgroup k * 8 + x.  Every workgroup counts all the
+// tiles' costs itself (4 B per tile), so no counters cross workgroups.
 __global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __restrict__ cost,
                                                               int n,
-                                                              const uint32_t* __restrict__ hist,
-                                                              uint32_t* __restrict__ cursor,
                                                               uint32_t* __restrict__ block_tile) {
   constexpr int kBins = kNumXcd * kCostBuckets;
-  __shared__ uint32_t h[kBins], base[kBins], total[kBins];
+  __shared__ uint32_t total[kBins], before[kBins], h[kBins];
   const int tid = (int)threadIdx.x;
   for (int k = tid; k < kBins; k += kThreads) {
+    total[k] = 0u;
+    before[k] = 0u;
     h[k] = 0u;
-    total[k] = hist[k];
   }
   __syncthreads();
-  const int t = (int)blockIdx.x * kThreads + tid;
-  int bin = 0;
-  uint32_t rank = 0;
+  const int first = (int)blockIdx.x * kThreads;
+  for (int t = tid; t < n; t += kThreads) {
+    const int bin = xcd_of_tile(t, n) * kCostBuckets + cost_bucket(cost[t]);
+    atomicAdd(&total[bin], 1u);
+    if (t < first) atomicAdd(&before[bin], 1u);
+  }
+  __syncthreads();
+  const int t = first + tid;
   if (t < n) {
-    bin = xcd_of_tile(t, n) * kCostBuckets + cost_bucket(cost[t]);
-    rank = atomicAdd(&h[bin], 1u);
-  }
-  __syncthreads();
-  for (int k = tid; k < kBins; k += kThreads) {
-    if (!h[k]) continue;
-    const int x = k / kCostBuckets, b = k % kCostBuckets;
-    uint32_t start = 0;
-    for (int c = kCostBuckets - 1; c > b; --c) start += total[x * kCostBuckets + c];
-    base[k] = start + atomicAdd(&cursor[k], h[k]);
-  }
-  __syncthreads();
-  if (t < n) {
-    const uint32_t k = base[bin] + rank;
-    block_tile[k * kNumXcd + (uint32_t)(bin / kCostBuckets)] = (uint32_t)t;
+    const int x = xcd_of_tile(t, n), b = cost_bucket(cost[t]);
+    const int bin = x * kCostBuckets + b;
+    uint32_t k = before[bin] + atomicAdd(&h[bin], 1u);
+    for (int c = kCostBuckets - 1; c > b; --c) k += total[x * kCostBuckets + c];
+    block_tile[k * kNumXcd + (uint32_t)x] = (uint32_t)t;
   }
 }
 
 }  // namespace
 
-hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* sched,
-                                uint32_t* block_tile, hipStream_t s) {
+hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* block_tile,
+                                hipStream_t s) {
   if (num_tiles == 0) return hipSuccess;
   const int blocks = (num_tiles + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_xcd_lpt_scatter, dim3(blocks), dim3(kThreads), 0, s, cost, num_tiles,
-                     sched + kSchedXHist, sched + kSchedXCursor, block_tile);
+                     block_tile);
   return hipGetLastError();
 }
 

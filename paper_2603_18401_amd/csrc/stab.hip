@@ -259,12 +259,11 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
     tq.i = i;
     tq.flag = flag;
     tq.key = key;
-    if (flag != kQueryEmpty) {
-      // the line of Eq. 2 and its norm, once per query for the tile passes
-      epipolar_line(A.pairs[T.pair].F, A.kp1[2 * i], A.kp1[2 * i + 1], tq.a, tq.b, tq.c);
-      tq.n = line_norm(tq.a, tq.b);
-    }
-    A.qline[i] = make_double4(tq.a, tq.b, tq.c, tq.n);
+    const double4 L = A.qline[i];  // the line of Eq. 2 and its norm, from the key pass
+    tq.a = L.x;
+    tq.b = L.y;
+    tq.c = L.z;
+    tq.n = L.w;
   }
   A.tile_q[(int64_t)t * kTileQ + lane] = tq;
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
@@ -325,8 +324,6 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
       const uint64_t c = nn * wlen + nb * (uint64_t)A.pairs[T.pair].n + (uint64_t)T.count;
       const uint32_t c32 = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
       A.tile_cost[t] = c32;
-      if (A.xcd_hist)
-        atomicAdd(&A.xcd_hist[xcd_of_tile(t, A.num_tiles) * kCostBuckets + cost_bucket(c32)], 1u);
     }
   }
 }
