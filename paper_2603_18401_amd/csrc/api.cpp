@@ -450,7 +450,8 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   }
   EPM_HIP(launch_query_keys(A.pairs, A.qstart, idx->P, n1, A.kp1, idx->at<uint32_t>(L.qkey),
                             idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
-                            idx->at<uint32_t>(L.qv0), A.qline, stream));
+                            idx->at<uint32_t>(L.qv0), A.qline, A.stats,
+                            idx->at<uint32_t>(L.sched), A.match_stats, stream));
   bool in1 = false;
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
                                idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
@@ -465,8 +466,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   const bool lpt = persistent && S.lpt == 1;
   // one workgroup per tile: the tiles of every XCD run longest first
   const bool xcd_lpt = S.stab_workgroups == 0;
-  uint32_t* sched = idx->at<uint32_t>(L.sched);
-  EPM_HIP(launch_clear_stats(A.stats, stream, sched, A.match_stats));
+  uint32_t* sched = idx->at<uint32_t>(L.sched);  // cleared by the key pass
   A.tile_cost = lpt || xcd_lpt ? idx->at<uint32_t>(L.tile_cost) : nullptr;
   EPM_HIP(launch_tile_windows(A, stream));
   if (lpt) {

@@ -113,7 +113,14 @@ __global__ __launch_bounds__(256) void k_query_keys(
     const PairDev* __restrict__ pairs, const int64_t* __restrict__ qstart, int num_pairs,
     int64_t n1, const float* __restrict__ kp1, uint32_t* __restrict__ qkey,
     uint32_t* __restrict__ qflag, uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val,
-    double4* __restrict__ qline) {
+    double4* __restrict__ qline, unsigned long long* __restrict__ stats,
+    uint32_t* __restrict__ sched, unsigned long long* __restrict__ match_stats) {
+  if (blockIdx.x == 0) {  // the query's counters start from zero
+    if (stats && threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
+    if (match_stats && threadIdx.x < kMatchStatWords) match_stats[threadIdx.x] = 0ull;
+    if (sched)
+      for (int k = (int)threadIdx.x; k < kSchedWords; k += (int)blockDim.x) sched[k] = 0u;
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n1) return;
   const int p = find_pair(qstart, num_pairs, i);
@@ -222,11 +229,13 @@ hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num
 hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
                              int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
                              uint32_t* sort_key, uint32_t* sort_val, double4* qline,
-                             hipStream_t s) {
-  if (n1 == 0) return hipSuccess;
+                             unsigned long long* stats, uint32_t* sched,
+                             unsigned long long* match_stats, hipStream_t s) {
+  if (n1 == 0) return launch_clear_stats(stats, s, sched, match_stats);
   const int64_t blocks = (n1 + 255) / 256;
   hipLaunchKernelGGL(k_query_keys, dim3((unsigned)blocks), dim3(256), 0, s, pairs, qstart,
-                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val, qline);
+                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val, qline, stats, sched,
+                     match_stats);
   return hipGetLastError();
 }
 

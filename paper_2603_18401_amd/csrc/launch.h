@@ -14,11 +14,13 @@ hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num
                             uint32_t* recH, hipStream_t s);
 
 // Also writes every query's line (a, b, c, sqrt(a^2 + b^2)) to qline (zero for
-// a query without a line).
+// a query without a line), and its first workgroup clears the counters as
+// launch_clear_stats does (each pointer may be NULL).
 hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
                              int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
                              uint32_t* sort_key, uint32_t* sort_val, double4* qline,
-                             hipStream_t s);
+                             unsigned long long* stats, uint32_t* sched,
+                             unsigned long long* match_stats, hipStream_t s);
 
 hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n2,
                                  const uint32_t* sorted_val, const float* kp2, const float* eps2,
