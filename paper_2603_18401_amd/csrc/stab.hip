@@ -719,6 +719,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_long(StabArgs A) {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;
+constexpr int64_t kScanDirectBlocks = 4096;  // up to 8 M counts: no top-level scan launch
 
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
   const int tid = threadIdx.x;
@@ -764,6 +765,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
     carry += tot;
   }
   if (threadIdx.x == 0) partials[nb] = carry;
+}
+
+// Sum of partials[0 .. nb) by one workgroup (every thread gets it).
+__device__ __forceinline__ int64_t block_sum(const int64_t* __restrict__ partials, int64_t nb,
+                                             int64_t* sh) {
+  int64_t v = 0;
+  for (int64_t k = threadIdx.x; k < nb; k += kScanThreads) v += partials[k];
+  int64_t tot;
+  block_exclusive_scan(v, sh, &tot);
+  return tot;
+}
+
+// Final pass without the top-level scan (few blocks): block b adds up the
+// partial sums of blocks 0 .. b - 1 itself; the last block writes offsets[n].
+__global__ __launch_bounds__(kScanThreads) void k_scan_final_direct(
+    const uint32_t* __restrict__ counts, int64_t n, const int64_t* __restrict__ partials,
+    int64_t nb, int64_t* __restrict__ offsets) {
+  __shared__ int64_t sh[kScanThreads];
+  const int64_t before = block_sum(partials, (int64_t)blockIdx.x, sh);
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? counts[base + k] : 0u;
+    s += v[k];
+  }
+  int64_t tot;
+  int64_t run = before + block_exclusive_scan(s, sh, &tot);
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) offsets[base + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) offsets[n] = before + tot;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __restrict__ counts,
@@ -852,6 +886,11 @@ hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offset
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n,
                      partials);
+  if (nb <= kScanDirectBlocks) {  // every block sums the partials before it
+    hipLaunchKernelGGL(k_scan_final_direct, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts,
+                       n, partials, nb, offsets);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n,
                      partials, nb, offsets);
