@@ -266,6 +266,7 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
     tq.n = L.w;
   }
   A.tile_q[(int64_t)t * kTileQ + lane] = tq;
+  if (lane == 0) A.tile_wide[t] = 0u;  // set by the tile pass when a row is wide
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
   const uint32_t kmax = wave_max_u32(normal ? key : 0u);
   const bool any = ballot(normal) != 0;
@@ -348,7 +349,11 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // queries, windows longer than kKeepJ) are marked for the fill pass to
 // rebuild, and those queries are listed for the listed-query match after the
 // CSR is complete; empty rows get their (-1, inf, inf) here.  The LDS and
-// register budget allows three workgroups per CU.
+// register budget allows three workgroups per CU.  After the pair test every
+// wavefront works on its own 16 queries until the descriptor rows are staged,
+// so the tile needs only the barriers of the record and row chunks; its
+// counters gather in LDS and go to global memory once per tile (per-wavefront
+// global atomics on the same counters cost more than a barrier).
 constexpr int kFuseRows = 48;
 constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
 constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
-  __shared__ unsigned long long tile_stats[3];
+  __shared__ uint32_t tile_stats[4];  // scanned, angle hits, brute-force and empty queries
   __shared__ int next_tile;
 
   // one tile per workgroup, or (persistent) tiles from the queue until it is
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       qmode[lane] = tq.flag;
       qidx[lane] = tq.i;
       cnt[lane] = 0;
-      if (lane < 3) tile_stats[lane] = 0ull;
+      if (lane < 4) tile_stats[lane] = 0u;
     }
     {
       const TileWindow* w = A.windows + tile;
@@ -548,34 +553,30 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       }
       if (lane == 0) cnt[q] = c0;
     }
-    if (A.stats) {
+    // From here to the match phase every wavefront works on its own 16
+    // queries only (their hits and counts were written by this wavefront),
+    // so no barrier is needed.
+    {
+      // the tile's counters gather in LDS; one thread adds them to the
+      // query's counters once every wavefront has passed a later barrier
+      const bool own = lane < kQPerWave && lq < T.count;
+      const uint32_t nbrute = (uint32_t)__popcll(ballot(own && qmode[lq] == kQueryBrute));
+      const uint32_t empty = (uint32_t)__popcll(ballot(own && qmode[lq] == kQueryEmpty));
       scanned = wave_sum_u32(scanned);
       angle_hits = wave_sum_u32(angle_hits);
+      // rows longer than kStage of normal queries are written (and, fused,
+      // matched) by the wide-row pass over the tile; the window pass cleared
+      // the flag
+      const uint64_t wm = ballot(own && qmode[lq] == kQueryNormal && cnt[lq] > (uint32_t)kStage);
       if (lane == 0) {
-        atomicAdd(&tile_stats[0], (unsigned long long)scanned);
-        atomicAdd(&tile_stats[1], (unsigned long long)angle_hits);
+        atomicAdd(&tile_stats[0], scanned);
+        atomicAdd(&tile_stats[1], angle_hits);
+        atomicAdd(&tile_stats[2], nbrute);
+        atomicAdd(&tile_stats[3], empty);
+        if (wm != 0ull) A.tile_wide[tile] = 1u;
       }
-    }
-    __syncthreads();
-    if (A.stats && tid == 0) {
-      uint64_t empty = 0, nbrute = 0;
-      for (int q = 0; q < T.count; ++q) {
-        empty += qmode[q] == kQueryEmpty;
-        nbrute += qmode[q] == kQueryBrute;
-      }
-      if (nbrute) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nbrute);
-      atomicAdd(&A.stats[kStatRecords], tile_stats[0] + nbrute * (uint64_t)pd.n);
-      atomicAdd(&A.stats[kStatAngleHits], tile_stats[1] + nbrute * (uint64_t)pd.n);
-      if (empty) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)empty);
     }
     (void)brute;
-    // rows longer than kStage of normal queries are written (and, fused,
-    // matched) by the wide-row pass over the tile
-    if (wave == 0) {
-      const bool wide = lane < T.count && qmode[lane] == kQueryNormal && cnt[lane] > (uint32_t)kStage;
-      const uint64_t wm = ballot(wide);
-      if (lane == 0) A.tile_wide[tile] = wm != 0 ? 1u : 0u;
-    }
 
     // FUSE: four threads per query select its match
     const int q = tid >> 2, part = tid & 3;
@@ -587,7 +588,7 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
     // row, each placing a quarter of its hits by rank (the j of a row are
     // distinct, so a hit's place is the number of smaller hits); a thread
     // ranks up to four of its hits in one pass over the row
-    if (tid < T.count) A.counts[qidx[tid]] = qmode[tid] == kQueryEmpty ? 0u : cnt[tid];
+    if (part == 0 && q < T.count) A.counts[qidx[q]] = qmode[q] == kQueryEmpty ? 0u : cnt[q];
     {
       const uint32_t n = q < T.count && qmode[q] != kQueryEmpty ? cnt[q] : 0u;
       // FUSE keeps only the hits of normal queries in fused windows; other
@@ -619,14 +620,14 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
     }
 
     if (FUSE) {
-      if (tid < T.count) {
-        const uint32_t mode = qmode[tid];
+      if (part == 0 && q < T.count) {
+        const uint32_t mode = qmode[q];
         if (mode == kQueryEmpty) {
-          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[tid], Top2(),
+          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], Top2(),
                          false);
-        } else if (mode != kQueryNormal || (cnt[tid] <= (uint32_t)kStage && !fusable)) {
+        } else if (mode != kQueryNormal || (cnt[q] <= (uint32_t)kStage && !fusable)) {
           const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
-          A.rest[at] = (uint32_t)qidx[tid];
+          A.rest[at] = (uint32_t)qidx[q];
         }
       }
       const int nq = mine ? (int)cnt[q] : 0;
@@ -641,13 +642,13 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       }
       Top2 best;
       int cur = part;
-      // tiles whose rows are all long (or empty) stage no descriptor rows
-      const bool any_mine = __syncthreads_or(mine) != 0;
-      if (fusable && total_len > 0 && any_mine) {
+      // the record chunk is dead since the pair test's last barrier, so the
+      // first rows go in without one
+      if (fusable && total_len > 0) {
         const int wlen = (int)total_len;
         for (int c0 = 0; c0 < wlen; c0 += kFuseRows) {
           const int nr = wlen - c0 < kFuseRows ? wlen - c0 : kFuseRows;
-          __syncthreads();  // the previous rows (or the record chunk) are no longer read
+          if (c0 > 0) __syncthreads();  // the previous rows are no longer read
           fuse_stage(A, c0, nr, kb, sJ_keep, rows4, wave, lane);
           wait_lds_copies();
           __syncthreads();
@@ -677,7 +678,18 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       if (mine && part == 0)
         write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], best, false);
     }
-    if (PERSIST || FUSE) __syncthreads();  // the tile's LDS is dead before the next one starts
+    // the tile's counters: complete once every wavefront has passed a barrier
+    // after adding its share (the match phase has one unless it was skipped)
+    if (!FUSE || !(fusable && total_len > 0)) __syncthreads();
+    if (A.stats && tid == 0) {
+      const uint64_t nb = tile_stats[2];
+      if (nb) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nb);
+      atomicAdd(&A.stats[kStatRecords], (unsigned long long)tile_stats[0] + nb * (uint64_t)pd.n);
+      atomicAdd(&A.stats[kStatAngleHits],
+                (unsigned long long)tile_stats[1] + nb * (uint64_t)pd.n);
+      if (tile_stats[3]) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)tile_stats[3]);
+    }
+    if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
 }
 
