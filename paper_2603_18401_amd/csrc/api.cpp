@@ -26,7 +26,7 @@ struct Layout {
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
-      qline, tile_q;
+      qline, tile_q, tile_counts;
   size_t total;
 };
 
@@ -85,6 +85,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.tile_wide = take(sizeof(uint32_t) * ts);
   L.qline = take(sizeof(double4) * N1);
   L.tile_q = take(sizeof(TileQuery) * kTileQ * (size_t)ts);
+  L.tile_counts = take(sizeof(unsigned long long) * kTileCounts * (size_t)ts);
   L.total = off;
   return L;
 }
@@ -417,6 +418,7 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.order = nullptr;
   A.queue = nullptr;
   A.tile_q = idx->at<TileQuery>(L.tile_q);
+  A.tile_counts = idx->at<unsigned long long>(L.tile_counts);
   A.block_tile = nullptr;
   A.desc1 = nullptr;
   A.desc2 = nullptr;
@@ -1220,18 +1222,25 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->queries = idx->N1;
   if (!idx->have_stats) return EPM_OK;
-  unsigned long long c[kNumStats] = {};
+  // the tile pass leaves its counters per tile: summed here
+  const size_t nt = idx->stiles.size();
+  std::vector<unsigned long long> tc((size_t)kTileCounts * nt);
   int64_t nnz = 0;
-  EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.stats), sizeof(c),
-                         hipMemcpyDeviceToHost, idx->last_stream));
+  if (nt > 0)
+    EPM_HIP(hipMemcpyAsync(tc.data(), idx->at<unsigned long long>(idx->L.tile_counts),
+                           sizeof(unsigned long long) * tc.size(), hipMemcpyDeviceToHost,
+                           idx->last_stream));
   EPM_HIP(hipMemcpyAsync(&nnz, idx->last_offsets + idx->N1, sizeof(nnz), hipMemcpyDeviceToHost,
                          idx->last_stream));
   EPM_HIP(hipStreamSynchronize(idx->last_stream));
+  unsigned long long sum[kTileCounts] = {};
+  for (size_t t = 0; t < nt; ++t)
+    for (int k = 0; k < kTileCounts; ++k) sum[k] += tc[t * kTileCounts + k];
   out->candidates = nnz;
-  out->scanned_queries = (int64_t)c[kStatScannedQueries];
-  out->records_scanned = (int64_t)c[kStatRecords];
-  out->angle_hits = (int64_t)c[kStatAngleHits];
-  out->empty_queries = (int64_t)c[kStatEmpty];
+  out->records_scanned = (int64_t)sum[0];
+  out->angle_hits = (int64_t)sum[1];
+  out->scanned_queries = (int64_t)sum[2];
+  out->empty_queries = (int64_t)sum[3];
   return EPM_OK;
 }
 
@@ -1240,7 +1249,7 @@ epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->queries = idx->N1;
   if (!idx->have_match_stats) return EPM_OK;
-  unsigned long long c[kNumStats] = {};
+  unsigned long long c[kNumMatchStats] = {};
   EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.match_stats),
                          sizeof(unsigned long long) * kNumMatchStats, hipMemcpyDeviceToHost,
                          idx->match_stream));

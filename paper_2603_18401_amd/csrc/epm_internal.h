@@ -94,6 +94,8 @@ struct TileWindow {
   uint32_t slot_pref[kSlots + 1];
 };
 
+constexpr int kTileCounts = 4;
+
 struct StabTile {
   int64_t begin;  // first angle-sorted query position of the tile
   int32_t count;  // queries in the tile (<= kTileQ)

@@ -76,6 +76,10 @@ struct StabArgs {
   int num_tiles;
   int32_t* staging;  // [n1][kStage], indexed by the original query index
   unsigned long long* stats;  // kNumStats counters, cleared by launch_clear_stats
+  // [num_tiles][kTileCounts] per-tile counters of the tile pass (records
+  // scanned, angle hits, brute-force queries, empty queries), summed on the
+  // host when asked for: no global atomics on shared counters in the pass
+  unsigned long long* tile_counts;
   uint32_t* long_rows;        // [n1] queue of brute-force rows longer than kStage
   uint32_t* tile_wide;        // [num_tiles] 1: the tile has a normal row longer than kStage
   TileWindow* windows;        // [num_tiles], written by launch_tile_windows
@@ -122,9 +126,10 @@ hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* b
 // One wavefront per tile finds the tile's window in every width class.
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s);
 
-constexpr int kStatScannedQueries = 0, kStatRecords = 1, kStatAngleHits = 2, kStatEmpty = 3,
-              kStatLongRows = 4, kStatRest = 5;
-constexpr int kNumStats = 6;
+// Device-wide counters of a query: the lengths of its two queues (long rows
+// for the fill pass, rows left to the listed-query match).
+constexpr int kStatLongRows = 0, kStatRest = 1;
+constexpr int kNumStats = 2;
 // Clears the kNumStats counters unless stats is NULL, the kSchedWords
 // scheduling words unless sched is NULL and the kMatchStatWords match counters
 // unless match_stats is NULL.

@@ -679,15 +679,16 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
         write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], best, false);
     }
     // the tile's counters: complete once every wavefront has passed a barrier
-    // after adding its share (the match phase has one unless it was skipped)
+    // after adding its share (the match phase has one unless it was skipped);
+    // written per tile, summed on the host when they are asked for
     if (!FUSE || !(fusable && total_len > 0)) __syncthreads();
-    if (A.stats && tid == 0) {
+    if (A.tile_counts && tid == 0) {
       const uint64_t nb = tile_stats[2];
-      if (nb) atomicAdd(&A.stats[kStatScannedQueries], (unsigned long long)nb);
-      atomicAdd(&A.stats[kStatRecords], (unsigned long long)tile_stats[0] + nb * (uint64_t)pd.n);
-      atomicAdd(&A.stats[kStatAngleHits],
-                (unsigned long long)tile_stats[1] + nb * (uint64_t)pd.n);
-      if (tile_stats[3]) atomicAdd(&A.stats[kStatEmpty], (unsigned long long)tile_stats[3]);
+      unsigned long long* tc = A.tile_counts + (int64_t)tile * kTileCounts;
+      tc[0] = (unsigned long long)tile_stats[0] + nb * (uint64_t)pd.n;
+      tc[1] = (unsigned long long)tile_stats[1] + nb * (uint64_t)pd.n;
+      tc[2] = nb;
+      tc[3] = tile_stats[3];
     }
     if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
