@@ -270,34 +270,45 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
   const uint32_t kmax = wave_max_u32(normal ? key : 0u);
   const bool any = ballot(normal) != 0;
-  int64_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
-  if (lane < kNumClasses && any) {
+  // lane c < 32 searches the start of class c's window, lane c + 32 its end:
+  // the two searches run side by side
+  const int c = lane & (kNumClasses - 1);
+  static_assert(2 * kNumClasses == kWave, "two lanes per width class");
+  int64_t beg = 0, end = 0, r = 0;
+  bool full = false, wrap = false;
+  if (any) {
     const int64_t* cb = A.class_begin + (int64_t)T.pair * kClassSlots;
-    const int64_t beg = cb[lane], end = cb[lane + 1];
+    beg = cb[c];
+    end = cb[c + 1];
     if (beg < end) {
-      const uint32_t span = lane == kWideClass ? 0u : (1u << lane) - 1u;
+      const uint32_t span = c == kWideClass ? 0u : (1u << c) - 1u;
       const uint64_t width = (uint64_t)(kmax - kmin) + 2ull * span;
-      if (lane == kWideClass || width >= 0xFFFFE000ull) {
-        b0 = beg;
-        l0 = end - beg;
-      } else {
+      full = c == kWideClass || width >= 0xFFFFE000ull;
+      if (!full) {
         const uint32_t lo = kmin - span, hi = kmax + span;
-        const uint32_t cls = (uint32_t)lane << kCentreBits;
+        const uint32_t cls = (uint32_t)c << kCentreBits;
         const uint32_t blo = cls | (lo >> kCentreShift), bhi = cls | (hi >> kCentreShift);
-        if (lo <= hi) {
-          const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
-          const int64_t r1 = lower_bound_scalar(A.skey, r0, end, bhi + 1u);
-          b0 = r0;
-          l0 = r1 - r0;
-        } else {
-          const int64_t r0 = lower_bound_scalar(A.skey, beg, end, blo);
-          const int64_t r1 = lower_bound_scalar(A.skey, beg, r0, bhi + 1u);
-          b0 = r0;
-          l0 = end - r0;
-          b1 = beg;
-          l1 = r1 - beg;
-        }
+        wrap = lo > hi;
+        // bhi + 1 > blo without a wrap; through angle 0 the gap between hi
+        // and lo is over 2^13 key units, so bhi + 1 <= blo
+        r = lower_bound_scalar(A.skey, beg, end, lane < kNumClasses ? blo : bhi + 1u);
       }
+    }
+  }
+  const int64_t r_end = __shfl(r, c + kNumClasses);
+  int64_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
+  if (lane < kNumClasses && any && beg < end) {
+    if (full) {
+      b0 = beg;
+      l0 = end - beg;
+    } else if (!wrap) {
+      b0 = r;
+      l0 = r_end - r;
+    } else {
+      b0 = r;
+      l0 = end - r;
+      b1 = beg;
+      l1 = (r_end < r ? r_end : r) - beg;
     }
   }
   // slot s = class s/2, part s%2; inclusive scan of the 64 slot lengths
