@@ -360,16 +360,17 @@ epm_status enqueue_build(epm_index* idx, const float* kp2_xy, const float* eps2,
   const int64_t n2 = idx->N2;
   const PairDev* dpairs = idx->at<PairDev>(L.pairs);
   const int64_t* dkstart = idx->at<int64_t>(L.kstart);
-  EPM_HIP(launch_intervals(dpairs, dkstart, P, n2, kp2_xy, eps2, eps_scalar,
-                           idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
-                           idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH), stream));
+  EPM_HIP(launch_intervals(dpairs, idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(), kp2_xy,
+                           eps2, eps_scalar, idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
+                           idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH),
+                           idx->at<uint32_t>(L.hist), sort_passes(kSortBits) - 1, stream));
   bool in1 = false;
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.rk0), idx->at<uint32_t>(L.rv0),
                                idx->at<uint32_t>(L.rk1), idx->at<uint32_t>(L.rv1),
                                idx->at<SortTile>(L.rtiles), (int)idx->rtiles.size(),
                                idx->at<SortSeg>(L.rsegs), P, max_tiles(idx->rsegs),
                                idx->at<uint32_t>(L.hist), kSortBits, &in1, stream,
-                               idx->at<uint32_t>(L.digit_base)));
+                               idx->at<uint32_t>(L.digit_base), true));
   const uint32_t* skey = idx->at<uint32_t>(in1 ? L.rk1 : L.rk0);
   const uint32_t* sval = idx->at<uint32_t>(in1 ? L.rv1 : L.rv0);
   EPM_HIP(launch_gather_records(dkstart, P, n2, sval, kp2_xy, eps2, eps_scalar,
@@ -450,16 +451,17 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
     if (A.match_stats) EPM_HIP(launch_clear_stats(nullptr, stream, nullptr, A.match_stats));
     return EPM_OK;
   }
-  EPM_HIP(launch_query_keys(A.pairs, A.qstart, idx->P, n1, A.kp1, idx->at<uint32_t>(L.qkey),
-                            idx->at<uint32_t>(L.qflag), idx->at<uint32_t>(L.qk0),
-                            idx->at<uint32_t>(L.qv0), A.qline, A.stats,
+  EPM_HIP(launch_query_keys(A.pairs, idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
+                            A.kp1, idx->at<uint32_t>(L.qkey), idx->at<uint32_t>(L.qflag),
+                            idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0), A.qline,
+                            idx->at<uint32_t>(L.hist), sort_passes(16) - 1, A.stats,
                             idx->at<uint32_t>(L.sched), A.match_stats, stream));
   bool in1 = false;
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
                                idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
                                idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
                                idx->at<SortSeg>(L.qsegs), idx->P, max_tiles(idx->qsegs),
-                               idx->at<uint32_t>(L.hist), 16, &in1, stream));
+                               idx->at<uint32_t>(L.hist), 16, &in1, stream, nullptr, true));
   idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
   idx->have_qperm = true;
   A.qperm = idx->qperm;

@@ -85,78 +85,112 @@ __device__ void circle_interval(const PairDev& pd, float xf, float yf, float ef,
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_intervals(
-    const PairDev* __restrict__ pairs, const int64_t* __restrict__ kstart, int num_pairs,
-    int64_t n2, const float* __restrict__ kp2, const float* __restrict__ eps2, float eps_scalar,
+constexpr int kRadixDigits = 256;  // digits of one 8-bit radix pass
+
+// Per-tile digit counts of the first radix pass of the keys this workgroup
+// wrote (tile blockIdx.x), and zero counts for the next zero_passes passes:
+// the segmented sort then starts with its scatter.
+__device__ __forceinline__ void first_pass_counts(uint32_t* h, uint32_t* __restrict__ hist,
+                                                  int num_tiles, int zero_passes) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid >= kRadixDigits) return;
+  hist[(int64_t)blockIdx.x * kRadixDigits + tid] = h[tid];
+  for (int p = 1; p <= zero_passes; ++p)
+    hist[((int64_t)p * num_tiles + blockIdx.x) * kRadixDigits + tid] = 0u;
+}
+
+// One workgroup per record sort tile (kSortTile keypoints of one pair, one
+// per thread).
+__global__ __launch_bounds__(kSortTile) void k_intervals(
+    const PairDev* __restrict__ pairs, const SortTile* __restrict__ tiles, int num_tiles,
+    const float* __restrict__ kp2, const float* __restrict__ eps2, float eps_scalar,
     uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val, uint32_t* __restrict__ recC,
-    uint32_t* __restrict__ recH) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n2) return;
-  const int p = find_pair(kstart, num_pairs, r);
-  const PairDev& pd = pairs[p];
-  const float xf = kp2[2 * r], yf = kp2[2 * r + 1];
-  const float ef = eps2 ? eps2[r] : eps_scalar;
-  uint32_t C = 0, H = kFullHalf;
-  // keypoints the interval formula cannot describe are always scanned and
-  // left to the exact test
-  if (ef > 0.0f && isfinite(ef) && isfinite(xf) && isfinite(yf)) circle_interval(pd, xf, yf, ef, C, H);
-  const uint32_t cls = (uint32_t)width_class(H);
-  sort_key[r] = (cls << kCentreBits) | (C >> kCentreShift);
-  sort_val[r] = (uint32_t)r;
-  recC[r] = C;
-  recH[r] = H;
+    uint32_t* __restrict__ recH, uint32_t* __restrict__ hist, int zero_passes) {
+  __shared__ uint32_t h[kRadixDigits];
+  if (threadIdx.x < kRadixDigits) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const SortTile t = tiles[blockIdx.x];
+  const PairDev& pd = pairs[t.seg];
+  for (int k = threadIdx.x; k < t.count; k += kSortTile) {
+    const int64_t r = t.begin + k;
+    const float xf = kp2[2 * r], yf = kp2[2 * r + 1];
+    const float ef = eps2 ? eps2[r] : eps_scalar;
+    uint32_t C = 0, H = kFullHalf;
+    // keypoints the interval formula cannot describe are always scanned and
+    // left to the exact test
+    if (ef > 0.0f && isfinite(ef) && isfinite(xf) && isfinite(yf))
+      circle_interval(pd, xf, yf, ef, C, H);
+    const uint32_t cls = (uint32_t)width_class(H);
+    const uint32_t key = (cls << kCentreBits) | (C >> kCentreShift);
+    sort_key[r] = key;
+    sort_val[r] = (uint32_t)r;
+    recC[r] = C;
+    recH[r] = H;
+    atomicAdd(&h[key & (kRadixDigits - 1)], 1u);
+  }
+  first_pass_counts(h, hist, num_tiles, zero_passes);
 }
 
 // Eq. 2 and Eq. 7: the angle of each query's epipolar line in the pencil,
 // reduced mod pi (an undirected line).
-__global__ __launch_bounds__(256) void k_query_keys(
-    const PairDev* __restrict__ pairs, const int64_t* __restrict__ qstart, int num_pairs,
-    int64_t n1, const float* __restrict__ kp1, uint32_t* __restrict__ qkey,
-    uint32_t* __restrict__ qflag, uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val,
-    double4* __restrict__ qline, unsigned long long* __restrict__ stats,
-    uint32_t* __restrict__ sched, unsigned long long* __restrict__ match_stats) {
+// One workgroup per query sort tile (kSortTile queries of one pair, one per
+// thread).
+__global__ __launch_bounds__(kSortTile) void k_query_keys(
+    const PairDev* __restrict__ pairs, const SortTile* __restrict__ tiles, int num_tiles,
+    const float* __restrict__ kp1, uint32_t* __restrict__ qkey, uint32_t* __restrict__ qflag,
+    uint32_t* __restrict__ sort_key, uint32_t* __restrict__ sort_val,
+    double4* __restrict__ qline, uint32_t* __restrict__ hist, int zero_passes,
+    unsigned long long* __restrict__ stats, uint32_t* __restrict__ sched,
+    unsigned long long* __restrict__ match_stats) {
+  __shared__ uint32_t h[kRadixDigits];
+  if (threadIdx.x < kRadixDigits) h[threadIdx.x] = 0u;
   if (blockIdx.x == 0) {  // the query's counters start from zero
     if (stats && threadIdx.x < kNumStats) stats[threadIdx.x] = 0ull;
     if (match_stats && threadIdx.x < kMatchStatWords) match_stats[threadIdx.x] = 0ull;
     if (sched)
       for (int k = (int)threadIdx.x; k < kSchedWords; k += (int)blockDim.x) sched[k] = 0u;
   }
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n1) return;
-  const int p = find_pair(qstart, num_pairs, i);
-  const PairDev& pd = pairs[p];
-  double a, b, c;
-  epipolar_line(pd.F, kp1[2 * i], kp1[2 * i + 1], a, b, c);
-  uint32_t flag = kQueryNormal, key = 0;
-  if (a == 0.0 && b == 0.0) {
-    flag = kQueryEmpty;
-  } else if (!isfinite(a) || !isfinite(b) || !isfinite(c)) {
-    flag = kQueryBrute;
-  } else {
-    // the same line in normalised image-2 coordinates (scaled by 1/s)
-    const double l3 = pd.s * (a * pd.cx + b * pd.cy + c);
-    const double lam = pd.u[0] * a + pd.u[1] * b + pd.u[2] * l3;
-    const double mu = pd.v[0] * a + pd.v[1] * b + pd.v[2] * l3;
-    const double nu = pd.e[0] * a + pd.e[1] * b + pd.e[2] * l3;
-    const double n1c = lam * pd.u[0] + mu * pd.v[0];
-    const double n2c = lam * pd.u[1] + mu * pd.v[1];
-    const double nrm = sqrt(n1c * n1c + n2c * n2c);
-    if (!(fabs(nu) <= pd.kappa * nrm)) {
-      flag = kQueryBrute;  // the line misses the epipole by more than absorbed
+  __syncthreads();
+  const SortTile t = tiles[blockIdx.x];
+  const PairDev& pd = pairs[t.seg];
+  for (int kk = threadIdx.x; kk < t.count; kk += kSortTile) {
+    const int64_t i = t.begin + kk;
+    double a, b, c;
+    epipolar_line(pd.F, kp1[2 * i], kp1[2 * i + 1], a, b, c);
+    uint32_t flag = kQueryNormal, key = 0;
+    if (a == 0.0 && b == 0.0) {
+      flag = kQueryEmpty;
+    } else if (!isfinite(a) || !isfinite(b) || !isfinite(c)) {
+      flag = kQueryBrute;
     } else {
-      double phi = atan2(mu, lam);
-      if (phi < 0.0) phi += M_PI;
-      if (phi >= M_PI) phi -= M_PI;
-      key = angle_key(phi);
+      // the same line in normalised image-2 coordinates (scaled by 1/s)
+      const double l3 = pd.s * (a * pd.cx + b * pd.cy + c);
+      const double lam = pd.u[0] * a + pd.u[1] * b + pd.u[2] * l3;
+      const double mu = pd.v[0] * a + pd.v[1] * b + pd.v[2] * l3;
+      const double nu = pd.e[0] * a + pd.e[1] * b + pd.e[2] * l3;
+      const double n1c = lam * pd.u[0] + mu * pd.v[0];
+      const double n2c = lam * pd.u[1] + mu * pd.v[1];
+      const double nrm = sqrt(n1c * n1c + n2c * n2c);
+      if (!(fabs(nu) <= pd.kappa * nrm)) {
+        flag = kQueryBrute;  // the line misses the epipole by more than absorbed
+      } else {
+        double phi = atan2(mu, lam);
+        if (phi < 0.0) phi += M_PI;
+        if (phi >= M_PI) phi -= M_PI;
+        key = angle_key(phi);
+      }
     }
+    qkey[i] = key;
+    qflag[i] = flag;
+    sort_key[i] = key >> 16;
+    sort_val[i] = (uint32_t)i;
+    // the line and its norm for the tile passes (the denominator of Eq. 3)
+    qline[i] = flag == kQueryEmpty ? make_double4(0.0, 0.0, 0.0, 0.0)
+                                   : make_double4(a, b, c, line_norm(a, b));
+    atomicAdd(&h[(key >> 16) & (kRadixDigits - 1)], 1u);
   }
-  qkey[i] = key;
-  qflag[i] = flag;
-  sort_key[i] = key >> 16;
-  sort_val[i] = (uint32_t)i;
-  // the line and its norm for the tile passes (the denominator of Eq. 3)
-  qline[i] = flag == kQueryEmpty ? make_double4(0.0, 0.0, 0.0, 0.0)
-                                 : make_double4(a, b, c, line_norm(a, b));
+  first_pass_counts(h, hist, num_tiles, zero_passes);
 }
 
 // Sorted layout: structure-of-arrays in angle order, plus the inverse
@@ -215,27 +249,26 @@ hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
   return hipGetLastError();
 }
 
-hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num_pairs,
-                            int64_t n2, const float* kp2, const float* eps2, float eps_scalar,
+hipError_t launch_intervals(const PairDev* pairs, const SortTile* tiles, int num_tiles,
+                            const float* kp2, const float* eps2, float eps_scalar,
                             uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,
-                            uint32_t* recH, hipStream_t s) {
-  if (n2 == 0) return hipSuccess;
-  const int64_t blocks = (n2 + 255) / 256;
-  hipLaunchKernelGGL(k_intervals, dim3((unsigned)blocks), dim3(256), 0, s, pairs, kstart,
-                     num_pairs, n2, kp2, eps2, eps_scalar, sort_key, sort_val, recC, recH);
+                            uint32_t* recH, uint32_t* hist, int zero_passes, hipStream_t s) {
+  if (num_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intervals, dim3((unsigned)num_tiles), dim3(kSortTile), 0, s, pairs,
+                     tiles, num_tiles, kp2, eps2, eps_scalar, sort_key, sort_val, recC, recH,
+                     hist, zero_passes);
   return hipGetLastError();
 }
 
-hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
-                             int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
+hipError_t launch_query_keys(const PairDev* pairs, const SortTile* tiles, int num_tiles,
+                             const float* kp1, uint32_t* qkey, uint32_t* qflag,
                              uint32_t* sort_key, uint32_t* sort_val, double4* qline,
-                             unsigned long long* stats, uint32_t* sched,
-                             unsigned long long* match_stats, hipStream_t s) {
-  if (n1 == 0) return launch_clear_stats(stats, s, sched, match_stats);
-  const int64_t blocks = (n1 + 255) / 256;
-  hipLaunchKernelGGL(k_query_keys, dim3((unsigned)blocks), dim3(256), 0, s, pairs, qstart,
-                     num_pairs, n1, kp1, qkey, qflag, sort_key, sort_val, qline, stats, sched,
-                     match_stats);
+                             uint32_t* hist, int zero_passes, unsigned long long* stats,
+                             uint32_t* sched, unsigned long long* match_stats, hipStream_t s) {
+  if (num_tiles == 0) return launch_clear_stats(stats, s, sched, match_stats);
+  hipLaunchKernelGGL(k_query_keys, dim3((unsigned)num_tiles), dim3(kSortTile), 0, s, pairs,
+                     tiles, num_tiles, kp1, qkey, qflag, sort_key, sort_val, qline, hist,
+                     zero_passes, stats, sched, match_stats);
   return hipGetLastError();
 }
 

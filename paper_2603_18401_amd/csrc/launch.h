@@ -8,19 +8,23 @@
 
 namespace epm {
 
-hipError_t launch_intervals(const PairDev* pairs, const int64_t* kstart, int num_pairs,
-                            int64_t n2, const float* kp2, const float* eps2, float eps_scalar,
+// One workgroup per record sort tile; also leaves the first radix pass's
+// per-tile digit counts in hist (and zero counts for the later passes), so
+// that segmented_radix_sort(..., first_counts_ready = true) skips its count.
+hipError_t launch_intervals(const PairDev* pairs, const SortTile* tiles, int num_tiles,
+                            const float* kp2, const float* eps2, float eps_scalar,
                             uint32_t* sort_key, uint32_t* sort_val, uint32_t* recC,
-                            uint32_t* recH, hipStream_t s);
+                            uint32_t* recH, uint32_t* hist, int zero_passes, hipStream_t s);
 
-// Also writes every query's line (a, b, c, sqrt(a^2 + b^2)) to qline (zero for
-// a query without a line), and its first workgroup clears the counters as
-// launch_clear_stats does (each pointer may be NULL).
-hipError_t launch_query_keys(const PairDev* pairs, const int64_t* qstart, int num_pairs,
-                             int64_t n1, const float* kp1, uint32_t* qkey, uint32_t* qflag,
+// One workgroup per query sort tile.  Also writes every query's line (a, b,
+// c, sqrt(a^2 + b^2)) to qline (zero for a query without a line), the first
+// radix pass's counts as launch_intervals does, and its first workgroup
+// clears the counters as launch_clear_stats does (each pointer may be NULL).
+hipError_t launch_query_keys(const PairDev* pairs, const SortTile* tiles, int num_tiles,
+                             const float* kp1, uint32_t* qkey, uint32_t* qflag,
                              uint32_t* sort_key, uint32_t* sort_val, double4* qline,
-                             unsigned long long* stats, uint32_t* sched,
-                             unsigned long long* match_stats, hipStream_t s);
+                             uint32_t* hist, int zero_passes, unsigned long long* stats,
+                             uint32_t* sched, unsigned long long* match_stats, hipStream_t s);
 
 hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n2,
                                  const uint32_t* sorted_val, const float* kp2, const float* eps2,
@@ -49,7 +53,8 @@ hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
                                 int num_segs, int max_seg_tiles, uint32_t* hist, int bits,
                                 bool* sorted_in_1, hipStream_t s,
-                                uint32_t* last_digit_base = nullptr);
+                                uint32_t* last_digit_base = nullptr,
+                                bool first_counts_ready = false);
 
 struct StabArgs {
   const PairDev* pairs;

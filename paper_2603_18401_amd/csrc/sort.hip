@@ -248,16 +248,19 @@ int sort_passes(int bits) { return (bits + 7) / 8; }
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
                                 int num_segs, int max_seg_tiles, uint32_t* hist, int bits,
-                                bool* sorted_in_1, hipStream_t s, uint32_t* last_digit_base) {
+                                bool* sorted_in_1, hipStream_t s, uint32_t* last_digit_base,
+                                bool first_counts_ready) {
   *sorted_in_1 = false;
   if (num_tiles == 0) return hipSuccess;
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   if (max_seg_tiles <= kFusedTiles) {
     const int npass = sort_passes(bits);
     // counts of passes 1 .. npass-1 are accumulated by the previous pass
-    // into rows this launch clears
-    hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, 0,
-                       hist, npass - 1);
+    // into rows this launch clears (or the kernel that wrote the keys did
+    // both)
+    if (!first_counts_ready)
+      hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles, 0,
+                         hist, npass - 1);
     for (int p = 0; p < npass; ++p) {
       const bool last = p + 1 == npass;
       uint32_t* h = hist + (int64_t)p * num_tiles * kRadix;
