@@ -377,11 +377,12 @@ epm_status enqueue_build(epm_index* idx, const float* kp2_xy, const float* eps2,
                                 idx->at<uint32_t>(L.recC), idx->at<uint32_t>(L.recH),
                                 idx->at<uint32_t>(L.rC), idx->at<uint32_t>(L.rH),
                                 idx->at<int32_t>(L.rj), idx->at<float2>(L.rxy),
-                                idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv), stream));
+                                idx->at<float>(L.reps), idx->at<uint32_t>(L.rinv),
+                                idx->at<uint32_t>(L.digit_base), idx->at<int64_t>(L.class_begin),
+                                stream));
   idx->skey_off = in1 ? L.rk1 : L.rk0;
-  EPM_HIP(n2 > 0 ? launch_class_bounds_from_digits(dkstart, P, idx->at<uint32_t>(L.digit_base),
-                                                   idx->at<int64_t>(L.class_begin), stream)
-                 : launch_class_bounds(dkstart, P, skey, idx->at<int64_t>(L.class_begin), stream));
+  // with keypoints the gather wrote the class starts
+  if (n2 == 0) EPM_HIP(launch_class_bounds(dkstart, P, skey, idx->at<int64_t>(L.class_begin), stream));
   return EPM_OK;
 }
 

@@ -201,8 +201,17 @@ __global__ __launch_bounds__(256) void k_gather_records(
     const float* __restrict__ eps2, float eps_scalar, const uint32_t* __restrict__ recC,
     const uint32_t* __restrict__ recH, uint32_t* __restrict__ rC, uint32_t* __restrict__ rH,
     int32_t* __restrict__ rj, float2* __restrict__ rxy, float* __restrict__ reps,
-    uint32_t* __restrict__ rinv) {
+    uint32_t* __restrict__ rinv, const uint32_t* __restrict__ digit_base,
+    int64_t* __restrict__ class_begin) {
   const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (digit_base && pos < (int64_t)num_pairs * kClassSlots) {
+    // the start of width class c of pair p: the last radix pass's digit
+    // (class, top centre bits) starts, as the sort left them
+    const int p = (int)(pos / kClassSlots), c = (int)(pos % kClassSlots);
+    class_begin[pos] = c == kNumClasses
+                           ? kstart[p + 1]
+                           : (int64_t)digit_base[(int64_t)p * 256 + (c << (kSortBits - 16 - kClassBits))];
+  }
   if (pos >= n2) return;
   const uint32_t r = sorted_val[pos];
   const int p = find_pair(kstart, num_pairs, (int64_t)r);
@@ -226,27 +235,6 @@ __global__ __launch_bounds__(64) void k_class_bounds(const int64_t* __restrict__
     const int64_t b = cc == kNumClasses ? hi : wave_lower_bound(skey, lo, hi, (uint32_t)cc << kCentreBits);
     if (c == 0) class_begin[(int64_t)p * kClassSlots + cc] = b;
   }
-}
-
-__global__ __launch_bounds__(64) void k_class_bounds_from_digits(
-    const int64_t* __restrict__ kstart, const uint32_t* __restrict__ digit_base,
-    int64_t* __restrict__ class_begin) {
-  const int p = blockIdx.x;
-  const int c = threadIdx.x;
-  if (c > kNumClasses) return;
-  const int64_t v = c == kNumClasses
-                        ? kstart[p + 1]
-                        : (int64_t)digit_base[(int64_t)p * 256 + (c << (kSortBits - 16 - kClassBits))];
-  class_begin[(int64_t)p * kClassSlots + c] = v;
-}
-
-hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
-                                           const uint32_t* digit_base, int64_t* class_begin,
-                                           hipStream_t s) {
-  if (num_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_class_bounds_from_digits, dim3(num_pairs), dim3(64), 0, s, kstart,
-                     digit_base, class_begin);
-  return hipGetLastError();
 }
 
 hipError_t launch_intervals(const PairDev* pairs, const SortTile* tiles, int num_tiles,
@@ -276,12 +264,14 @@ hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n
                                  const uint32_t* sorted_val, const float* kp2, const float* eps2,
                                  float eps_scalar, const uint32_t* recC, const uint32_t* recH,
                                  uint32_t* rC, uint32_t* rH, int32_t* rj, float2* rxy,
-                                 float* reps, uint32_t* rinv, hipStream_t s) {
+                                 float* reps, uint32_t* rinv, const uint32_t* digit_base,
+                                 int64_t* class_begin, hipStream_t s) {
   if (n2 == 0) return hipSuccess;
-  const int64_t blocks = (n2 + 255) / 256;
+  const int64_t items = n2 > (int64_t)num_pairs * kClassSlots ? n2 : (int64_t)num_pairs * kClassSlots;
+  const int64_t blocks = (items + 255) / 256;
   hipLaunchKernelGGL(k_gather_records, dim3((unsigned)blocks), dim3(256), 0, s, kstart,
                      num_pairs, n2, sorted_val, kp2, eps2, eps_scalar, recC, recH, rC, rH, rj,
-                     rxy, reps, rinv);
+                     rxy, reps, rinv, digit_base, class_begin);
   return hipGetLastError();
 }
 

@@ -30,15 +30,13 @@ hipError_t launch_gather_records(const int64_t* kstart, int num_pairs, int64_t n
                                  const uint32_t* sorted_val, const float* kp2, const float* eps2,
                                  float eps_scalar, const uint32_t* recC, const uint32_t* recH,
                                  uint32_t* rC, uint32_t* rH, int32_t* rj, float2* rxy,
-                                 float* reps, uint32_t* rinv, hipStream_t s);
+                                 float* reps, uint32_t* rinv, const uint32_t* digit_base,
+                                 int64_t* class_begin, hipStream_t s);
+// digit_base non-NULL: the gather also writes class_begin from the digit
+// starts of the last sort pass (digit = class << 3 | top three centre bits).
 
 hipError_t launch_class_bounds(const int64_t* kstart, int num_pairs, const uint32_t* skey,
                                int64_t* class_begin, hipStream_t s);
-// Class starts from the digit bases of the last sort pass (digit = class << 3
-// | top three centre bits).
-hipError_t launch_class_bounds_from_digits(const int64_t* kstart, int num_pairs,
-                                           const uint32_t* digit_base, int64_t* class_begin,
-                                           hipStream_t s);
 
 // Stable LSD radix sort of (key, value) u32 pairs inside every segment, over
 // the low `bits` bits of the keys, 8 bits per pass.  Ping-pongs between

@@ -12,7 +12,8 @@
 // When no segment has more than kFusedTiles tiles, a pass is one launch:
 // k_sort_pass finds its tile's offsets from the per-tile counts of its
 // segment itself and, while writing, counts the next pass's digits into the
-// tiles the elements land in, so only the first pass needs k_sort_hist.
+// tiles the elements land in, so only the first pass needs counts, from
+// k_sort_hist or from the kernel that wrote the keys.
 #include "device_common.h"
 #include "launch.h"
 
