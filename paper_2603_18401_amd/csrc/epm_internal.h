@@ -67,7 +67,7 @@ struct SortSeg {
   int32_t tile_begin, tile_count;
 };
 
-constexpr int kSortTile = 1024;     // elements per sort tile
+constexpr int kSortTile = 512;      // elements per sort tile
 constexpr int kSortThreads = 256;
 
 constexpr int kClassSlots = kNumClasses + 1;  // class_begin entries per pair

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
 }
 
-constexpr int kFusedTiles = 64;
+constexpr int kFusedTiles = 128;
 
 // One pass of the fused sort.  hist: this pass's per-tile digit counts;
 // hist_next: the next pass's (zero on entry), or NULL on the last pass.
