@@ -71,6 +71,28 @@ def test_cfg1_fused_equals_oracle(motion, eps):
     assert idx.stats()["candidates"] == int(got[0][-1])
 
 
+def test_counters_of_the_fused_and_plain_query_agree():
+    """The tile pass leaves its counters per tile whether or not it also
+    matches: both calls report the same scan, angle hits and candidates, and
+    the brute-force queries of an off-rank F are counted."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    p = synth.cfg0_pair(1)
+    F = p.F + 1e-3 * np.abs(p.F).max() * np.random.default_rng(11).standard_normal((3, 3))
+    p.F = F
+    log("counters: query vs query_match, full-rank F")
+    k1, k2 = _dev(torch, p.kp1), _dev(torch, p.kp2)
+    idx = E.Index(specs_of([p]), k2, eps=3.0)
+    o, _ = idx.query(k1)
+    st_q = idx.stats()
+    idx.query_match(k1, _dev(torch, p.desc1), _dev(torch, p.desc2))
+    st_m = idx.stats()
+    assert st_q == st_m
+    assert st_q["candidates"] == int(o.cpu().numpy()[-1])
+    assert st_q["scanned_queries"] > 0
+    assert st_q["candidates"] <= st_q["angle_hits"] <= st_q["records_scanned"]
+
+
 def test_long_rows_take_the_wide_row_pass():
     """A wide tolerance gives rows beyond the on-chip list (more than 128
     candidates); the wide-row pass writes and matches them."""
