@@ -282,8 +282,11 @@ epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);
  * stabbing with the FP64 test, CSR compaction and descriptor matching
  * (Algorithm 1, preprocessing and matching loop) -- for the buffers named in
  * `desc` into one HIP graph: kernels only, no host synchronisation, no
- * memset or memcpy nodes.  FP32 descriptors on the tiled path use the fused
- * pass of epm_query_match.  epm_batch_launch replays it on a stream; every
+ * memset or memcpy nodes.  The interval build and the query keys with their
+ * sort are two branches of the graph (they read disjoint inputs and write
+ * disjoint buffers) that join before the first kernel reading the records.
+ * FP32 descriptors on the tiled path use the fused pass of epm_query_match.
+ * epm_batch_launch replays it on a stream; every
  * replay recomputes every output from the current contents of the input
  * buffers, so new keypoints and descriptors of the same sizes can be written
  * between replays (the pairs' F and slices are fixed at creation).

@@ -22,7 +22,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Offsets of every device buffer inside the caller's workspace.
 struct Layout {
-  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist;
+  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist, qhist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
@@ -47,9 +47,10 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.qtiles = take(sizeof(SortTile) * tq);
   L.qsegs = take(sizeof(SortSeg) * P);
   L.stiles = take(sizeof(StabTile) * ts);
-  // per-tile digit counts of every pass of the record (3) or query (2) sort
-  L.hist = take(sizeof(uint32_t) * 256 * (size_t)sort_passes(kSortBits) *
-                (size_t)(tr > tq ? tr : tq));
+  // per-tile digit counts of every pass of the record (3) and of the query
+  // (2) sort: separate, so that the two sorts may run side by side
+  L.hist = take(sizeof(uint32_t) * 256 * (size_t)sort_passes(kSortBits) * (size_t)tr);
+  L.qhist = take(sizeof(uint32_t) * 256 * (size_t)sort_passes(kQuerySortBits) * (size_t)tq);
   L.rk0 = take(4 * N2);
   L.rv0 = take(4 * N2);
   L.rk1 = take(4 * N2);
@@ -440,13 +441,18 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
 
 // Query keys and their sort, the tile windows, the stabbing pass and the
 // scan of the row lengths into row_offsets (Algorithm 1, matching loop).
+// records_ready: the record build runs on another stream and completes this
+// event; the stream waits for it after the query sort, before the first
+// kernel that reads the records.
 epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
-                         hipStream_t stream, bool fuse = false) {
+                         hipStream_t stream, bool fuse = false,
+                         hipEvent_t records_ready = nullptr) {
   const Layout& L = idx->L;
   const int64_t n1 = idx->N1;
   idx->have_order = false;
   idx->have_block_tile = false;
   if (n1 == 0) {
+    if (records_ready) EPM_HIP(hipStreamWaitEvent(stream, records_ready, 0));
     // row_offsets[0] = 0 (two zero words, by kernel); the counters read zero
     EPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(row_offsets), 2, 0u, stream));
     if (A.match_stats) EPM_HIP(launch_clear_stats(nullptr, stream, nullptr, A.match_stats));
@@ -455,17 +461,19 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   EPM_HIP(launch_query_keys(A.pairs, idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
                             A.kp1, idx->at<uint32_t>(L.qkey), idx->at<uint32_t>(L.qflag),
                             idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0), A.qline,
-                            idx->at<uint32_t>(L.hist), sort_passes(16) - 1, A.stats,
+                            idx->at<uint32_t>(L.qhist), sort_passes(kQuerySortBits) - 1, A.stats,
                             idx->at<uint32_t>(L.sched), A.match_stats, stream));
   bool in1 = false;
   EPM_HIP(segmented_radix_sort(idx->at<uint32_t>(L.qk0), idx->at<uint32_t>(L.qv0),
                                idx->at<uint32_t>(L.qk1), idx->at<uint32_t>(L.qv1),
                                idx->at<SortTile>(L.qtiles), (int)idx->qtiles.size(),
                                idx->at<SortSeg>(L.qsegs), idx->P, max_tiles(idx->qsegs),
-                               idx->at<uint32_t>(L.hist), 16, &in1, stream, nullptr, true));
+                               idx->at<uint32_t>(L.qhist), kQuerySortBits, &in1, stream, nullptr,
+                               true));
   idx->qperm = idx->at<uint32_t>(in1 ? L.qv1 : L.qv0);
   idx->have_qperm = true;
   A.qperm = idx->qperm;
+  if (records_ready) EPM_HIP(hipStreamWaitEvent(stream, records_ready, 0));
   const epm_sched& S = idx->sched;
   const bool persistent = S.stab_workgroups > 0 || S.match_workgroups > 0;
   const bool lpt = persistent && S.lpt == 1;
@@ -687,7 +695,8 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
 // selection, and the listed-query match of the rows the two passes left.
 // nnz_host as in epm_query_candidates.
 epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets,
-                               int64_t* nnz_host, const MatchCall& c, hipStream_t stream) {
+                               int64_t* nnz_host, const MatchCall& c, hipStream_t stream,
+                               hipEvent_t records_ready = nullptr) {
   const int64_t n1 = idx->N1;
   A.desc1 = static_cast<const float*>(c.desc1);
   A.desc2 = static_cast<const float*>(c.desc2);
@@ -699,7 +708,7 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);  // cleared with the counters
   idx->have_match_stats = true;
   idx->match_stream = stream;
-  const epm_status st = enqueue_count(idx, A, row_offsets, stream, true);
+  const epm_status st = enqueue_count(idx, A, row_offsets, stream, true, records_ready);
   if (st != EPM_OK) return st;
   if (n1 == 0) return EPM_OK;
   idx->last_stream = stream;
@@ -930,24 +939,33 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
   b->row_offsets = d->row_offsets;
   b->capacity = d->capacity;
 
-  // record on a private stream: kernels only
-  hipStream_t cs = nullptr;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-    delete b;
-    return EPM_ERR_HIP;
-  }
+  // record on private streams, kernels only: the record build forks onto a
+  // second stream beside the query keys and their sort, and joins before the
+  // tile windows (two branches of the graph)
+  hipStream_t cs = nullptr, cs2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   st = EPM_OK;
-  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = EPM_ERR_HIP;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+    st = EPM_ERR_HIP;
+  if (st == EPM_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    st = EPM_ERR_HIP;
   if (st == EPM_OK) {
-    epm_status r = enqueue_build(idx, d->kp2_xy, d->eps2, d->eps_scalar, cs);
+    epm_status r = EPM_OK;
+    if (hipEventRecord(fork, cs) != hipSuccess || hipStreamWaitEvent(cs2, fork, 0) != hipSuccess)
+      r = EPM_ERR_HIP;
+    if (r == EPM_OK) r = enqueue_build(idx, d->kp2_xy, d->eps2, d->eps_scalar, cs2);
+    if (r == EPM_OK && hipEventRecord(join, cs2) != hipSuccess) r = EPM_ERR_HIP;
     // after the build: the stab arguments name the sorted key buffer it chose
     StabArgs A = stab_args(idx, d->kp1_xy, d->row_offsets, d->col_indices, d->capacity);
     // FP32 on the tiled path: selection fused into the stabbing pass
     const bool fused = c.dtype == EPM_F32 && c.algo != EPM_ALGO_PLAIN;
     if (fused) {
-      if (r == EPM_OK) r = enqueue_query_match(idx, A, d->row_offsets, nullptr, c, cs);
+      if (r == EPM_OK) r = enqueue_query_match(idx, A, d->row_offsets, nullptr, c, cs, join);
     } else {
-      if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs);
+      if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs, false, join);
       if (r == EPM_OK) r = enqueue_fill(idx, A, cs);
       if (r == EPM_OK) r = enqueue_match(idx, c, cs);
     }
@@ -959,7 +977,10 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
   }
   if (st == EPM_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
     st = EPM_ERR_HIP;
-  (void)hipStreamDestroy(cs);
+  if (join) (void)hipEventDestroy(join);
+  if (fork) (void)hipEventDestroy(fork);
+  if (cs2) (void)hipStreamDestroy(cs2);
+  if (cs) (void)hipStreamDestroy(cs);
   if (st != EPM_OK) {
     delete b;
     return st;

@@ -28,6 +28,8 @@ constexpr int kCentreBits = 19;
 constexpr int kCentreShift = 32 - kCentreBits;  // centre key >> 13
 constexpr int kSortBits = kClassBits + kCentreBits;  // 24 -> three 8-bit passes
 constexpr int kWideClass = 31;
+// Queries are sorted by the top 16 bits of their key (two 8-bit passes).
+constexpr int kQuerySortBits = 16;
 
 // Query flags.
 constexpr uint32_t kQueryNormal = 0;

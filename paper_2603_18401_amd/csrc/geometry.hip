@@ -183,12 +183,12 @@ __global__ __launch_bounds__(kSortTile) void k_query_keys(
     }
     qkey[i] = key;
     qflag[i] = flag;
-    sort_key[i] = key >> 16;
+    sort_key[i] = key >> (32 - kQuerySortBits);
     sort_val[i] = (uint32_t)i;
     // the line and its norm for the tile passes (the denominator of Eq. 3)
     qline[i] = flag == kQueryEmpty ? make_double4(0.0, 0.0, 0.0, 0.0)
                                    : make_double4(a, b, c, line_norm(a, b));
-    atomicAdd(&h[(key >> 16) & (kRadixDigits - 1)], 1u);
+    atomicAdd(&h[(key >> (32 - kQuerySortBits)) & (kRadixDigits - 1)], 1u);
   }
   first_pass_counts(h, hist, num_tiles, zero_passes);
 }
