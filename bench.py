@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+EVENT_STRIDE = 10  # timed steps per launch of the dominant kernel bracketed by events
 METRIC = "keypoint queries/s (retrieve+match), exact candidate sets, vs plain GPU path"
 
 
@@ -745,18 +746,23 @@ def main():
         return step
 
     step = make_step(args.algo)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    # the dominant kernel is bracketed by timing events on every
+    # EVENT_STRIDE-th timed step (always the first): two timing events add
+    # about 13 us to a 0.23 ms step, while the kernel's average is the same
+    # whether every launch or every tenth is timed
+    sampled = list(range(0, args.steps, EVENT_STRIDE))
+    evs = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in sampled}
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step(evs.get(k))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     qps = N1 * args.steps / elapsed
-    kernel_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    kernel_ms = [evs[k][0].elapsed_time(evs[k][1]) for k in sampled]
     assert int(row_offsets[-1].item()) == nnz
     ref_out = [x.clone() for x in outs]
 
@@ -870,6 +876,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(src, tfile),
                 "avg_launch_ms": round(kern_ms, 5),
+                "timed_launches": len(kernel_ms), "timed_every_nth_step": EVENT_STRIDE,
                 "algorithmic_bytes_per_launch": int(kernel_bytes),
                 "kernel_source_sha256": source_hash(src)}
 
