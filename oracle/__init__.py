@@ -15,6 +15,11 @@ Parity status of each function (pins are the tests in tests/test_oracle*.py):
   match (float)     pinned: canonical FP32 chain vs exact rational rounding,
                     selection vs sorted (distance, j), brute-force NN limit.
   match (binary)    pinned: Hamming vs numpy bit counts.
+  point_line_dist,  pinned: hand values of the wrap-around case (Sec. 4.4),
+  candidate_terms   integer lines with exact terms, the scanline case with
+                    scalar and per-keypoint eps.
+  desc_dist_f64     pinned: hand cases with exact dyadic sums, and exact
+                    rational distances within its FP64 rounding bound.
   paper_angle_*     pinned against the brute-force candidates (agreement
                     outside a 1e-6 px boundary band).
   mutual.*          pinned: both directions keep noiseless true matches only

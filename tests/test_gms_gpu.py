@@ -1,9 +1,11 @@
-"""GMS validation on the GPU (epm_gms) against the oracle, bit for bit, on
-the matches the library itself selects."""
+"""GMS validation on the GPU (epm_gms) against the oracle, bit for bit: the
+library's matches must equal the oracle's, and its GMS decisions must equal
+the oracle's GMS over the oracle's matches."""
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from oracle.gms import gms as oracle_gms
 from tests.gpu_util import specs_of, torch_gpu
@@ -28,8 +30,12 @@ def _check(pairs, eps, grid=20, alpha=6.0, ratio=0.0):
     best, out = best.cpu().numpy(), out.cpu().numpy()
     q0 = 0
     for p in pairs:
-        ref = oracle_gms(p.kp1, p.kp2, best[q0:q0 + p.m], p.W, p.H, p.W, p.H, grid=grid,
-                         alpha=alpha)
+        # the oracle chain starts from the oracle's own matches: candidates
+        # (Eq. 3-4) -> nearest neighbour (Sec. 4.3) -> GMS
+        ro, rc, _ = oracle.candidates(p.F, p.kp1, p.kp2, eps)
+        ref_best, _, _ = oracle.match(p.desc1, p.desc2, ro, rc, ratio=ratio)
+        assert np.array_equal(best[q0:q0 + p.m], ref_best)
+        ref = oracle_gms(p.kp1, p.kp2, ref_best, p.W, p.H, p.W, p.H, grid=grid, alpha=alpha)
         assert np.array_equal(out[q0:q0 + p.m], ref)
         q0 += p.m
     return best, out

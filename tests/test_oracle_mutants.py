@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from tests import test_oracle as pins
+from tests import test_oracle_terms as term_pins
 
 ORACLE_SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -31,6 +32,14 @@ MATCH_PINS = [
     pins.test_h5_eps_beyond_diagonal_is_brute_force,
 ]
 
+TERM_PINS = [
+    term_pins.test_point_line_dist_wraparound_hand_values,
+    term_pins.test_terms_on_integer_lines_are_exact,
+    term_pins.test_terms_scalar_and_per_keypoint_eps,
+    term_pins.test_desc_dist_f64_hand_cases,
+    term_pins.test_desc_dist_f64_within_its_rounding_bound,
+]
+
 MUTANTS = {
     "dropped_c_term": ("*a = F[0] * x + F[1] * y + F[2];", "*a = F[0] * x + F[1] * y;"),
     "transposed_F": ("*b = F[3] * x + F[4] * y + F[5];", "*b = F[1] * x + F[4] * y + F[7];"),
@@ -49,6 +58,18 @@ MUTANTS = {
     "hamming_and": ("h += popcount32(a[w] ^ b[w]);", "h += popcount32(a[w] & b[w]);"),
     "second_is_worst": ("float sd = k > 1 ? buf[1].d : INFINITY;",
                         "float sd = k > 1 ? buf[k - 1].d : INFINITY;"),
+    # listed-pair helpers (Eq. 3 distance, both sides of Eq. 3-4, FP64 distance)
+    "dist_no_sqrt": ("out[t] = num / sqrt(a * a + b * b);", "out[t] = num / (a * a + b * b);"),
+    "dist_swapped_xy": ("double num = fabs(a * (double)kp2[2 * j] + b * (double)kp2[2 * j + 1] + c);",
+                        "double num = fabs(a * (double)kp2[2 * j + 1] + b * (double)kp2[2 * j] + c);"),
+    "terms_wrong_norm": ("rhs[t] = eps * sqrt(a * a + b * b);", "rhs[t] = eps * sqrt(a * a + b * a);"),
+    "terms_wrong_sign": ("num[t] = fabs(a * (double)kp2[2 * j] + b * (double)kp2[2 * j + 1] + c);",
+                         "num[t] = fabs(a * (double)kp2[2 * j] + b * (double)kp2[2 * j + 1] - c);"),
+    "terms_scalar_eps_ignored": ("double eps = (double)(eps2 ? eps2[j] : eps_scalar);",
+                                 "double eps = (double)(eps2 ? eps2[j] : 1.0f);"),
+    "f64_diff_as_sum": ("double t = (double)a[k] - (double)b[k];",
+                        "double t = (double)a[k] + (double)b[k];"),
+    "f64_term_in_f32": ("acc += t * t;", "acc += (float)(t * t);"),
 }
 
 
@@ -66,7 +87,7 @@ def test_pins_catch_planted_mistake(name):
         so = oracle.build(force=True, src=path, out=os.path.join(d, "libmutant.so"))
         mutant = oracle.OracleLib(so)
         caught = []
-        for pin in CANDIDATE_PINS + MATCH_PINS:
+        for pin in CANDIDATE_PINS + MATCH_PINS + TERM_PINS:
             try:
                 pin(mutant)
             except (AssertionError, IndexError, ValueError):
