@@ -296,9 +296,19 @@ def cfg3_pair(r, float_desc=True, max_kp=30000, min_kp=500):
                      float_desc=float_desc, tag=f"cfg3 {kind} {W}x{H} m={m} n={n}")
 
 
-def cfg3_batch(num_pairs=512, float_desc=True, max_kp=30000, min_kp=500):
-    return [cfg3_pair(r, float_desc=float_desc, max_kp=max_kp, min_kp=min_kp)
-            for r in range(num_pairs)]
+def cfg3_batch(num_pairs=512, float_desc=True, max_kp=30000, min_kp=500, workers=8):
+    """The pairs 0 .. num_pairs-1 of the batching workload, generated on a
+    thread pool (every pair draws from its own seed, so the result does not
+    depend on the number of workers)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(r):
+        return cfg3_pair(r, float_desc=float_desc, max_kp=max_kp, min_kp=min_kp)
+
+    if workers <= 1:
+        return [one(r) for r in range(num_pairs)]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(one, range(num_pairs)))
 
 
 def cfg4_pair(r, n_kp=10000, float_desc=True):
