@@ -24,8 +24,10 @@
  *  - Every array argument is a DEVICE pointer owned by the caller (for
  *    instance the data_ptr() of a torch tensor).  The library never
  *    allocates device memory: all of its scratch lives in the caller's
- *    workspace (see epm_workspace_bytes).  Host-side bookkeeping lives in the
- *    opaque epm_index, released with epm_index_destroy.
+ *    workspace (see epm_workspace_bytes), except for
+ *    epm_query_match_noalloc, whose scratch is a fixed array of the library.
+ *    Host-side bookkeeping lives in the opaque epm_index, released with
+ *    epm_index_destroy.
  *  - `pairs` is a HOST array.  A batch of image pairs is concatenated along
  *    the keypoint axis: pair p owns image-1 rows [q_begin, q_begin + m) of
  *    kp1/desc1 and image-2 rows [k_begin, k_begin + n) of kp2/eps2/desc2.
@@ -236,6 +238,41 @@ epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_off
                            const float* desc1, const float* desc2, float ratio,
                            int32_t* best_idx, float* best_dist, float* second_dist,
                            hipStream_t stream);
+
+/*
+ * Allocation-free form of epm_build_intervals followed by epm_query_match,
+ * for callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Inputs and outputs are those of the two calls (pairs in host
+ * memory; kp1, kp2, eps2, FP32 descriptors, CSR and match outputs in device
+ * memory, owned by the caller) and the results are identical to theirs.
+ *
+ * Instead of a workspace the index lives in the library's own device array
+ * of EPM_NOALLOC_SCRATCH_BYTES bytes, one per GPU, which exists from the
+ * time the library's code is loaded on that GPU until the process ends.  A
+ * batch whose index needs more (epm_workspace_bytes(pairs, num_pairs) >
+ * EPM_NOALLOC_SCRATCH_BYTES) is refused with EPM_ERR_WORKSPACE before
+ * anything is enqueued.  No call allocates device memory: the first call on
+ * a device (with that device current) looks up the array's address and
+ * creates two events, later calls reuse them.
+ *
+ * Every call on one GPU uses that GPU's one array, which keeps whatever the
+ * last call left in it; each call rebuilds everything it reads.  Calls in
+ * sequence on one stream are safe; calls that overlap on one GPU (on
+ * different streams, or from threads racing each other) race and give
+ * undefined results.  Host synchronisation: as epm_query_match with
+ * nnz_host; besides, a call waits for the table upload of the call two
+ * before it when the host runs that far ahead of the stream.
+ * Errors: as epm_build_intervals and epm_query_match; EPM_ERR_UNSUPPORTED on
+ * a device ordinal >= 64.
+ */
+#define EPM_NOALLOC_SCRATCH_BYTES (64u << 20)
+epm_status epm_query_match_noalloc(const epm_pair* pairs, int32_t num_pairs, const float* kp1_xy,
+                                   const float* kp2_xy, const float* eps2, float eps_scalar,
+                                   int64_t* row_offsets, int32_t* col_indices, int64_t capacity,
+                                   int64_t* nnz_host, const float* desc1, const float* desc2,
+                                   float ratio, int32_t* best_idx, float* best_dist,
+                                   float* second_dist, hipStream_t stream);
 
 /*
  * Work distribution of the angle-tile kernels (the stabbing pass of

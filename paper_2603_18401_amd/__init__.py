@@ -41,7 +41,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
-           "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms"]
+           "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc"]
 
 
 class EpmError(RuntimeError):
@@ -192,6 +192,9 @@ def load_library(path=None):
     lib.epm_index_set_timing_kernel.restype = ctypes.c_int
     lib.epm_quantize.argtypes = [V, i64, i32, ctypes.c_int, V, V, V]
     lib.epm_quantize.restype = ctypes.c_int
+    lib.epm_query_match_noalloc.argtypes = [P, i32, V, V, V, f32, V, V, i64,
+                                            ctypes.POINTER(i64), V, V, f32, V, V, V, V]
+    lib.epm_query_match_noalloc.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -571,6 +574,40 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def query_match_noalloc(pairs, kp1, kp2, desc1, desc2, eps2=None, eps=0.0, ratio=0.0,
+                        row_offsets=None, col_indices=None, out=None, stream=None):
+    """epm_query_match_noalloc: build + fused query/match with the index in the
+    library's static device array (no workspace, no device allocation by the
+    library).  row_offsets [N1+1] and col_indices (its length is the capacity)
+    may be preallocated by the caller; the call synchronises once to read nnz.
+    Returns (row_offsets, col_indices[:nnz], best_idx, best_dist, second_dist)."""
+    torch = _torch()
+    lib = load_library()
+    specs = list(pairs)
+    arr, n1, n2 = _pair_array(specs)
+    dev = kp2.device
+    if row_offsets is None:
+        row_offsets = torch.empty(n1 + 1, dtype=torch.int64, device=dev)
+    if col_indices is None:
+        col_indices = torch.empty(max(1024, 64 * n1), dtype=torch.int32, device=dev)
+    if out is None:
+        out = (torch.empty(n1, dtype=torch.int32, device=dev),
+               torch.empty(n1, dtype=torch.float32, device=dev),
+               torch.empty(n1, dtype=torch.float32, device=dev))
+    best, bd, sd = out
+    nnz = ctypes.c_int64(0)
+    st = lib.epm_query_match_noalloc(arr, len(specs), _dptr(kp1), _dptr(kp2), _dptr(eps2),
+                                     float(eps), _dptr(row_offsets), _dptr(col_indices),
+                                     col_indices.numel(), ctypes.byref(nnz), _dptr(desc1),
+                                     _dptr(desc2), float(ratio), _dptr(best), _dptr(bd),
+                                     _dptr(sd), _stream(torch, dev, stream))
+    _check(st, "epm_query_match_noalloc")
+    return row_offsets, col_indices[: nnz.value], best, bd, sd
 
 
 def quantize(desc, dtype, stream=None):

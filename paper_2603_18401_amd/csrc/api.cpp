@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "epm.h"
@@ -730,6 +732,51 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free variant
+// epm_query_match_noalloc keeps the whole index in this file-scope device
+// array instead of a caller workspace.  Host code never passes the array's
+// name to a kernel or a copy: on every device the library runs on, the first
+// call (with that device current) looks its address up once with
+// hipGetSymbolAddress and every later use goes through that pointer.
+static __device__ __align__(256) unsigned char scratch[EPM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+
+// Per-device state of the allocation-free variant.  The host image of the
+// index tables is uploaded asynchronously, so it must stay untouched until
+// the copy has run: two host images alternate, each with an event recorded
+// after its upload, and a call waits for that event only before reusing an
+// image (that is, when the host runs two calls ahead of the stream).
+struct NoAllocDevice {
+  bool ready = false;
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this device
+  std::vector<char> head[2];
+  hipEvent_t uploaded[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int next = 0;
+};
+
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+// Set-up on the current device: the array's address and the two events.
+epm_status noalloc_setup(NoAllocDevice& d) {
+  if (d.ready) return EPM_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EPM_ERR_HIP;
+  for (int k = 0; k < 2; ++k)
+    if (!d.uploaded[k] &&
+        hipEventCreateWithFlags(&d.uploaded[k], hipEventDisableTiming) != hipSuccess)
+      return EPM_ERR_HIP;
+  d.ptr = static_cast<unsigned char*>(p);
+  d.ready = true;
+  return EPM_OK;
+}
+
+}  // namespace
+
 // A recorded pipeline: the index it runs on and the instantiated graph.
 struct epm_batch {
   epm_index* idx = nullptr;
@@ -891,6 +938,76 @@ epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_off
   if (v != EPM_OK) return v;
   StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
   return enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
+}
+
+epm_status epm_query_match_noalloc(const epm_pair* pairs, int32_t num_pairs, const float* kp1_xy,
+                                   const float* kp2_xy, const float* eps2, float eps_scalar,
+                                   int64_t* row_offsets, int32_t* col_indices, int64_t capacity,
+                                   int64_t* nnz_host, const float* desc1, const float* desc2,
+                                   float ratio, int32_t* best_idx, float* best_dist,
+                                   float* second_dist, hipStream_t stream) {
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2)) return EPM_ERR_ARG;
+  if (!build_args_ok(n2, kp2_xy, eps2, eps_scalar)) return EPM_ERR_ARG;
+  if (!row_offsets || capacity < 0 || (n1 > 0 && !kp1_xy)) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  {
+    // the size limit is a host check: nothing runs when it fails
+    int64_t tr = 0, tq = 0, ts = 0;
+    for (int p = 0; p < num_pairs; ++p) {
+      tr += tiles_of(pairs[p].n);
+      tq += tiles_of(pairs[p].m);
+      ts += stab_tiles_of(pairs[p].m);
+    }
+    if (make_layout(num_pairs, n1, n2, tr, tq, ts).total > (size_t)EPM_NOALLOC_SCRATCH_BYTES)
+      return EPM_ERR_WORKSPACE;
+  }
+  MatchCall c;
+  c.row_offsets = row_offsets;
+  c.col_indices = col_indices;
+  c.dtype = EPM_F32;
+  c.dim = 128;
+  c.desc1 = desc1;
+  c.desc2 = desc2;
+  c.scale1 = c.scale2 = c.desc1_f32 = c.desc2_f32 = nullptr;
+  c.ratio = ratio;
+  c.best_idx = best_idx;
+  c.best_dist = best_dist;
+  c.second_dist = second_dist;
+  c.algo = EPM_ALGO_TILED;
+  c.capacity = nnz_host ? -1 : capacity;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return EPM_ERR_HIP;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return EPM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& D = g_noalloc[dev];
+  epm_status st = noalloc_setup(D);
+  if (st != EPM_OK) return st;
+  epm_index* idx = nullptr;
+  st = index_prepare(pairs, num_pairs, D.ptr, (size_t)EPM_NOALLOC_SCRATCH_BYTES, &idx);
+  if (st != EPM_OK) return st;
+  st = validate_match(idx, c);
+  if (st == EPM_OK) {
+    // the table image goes up from one of the two host images
+    const int slot = D.next;
+    D.next ^= 1;
+    if (D.pending[slot] && hipEventSynchronize(D.uploaded[slot]) != hipSuccess) st = EPM_ERR_HIP;
+    if (st == EPM_OK) {
+      std::swap(D.head[slot], idx->head);
+      if (hipMemcpyAsync(D.ptr, D.head[slot].data(), idx->L.hist, hipMemcpyHostToDevice,
+                         stream) != hipSuccess ||
+          hipEventRecord(D.uploaded[slot], stream) != hipSuccess)
+        st = EPM_ERR_HIP;
+      D.pending[slot] = true;
+    }
+  }
+  if (st == EPM_OK) st = enqueue_build(idx, kp2_xy, eps2, eps_scalar, stream);
+  if (st == EPM_OK) {
+    StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
+    st = enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
+  }
+  delete idx;
+  return st;
 }
 
 epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_batch_desc* d,

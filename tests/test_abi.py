@@ -246,3 +246,23 @@ def test_gms_argument_errors(lib):
     size1 = (ctypes.c_int32 * 2)(640, 480)
     assert lib.epm_gms_workspace_bytes(None, 20) == 0
     assert lib.epm_gms(None, size1, 20, 6.0, None, None, None, None, None, 0, None) == 1
+
+
+def test_noalloc_refuses_batches_beyond_its_scratch(lib):
+    """epm_query_match_noalloc checks the index size against its fixed array
+    on the host: a batch that needs more is refused before anything runs."""
+    import paper_2603_18401_amd as E
+    F = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 0]], float)
+    big = [E.PairSpec(F, 640, 480, 150000, 1000)]
+    arr, n1, _ = _pairs(big)
+    assert lib.epm_workspace_bytes(arr, 1) > E.NOALLOC_SCRATCH_BYTES
+    V = ctypes.c_void_p
+    nnz = ctypes.c_int64(0)
+    st = lib.epm_query_match_noalloc(arr, 1, V(256), V(256), None, 2.0, V(256), V(256), 10,
+                                     ctypes.byref(nnz), V(256), V(256), 0.0, V(256), V(256),
+                                     V(256), None)
+    assert st == 4  # EPM_ERR_WORKSPACE
+    st = lib.epm_query_match_noalloc(arr, 1, None, V(256), None, 2.0, V(256), V(256), 10,
+                                     ctypes.byref(nnz), V(256), V(256), 0.0, V(256), V(256),
+                                     V(256), None)
+    assert st == 1  # kp1 missing: EPM_ERR_ARG
