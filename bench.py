@@ -271,6 +271,15 @@ def batch_workload(args):
     esec = time_steps(torch, eager_step, args.steps, args.warmup)
     same = all(torch.equal(a, r) for a, r in zip(out, res_graph))
 
+    def fused_step():
+        idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+        idx.query_match_bf16(kp1, q1, q2, m1, m2, row_offsets=offs, col_indices=cols, out=out,
+                             sync=False)
+        idx.close()
+
+    fsec = time_steps(torch, fused_step, args.steps, args.warmup)
+    fsame = all(torch.equal(a, r) for a, r in zip(out, res_graph))
+
     # ---- plain path: one pipeline per pair
     qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
     kb = np.concatenate([[0], np.cumsum([p.n for p in pairs])])
@@ -305,6 +314,8 @@ def batch_workload(args):
             "match_stats": gmatch, "query_stats": gstats,
             "eager_batched": {"value": round(N1 / esec, 1), "ms_per_step": round(esec * 1e3, 4),
                               "identical_matches": bool(same)},
+            "eager_fused_bf16": {"value": round(N1 / fsec, 1), "ms_per_step": round(fsec * 1e3, 4),
+                                 "identical_matches": bool(fsame)},
             "plain_gpu": None if args.no_plain else {"value": round(N1 / psec, 1),
                                                      "ms_per_step": round(psec * 1e3, 2)},
             "speedup_vs_plain": None if args.no_plain else round(psec / sec, 3)}

@@ -240,6 +240,30 @@ epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_off
                            hipStream_t stream);
 
 /*
+ * epm_query_match with BF16 descriptors (Algorithm 1 matching loop, selection
+ * of Sec. 4.3): desc1/desc2 are BF16 codes [N][128] (uint16 bit patterns) that
+ * must be the round-to-nearest-even values of the FP32 masters
+ * desc1_f32/desc2_f32 [N][128] (as epm_quantize writes them).  Every query's
+ * hits are scored on MFMA against the BF16 rows of its tile's window while
+ * they are still on chip; each score gives certified lower and upper bounds
+ * on the exact canonical FP32 distance of the masters (the format's rounding
+ * bound for the image-2 rows, the measured rounding error of the query row,
+ * the FP32 accumulation bound), and only the candidates whose lower bound is
+ * not above the row's second-smallest upper bound are evaluated exactly on
+ * the masters.  Outputs -- the CSR with the capacity and nnz_host contract of
+ * epm_query_candidates, best_idx / best_dist / second_dist -- are identical
+ * to epm_query_candidates + epm_match(EPM_F32) on the masters; rows whose
+ * bounds cannot be certified are matched exactly (counted by
+ * epm_get_match_stats).  Errors: EPM_ERR_ARG, EPM_ERR_CAPACITY, EPM_ERR_HIP.
+ */
+epm_status epm_query_match_bf16(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                                const uint16_t* desc1, const uint16_t* desc2,
+                                const float* desc1_f32, const float* desc2_f32, float ratio,
+                                int32_t* best_idx, float* best_dist, float* second_dist,
+                                hipStream_t stream);
+
+/*
  * Allocation-free form of epm_build_intervals followed by epm_query_match,
  * for callers that cannot allocate device memory or hand over a workspace
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -322,11 +346,18 @@ epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);
  * memset or memcpy nodes.  The interval build and the query keys with their
  * sort are two branches of the graph (they read disjoint inputs and write
  * disjoint buffers) that join before the first kernel reading the records.
- * FP32 descriptors on the tiled path use the fused pass of epm_query_match.
+ * FP32 and BF16 descriptors on the tiled path use the fused passes of
+ * epm_query_match and epm_query_match_bf16.
  * epm_batch_launch replays it on a stream; every
  * replay recomputes every output from the current contents of the input
  * buffers, so new keypoints and descriptors of the same sizes can be written
- * between replays (the pairs' F and slices are fixed at creation).
+ * between replays.  The slices are fixed at creation; F is too unless
+ * desc->F_dev is given, in which case the graph's first node recomputes the
+ * pair setup of Algorithm 1 (e2 = null(F^T), the pencil basis) on the device
+ * from F_dev on every replay.  A replayed F that is non-finite, zero or of
+ * rank <= 1 gets no pencil: its pair's queries are then tested against every
+ * keypoint of the pair (scanned_queries counts them), so the CSR still is
+ * exactly the set of Eq. 4.
  *
  * The CSR capacity cannot be checked on the host inside a graph: rows are
  * written up to `capacity` and nothing is read past it; when the total
@@ -357,6 +388,10 @@ typedef struct {
   float* second_dist;
   epm_algo algo;             /* matching algorithm                                   */
   epm_sched sched;           /* work distribution of the tile kernels                */
+  const double* F_dev;       /* [num_pairs][9] row-major F in device memory, or NULL:
+                                when set, every replay first redoes the pair setup
+                                (epipole, pencil basis) on the device from it, so new
+                                F of the same pairs may be written between replays */
 } epm_batch_desc;
 
 typedef struct epm_batch epm_batch;
@@ -471,9 +506,10 @@ epm_status epm_get_query_stats(const epm_index* idx, epm_query_stats* out);
 /* Counters of the last reduced-precision (BF16 / FP8) epm_match on an index. */
 typedef struct {
   int64_t queries;        /* image-1 queries                                         */
-  int64_t reranked_rows;  /* non-empty rows ranked on MFMA with the top-4 re-ranked    */
+  int64_t reranked_rows;  /* rows ranked on MFMA bounds with a few candidates re-ranked */
   int64_t fallback_rows;  /* of those, not certified: every candidate evaluated exactly */
   int64_t long_rows;      /* rows beyond a tile's 8192-entry list: evaluated exactly  */
+  int64_t exact_distances; /* epm_query_match_bf16: exact FP32 distances of the re-rank */
 } epm_match_stats;
 
 /*

@@ -41,7 +41,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_batch_destroy", "epm_eps_workspace_bytes", "epm_eps_features", "epm_eps_infer",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
-           "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc"]
+           "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc",
+           "epm_query_match_bf16"]
 
 
 class EpmError(RuntimeError):
@@ -64,7 +65,7 @@ class _QueryStats(ctypes.Structure):
 
 class _MatchStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("queries", "reranked_rows", "fallback_rows",
-                                               "long_rows")]
+                                               "long_rows", "exact_distances")]
 
 
 class _MatchOpts(ctypes.Structure):
@@ -86,7 +87,8 @@ class _BatchDesc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("dim", ctypes.c_int32), ("desc1", _V), ("desc2", _V),
                 ("scale1", _V), ("scale2", _V), ("desc1_f32", _V), ("desc2_f32", _V),
                 ("ratio", ctypes.c_float), ("best_idx", _V), ("best_dist", _V),
-                ("second_dist", _V), ("algo", ctypes.c_int32), ("sched", _Sched)]
+                ("second_dist", _V), ("algo", ctypes.c_int32), ("sched", _Sched),
+                ("F_dev", _V)]
 
 
 class Sched:
@@ -129,6 +131,9 @@ def load_library(path=None):
     p = path or _LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: run `python -m paper_2603_18401_amd.build`")
+    # torch first: the library must bind to the HIP runtime torch uses (the
+    # wheel ships its own), or torch's device pointers are foreign to it
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     V, P, i64, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.epm_workspace_bytes.argtypes = [P, i32]
@@ -186,6 +191,9 @@ def load_library(path=None):
     lib.epm_gms.restype = ctypes.c_int
     lib.epm_query_match.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, f32, V, V, V, V]
     lib.epm_query_match.restype = ctypes.c_int
+    lib.epm_query_match_bf16.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, V, V, f32,
+                                         V, V, V, V]
+    lib.epm_query_match_bf16.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
     lib.epm_index_set_timing_events.restype = ctypes.c_int
     lib.epm_index_set_timing_kernel.argtypes = [V, i32]
@@ -352,6 +360,47 @@ class Index:
         _check(st, "epm_query_match")
         return row_offsets, col_indices[: nnz.value], best, bd, sd
 
+    def query_match_bf16(self, kp1, desc1, desc2, desc1_f32, desc2_f32, ratio=0.0,
+                         capacity=None, row_offsets=None, col_indices=None, out=None,
+                         sync=True):
+        """epm_query_match_bf16: the candidate CSR and the matches of the FP32
+        masters, selected through BF16 MFMA bounds (desc1/desc2: int16 BF16
+        codes [N, 128], the round-to-nearest-even values of the masters).
+        Returns (row_offsets, col_indices, best_idx, best_dist, second_dist)."""
+        torch = self._torch
+        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
+            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
+        dev = self.device
+        if row_offsets is None:
+            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
+        if col_indices is None:
+            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
+            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if out is None:
+            out = (torch.empty(self.n1, dtype=torch.int32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev))
+        best, bd, sd = out
+        st_ptr = _stream(torch, dev, self.stream)
+
+        def call(cols, nnz_ref):
+            return self.lib.epm_query_match_bf16(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                                 _dptr(cols), cols.numel(), nnz_ref,
+                                                 _dptr(desc1), _dptr(desc2), _dptr(desc1_f32),
+                                                 _dptr(desc2_f32), float(ratio), _dptr(best),
+                                                 _dptr(bd), _dptr(sd), st_ptr)
+
+        if not sync:
+            _check(call(col_indices, None), "epm_query_match_bf16")
+            return row_offsets, col_indices, best, bd, sd
+        nnz = ctypes.c_int64(0)
+        st = call(col_indices, ctypes.byref(nnz))
+        if st == 3:
+            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+            st = call(col_indices, ctypes.byref(nnz))
+        _check(st, "epm_query_match_bf16")
+        return row_offsets, col_indices[: nnz.value], best, bd, sd
+
     def stats(self):
         """Counters of the last query (dict; waits for its stream)."""
         st = _QueryStats()
@@ -477,13 +526,16 @@ class Batch:
     of pairs, recorded once as a HIP graph and replayed by launch().
 
     Inputs and outputs are fixed device tensors (new contents of the same
-    sizes may be written between launches).  capacity: length of the CSR
+    sizes may be written between launches).  F_dev (float64 [P, 9], device):
+    when given, every launch redoes the pair setup on the device from it, so
+    new F may be written there between launches.  capacity: length of the CSR
     column buffer; nnz() reports the total of the last launch and raises
     EpmError(EPM_ERR_CAPACITY) when it did not fit."""
 
     def __init__(self, pairs, kp1, kp2, desc1, desc2, capacity, eps2=None, eps=0.0,
                  dtype="f32", scale1=None, scale2=None, desc1_f32=None, desc2_f32=None,
-                 ratio=0.0, algo="auto", sched=None, stream=None, workspace=None):
+                 ratio=0.0, algo="auto", sched=None, stream=None, workspace=None,
+                 F_dev=None):
         torch = _torch()
         self._torch = torch
         self.lib = load_library()
@@ -522,8 +574,13 @@ class Batch:
                                                   self.second_dist.data_ptr())
         d.algo = ALGOS[algo]
         d.sched = self.sched._c()
+        if F_dev is not None:
+            if tuple(F_dev.shape) != (len(self.specs), 9) or F_dev.dtype != torch.float64 \
+                    or not F_dev.is_contiguous():
+                raise ValueError("F_dev must be a contiguous float64 [num_pairs, 9] device tensor")
+            d.F_dev = F_dev.data_ptr()
         # the graph reads these buffers on every replay
-        self._keep = (kp1, kp2, eps2, desc1, desc2, scale1, scale2, desc1_f32, desc2_f32)
+        self._keep = (kp1, kp2, eps2, desc1, desc2, scale1, scale2, desc1_f32, desc2_f32, F_dev)
         self.stream = stream
         h = ctypes.c_void_p()
         st = self.lib.epm_batch_create(self._pairs, len(self.specs), ctypes.byref(d),

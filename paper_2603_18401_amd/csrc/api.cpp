@@ -249,6 +249,7 @@ struct epm_index {
   const int64_t* last_offsets = nullptr;
   bool have_stats = false;
   bool have_match_stats = false;
+  bool match_from_tiles = false;  // the last match was fused into the tile pass
   hipStream_t match_stream = nullptr;
   epm_sched sched{};         // work distribution of the tile kernels
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // around the dominant kernel of a call
@@ -447,7 +448,7 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
 // event; the stream waits for it after the query sort, before the first
 // kernel that reads the records.
 epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
-                         hipStream_t stream, bool fuse = false,
+                         hipStream_t stream, int mode = kStabCount,
                          hipEvent_t records_ready = nullptr) {
   const Layout& L = idx->L;
   const int64_t n1 = idx->N1;
@@ -500,7 +501,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   }
   const bool timed = idx->ev_start && idx->timed == EPM_TIMED_STAB;
   if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
-  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, fuse, stream));
+  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, mode, stream));
   if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
@@ -633,6 +634,7 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
   const bool wide = tiled && (c.dtype == EPM_F32 || c.dtype == EPM_BF16);
   if (reduced || wide) {
     idx->have_match_stats = true;
+    idx->match_from_tiles = false;
     idx->match_stream = stream;
     EPM_HIP(launch_clear_stats(nullptr, stream, nullptr, A.match_stats));
   }
@@ -700,8 +702,14 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
                                int64_t* nnz_host, const MatchCall& c, hipStream_t stream,
                                hipEvent_t records_ready = nullptr) {
   const int64_t n1 = idx->N1;
-  A.desc1 = static_cast<const float*>(c.desc1);
-  A.desc2 = static_cast<const float*>(c.desc2);
+  const bool bf = c.dtype == EPM_BF16;
+  if (!bf && c.dtype != EPM_F32) return EPM_ERR_UNSUPPORTED;
+  // BF16: the codes feed the bounds, the FP32 masters every exact distance
+  // (and the wide-row pass, which rounds them to BF16 on chip itself)
+  A.desc1 = static_cast<const float*>(bf ? c.desc1_f32 : c.desc1);
+  A.desc2 = static_cast<const float*>(bf ? c.desc2_f32 : c.desc2);
+  A.codes1 = bf ? static_cast<const uint16_t*>(c.desc1) : nullptr;
+  A.codes2 = bf ? static_cast<const uint16_t*>(c.desc2) : nullptr;
   A.ratio = c.ratio;
   A.best_idx = c.best_idx;
   A.best_dist = c.best_dist;
@@ -709,8 +717,10 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   // counters of the wide-row selection (certified / listed rows)
   A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);  // cleared with the counters
   idx->have_match_stats = true;
+  idx->match_from_tiles = true;
   idx->match_stream = stream;
-  const epm_status st = enqueue_count(idx, A, row_offsets, stream, true, records_ready);
+  const epm_status st =
+      enqueue_count(idx, A, row_offsets, stream, bf ? kStabBF16 : kStabF32, records_ready);
   if (st != EPM_OK) return st;
   if (n1 == 0) return EPM_OK;
   idx->last_stream = stream;
@@ -726,6 +736,8 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   const epm_status fs = enqueue_fill(idx, A, stream, true);
   if (fs != EPM_OK) return fs;
   MatchArgs M = match_args(idx, c);
+  M.desc1 = A.desc1;  // FP32 rows (the masters for BF16)
+  M.desc2 = A.desc2;
   EPM_HIP(launch_match_listed_f32(M, A.rest, A.stats + kStatRest, n1, stream));
   return EPM_OK;
 }
@@ -940,6 +952,37 @@ epm_status epm_query_match(epm_index* idx, const float* kp1_xy, int64_t* row_off
   return enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
 }
 
+epm_status epm_query_match_bf16(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                                int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                                const uint16_t* desc1, const uint16_t* desc2,
+                                const float* desc1_f32, const float* desc2_f32, float ratio,
+                                int32_t* best_idx, float* best_dist, float* second_dist,
+                                hipStream_t stream) {
+  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
+  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  MatchCall c;
+  c.row_offsets = row_offsets;
+  c.col_indices = col_indices;
+  c.dtype = EPM_BF16;
+  c.dim = 128;
+  c.desc1 = desc1;
+  c.desc2 = desc2;
+  c.scale1 = c.scale2 = nullptr;
+  c.desc1_f32 = desc1_f32;
+  c.desc2_f32 = desc2_f32;
+  c.ratio = ratio;
+  c.best_idx = best_idx;
+  c.best_dist = best_dist;
+  c.second_dist = second_dist;
+  c.algo = EPM_ALGO_TILED;
+  c.capacity = nnz_host ? -1 : capacity;
+  const epm_status v = validate_match(idx, c);
+  if (v != EPM_OK) return v;
+  StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
+  return enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
+}
+
 epm_status epm_query_match_noalloc(const epm_pair* pairs, int32_t num_pairs, const float* kp1_xy,
                                    const float* kp2_xy, const float* eps2, float eps_scalar,
                                    int64_t* row_offsets, int32_t* col_indices, int64_t capacity,
@@ -1071,18 +1114,23 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
     st = EPM_ERR_HIP;
   if (st == EPM_OK) {
     epm_status r = EPM_OK;
-    if (hipEventRecord(fork, cs) != hipSuccess || hipStreamWaitEvent(cs2, fork, 0) != hipSuccess)
+    // the pair setup on the device from F_dev heads the graph: both branches read it
+    if (d->F_dev &&
+        launch_pair_setup(idx->at<PairDev>(idx->L.pairs), d->F_dev, idx->P, cs) != hipSuccess)
+      r = EPM_ERR_HIP;
+    if (r == EPM_OK &&
+        (hipEventRecord(fork, cs) != hipSuccess || hipStreamWaitEvent(cs2, fork, 0) != hipSuccess))
       r = EPM_ERR_HIP;
     if (r == EPM_OK) r = enqueue_build(idx, d->kp2_xy, d->eps2, d->eps_scalar, cs2);
     if (r == EPM_OK && hipEventRecord(join, cs2) != hipSuccess) r = EPM_ERR_HIP;
     // after the build: the stab arguments name the sorted key buffer it chose
     StabArgs A = stab_args(idx, d->kp1_xy, d->row_offsets, d->col_indices, d->capacity);
-    // FP32 on the tiled path: selection fused into the stabbing pass
-    const bool fused = c.dtype == EPM_F32 && c.algo != EPM_ALGO_PLAIN;
+    // FP32 and BF16 on the tiled path: selection fused into the stabbing pass
+    const bool fused = (c.dtype == EPM_F32 || c.dtype == EPM_BF16) && c.algo != EPM_ALGO_PLAIN;
     if (fused) {
       if (r == EPM_OK) r = enqueue_query_match(idx, A, d->row_offsets, nullptr, c, cs, join);
     } else {
-      if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs, false, join);
+      if (r == EPM_OK) r = enqueue_count(idx, A, d->row_offsets, cs, kStabCount, join);
       if (r == EPM_OK) r = enqueue_fill(idx, A, cs);
       if (r == EPM_OK) r = enqueue_match(idx, c, cs);
     }
@@ -1394,10 +1442,24 @@ epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out) {
   EPM_HIP(hipMemcpyAsync(c, idx->at<unsigned long long>(idx->L.match_stats),
                          sizeof(unsigned long long) * kNumMatchStats, hipMemcpyDeviceToHost,
                          idx->match_stream));
+  // a match fused into the tile pass leaves its BF16 counters per tile
+  const size_t nt = idx->match_from_tiles ? idx->stiles.size() : 0;
+  std::vector<unsigned long long> tc((size_t)kTileCounts * nt);
+  if (nt > 0)
+    EPM_HIP(hipMemcpyAsync(tc.data(), idx->at<unsigned long long>(idx->L.tile_counts),
+                           sizeof(unsigned long long) * tc.size(), hipMemcpyDeviceToHost,
+                           idx->match_stream));
   EPM_HIP(hipStreamSynchronize(idx->match_stream));
-  out->reranked_rows = (int64_t)c[0];
-  out->fallback_rows = (int64_t)c[1];
+  unsigned long long ranked = 0, unc = 0, evals = 0;
+  for (size_t t = 0; t < nt; ++t) {
+    ranked += tc[t * kTileCounts + 4];
+    unc += tc[t * kTileCounts + 5];
+    evals += tc[t * kTileCounts + 6];
+  }
+  out->reranked_rows = (int64_t)(c[0] + ranked);
+  out->fallback_rows = (int64_t)(c[1] + unc);
   out->long_rows = (int64_t)c[2];
+  out->exact_distances = (int64_t)evals;
   return EPM_OK;
 }
 

@@ -96,7 +96,10 @@ struct TileWindow {
   uint32_t slot_pref[kSlots + 1];
 };
 
-constexpr int kTileCounts = 4;
+// per-tile counters of the tile pass: records scanned, angle hits,
+// brute-force queries, empty queries; BF16 fused selection: rows ranked on
+// bounds, rows left uncertified, exact distances evaluated; one spare
+constexpr int kTileCounts = 8;
 
 struct StabTile {
   int64_t begin;  // first angle-sorted query position of the tile

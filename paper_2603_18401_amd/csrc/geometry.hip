@@ -33,6 +33,11 @@ __device__ __forceinline__ uint32_t angle_key(double phi) {
 // Conservative interval of one keypoint: centre key and half-width key.
 __device__ void circle_interval(const PairDev& pd, float xf, float yf, float ef, uint32_t& C,
                                 uint32_t& H) {
+  if (pd.kappa < 0.0) {  // no pencil: the pair's queries scan every record
+    C = 0;
+    H = kFullHalf;
+    return;
+  }
   const double px = pd.s * ((double)xf - pd.cx);
   const double py = pd.s * ((double)yf - pd.cy);
   const double w1 = pd.u[0] * px + pd.u[1] * py + pd.u[2];
@@ -84,6 +89,100 @@ __device__ void circle_interval(const PairDev& pd, float xf, float yf, float ef,
 }
 
 }  // namespace
+
+// ------------------------------------------------------------ pair setup
+// Algorithm 1, preprocessing, on the device: the image-2 epipole e2 = null(F^T)
+// in normalised line coordinates and an orthonormal basis (u, v) of the
+// pencil of lines through it, from F in device memory (one thread per pair).
+// The normalisation (s, cx, cy from the image size) and the slices are kept
+// from the pair record.  A pair without a pencil (F non-finite, zero, or of
+// rank <= 1) gets kappa = -1: its queries are then tested against every
+// keypoint of the pair, which keeps the result exact.
+__device__ __forceinline__ void dcross(const double* a, const double* b, double* r) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double dnorm3(const double* a) {
+  return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+}
+
+__device__ bool pencil_of(PairDev& pd) {
+  const double* F = pd.F;
+  double fn = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    if (!isfinite(F[k])) return false;
+    fn += F[k] * F[k];
+  }
+  if (!(fn > 0.0) || !isfinite(fn)) return false;
+  // M = N F T^-1 (lines in normalised image-2 coordinates as functions of
+  // normalised image-1 coordinates), scaled to a largest entry of 1
+  double M[3][3];
+  const double is = 1.0 / pd.s;
+  double mx = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double NF[3];
+    for (int k = 0; k < 3; ++k)
+      NF[k] = r == 0 ? F[k] : r == 1 ? F[3 + k] : pd.s * (F[k] * pd.cx + F[3 + k] * pd.cy + F[6 + k]);
+    // T^-1 = [[1/s, 0, cx], [0, 1/s, cy], [0, 0, 1]]
+    M[r][0] = NF[0] * is;
+    M[r][1] = NF[1] * is;
+    M[r][2] = NF[0] * pd.cx + NF[1] * pd.cy + NF[2];
+    for (int k = 0; k < 3; ++k) mx = fmax(mx, fabs(M[r][k]));
+  }
+  if (!(mx > 0.0) || !isfinite(mx)) return false;
+  double col[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) col[k][d] = M[d][k] / mx;
+  // the left null vector is orthogonal to every column: the largest cross
+  // product of two columns
+  double best[3] = {0.0, 0.0, 0.0}, bn = 0.0;
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int t = 0; t < 3; ++t) {
+    double cr[3];
+    dcross(col[pa[t]], col[pb[t]], cr);
+    const double cn = dnorm3(cr);
+    if (cn > bn) {
+      bn = cn;
+      for (int d = 0; d < 3; ++d) best[d] = cr[d];
+    }
+  }
+  if (!(bn > 1e-12)) return false;
+  for (int d = 0; d < 3; ++d) pd.e[d] = best[d] / bn;
+  int ax = 0;
+  for (int d = 1; d < 3; ++d)
+    if (fabs(pd.e[d]) < fabs(pd.e[ax])) ax = d;
+  double axis[3] = {0.0, 0.0, 0.0};
+  axis[ax] = 1.0;
+  dcross(pd.e, axis, pd.u);
+  const double un = dnorm3(pd.u);
+  for (int d = 0; d < 3; ++d) pd.u[d] /= un;
+  dcross(pd.e, pd.u, pd.v);
+  const double vn = dnorm3(pd.v);
+  for (int d = 0; d < 3; ++d) pd.v[d] /= vn;
+  pd.G11 = pd.u[0] * pd.u[0] + pd.u[1] * pd.u[1];
+  pd.G12 = pd.u[0] * pd.v[0] + pd.u[1] * pd.v[1];
+  pd.G22 = pd.v[0] * pd.v[0] + pd.v[1] * pd.v[1];
+  pd.e12 = sqrt(pd.e[0] * pd.e[0] + pd.e[1] * pd.e[1]);
+  pd.kappa = kKappaBuild;
+  return true;
+}
+
+__global__ __launch_bounds__(64) void k_pair_setup(PairDev* __restrict__ pairs,
+                                                   const double* __restrict__ F, int num_pairs) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= num_pairs) return;
+  PairDev pd = pairs[p];
+  for (int k = 0; k < 9; ++k) pd.F[k] = F[9 * (int64_t)p + k];
+  if (!pencil_of(pd)) {
+    // no pencil: every query scans its pair, every record is a full interval
+    for (int d = 0; d < 3; ++d) pd.u[d] = pd.v[d] = pd.e[d] = 0.0;
+    pd.G11 = pd.G12 = pd.G22 = pd.e12 = 0.0;
+    pd.kappa = -1.0;
+  }
+  pairs[p] = pd;
+}
 
 constexpr int kRadixDigits = 256;  // digits of one 8-bit radix pass
 
@@ -172,7 +271,7 @@ __global__ __launch_bounds__(kSortTile) void k_query_keys(
       const double n1c = lam * pd.u[0] + mu * pd.v[0];
       const double n2c = lam * pd.u[1] + mu * pd.v[1];
       const double nrm = sqrt(n1c * n1c + n2c * n2c);
-      if (!(fabs(nu) <= pd.kappa * nrm)) {
+      if (pd.kappa < 0.0 || !(fabs(nu) <= pd.kappa * nrm)) {
         flag = kQueryBrute;  // the line misses the epipole by more than absorbed
       } else {
         double phi = atan2(mu, lam);
@@ -235,6 +334,13 @@ __global__ __launch_bounds__(64) void k_class_bounds(const int64_t* __restrict__
     const int64_t b = cc == kNumClasses ? hi : wave_lower_bound(skey, lo, hi, (uint32_t)cc << kCentreBits);
     if (c == 0) class_begin[(int64_t)p * kClassSlots + cc] = b;
   }
+}
+
+hipError_t launch_pair_setup(PairDev* pairs, const double* F, int num_pairs, hipStream_t s) {
+  if (num_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_setup, dim3((unsigned)((num_pairs + 63) / 64)), dim3(64), 0, s, pairs,
+                     F, num_pairs);
+  return hipGetLastError();
 }
 
 hipError_t launch_intervals(const PairDev* pairs, const SortTile* tiles, int num_tiles,

@@ -8,6 +8,11 @@
 
 namespace epm {
 
+// Pair setup on the device (one thread per pair): F from F[9 p .. 9 p + 8]
+// into the pair record, with the epipole, pencil basis and guard; a pair
+// without a pencil gets kappa = -1 (its queries then scan the whole pair).
+hipError_t launch_pair_setup(PairDev* pairs, const double* F, int num_pairs, hipStream_t s);
+
 // One workgroup per record sort tile; also leaves the first radix pass's
 // per-tile digit counts in hist (and zero counts for the later passes), so
 // that segmented_radix_sort(..., first_counts_ready = true) skips its count.
@@ -141,10 +146,15 @@ hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t
 
 // Tiled count pass (also parks rows of <= kStage candidates).  grid 0: one
 // workgroup per tile; grid > 0: that many workgroups take tiles from a.queue.
-// fuse: also selects the FP32 matches of the rows it can (desc1/desc2 and the
-// outputs in a); the other queries are appended to a.rest, counted in
-// stats[kStatRest], for launch_match_listed_f32 once the CSR is complete.
-hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t s);
+// mode kStabF32 / kStabBF16: also selects the FP32 matches of the rows it can
+// (desc1/desc2 and the outputs in a); the other queries are appended to
+// a.rest, counted in stats[kStatRest], for launch_match_listed_f32 once the
+// CSR is complete.
+// mode kStabBF16: BF16 codes in codes1/codes2 with the FP32 masters in
+// desc1/desc2; the match is selected through certified MFMA bounds and an
+// exact re-rank on the masters (rows it cannot certify go to a.rest).
+constexpr int kStabCount = 0, kStabF32 = 1, kStabBF16 = 2;
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, hipStream_t s);
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the
 // brute-force long rows.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);

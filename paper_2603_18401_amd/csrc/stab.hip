@@ -14,6 +14,7 @@
 #include "device_common.h"
 #include "launch.h"
 #include "match_common.h"
+#include "mfma_bounds.h"
 
 namespace epm {
 
@@ -407,14 +408,120 @@ __device__ __forceinline__ void fuse_stage(const StabArgs& A, int c0, int nr, in
 // s_waitcnt vmcnt(0): this wavefront's copies to LDS have landed.
 __device__ __forceinline__ void wait_lds_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// FUSE: three workgroups per CU (LDS and registers are sized for it)
-template <bool PERSIST, bool FUSE>
-__global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A) {
+// ------------------------------------------------ BF16 fused selection
+// MODE kStabBF16: the caller's descriptors are BF16 codes with FP32 masters,
+// and the final matches must be the canonical FP32 selection on the masters.
+// The window's BF16 rows are staged kBfRows at a time; wavefront w scores its
+// 16 queries against them on MFMA (A = the window rows, B = the queries, so
+// lane l holds query l & 15 against rows 16 cb + 4 (l >> 4) + i).  Every hit
+// gets certified bounds D_lo <= D <= D_hi on its exact canonical distance D:
+//   |q^ - w^|^2 is within em = 3e-5 (|q^| + |w^|)^2 of |q^|^2 + |w^|^2 - 2 q^.w^
+//   (FP32 accumulation), |q - w| is within eps_q + eps_w of |q^ - w^| (eps_q
+//   the measured norm of the query's rounding error, exact in FP32 from its
+//   master; eps_w the BF16 bound u |w^| / (1 - u), u = 2^-8, of a row rounded
+//   to nearest even), and D is within 2e-5 (relative) of |q - w|^2 (130
+//   roundings of 2^-24).
+// Let U2 be the second smallest D_hi of the row.  Two candidates have D <= U2,
+// so a candidate with D_lo > U2 is strictly worse than both and is neither
+// best nor second: the candidates with D_lo <= U2 are evaluated exactly
+// (canonical chains on the masters) and their top-2 is the row's.  Each lane
+// keeps its kBfKeep smallest D_lo (dropping those above its own running U2,
+// which only shrinks); a row whose smallest dropped bound is not above U2 is
+// left to the listed-query match, exact either way.
+constexpr int kBfRows = 64;                 // window rows per chunk
+constexpr int kBfStride = 256 + 16;         // LDS bytes per row: 16 rows' reads hit distinct banks
+constexpr int kBfPieces = kBfStride / 16;   // 16-byte pieces per row (the last repeats one)
+constexpr int kBfCopies = (kBfRows * kBfPieces + kWave - 1) / kWave;
+constexpr int kBfRowBytes = kBfCopies * kWave * 16;
+constexpr int kBfKeep = 3;
+static_assert(kBfRows == 64, "the hit mask of a chunk is one 64-bit word");
+// Exact distances a query can list: kBfKeep per lane, four lanes.
+constexpr int kBfQTasks = 4 * kBfKeep;
+// After the pair test the record chunk holds the chunk's row terms and the
+// per-query task lists.
+constexpr int kBfScratch = 3 * kBfRows * 4 + kTileQ * kBfQTasks * 2;
+
+// Starts the copy of BF16 rows [c0, c0 + nr) of the window to LDS (stride
+// kBfStride, 0 < nr <= kBfRows); rows past nr and the padding piece repeat
+// real data.  The copies complete asynchronously (wait_lds_copies).
+__device__ __forceinline__ void bf16_stage(const StabArgs& A, int c0, int nr, int64_t kb,
+                                           const int32_t* sJ, uint8_t* rows, int wave, int lane) {
+  for (int g = wave; g < kBfCopies; g += kWaves) {
+    const int p = g * kWave + lane;
+    int r = p / kBfPieces;
+    int c = p - r * kBfPieces;
+    r = r < nr ? r : nr - 1;
+    c = c < 16 ? c : 15;
+    const uint4* src = reinterpret_cast<const uint4*>(A.codes2) + (kb + sJ[c0 + r]) * 16 + c;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)(rows + g * kWave * 16),
+                                     16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, off);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), off);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Per-lane state of one query's bounds (lane group g of its four lanes).
+struct BfState {
+  float u1 = __builtin_inff(), u2 = __builtin_inff();  // two smallest D_hi seen by this lane
+  float lo[kBfKeep];                                   // kept D_lo, ascending
+  int32_t pos[kBfKeep];                                // their window positions
+  float drop = __builtin_inff();                       // smallest D_lo dropped while needed
+  bool bad = false;                                    // a non-finite bound: not certifiable
+
+  __device__ __forceinline__ BfState() {
+    #pragma unroll
+    for (int t = 0; t < kBfKeep; ++t) {
+      lo[t] = __builtin_inff();
+      pos[t] = -1;
+    }
+  }
+
+  __device__ __forceinline__ void add(float dlo, float dhi, int32_t v) {
+    bad |= !(dlo == dlo) || !(dhi == dhi);
+    if (dhi < u1) {
+      u2 = u1;
+      u1 = dhi;
+    } else if (dhi < u2) {
+      u2 = dhi;
+    }
+    if (dlo > u2) return;  // above this lane's U2, hence above the row's
+    float x = dlo;
+    int32_t y = v;
+    #pragma unroll
+    for (int t = 0; t < kBfKeep; ++t) {
+      if (x < lo[t]) {
+        const float tx = lo[t];
+        const int32_t ty = pos[t];
+        lo[t] = x;
+        pos[t] = y;
+        x = tx;
+        y = ty;
+      }
+    }
+    if (y >= 0) drop = fminf(drop, x);  // the entry pushed out of the list
+  }
+};
+
+// MODE: kStabCount (count and park rows), kStabF32 (FP32 selection fused),
+// kStabBF16 (BF16 bounds with an exact FP32 re-rank, fused).
+// Fused: three workgroups per CU (LDS and registers are sized for it)
+template <bool PERSIST, int MODE>
+__global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
+  constexpr bool FUSE = MODE != kStabCount;
   // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps the window's j
   // in sJ_keep), reused for descriptor rows in the match phase
   constexpr int kRecRaw = FUSE ? kRecBytes - kChunk * 4 : kRecBytes;
-  constexpr int kRaw = FUSE && kFuseBytes > kRecRaw ? kFuseBytes : kRecRaw;
+  constexpr int kMatchRaw = MODE == kStabF32 ? kFuseBytes : MODE == kStabBF16 ? kBfScratch : 0;
+  constexpr int kRaw = kMatchRaw > kRecRaw ? kMatchRaw : kRecRaw;
   __shared__ __attribute__((aligned(16))) unsigned char raw[kRaw];
+  // BF16: the window's BF16 rows, kBfRows at a time (the first chunk is
+  // copied in while the pair test runs)
+  __shared__ __attribute__((aligned(16))) uint8_t bfrows[MODE == kStabBF16 ? kBfRowBytes : 16];
   __shared__ int32_t sJ_keep[FUSE ? kKeepJ : 1];
   uint32_t* sC = reinterpret_cast<uint32_t*>(raw);
   uint32_t* sH = sC + kChunk;
@@ -435,7 +542,9 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
   __shared__ uint32_t qk[kTileQ], qmode[kTileQ], cnt[kTileQ];
   __shared__ int64_t qidx[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
-  __shared__ uint32_t tile_stats[4];  // scanned, angle hits, brute-force and empty queries
+  // scanned, angle hits, brute-force and empty queries; BF16 fused: rows
+  // ranked on bounds, rows left uncertified, exact distances evaluated
+  __shared__ uint32_t tile_stats[kTileCounts];
   __shared__ int next_tile;
 
   // one tile per workgroup, or (persistent) tiles from the queue until it is
@@ -468,7 +577,7 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       qmode[lane] = tq.flag;
       qidx[lane] = tq.i;
       cnt[lane] = 0;
-      if (lane < 4) tile_stats[lane] = 0u;
+      if (lane < kTileCounts) tile_stats[lane] = 0u;
     }
     {
       const TileWindow* w = A.windows + tile;
@@ -478,6 +587,7 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
     __syncthreads();
 
     const int64_t total_len = slot_pref[kSlots];
+    const bool fusable = total_len <= kFuseMaxWindow;
     uint32_t scanned = 0, angle_hits = 0;
     // this lane's query of the pair test: its line stays in registers
     const int lq = wave * kQPerWave + (lane & (kQPerWave - 1));
@@ -506,6 +616,12 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
           sJ_keep[virt] = A.rj[pos];
       }
       __syncthreads();
+      if constexpr (MODE == kStabBF16) {
+        // the first BF16 rows of the window go to LDS behind the pair test
+        if (base == 0 && fusable && total_len > 0)
+          bf16_stage(A, 0, total_len < kBfRows ? (int)total_len : kBfRows, pd.k_begin, sJ_keep,
+                     bfrows, wave, lane);
+      }
       if (any_live) {
         // this wave's 16 queries (lane & 15) against four records per step
         // (lane >> 4); a hit's slot is the query's count plus its rank among
@@ -591,7 +707,6 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
 
     // FUSE: four threads per query select its match
     const int q = tid >> 2, part = tid & 3;
-    const bool fusable = total_len <= kFuseMaxWindow;
     const bool mine = FUSE && q < T.count && qmode[q] == kQueryNormal &&
                       cnt[q] <= (uint32_t)kStage && fusable;
 
@@ -641,6 +756,8 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
           A.rest[at] = (uint32_t)qidx[q];
         }
       }
+    }
+    if constexpr (MODE == kStabF32) {
       const int nq = mine ? (int)cnt[q] : 0;
       const int64_t kb = pd.k_begin;
       float4* rows4 = reinterpret_cast<float4*>(raw);
@@ -688,11 +805,252 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       }
       if (mine && part == 0)
         write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], best, false);
+    } else if constexpr (MODE == kStabBF16) {
+      // lane l of wavefront w: query 16 w + (l & 15), lane group g = l >> 4
+      const int q2 = wave * kQPerWave + (lane & (kQPerWave - 1));
+      const int g = lane >> 4;
+      const bool mine2 = q2 < T.count && qmode[q2] == kQueryNormal &&
+                         cnt[q2] <= (uint32_t)kStage && fusable;
+      const int nq = mine2 ? (int)cnt[q2] : 0;
+      const int64_t kb = pd.k_begin;
+      const int64_t qi2 = qidx[q2];
+      // per chunk row: (|w^|^2, bound norm, rounding bound) -- the record
+      // chunk is dead -- then the per-query task lists
+      float4* w_terms = reinterpret_cast<float4*>(raw);
+      uint16_t* qtask = reinterpret_cast<uint16_t*>(w_terms + kBfRows);  // [kTileQ][kBfQTasks]
+      // B operands: this lane's BF16 values of its query at dimensions
+      // 32 kk + 8 g .. + 7; and its quarter of the query, dimensions
+      // 32 g .. 32 g + 31, as BF16 codes and as the FP32 master (the exact
+      // chains pass their sum from quarter to quarter)
+      bf16x8 bq[4];
+      uint4 qc[4];
+      float4 qx[8];
+      #pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint4 c = mine2 ? reinterpret_cast<const uint4*>(A.codes1)[qi2 * 16 + kk * 4 + g]
+                              : make_uint4(0u, 0u, 0u, 0u);
+        bq[kk] = __builtin_bit_cast(bf16x8, c);
+        qc[kk] = mine2 ? reinterpret_cast<const uint4*>(A.codes1)[qi2 * 16 + g * 4 + kk]
+                       : make_uint4(0u, 0u, 0u, 0u);
+      }
+      #pragma unroll
+      for (int u = 0; u < 8; ++u)
+        qx[u] = mine2 ? reinterpret_cast<const float4*>(A.desc1)[qi2 * 32 + g * 8 + u]
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+      // the query's BF16 norm and the measured norm of its rounding error
+      // (x - x^, exact in FP32), summed over its four quarters
+      float qn_part = 0.0f, qe_part = 0.0f;
+      #pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t w[4] = {qc[kk].x, qc[kk].y, qc[kk].z, qc[kk].w};
+        const float4 xa = qx[2 * kk], xb = qx[2 * kk + 1];
+        const float x[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        #pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float y = __uint_as_float(e & 1 ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16));
+          qn_part = __builtin_fmaf(y, y, qn_part);
+          const float d = x[e] - y;
+          qe_part = __builtin_fmaf(d, d, qe_part);
+        }
+      }
+      qn_part += __shfl_xor(qn_part, 16);
+      qe_part += __shfl_xor(qe_part, 16);
+      qn_part += __shfl_xor(qn_part, 32);
+      qe_part += __shfl_xor(qe_part, 32);
+      // per-query bound terms, inflated for the FP32 sums (2^-24 per term)
+      const float q_nb = sqrtf(qn_part) * (1.0f + 2e-5f);
+      const float q_db = sqrtf(qe_part) * (1.0f + 2e-5f) + 1e-30f;
+      BfState st;
+      int cur = g;
+      Top2 best;
+      uint32_t evals = 0;
+      bool cert = mine2;  // a tile without window records has only empty rows
+      if (fusable && total_len > 0) {
+        const int wlen = (int)total_len;
+        for (int c0 = 0; c0 < wlen; c0 += kBfRows) {
+          const int nr = wlen - c0 < kBfRows ? wlen - c0 : kBfRows;
+          if (c0 > 0) {
+            __syncthreads();  // the previous rows are no longer read
+            bf16_stage(A, c0, nr, kb, sJ_keep, bfrows, wave, lane);
+          }  // the first rows were started during the pair test
+          // this query's hits in the chunk (the row is in ascending window
+          // position; each lane resumes where the last chunk left it)
+          uint64_t hmask = 0ull;
+          for (; cur < nq; cur += 4) {
+            const int v = hits_v[q2][cur];
+            if (v >= c0 + nr) break;
+            hmask |= 1ull << (v - c0);
+          }
+          hmask |= shfl_xor_u64(hmask, 16);
+          hmask |= shfl_xor_u64(hmask, 32);
+          wait_lds_copies();
+          __syncthreads();
+          {
+            // norms of the chunk's rows: four threads per row, 32 values each
+            const int r = tid >> 2, part4 = tid & 3;
+            const uint4* rp = reinterpret_cast<const uint4*>(bfrows + r * kBfStride + part4 * 64);
+            float sn = 0.0f;
+            #pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const uint4 c = rp[t];
+              const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+              #pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const float y =
+                    __uint_as_float(e & 1 ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16));
+                sn = __builtin_fmaf(y, y, sn);
+              }
+            }
+            sn += __shfl_xor(sn, 1);
+            sn += __shfl_xor(sn, 2);
+            if (part4 == 0) {
+              const float nb = sqrtf(sn) * (1.0f + 2e-5f);
+              // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
+              const float db =
+                  nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
+              w_terms[r] = make_float4(sn, nb, db, 0.0f);
+            }
+          }
+          __syncthreads();
+          if (ballot(hmask != 0ull) != 0ull) {
+            // S^T = W^ Q^T on MFMA: rows 16 cb + (l & 15) against the queries
+            f32x4 acc[4];
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+              #pragma unroll
+              for (int kk = 0; kk < 4; ++kk) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(
+                    bfrows + (cb * 16 + (lane & 15)) * kBfStride + (kk * 32 + g * 8) * 2);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[kk], acc[cb], 0, 0, 0);
+              }
+            }
+            // this lane's hits among its 16 scores: slot 4 cb + i is row
+            // 16 cb + 4 g + i; only set slots are visited
+            uint32_t slots = 0u;
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+              slots |= (uint32_t)((hmask >> (16 * cb + 4 * g)) & 0xFull) << (4 * cb);
+            while (slots != 0u) {
+              const int sl = __builtin_ctz(slots);
+              slots &= slots - 1u;
+              const f32x4 a01 = (sl & 4) ? acc[1] : acc[0];
+              const f32x4 a23 = (sl & 4) ? acc[3] : acc[2];
+              const f32x4 av = (sl & 8) ? a23 : a01;
+              const float sc = (sl & 2) ? ((sl & 1) ? av[3] : av[2]) : ((sl & 1) ? av[1] : av[0]);
+              const int r = 16 * (sl >> 2) + 4 * g + (sl & 3);
+              const float4 wt = w_terms[r];
+              const float sum = q_nb + wt.y;
+              const float em = 3e-5f * sum * sum;
+              const float at = (qn_part + wt.x) - 2.0f * sc;
+              // sqrt(at +- em) from the hardware reciprocal square root (within
+              // a few ulps): the 1e-6 factors cover it; arguments under 2^-100
+              // take the trivially valid bounds 0 and 2^-50
+              const float th = fmaxf(at, 0.0f) + em;
+              const float tl = at - em;
+              const float r_hi =
+                  th > 0x1p-100f ? th * __builtin_amdgcn_rsqf(th) * (1.0f + 1e-6f) : 0x1p-50f;
+              const float r_lo =
+                  tl > 0x1p-100f ? tl * __builtin_amdgcn_rsqf(tl) * (1.0f - 1e-6f) : 0.0f;
+              const float ew = q_db + wt.z;
+              // the 1e-6 r_lo term covers the rounding of the two subtractions
+              const float e_lo = fmaxf(r_lo - ew - 1e-6f * r_lo, 0.0f);
+              const float e_hi = r_hi + ew;
+              const float dlo = e_lo * e_lo * (1.0f - 3e-5f);
+              const float dhi = e_hi * e_hi * (1.0f + 3e-5f);
+              st.add(dlo, dhi, c0 + r);
+            }
+          }
+        }
+        // the row's U2 and smallest dropped bound over its four lanes
+        float u1 = st.u1, u2 = st.u2, dmin = st.drop;
+        bool bad = st.bad;
+        #pragma unroll
+        for (int off = 16; off < kWave; off <<= 1) {
+          const float o1 = __shfl_xor(u1, off), o2 = __shfl_xor(u2, off);
+          u2 = fminf(fmaxf(u1, o1), fminf(u2, o2));
+          u1 = fminf(u1, o1);
+          dmin = fminf(dmin, __shfl_xor(dmin, off));
+          bad |= __shfl_xor((int)bad, off) != 0;
+        }
+        // nothing dropped (dmin = +inf): every candidate that can be best or
+        // second is kept, including rows of fewer than two candidates (U2 = +inf)
+        cert = mine2 && !bad && (dmin == __builtin_inff() || dmin > u2);
+        // the row's exact distances (kept candidates within U2) are listed
+        // per query and dealt to its four lanes
+        uint32_t tmask = 0u;
+        #pragma unroll
+        for (int t = 0; t < kBfKeep; ++t)
+          if (cert && st.pos[t] >= 0 && st.lo[t] <= u2) tmask |= 1u << t;
+        const uint32_t myn = (uint32_t)__popc(tmask);
+        const int qlane = lane & (kQPerWave - 1);
+        const uint32_t n0 = (uint32_t)__shfl((int)myn, qlane), n1 = (uint32_t)__shfl((int)myn, qlane + 16),
+                       n2 = (uint32_t)__shfl((int)myn, qlane + 32), n3 = (uint32_t)__shfl((int)myn, qlane + 48);
+        const uint32_t before = (g > 0 ? n0 : 0u) + (g > 1 ? n1 : 0u) + (g > 2 ? n2 : 0u);
+        const uint32_t qtotal = n0 + n1 + n2 + n3;
+        uint16_t* mylist = qtask + q2 * kBfQTasks;
+        {
+          uint32_t k = before;
+          #pragma unroll
+          for (int t = 0; t < kBfKeep; ++t)
+            if ((tmask >> t) & 1u) mylist[k++] = (uint16_t)st.pos[t];
+        }
+        wave_sync_lds();
+        // one task of each query per round: the query's four lanes load their
+        // quarters of the candidate's FP32 row (the next round's while this
+        // one is summed) and pass the canonical sum on from quarter to
+        // quarter, so it runs over dimensions 0 .. 127 in order
+        const uint32_t rounds = wave_max_u32(qtotal);
+        const float4* w2 = reinterpret_cast<const float4*>(A.desc2);
+        auto wslice = [&](uint32_t k, float4* dst) {
+          const bool has = k < qtotal;
+          const int32_t j = has ? sJ_keep[mylist[k]] : 0;
+          const float4* wr = w2 + (kb + j) * 32 + g * 8;
+          #pragma unroll
+          for (int u = 0; u < 8; ++u) dst[u] = has ? wr[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        };
+        float4 wcur[8], wnext[8];
+        if (rounds > 0) wslice(0, wcur);
+        for (uint32_t rd = 0; rd < rounds; ++rd) {
+          if (rd + 1 < rounds) wslice(rd + 1, wnext);
+          float sum = 0.0f;
+          #pragma unroll
+          for (int gp = 0; gp < 4; ++gp) {
+            float acc = sum;
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) acc = canonical_step4(acc, qx[u], wcur[u]);
+            sum = __shfl(acc, qlane + 16 * gp);  // quarter gp's result
+          }
+          if (rd < qtotal && g == 0) {
+            best.insert(sum, sJ_keep[mylist[rd]]);
+            ++evals;
+          }
+          #pragma unroll
+          for (int u = 0; u < 8; ++u) wcur[u] = wnext[u];
+        }
+      }
+      if (mine2 && g == 0) {  // lane group 0 holds the query's selection
+        if (cert) {
+          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qi2, best, false);
+        } else {
+          const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
+          A.rest[at] = (uint32_t)qi2;
+        }
+      }
+      const uint32_t n_rank = (uint32_t)__popcll(ballot(mine2 && g == 0));
+      const uint32_t n_unc = (uint32_t)__popcll(ballot(mine2 && g == 0 && !cert));
+      const uint32_t n_ev = wave_sum_u32(evals);
+      if (lane == 0) {
+        atomicAdd(&tile_stats[4], n_rank);
+        atomicAdd(&tile_stats[5], n_unc);
+        atomicAdd(&tile_stats[6], n_ev);
+      }
     }
     // the tile's counters: complete once every wavefront has passed a barrier
     // after adding its share (the match phase has one unless it was skipped);
     // written per tile, summed on the host when they are asked for
-    if (!FUSE || !(fusable && total_len > 0)) __syncthreads();
+    // (the BF16 phase adds its counters after its last barrier: one more)
+    if (!FUSE || MODE == kStabBF16 || !(fusable && total_len > 0)) __syncthreads();
     if (A.tile_counts && tid == 0) {
       const uint64_t nb = tile_stats[2];
       unsigned long long* tc = A.tile_counts + (int64_t)tile * kTileCounts;
@@ -700,6 +1058,10 @@ __global__ __launch_bounds__(kThreads, FUSE ? 3 : 2) void k_stab_tile(StabArgs A
       tc[1] = (unsigned long long)tile_stats[1] + nb * (uint64_t)pd.n;
       tc[2] = nb;
       tc[3] = tile_stats[3];
+      tc[4] = tile_stats[4];
+      tc[5] = tile_stats[5];
+      tc[6] = tile_stats[6];
+      tc[7] = 0ull;
     }
     if (PERSIST) __syncthreads();  // the tile's LDS is dead before the next one starts
   }
@@ -869,22 +1231,35 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stab_tiles(const StabArgs& a, int grid, bool fuse, hipStream_t s) {
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
   if (grid > 0 && !a.queue) return hipErrorInvalidValue;
-  if (fuse && (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest))
+  if (mode != kStabCount &&
+      (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest))
     return hipErrorInvalidValue;
+  if (mode == kStabBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
-  if (fuse) {
-    if (grid > 0)
-      hipLaunchKernelGGL((k_stab_tile<true, true>), g, dim3(kThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_stab_tile<false, true>), g, dim3(kThreads), 0, s, a);
-  } else {
-    if (grid > 0)
-      hipLaunchKernelGGL((k_stab_tile<true, false>), g, dim3(kThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_stab_tile<false, false>), g, dim3(kThreads), 0, s, a);
+  switch (mode) {
+    case kStabCount:
+      if (grid > 0)
+        hipLaunchKernelGGL((k_stab_tile<true, kStabCount>), g, dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_stab_tile<false, kStabCount>), g, dim3(kThreads), 0, s, a);
+      break;
+    case kStabF32:
+      if (grid > 0)
+        hipLaunchKernelGGL((k_stab_tile<true, kStabF32>), g, dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_stab_tile<false, kStabF32>), g, dim3(kThreads), 0, s, a);
+      break;
+    case kStabBF16:
+      if (grid > 0)
+        hipLaunchKernelGGL((k_stab_tile<true, kStabBF16>), g, dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_stab_tile<false, kStabBF16>), g, dim3(kThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -127,10 +127,9 @@ def test_graph_capacity_overflow_is_reported(case, dtype):
     assert ei.value.status == 3
     torch.cuda.synchronize()
     assert np.array_equal(b.row_offsets.cpu().numpy(), case.ref[0])
-    # the columns that fit are the leading ones of the full CSR
+    # the columns that fit are the leading ones of the full CSR; both dtypes
+    # match in the fused pass, whose outputs are then incomplete (reported)
     assert np.array_equal(b.col_indices.cpu().numpy(), case.ref[1][: nnz // 2])
-    if dtype == "bf16":  # the separate match pass skips an incomplete CSR entirely
-        assert bool((b.best_idx == -7).all())
     b.close()
 
 

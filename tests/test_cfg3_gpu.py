@@ -5,7 +5,9 @@ infinite epipole, forward motion, general motion), BF16 descriptors with FP32
 masters, eps = 2 px.  The recorded graph (persistent longest-first schedule)
 and the eager calls (one workgroup per tile) must both return the oracle's
 CSR (Eq. 3-4, brute force in FP64) and the oracle's FP32 matches (Sec. 4.3),
-element for element."""
+element for element; so must the fused BF16 call (epm_query_match_bf16).  The
+graph uses the fused BF16 pass, the eager calls the separate query and
+window-kernel match."""
 
 import os
 
@@ -79,6 +81,17 @@ def test_cfg3_full_batch_equals_oracle(cfg3):
     got = [t.cpu().numpy() for t in (offs, cols, best, bd, sd)]
     idx.close()
     _assert_same(got, ref, "eager")
+
+    # eager, BF16 selection fused into the stabbing pass
+    print("cfg3: eager fused BF16 call", flush=True)
+    idx = E.Index(specs, kp2, eps=EPS)
+    got = idx.query_match_bf16(kp1, q1, q2, m1, m2, capacity=cap)
+    torch.cuda.synchronize()
+    got = [t.cpu().numpy() for t in got]
+    ms = idx.match_stats()
+    idx.close()
+    _assert_same(got, ref, "eager fused BF16")
+    print(f"cfg3: fused BF16 match stats {ms}", flush=True)
 
     # graph: persistent longest-first schedule, replayed twice
     print("cfg3: graph replays", flush=True)
