@@ -1,23 +1,28 @@
 """Throughput of exact epipolar-guided matching (retrieve + match) on one MI355X.
 
-Workload (the at-scale configuration): image pairs of 6048x4032 px, f = 3400
-px, 20000 keypoints per image (70% true matches, 30% outliers), 128-d FP32
-unit descriptors, sideways motion (epipole far outside the image) and
-forward motion (epipole at the image centre), each at eps = 1, 2 and 4 px.
-One step processes the six (motion, eps) pairs: 120000 image-1 queries, each
-retrieving its exact candidate set and selecting its best match.  Inputs are
-synthetic (seeded), resident in HBM before the timed region.
+Default workload (the batching configuration): 512 synthetic image pairs of
+1920x1080 / 4032x3024 / 6048x4032 px with 500-30000 keypoints per image
+(near-pure sideways motion with the epipole 1e6-1e9 px away, one exactly
+infinite epipole, forward motion with the epipole in the image, general
+motion), 128-d BF16 descriptors with FP32 masters, eps = 2 px.  One step
+builds the angle-sorted intervals of every pair (FP64 pair setup on the host,
+tables uploaded) and runs the fused query + BF16 match over the whole batch:
+3.96 M image-1 queries, each retrieving its exact candidate set (Eq. 3-4) and
+selecting its exact FP32 match (Sec. 4.3).  Inputs are seeded, resident in HBM
+before the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 
-Prints one JSON line.  `value` is keypoint queries/s of one step through
-epm_build_intervals + epm_query_match (the six pairs as one batch, selection
-fused into the stabbing pass); `separate_calls` is the same step through
-epm_query_candidates + epm_match, `graph` the step recorded as one HIP graph
-(autotuned tile schedule), and `plain_gpu` the plain path (one pipeline per
-pair, host-synchronised CSR sizing, gather-based matching).  Other workloads:
---workload precision | batch | learned | paper (the tolerances of the paper's
-experiments: 50000 keypoints per image, eps 25 / 50 / 100 px).
+Prints one JSON line: `value` is keypoint queries/s over K back-to-back steps;
+`roofline` is the dominant kernel (the fused stabbing + BF16 selection pass)
+against 8 TB/s, timed with HIP events on the step's stream; `cpu_baseline` is
+the CPU oracle on a sample of the same pairs (which also checks them); beside
+them the step's warm and MALL-flushed cold distributions, the same batch as a
+HIP graph replay (pair setup on the device), through the FP32 masters,
+through the separate calls, and the plain GPU path (one pipeline per pair).
+Other workloads: --workload scale (six 20000-keypoint pairs, FP32) |
+precision | learned | paper (the tolerances of the paper's experiments) |
+noise.
 """
 
 import argparse
@@ -40,8 +45,12 @@ METRIC = "keypoint queries/s (retrieve+match), exact candidate sets, vs plain GP
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cold-steps", type=int, default=5,
+                    help="batch workload: steps timed after flushing the MALL")
+    ap.add_argument("--cpu-every", type=int, default=1,
+                    help="batch workload: the oracle baseline runs every n-th pair")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000,
@@ -50,12 +59,12 @@ def parse():
                     help="fused: epm_query_match; otherwise query + match with this algo")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="scale",
-                    choices=["scale", "precision", "batch", "learned", "paper", "noise"],
-                    help="scale: six 20000-keypoint pairs (default); precision: one "
-                         "60000-keypoint pair in FP32/BF16/FP8/binary; batch: uneven pairs; "
-                         "paper: six 50000-keypoint pairs at eps 25/50/100 px; noise: "
-                         "pose-noise sweep at eps 200 px")
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "scale", "precision", "learned", "paper", "noise"],
+                    help="batch: 512 uneven pairs, BF16 (default); scale: six "
+                         "20000-keypoint pairs, FP32; precision: one 60000-keypoint pair in "
+                         "FP32/BF16/FP8/binary; paper: six 50000-keypoint pairs at eps "
+                         "25/50/100 px; noise: pose-noise sweep at eps 200 px")
     ap.add_argument("--pairs", type=int, default=512, help="pairs of the batch workload")
     ap.add_argument("--train-pairs", type=int, default=2000,
                     help="learned workload: training pairs")
@@ -86,6 +95,9 @@ KERNELS = {
     "auto": ("k_match_window_f32", os.path.join(CSRC, "match_window.hip"),
              os.path.join(ROOT, "profiles", "match_window_traffic.md")),
     "plain": ("k_match_plain_f32", os.path.join(CSRC, "match_plain.hip"), None),
+    "bf16": ("k_stab_tile<false, 2> (stabbing + BF16 bounds + exact FP32 re-rank)",
+             os.path.join(CSRC, "stab.hip"),
+             os.path.join(ROOT, "profiles", "stab_bf16_fused_traffic.md")),
 }
 
 
@@ -202,13 +214,40 @@ def precision_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu's 'Model name', from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_threads():
+    """Threads for the CPU oracle: the cores this process may run on (on the
+    GPU machine that is the CPU share of one GPU, 16 threads)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def pct(v, q):
+    return round(float(np.percentile(np.asarray(v, np.float64), q)), 4)
+
+
 def batch_workload(args):
-    """Uneven pairs (1920x1080 / 4032x3024 / 6048x4032, 500-30000 keypoints,
-    far, infinite, forward and general epipoles), BF16 descriptors with FP32
-    masters, eps = 2 px.  Timed: replays of the whole batch (build, query,
-    match) recorded as one HIP graph with the autotuned tile schedule.  Beside
-    it: the same batch through the eager calls, and the plain path (one
-    pipeline per pair, FP32 gathers)."""
+    """The batching configuration: 512 uneven pairs (1920x1080 / 4032x3024 /
+    6048x4032, 500-30000 keypoints per image, near-pure sideways motion with
+    the epipole 1e6-1e9 px away plus one exactly infinite epipole, forward and
+    general motion), 128-d BF16 descriptors with their FP32 masters, eps = 2
+    px.  One step = epm_build_intervals (with the FP64 pair setup on the host
+    and the upload of the pair tables) + epm_query_match_bf16 (stabbing, FP64
+    test, BF16 MFMA bounds, exact FP32 re-rank) for the whole batch; inputs
+    resident in HBM, capacity preset (no host synchronisation in the step)."""
     import torch
 
     import paper_2603_18401_amd as E
@@ -216,11 +255,7 @@ def batch_workload(args):
     from paper_2603_18401_amd import autotune
     dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
-    pairs = []
-    for r in range(args.pairs):
-        pairs.append(synth.cfg3_pair(r))
-        if (r + 1) % 64 == 0:
-            print(f"batch: {r + 1} pairs generated", file=sys.stderr, flush=True)
+    pairs = synth.cfg3_batch(args.pairs, workers=host_threads())
     print(f"batch: generated {len(pairs)} pairs in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
@@ -238,87 +273,220 @@ def batch_workload(args):
     idx0.close()
     del o, c
     cap = nnz + 1024
+    offs = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(cap, dtype=torch.int32, device=dev)
+    out = (torch.empty(N1, dtype=torch.int32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev),
+           torch.empty(N1, dtype=torch.float32, device=dev))
+    holder = {}
 
-    # ---- autotuned schedule, then graph replays
-    if args.no_tune:
+    def step(ev=None):
+        idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+        if ev is not None:
+            idx.set_timing_events(*ev)
+        idx.query_match_bf16(kp1, q1, q2, m1, m2, row_offsets=offs, col_indices=cols, out=out,
+                             sync=False)
+        holder["idx"] = idx
+
+    # ---- the timed region: K back-to-back steps; the dominant kernel (the
+    # fused stabbing + BF16 selection pass) is bracketed by events on every
+    # EVENT_STRIDE-th step, every step by a pair of events on the stream
+    stream = torch.cuda.current_stream(dev)
+    sampled = set(range(0, args.steps, EVENT_STRIDE))
+    kev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in sampled}
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sev[k][0].record(stream)
+        step(kev.get(k))
+        sev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sec = elapsed / args.steps
+    kernel_ms = [kev[k][0].elapsed_time(kev[k][1]) for k in sorted(sampled)]
+    warm_ms = [e[0].elapsed_time(e[1]) for e in sev]
+    ref_out = [x.clone() for x in out]
+    ref_offs, ref_cols = offs.clone(), cols[:nnz].clone()
+    assert int(offs[-1].item()) == nnz
+    mstats = holder["idx"].match_stats()
+    qstats = holder["idx"].stats()
+
+    # ---- cold steps: the 256 MB MALL flushed by writing 1 GiB before each
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cold_ms = []
+    for _ in range(args.cold_steps):
+        flush.fill_(1)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        step()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        cold_ms.append(ev[0].elapsed_time(ev[1]))
+    del flush
+
+    # ---- the same batch as one HIP graph replay: the pair setup runs on
+    # the device from F in device memory (so it is part of every replay),
+    # autotuned tile schedule
+    Fd = g(np.stack([p.F.reshape(9) for p in pairs]))
+    graph = None
+    if args.no_graph or args.no_tune:
         sched, tinfo = E.Sched(), {"key": None, "cached": None}
     else:
         sched, tinfo = autotune.tune(specs, kp1, kp2, q1, q2, cap, dtype="bf16", eps=2.0,
                                      desc1_f32=m1, desc2_f32=m2, steps=3, warmup=1,
                                      cache=args.tune_cache,
                                      log=lambda msg: print(msg, file=sys.stderr, flush=True))
-    bt = E.Batch(specs, kp1, kp2, q1, q2, cap, eps=2.0, dtype="bf16", desc1_f32=m1,
-                 desc2_f32=m2, sched=sched, workspace=ws)
-    sec = time_steps(torch, bt.launch, args.steps, args.warmup)
-    assert bt.nnz() == nnz
-    gstats, gmatch = bt.stats(), bt.match_stats()
-    res_graph = [x.clone() for x in bt.outputs()[2:]]
-    bt.close()
+    if not args.no_graph:
+        bt = E.Batch(specs, kp1, kp2, q1, q2, cap, eps=2.0, dtype="bf16", desc1_f32=m1,
+                     desc2_f32=m2, sched=sched, workspace=ws, F_dev=Fd)
+        gsec = time_steps(torch, bt.launch, args.steps, args.warmup)
+        assert bt.nnz() == nnz
+        gsame = all(torch.equal(a, r) for a, r in zip(bt.outputs()[2:], ref_out))
+        bt.close()
+        graph = {"value": round(N1 / gsec, 1), "ms_per_step": round(gsec * 1e3, 4),
+                 "identical_matches": bool(gsame), "sched": sched.as_dict(),
+                 "includes_pair_setup": "on the device, from F in device memory",
+                 "autotune": {k: tinfo[k] for k in ("key", "cached")}}
 
-    # ---- the same batch through the eager calls (default schedule)
-    offs = torch.empty(N1 + 1, dtype=torch.int64, device=dev)
-    cols = torch.empty(cap, dtype=torch.int32, device=dev)
-    out = (torch.empty(N1, dtype=torch.int32, device=dev),
-           torch.empty(N1, dtype=torch.float32, device=dev),
-           torch.empty(N1, dtype=torch.float32, device=dev))
+    fp32 = separate = None
+    if not args.no_separate:
+        # ---- the same batch through the FP32 masters (fused FP32 selection)
+        def f32_step():
+            idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+            idx.query_match(kp1, m1, m2, row_offsets=offs, col_indices=cols, out=out, sync=False)
 
-    def eager_step():
-        idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
-        idx.query(kp1, row_offsets=offs, col_indices=cols, sync=False)
-        idx.match(offs, cols, q1, q2, dtype="bf16", desc1_f32=m1, desc2_f32=m2, out=out)
-        idx.close()
+        fsec = time_steps(torch, f32_step, args.steps, args.warmup)
+        fp32 = {"value": round(N1 / fsec, 1), "ms_per_step": round(fsec * 1e3, 4),
+                "identical_matches": all(torch.equal(a, r) for a, r in zip(out, ref_out))}
 
-    esec = time_steps(torch, eager_step, args.steps, args.warmup)
-    same = all(torch.equal(a, r) for a, r in zip(out, res_graph))
+        # ---- separate calls: query, then the BF16 window-kernel match
+        def sep_step():
+            idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+            idx.query(kp1, row_offsets=offs, col_indices=cols, sync=False)
+            idx.match(offs, cols, q1, q2, dtype="bf16", desc1_f32=m1, desc2_f32=m2, out=out)
 
-    def fused_step():
-        idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
-        idx.query_match_bf16(kp1, q1, q2, m1, m2, row_offsets=offs, col_indices=cols, out=out,
-                             sync=False)
-        idx.close()
+        ssec = time_steps(torch, sep_step, args.steps, args.warmup)
+        separate = {"value": round(N1 / ssec, 1), "ms_per_step": round(ssec * 1e3, 4),
+                    "identical_matches": all(torch.equal(a, r) for a, r in zip(out, ref_out))}
 
-    fsec = time_steps(torch, fused_step, args.steps, args.warmup)
-    fsame = all(torch.equal(a, r) for a, r in zip(out, res_graph))
+    # ---- plain path: one pipeline per pair, host-sized CSR, FP32 gathers
+    plain = None
+    if not args.no_plain:
+        qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
+        kb = np.concatenate([[0], np.cumsum([p.n for p in pairs])])
+        per = [(specs[i], kp1[qb[i]:qb[i + 1]], kp2[kb[i]:kb[i + 1]], m1[qb[i]:qb[i + 1]],
+                m2[kb[i]:kb[i + 1]]) for i in range(len(pairs))]
 
-    # ---- plain path: one pipeline per pair
-    qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
-    kb = np.concatenate([[0], np.cumsum([p.n for p in pairs])])
-    per = [(specs[i], kp1[qb[i]:qb[i + 1]], kp2[kb[i]:kb[i + 1]], m1[qb[i]:qb[i + 1]],
-            m2[kb[i]:kb[i + 1]]) for i in range(len(pairs))]
+        def plain_step():
+            for sp, a1, a2, d1, d2 in per:
+                idx = E.Index([sp], a2, eps=2.0)
+                o2, c2 = idx.query(a1)
+                idx.match(o2, c2, d1, d2, dtype="f32", algo="plain")
 
-    def plain_step():
-        for sp, a1, a2, d1, d2 in per:
-            idx = E.Index([sp], a2, eps=2.0)
-            o2, c2 = idx.query(a1)
-            idx.match(o2, c2, d1, d2, dtype="f32", algo="plain")
-            idx.close()
+        psec = time_steps(torch, plain_step, 2, 1)
+        plain = {"value": round(N1 / psec, 1), "unit": "queries/s",
+                 "ms_per_step": round(psec * 1e3, 2),
+                 "what": "one build + query + plain FP32 gather match per pair (512 "
+                         "pipelines, host-sized CSR with one synchronisation each)"}
 
-    psec = time_steps(torch, plain_step, 1, 1) if not args.no_plain else float("nan")
-    # algorithmic bytes of the batch (BF16 rows, FP32 masters read for the re-rank)
+    # ---- roofline of the dominant kernel: algorithmic bytes per launch
+    # (each input read once at the precision the path needs, each output
+    # written once; FP32 master rows counted once each, as the re-rank's
+    # upper bound): queries: kp1 8 + BF16 row 256 + FP32 master 512 + row
+    # length 4 + match 12; image-2 keypoints: record 24 + BF16 row 256 +
+    # FP32 master 512; candidates: 4 (parked column)
+    kern_ms = float(np.mean(kernel_ms))
+    kernel_bytes = N1 * (8 + 256 + 512 + 4 + 12) + N2 * (24 + 256 + 512) + 4 * nnz
+    name, src, tfile = KERNELS["bf16"]
+    achieved = kernel_bytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(src, tfile),
+                "avg_launch_ms": round(kern_ms, 5), "timed_launches": len(kernel_ms),
+                "timed_every_nth_step": EVENT_STRIDE,
+                "algorithmic_bytes_per_launch": int(kernel_bytes),
+                "kernel_source_sha256": source_hash(src)}
+    # whole step: kp 8 + BF16 row + row offset 8 + match 12 per query; kp 8 +
+    # eps 4 + BF16 row + record 24 per image-2 keypoint; 4 per candidate;
+    # the FP32 masters of both images once
     alg_bytes = N1 * (8 + 256 + 8 + 12) + N2 * (8 + 4 + 256 + 24) + 4 * nnz + 512 * (N1 + N2)
+
+    if args.calibrate_copy:  # a 2 GiB device copy for the traffic counters
+        src_b = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        dst_b = torch.empty_like(src_b)
+        for _ in range(3):
+            dst_b.copy_(src_b)
+        torch.cuda.synchronize()
+        del src_b, dst_b
+
+    # ---- CPU oracle on the pairs of the batch (every --cpu-every-th), which
+    # also checks the GPU result of those pairs element for element
+    cpu = None
+    oracle_check = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = host_threads()
+        sample = list(range(0, len(pairs), args.cpu_every))
+        ro_all, rc_all = ref_offs.cpu().numpy(), ref_cols.cpu().numpy()
+        bi_all = ref_out[0].cpu().numpy()
+        bd_all = ref_out[1].cpu().numpy()
+        sd_all = ref_out[2].cpu().numpy()
+        qb = np.concatenate([[0], np.cumsum([p.m for p in pairs])])
+        t0 = time.perf_counter()
+        done, same = 0, True
+        for i in sample:
+            p = pairs[i]
+            ro, rc, _ = oracle.candidates(p.F, p.kp1, p.kp2, 2.0, nthreads=threads)
+            rb, rbd, rsd = oracle.match(p.desc1, p.desc2, ro, rc, nthreads=threads)
+            done += p.m
+            go = ro_all[qb[i]:qb[i + 1] + 1] - ro_all[qb[i]]
+            gc = rc_all[ro_all[qb[i]]:ro_all[qb[i + 1]]]
+            same = same and np.array_equal(go, ro) and np.array_equal(gc, rc) \
+                and np.array_equal(bi_all[qb[i]:qb[i + 1]], rb) \
+                and np.array_equal(bd_all[qb[i]:qb[i + 1]].view(np.uint32), rbd.view(np.uint32)) \
+                and np.array_equal(sd_all[qb[i]:qb[i + 1]].view(np.uint32), rsd.view(np.uint32))
+        cel = time.perf_counter() - t0
+        cpu = {"value": round(done / cel, 1), "unit": "queries/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"every {args.cpu_every}th pair of the batch ({len(sample)} pairs, "
+                         f"{done} queries, each against all keypoints of its pair: brute-force "
+                         f"FP64 candidates + canonical FP32 matching on the masters, "
+                         f"{cel:.1f} s)",
+               "cpu": cpu_model()}
+        oracle_check = {"pairs": len(sample), "queries": done, "identical": bool(same)}
+
     line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16+f32+f64", "data": "synthetic",
-            "config": {"workload": f"batch: {len(pairs)} uneven pairs (cfg3 mix), eps 2 px, "
-                                   "BF16 descriptors with FP32 masters, one HIP graph replay "
-                                   "per step",
+            "config": {"workload": f"batch: {len(pairs)} uneven pairs (1920x1080 / 4032x3024 / "
+                                   "6048x4032, 500-30000 keypoints per image, far / infinite / "
+                                   "in-image epipoles), eps 2 px, BF16 descriptors with FP32 "
+                                   "masters; step = build (host pair setup) + fused query and "
+                                   "BF16 match",
                        "queries_per_step": N1, "keypoints2_per_step": N2,
                        "candidates_per_step": nnz, "kbar": round(nnz / N1, 2)},
-            "sched": sched.as_dict(), "autotune": {k: tinfo[k] for k in ("key", "cached")},
-            "autotune_candidates_ms": [[c, round(t * 1e3, 4)]
-                                       for c, t in tinfo.get("candidates", [])],
+            "roofline": roofline,
+            "cpu_baseline": cpu,
+            "step_ms_warm": {"median": pct(warm_ms, 50), "p10": pct(warm_ms, 10),
+                             "p90": pct(warm_ms, 90), "steps": len(warm_ms)},
+            "step_ms_cold": {"median": pct(cold_ms, 50), "p10": pct(cold_ms, 10),
+                             "p90": pct(cold_ms, 90), "steps": len(cold_ms),
+                             "flush": "1 GiB written before each step"} if cold_ms else None,
             "whole_step_hbm": {"algorithmic_bytes": int(alg_bytes),
                                "achieved_GBps": round(alg_bytes / sec / 1e9, 1),
                                "frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4)},
-            "match_stats": gmatch, "query_stats": gstats,
-            "eager_batched": {"value": round(N1 / esec, 1), "ms_per_step": round(esec * 1e3, 4),
-                              "identical_matches": bool(same)},
-            "eager_fused_bf16": {"value": round(N1 / fsec, 1), "ms_per_step": round(fsec * 1e3, 4),
-                                 "identical_matches": bool(fsame)},
-            "plain_gpu": None if args.no_plain else {"value": round(N1 / psec, 1),
-                                                     "ms_per_step": round(psec * 1e3, 2)},
-            "speedup_vs_plain": None if args.no_plain else round(psec / sec, 3)}
+            "oracle_check": oracle_check,
+            "match_stats": mstats, "query_stats": qstats,
+            "graph": graph,
+            "fp32_masters_fused": fp32,
+            "separate_calls_bf16": separate,
+            "plain_gpu": plain,
+            "speedup_vs_plain": round((N1 / sec) / plain["value"], 3) if plain else None}
     print(json.dumps(line), flush=True)
 
 
@@ -903,7 +1071,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         # the machine's CPU share, not the host's core count
-        threads = min(16, len(os.sched_getaffinity(0)))
+        threads = host_threads()
         s = args.cpu_sample
         t0 = time.perf_counter()
         done = 0
@@ -917,7 +1085,7 @@ def main():
                "sample": f"first {min(s, 20000)} queries of each of the {P} pairs against "
                          f"all 20000 keypoints ({done} queries, brute-force FP64 candidates "
                          f"+ FP32 matching, {cel:.1f} s)",
-               "cpu": platform.processor() or platform.machine()}
+               "cpu": cpu_model()}
 
     out = {
         "metric": METRIC,

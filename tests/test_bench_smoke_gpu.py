@@ -27,8 +27,8 @@ def _run(monkeypatch, capsys, argv):
 
 
 def test_scale_workload_line(monkeypatch, capsys):
-    line = _run(monkeypatch, capsys, ["--steps", "2", "--warmup", "1", "--no-plain",
-                                      "--no-graph", "--cpu-sample", "200"])
+    line = _run(monkeypatch, capsys, ["--workload", "scale", "--steps", "2", "--warmup", "1",
+                                      "--no-plain", "--no-graph", "--cpu-sample", "200"])
     r = line["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
@@ -42,9 +42,22 @@ def test_scale_workload_line(monkeypatch, capsys):
 
 
 def test_batch_workload_line(monkeypatch, capsys):
-    line = _run(monkeypatch, capsys, ["--workload", "batch", "--pairs", "8", "--steps", "1",
-                                      "--warmup", "0", "--no-plain", "--no-tune"])
-    assert line["eager_batched"]["identical_matches"]
+    """The default line (the batching configuration) on a few pairs: roofline
+    and CPU baseline present, every other form identical, the oracle sample
+    identical."""
+    line = _run(monkeypatch, capsys, ["--pairs", "8", "--steps", "2", "--warmup", "1",
+                                      "--cold-steps", "2", "--no-tune", "--cpu-every", "2"])
+    r = line["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r, k
+    assert r["peak"] == 8000.0 and 0 < r["frac"] < 1
+    c = line["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0
+    assert line["oracle_check"]["identical"] and line["oracle_check"]["pairs"] == 4
+    for k in ("graph", "fp32_masters_fused", "separate_calls_bf16"):
+        assert line[k]["identical_matches"], k
+    assert line["step_ms_cold"]["steps"] == 2
+    assert line["speedup_vs_plain"] > 1
 
 
 def test_precision_workload_line(monkeypatch, capsys):
