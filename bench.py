@@ -184,6 +184,15 @@ def precision_workload(args):
         "bf16": dict(desc1=b1, desc2=b2, dtype="bf16", desc1_f32=m1, desc2_f32=m2),
         "fp8": dict(desc1=c1, desc2=c2, dtype="fp8", scale1=s1, scale2=s2, desc1_f32=m1,
                     desc2_f32=m2),
+        # bounds from the measured per-row rounding errors (epm_rounding_error,
+        # computed once with the quantisation, outside the timed step)
+        "bf16_measured": dict(desc1=b1, desc2=b2, dtype="bf16", desc1_f32=m1, desc2_f32=m2,
+                              qerr1=E.rounding_error(m1, b1, "bf16"),
+                              qerr2=E.rounding_error(m2, b2, "bf16")),
+        "fp8_measured": dict(desc1=c1, desc2=c2, dtype="fp8", scale1=s1, scale2=s2,
+                             desc1_f32=m1, desc2_f32=m2,
+                             qerr1=E.rounding_error(m1, c1, "fp8", scale=s1),
+                             qerr2=E.rounding_error(m2, c2, "fp8", scale=s2)),
         "bin256": dict(desc1=n1, desc2=n2, dtype="bin256"),
     }
     res = {}
@@ -198,9 +207,27 @@ def precision_workload(args):
 
         sec = time_steps(torch, step, args.steps, args.warmup)
         entry = {"value": round(p.m / sec, 1), "ms_per_step": round(sec * 1e3, 4)}
-        if name in ("bf16", "fp8"):
+        if name.startswith(("bf16", "fp8")):
             entry["match_stats"] = holder["idx"].match_stats()
         res[name] = entry
+    # error of the distances the kernels compute against FP64 on the masters,
+    # over a sample of candidate pairs (relative: |d - d64| / d64)
+    import oracle
+    rng = np.random.default_rng(31)
+    ro, rc = o.cpu().numpy(), c.cpu().numpy()
+    rows = np.repeat(np.arange(p.m), np.diff(ro))
+    pick = rng.choice(len(rc), min(len(rc), 100000), replace=False)
+    qi, kj = rows[pick].astype(np.int64), rc[pick].astype(np.int64)
+    d64 = oracle.desc_dist_f64(p.desc1, p.desc2, qi, kj)
+    tq, tk = g(qi), g(kj)
+    errs = {}
+    for name, kw in (("f32_canonical", dict(desc1=m1, desc2=m2, dtype="f32")),
+                     ("bf16_mfma", dict(desc1=b1, desc2=b2, dtype="bf16")),
+                     ("fp8_mfma", dict(desc1=c1, desc2=c2, dtype="fp8", scale1=s1, scale2=s2))):
+        d = E.descriptor_distances(qi=tq, kj=tk, **kw).cpu().numpy().astype(np.float64)
+        rel = np.abs(d - d64) / d64
+        errs[name] = {"max_rel": float(f"{rel.max():.3e}"), "median_rel": float(f"{np.median(rel):.3e}")}
+    errs["pairs"] = int(len(pick))
     line = {"metric": METRIC, "value": res["bf16"]["value"], "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": res["bf16"]["ms_per_step"], "higher_is_better": True,
@@ -209,8 +236,9 @@ def precision_workload(args):
             "config": {"workload": "precision: 1 pair 6048x4032, 60000 keypoints/image, "
                                    "eps 2 px", "queries_per_step": p.m,
                        "candidates_per_step": nnz, "kbar": round(nnz / p.m, 2)},
-            "paths": res,
-            "speedup_vs_plain": round(res["bf16"]["value"] / res["f32_plain"]["value"], 3)}
+            "paths": res, "error_vs_fp64": errs,
+            "speedup_vs_plain": round(res["bf16"]["value"] / res["f32_plain"]["value"], 3),
+            "fp8_vs_plain": round(res["fp8_measured"]["value"] / res["f32_plain"]["value"], 3)}
     print(json.dumps(line), flush=True)
 
 

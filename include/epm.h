@@ -154,6 +154,12 @@ typedef struct {
                                epm_query_candidates with nnz_host == NULL)      */
   int64_t col_capacity;
   int32_t reserved[4];      /* zero                                               */
+  const float* qerr1;       /* BF16 / FP8: [N1] / [N2] per-row bounds on the norm of */
+  const float* qerr2;       /* x - dequant(x^) (epm_rounding_error), both or neither;
+                               tighter than the format's worst case, so fewer
+                               candidates need exact distances.  NULL: the
+                               format's bound (valid when the codes are rounded
+                               to nearest from the masters).                     */
 } epm_match_opts;
 
 /*
@@ -207,6 +213,18 @@ epm_status epm_quantize(const float* src, int64_t rows, int32_t dim, epm_dtype d
                         float* scale, hipStream_t stream);
 
 /*
+ * Per-row rounding error of reduced-precision descriptors against their FP32
+ * masters: err[r] >= |src_r - dequant(codes_r)| (computed in FP64, inflated
+ * by 1e-6), for the bound of the certified re-rank (epm_match_opts.qerr1/2).
+ * src [rows][dim] float32; codes as epm_quantize writes them (EPM_BF16:
+ * uint16 [rows][dim]; EPM_FP8_E4M3: uint8 [rows][dim] with scale [rows]).
+ * Errors: EPM_ERR_ARG.  Asynchronous.
+ */
+epm_status epm_rounding_error(const float* src, int64_t rows, int32_t dim, epm_dtype dtype,
+                              const void* codes, const float* scale, float* err,
+                              hipStream_t stream);
+
+/*
  * The two sides of the point-line test of Eq. 3 (multiplied through by the
  * denominator) for listed (query, keypoint) pairs, exactly as the candidate
  * search evaluates them on the device:
@@ -221,6 +239,23 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,
                                 hipStream_t stream);
+
+/*
+ * Descriptor distances of listed pairs exactly as the matching kernels
+ * compute them (Sec. 4.3 selection; a diagnostic for stating the error of the
+ * reduced-precision paths against a reference):
+ *   EPM_F32:       out[t] = the canonical FP32 squared distance (t_k = a_k - b_k,
+ *                  acc = fmaf(t_k, t_k, acc), k ascending) of rows qi[t] of
+ *                  desc1 and kj[t] of desc2 ([N][128] float32);
+ *   EPM_BF16 / EPM_FP8_E4M3: the MFMA approximation |q^|^2 + |w^|^2 - 2 s1 s2 q^.w^
+ *                  of the codes (FP8 with per-row scales scale1/scale2; the
+ *                  dot product on MFMA with FP32 accumulation), rounded to float.
+ * dim must be 128.  Device arrays; asynchronous.  Errors: EPM_ERR_ARG.
+ */
+epm_status epm_descriptor_distances(epm_dtype dtype, int32_t dim, const void* desc1,
+                                    const void* desc2, const float* scale1, const float* scale2,
+                                    const int64_t* qi, const int64_t* kj, int64_t count,
+                                    float* out, hipStream_t stream);
 
 /*
  * epm_query_candidates followed by epm_match with FP32 descriptors (EPM_F32,

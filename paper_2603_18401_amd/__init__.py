@@ -24,7 +24,8 @@ import os
 import numpy as np
 
 __all__ = ["EpmError", "Index", "Batch", "Sched", "PairSpec", "load_library", "library_path",
-           "point_line_terms", "quantize", "DTYPES", "ALGOS"]
+           "point_line_terms", "descriptor_distances", "quantize", "query_match_noalloc",
+           "DTYPES", "ALGOS"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libepm.so")
@@ -42,7 +43,7 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
            "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc",
-           "epm_query_match_bf16"]
+           "epm_query_match_bf16", "epm_descriptor_distances", "epm_rounding_error"]
 
 
 class EpmError(RuntimeError):
@@ -70,7 +71,8 @@ class _MatchStats(ctypes.Structure):
 
 class _MatchOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("check_capacity", ctypes.c_int32),
-                ("col_capacity", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+                ("col_capacity", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4),
+                ("qerr1", ctypes.c_void_p), ("qerr2", ctypes.c_void_p)]
 
 
 class _Sched(ctypes.Structure):
@@ -203,6 +205,10 @@ def load_library(path=None):
     lib.epm_query_match_noalloc.argtypes = [P, i32, V, V, V, f32, V, V, i64,
                                             ctypes.POINTER(i64), V, V, f32, V, V, V, V]
     lib.epm_query_match_noalloc.restype = ctypes.c_int
+    lib.epm_descriptor_distances.argtypes = [ctypes.c_int, i32, V, V, V, V, V, V, i64, V, V]
+    lib.epm_descriptor_distances.restype = ctypes.c_int
+    lib.epm_rounding_error.argtypes = [V, i64, i32, ctypes.c_int, V, V, V, V]
+    lib.epm_rounding_error.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -472,7 +478,7 @@ class Index:
 
     def match(self, row_offsets, col_indices, desc1, desc2, dtype="f32", scale1=None,
               scale2=None, desc1_f32=None, desc2_f32=None, ratio=0.0, algo="auto", out=None,
-              check_capacity=False):
+              check_capacity=False, qerr1=None, qerr2=None):
         """Nearest neighbour per query: (best_idx int32, best_dist f32, second_dist f32).
 
         check_capacity: the launch writes nothing when row_offsets[N1] exceeds
@@ -490,6 +496,8 @@ class Index:
         if check_capacity:
             opts.check_capacity = 1
             opts.col_capacity = col_indices.numel()
+        if qerr1 is not None:
+            opts.qerr1, opts.qerr2 = qerr1.data_ptr(), qerr2.data_ptr()
         st = self.lib.epm_match(self.handle, _dptr(row_offsets), _dptr(col_indices), DTYPES[dtype],
                                 dim, _dptr(desc1), _dptr(desc2), _dptr(scale1), _dptr(scale2),
                                 _dptr(desc1_f32), _dptr(desc2_f32), float(ratio), _dptr(best),
@@ -686,6 +694,33 @@ def quantize(desc, dtype, stream=None):
                           _stream(torch, desc.device, stream))
     _check(st, "epm_quantize")
     return (out, scale) if dtype == "fp8" else out
+
+
+def rounding_error(src, codes, dtype, scale=None, stream=None):
+    """epm_rounding_error: per-row bounds on |x - dequant(x^)| (float32 [N])."""
+    torch = _torch()
+    lib = load_library()
+    n, d = src.shape
+    err = torch.empty(n, dtype=torch.float32, device=src.device)
+    st = lib.epm_rounding_error(_dptr(src), n, d, DTYPES[dtype], _dptr(codes), _dptr(scale),
+                                _dptr(err), _stream(torch, src.device, stream))
+    _check(st, "epm_rounding_error")
+    return err
+
+
+def descriptor_distances(desc1, desc2, qi, kj, dtype="f32", scale1=None, scale2=None,
+                         stream=None):
+    """epm_descriptor_distances: for listed pairs (qi[t], kj[t]) the canonical
+    FP32 distance (dtype "f32") or the MFMA approximation of BF16 / FP8 codes
+    (dtype "bf16" / "fp8") as the matching kernels compute them (float32 [count])."""
+    torch = _torch()
+    lib = load_library()
+    out = torch.empty(qi.numel(), dtype=torch.float32, device=qi.device)
+    st = lib.epm_descriptor_distances(DTYPES[dtype], 128, _dptr(desc1), _dptr(desc2),
+                                      _dptr(scale1), _dptr(scale2), _dptr(qi), _dptr(kj),
+                                      qi.numel(), _dptr(out), _stream(torch, qi.device, stream))
+    _check(st, "epm_descriptor_distances")
+    return out
 
 
 def point_line_terms(F, kp1, kp2, qi, kj, eps2=None, eps=0.0, stream=None):

@@ -532,6 +532,8 @@ struct MatchCall {
   float *best_dist, *second_dist;
   epm_algo algo;
   int64_t capacity;  // < 0: trusted
+  const float* qerr1 = nullptr;  // measured rounding errors of the reduced rows, or NULL
+  const float* qerr2 = nullptr;
 };
 
 epm_status validate_match(const epm_index* idx, const MatchCall& c) {
@@ -593,6 +595,8 @@ MatchArgs match_args(epm_index* idx, const MatchCall& c) {
   A.queue = nullptr;
   A.skip_tiles = nullptr;
   A.block_tile = nullptr;
+  A.qerr1 = c.qerr1;
+  A.qerr2 = c.qerr2;
   return A;
 }
 
@@ -917,6 +921,9 @@ epm_status epm_match(const epm_index* idx, const int64_t* row_offsets,
       if (opts->col_capacity < 0) return EPM_ERR_ARG;
       c.capacity = opts->col_capacity;
     }
+    if ((opts->qerr1 == nullptr) != (opts->qerr2 == nullptr)) return EPM_ERR_ARG;
+    c.qerr1 = opts->qerr1;
+    c.qerr2 = opts->qerr2;
   }
   const epm_status v = validate_match(idx, c);
   if (v != EPM_OK) return v;
@@ -1394,6 +1401,17 @@ epm_status epm_quantize(const float* src, int64_t rows, int32_t dim, epm_dtype d
   return EPM_OK;
 }
 
+epm_status epm_rounding_error(const float* src, int64_t rows, int32_t dim, epm_dtype dtype,
+                              const void* codes, const float* scale, float* err,
+                              hipStream_t stream) {
+  if (rows < 0 || dim < 1 || dim > 4096) return EPM_ERR_ARG;
+  if (dtype != EPM_BF16 && dtype != EPM_FP8_E4M3) return EPM_ERR_ARG;
+  if (rows == 0) return EPM_OK;
+  if (!src || !codes || !err || (dtype == EPM_FP8_E4M3 && !scale)) return EPM_ERR_ARG;
+  EPM_HIP(launch_round_err(src, rows, dim, dtype == EPM_BF16 ? 0 : 1, codes, scale, err, stream));
+  return EPM_OK;
+}
+
 epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const float* kp2_xy,
                                 const float* eps2, float eps_scalar, const int64_t* qi,
                                 const int64_t* kj, int64_t count, double* num, double* rhs,
@@ -1403,6 +1421,20 @@ epm_status epm_point_line_terms(const double* F, const float* kp1_xy, const floa
   if (!kp1_xy || !kp2_xy || !qi || !kj || !num || !rhs) return EPM_ERR_ARG;
   EPM_HIP(launch_point_line_terms(F, kp1_xy, kp2_xy, eps2, eps_scalar, qi, kj, count, num, rhs,
                                   stream));
+  return EPM_OK;
+}
+
+epm_status epm_descriptor_distances(epm_dtype dtype, int32_t dim, const void* desc1,
+                                    const void* desc2, const float* scale1, const float* scale2,
+                                    const int64_t* qi, const int64_t* kj, int64_t count,
+                                    float* out, hipStream_t stream) {
+  if (count < 0 || dim != 128) return EPM_ERR_ARG;
+  if (dtype != EPM_F32 && dtype != EPM_BF16 && dtype != EPM_FP8_E4M3) return EPM_ERR_ARG;
+  if (count == 0) return EPM_OK;
+  if (!desc1 || !desc2 || !qi || !kj || !out) return EPM_ERR_ARG;
+  if (dtype == EPM_FP8_E4M3 && (!scale1 || !scale2)) return EPM_ERR_ARG;
+  const int fmt = dtype == EPM_F32 ? -1 : dtype == EPM_BF16 ? 0 : 1;
+  EPM_HIP(launch_pair_distances(fmt, desc1, desc2, scale1, scale2, qi, kj, count, out, stream));
   return EPM_OK;
 }
 
@@ -1459,7 +1491,7 @@ epm_status epm_get_match_stats(const epm_index* idx, epm_match_stats* out) {
   out->reranked_rows = (int64_t)(c[0] + ranked);
   out->fallback_rows = (int64_t)(c[1] + unc);
   out->long_rows = (int64_t)c[2];
-  out->exact_distances = (int64_t)evals;
+  out->exact_distances = (int64_t)(c[3] + evals);
   return EPM_OK;
 }
 

@@ -210,10 +210,15 @@ struct MatchArgs {
   uint32_t* queue;             // persistent tiled launch: next-tile counter, zero at launch
   const uint32_t* skip_tiles;  // tiled kernels: tiles left to the wide-row pass, or NULL
   const uint32_t* block_tile;  // one workgroup per tile: tile of each workgroup, or NULL
+  // measured per-row rounding errors of the reduced rows (>= |x - dequant(x^)|),
+  // or NULL for the format's worst case
+  const float* qerr1;
+  const float* qerr2;
 };
 
-constexpr int kNumMatchStats = 3;  // re-ranked rows, uncertified (exact fallback), long rows
-constexpr int kMatchStatRest = 3;  // internal: rest-list length of the wide-row match
+// re-ranked rows, uncertified (exact fallback), long rows, exact distances of the re-rank
+constexpr int kNumMatchStats = 4;
+constexpr int kMatchStatRest = 4;  // internal: rest-list length of the wide-row match
 constexpr int kMatchStatWords = kMatchStatRest + 1;
 // fmt 0: BF16, 1: FP8-E4M3 with row scales.
 // grid as for launch_stab_tiles.
@@ -302,9 +307,19 @@ hipError_t launch_mutual(const int64_t* qstart, const int64_t* kstart, int num_p
                          const int32_t* best12, const int32_t* best21, int32_t* mutual,
                          hipStream_t s);
 
+// err[r] >= |src_r - dequant(codes_r)| (fmt 0: BF16; 1: E4M3 with scales).
+hipError_t launch_round_err(const float* src, int64_t rows, int dim, int fmt, const void* codes,
+                            const float* scale, float* err, hipStream_t s);
+
 // fmt 0: BF16 codes [rows][dim]; 1: E4M3 codes [rows][dim] and scales [rows].
 hipError_t launch_quantize(const float* src, int64_t rows, int dim, int fmt, void* dst,
                            float* scale, hipStream_t s);
+
+// fmt 0 / 1: MFMA approximate distances of BF16 / FP8 codes; -1: canonical
+// FP32 distances of FP32 rows; for pairs (qi[t], kj[t]).
+hipError_t launch_pair_distances(int fmt, const void* desc1, const void* desc2,
+                                 const float* scale1, const float* scale2, const int64_t* qi,
+                                 const int64_t* kj, int64_t count, float* out, hipStream_t s);
 
 hipError_t launch_point_line_terms(const double* F9, const float* kp1, const float* kp2,
                                   const float* eps2, float eps_scalar, const int64_t* qi,

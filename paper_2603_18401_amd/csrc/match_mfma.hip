@@ -2,23 +2,24 @@
 //
 // Descriptors stored as BF16 or as OCP FP8-E4M3 with a per-row FP32 scale are
 // compared on MFMA (dense query-tile x window-row score blocks, FP32
-// accumulation); the FP32 masters are used only to re-rank a few candidates.
-// Per workgroup (one angle tile of 64 queries):
+// accumulation); the FP32 masters are used only for the exact distances of a
+// few candidates.  Per workgroup (one angle tile of 64 queries):
 //   1. the tile's CSR rows are mapped to window indices (as in the FP32 window
 //      kernel);
 //   2. quantised query rows and, chunk by chunk, quantised window rows are
 //      staged in LDS; S = Q W^T on v_mfma_f32_16x16x32_{bf16,fp8_fp8};
-//   3. every candidate gets a rigorous lower bound LB on its exact canonical
-//      FP32 distance from the approximate distance |q^|^2 + |w^|^2 - 2 s S and
-//      the format's rounding bound;
-//   4. the four candidates with the smallest LB are re-ranked with canonical
-//      FP32 chains on the masters; when the smallest LB among the others
-//      exceeds the exact second distance (or the row has at most four
-//      candidates), best and second are certified exact;
-//   5. otherwise (and for rows that do not fit the tile's dense list of 8192
-//      entries) every candidate is evaluated exactly -- counted in the match
-//      statistics.
-// Final outputs therefore equal the FP32 path bit for bit.
+//   3. every candidate gets certified bounds LB <= D <= UB on its exact
+//      canonical FP32 distance D from the approximate distance
+//      |q^|^2 + |w^|^2 - 2 s S and the format's rounding bound, kept as two
+//      outward-rounded halves in the candidate's 32-bit list entry;
+//   4. with U2 the second smallest UB of a row, two candidates have D <= U2,
+//      so a candidate with LB > U2 is neither best nor second: every other
+//      candidate of the row is evaluated exactly on the masters (all threads
+//      over the tile's entries) and the row's top-2 is taken over those;
+//   5. rows that do not fit the tile's dense list of 8192 entries are
+//      evaluated exactly by gathers -- counted in the match statistics.
+// Final outputs therefore equal the FP32 path bit for bit, with no separate
+// certificate: the bounds only decide which candidates need exact distances.
 #include "device_common.h"
 #include "launch.h"
 #include "match_common.h"
@@ -34,12 +35,13 @@ constexpr int kChunkRows = 64;
 constexpr int kMaxPairs = 8192;  // dense (query, candidate) entries per tile
 constexpr uint32_t kPending = kEntPending;
 constexpr uint32_t kNoWindow = kEntNoWindow;
-constexpr int kReRank = 4;
 
 template <int FMT, bool PERSIST>
 __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   constexpr int RS = row_stride<FMT>();
-  __shared__ __attribute__((aligned(16))) uint8_t qrows[kTileQ * RS];
+  // the query rows, and after the last MFMA the list of exact distances to take
+  constexpr int kQBytes = kTileQ * RS > kMaxPairs * 2 ? kTileQ * RS : kMaxPairs * 2;
+  __shared__ __attribute__((aligned(16))) uint8_t qrows[kQBytes];
   constexpr int kScoreBytes = kTileQ * (kChunkRows + 1) * 4;
   constexpr int kWBytes = kChunkRows * RS > kScoreBytes ? kChunkRows * RS : kScoreBytes;
   __shared__ __attribute__((aligned(16))) uint8_t wrows[kWBytes];
@@ -52,14 +54,10 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
   // per-row terms of the bound: inflated norm and quantisation error bound
   __shared__ double q_nb[kTileQ], q_db[kTileQ], w_nb[kChunkRows], w_db[kChunkRows];
   __shared__ int32_t row_j[kChunkRows];
-  __shared__ uint32_t n_sorted_slots, n_fallback;
-  __shared__ uint16_t fallback_q[kTileQ];
+  __shared__ uint32_t n_sorted_slots;
   __shared__ float4 qdesc[kWaves][32];
-  // re-rank scratch: per query the four chosen entries and the fifth bound
-  __shared__ uint32_t pick[kTileQ][kReRank];
-  __shared__ int32_t pick_j[kTileQ][kReRank];  // image-2 index of each pick (from the CSR)
-  __shared__ float pick_d[kTileQ][kReRank];
-  __shared__ float lb5[kTileQ];
+  __shared__ float lb5[kTileQ];  // the second smallest upper bound of each row
+  __shared__ uint32_t wave_total[kWaves];
 
   __shared__ int next_tile;
   if (csr_overflow(A)) return;
@@ -121,10 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       }
       q_off[q + 1] = incl;
       q_in[q] = lane < nfit ? 1u : 0u;
-      if (lane == 0) {
-        q_off[0] = 0;
-        n_fallback = 0;
-      }
+      if (lane == 0) q_off[0] = 0;
       const uint32_t b = W->slot_b[lane];
       const uint32_t p0 = W->slot_pref[lane], p1 = W->slot_pref[lane + 1];
       slot_b[lane] = b;
@@ -166,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
       q_norm[tid] = n * s * s;  // squared norm of the dequantised row
       const double nb = sqrt((double)q_norm[tid]) * (1.0 + 1e-5);
       q_nb[tid] = nb;
-      q_db[tid] = row_delta<FMT>(nb, s);
+      q_db[tid] = A.qerr1 && tid < T.count ? (double)A.qerr1[q_i[tid]] : row_delta<FMT>(nb, s);
     }
 
     const uint32_t wlen = slot_pref[kSlots];
@@ -200,7 +195,8 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
         w_norm[tid] = n * s * s;
         const double nb = sqrt((double)w_norm[tid]) * (1.0 + 1e-5);
         w_nb[tid] = nb;
-        w_db[tid] = row_delta<FMT>(nb, s);
+        w_db[tid] = A.qerr2 && row_j[tid] >= 0 ? (double)A.qerr2[kb + row_j[tid]]
+                                               : row_delta<FMT>(nb, s);
       }
       // S = Q W^T: wavefront w owns queries 16w..16w+15 against all 64 rows
       f32x4 acc[4];
@@ -246,74 +242,79 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
         const double s = (double)score[q * (kChunkRows + 1) + r] * (double)q_scale[q] * (double)w_scale[r];
         const double dt = (double)q_norm[q] + (double)w_norm[r] - 2.0 * s;
         const double lb = lower_bound(dt, q_nb[q], w_nb[r], q_db[q], w_db[r]);
-        ent[e] = __float_as_uint((float)lb * (1.0f - 1e-6f));  // rounded down, >= 0
+        const double ub = upper_bound(dt, q_nb[q], w_nb[r], q_db[q], w_db[r]);
+        // both bounds as halves, rounded outward: upper << 16 | lower
+        ent[e] = half_up((float)(ub * (1.0 + 1e-7))) << 16 | half_down((float)(lb * (1.0 - 1e-7)));
       }
       __syncthreads();
     }
-    // candidates outside the window: bound 0 (always re-ranked or evaluated)
+    // candidates outside the window: bounds 0 and +inf (always evaluated)
     for (uint32_t e = tid; e < npairs; e += kThreads)
-      if (ent[e] & kPending) ent[e] = 0u;
+      if (ent[e] & kPending) ent[e] = 0x7C00u << 16;
     __syncthreads();
 
-    // choose, per query, the four smallest bounds and the fifth bound
+    // per query the second smallest upper bound U2: two candidates lie at
+    // or below it, so one whose lower bound exceeds U2 is neither best nor
+    // second
     if (tid < T.count && q_in[tid]) {
       const int q = tid;
-      float bd[kReRank + 1];
-      uint32_t be[kReRank + 1];
-      #pragma unroll
-      for (int u = 0; u <= kReRank; ++u) {
-        bd[u] = __builtin_inff();
-        be[u] = 0xFFFFFFFFu;
-      }
+      float u1 = __builtin_inff(), u2 = __builtin_inff();
       for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) {
-        float d = __uint_as_float(ent[e]);
-        uint32_t ee = e;
-        #pragma unroll
-        for (int u = 0; u <= kReRank; ++u) {
-          if (d < bd[u]) {
-            const float td = bd[u];
-            const uint32_t te = be[u];
-            bd[u] = d;
-            be[u] = ee;
-            d = td;
-            ee = te;
-          }
+        const float ub = half_value(ent[e] >> 16);
+        if (ub < u1) {
+          u2 = u1;
+          u1 = ub;
+        } else if (ub < u2) {
+          u2 = ub;
         }
       }
-      #pragma unroll
-      for (int u = 0; u < kReRank; ++u) pick[q][u] = be[u];
-      lb5[q] = bd[kReRank];
+      lb5[q] = u2;
     }
     __syncthreads();
-    // exact canonical distances of the picks: thread = (query, pick)
-    {
-      const int q = tid >> 2, u = tid & 3;
-      float d = __builtin_inff();
-      if (q < T.count && q_in[q] && pick[q][u] != 0xFFFFFFFFu) {
-        const int32_t j = A.cols[q_o0[q] + (pick[q][u] - q_off[q])];
-        pick_j[q][u] = j;
-        d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
-                           reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
-      }
-      pick_d[q][u] = d;
+    // every candidate within U2 of its row is listed (entry indices, in the
+    // query rows' area, dead since the last MFMA), then all threads take the
+    // list in turn for its exact canonical distances; a result replaces its
+    // entry with the distance's bits and the top bit set
+    uint16_t* todo = reinterpret_cast<uint16_t*>(qrows);
+    uint32_t mine = 0;
+    for (uint32_t e = tid; e < npairs; e += kThreads)
+      mine += half_value(ent[e]) <= lb5[entry_query(q_off, e)] ? 1u : 0u;
+    uint32_t incl = mine;
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (lane == kWave - 1) wave_total[wave] = incl;
+    __syncthreads();
+    uint32_t pos = incl - mine, nexact = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      pos += w < wave ? wave_total[w] : 0u;
+      nexact += wave_total[w];
+    }
+    for (uint32_t e = tid; e < npairs; e += kThreads)
+      if (half_value(ent[e]) <= lb5[entry_query(q_off, e)]) todo[pos++] = (uint16_t)e;
+    __syncthreads();
+    for (uint32_t k = tid; k < nexact; k += kThreads) {
+      const uint32_t e = todo[k];
+      const uint32_t q = entry_query(q_off, e);
+      const int32_t j = A.cols[q_o0[q] + (e - q_off[q])];
+      const float d = exact_distance(reinterpret_cast<const float4*>(A.desc1_f32) + q_i[q] * 32,
+                                     reinterpret_cast<const float4*>(A.desc2_f32) + (kb + j) * 32);
+      ent[e] = __float_as_uint(d) | 0x80000000u;
     }
     __syncthreads();
     if (tid < T.count && q_in[tid]) {
       const int q = tid;
       Top2 t;
-      #pragma unroll
-      for (int u = 0; u < kReRank; ++u)
-        if (pick[q][u] != 0xFFFFFFFFu) t.insert(pick_d[q][u], pick_j[q][u]);
-      const uint32_t k = q_k[q];
-      // certified when every candidate left out has a bound above the second
-      const bool ok = k <= (uint32_t)kReRank || lb5[q] > t.sd;
-      if (ok) {
-        write_match(A, q_i[q], t, false);
-      } else {
-        const uint32_t slot = atomicAdd(&n_fallback, 1u);
-        fallback_q[slot] = (uint16_t)q;
+      for (uint32_t e = q_off[q]; e < q_off[q + 1]; ++e) {
+        const uint32_t x = ent[e];
+        if (x & 0x80000000u) t.insert(__uint_as_float(x & 0x7FFFFFFFu), A.cols[q_o0[q] + (e - q_off[q])]);
       }
+      write_match(A, q_i[q], t, false);
     }
+    if (A.match_stats && tid == 0 && nexact)
+      atomicAdd(&A.match_stats[3], (unsigned long long)nexact);
     __syncthreads();
     if (A.match_stats && tid == 0) {
       uint32_t longs = 0, reranked = 0;
@@ -322,19 +323,12 @@ __global__ __launch_bounds__(kThreads) void k_match_window_mfma(MatchArgs A) {
         reranked += q_in[q] && q_k[q] > 0;
       }
       atomicAdd(&A.match_stats[0], (unsigned long long)reranked);
-      atomicAdd(&A.match_stats[1], (unsigned long long)n_fallback);
       atomicAdd(&A.match_stats[2], (unsigned long long)longs);
     }
     // fallback and long rows: every candidate exactly, one wavefront per query
-    const uint32_t nfb = n_fallback;
-    for (int t0 = wave; t0 < T.count + (int)nfb; t0 += kWaves) {
-      int q;
-      if (t0 < (int)nfb) {
-        q = fallback_q[t0];
-      } else {
-        q = t0 - (int)nfb;
-        if (q_in[q]) continue;
-      }
+    for (int t0 = wave; t0 < T.count; t0 += kWaves) {
+      const int q = t0;
+      if (q_in[q]) continue;
       const int64_t i = q_i[q];
       if (lane < 32) qdesc[wave][lane] = reinterpret_cast<const float4*>(A.desc1_f32)[i * 32 + lane];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

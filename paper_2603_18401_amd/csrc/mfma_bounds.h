@@ -4,6 +4,8 @@
 // wide-row MFMA kernels.
 #pragma once
 
+#include <hip/hip_fp16.h>
+
 #include "device_common.h"
 #include "match_common.h"
 
@@ -98,6 +100,34 @@ __device__ __forceinline__ double lower_bound(double dt, double nq, double nw, d
   const double root = sqrt(fmax(dt - em, 0.0));
   const double r = fmax(root - (dq + dw), 0.0);
   return (1.0 - 1e-5) * r * r;
+}
+
+// Upper bound on the exact canonical FP32 distance (the counterpart of
+// lower_bound): |q - w| <= sqrt(dt + em) + dq + dw, canonical <= (1 + 1e-5) |q - w|^2.
+__device__ __forceinline__ double upper_bound(double dt, double nq, double nw, double dq,
+                                              double dw) {
+  const double s = nq + nw;
+  const double em = 3e-5 * s * s;
+  const double r = sqrt(fmax(dt + em, 0.0)) + (dq + dw);
+  return (1.0 + 1e-5) * r * r;
+}
+
+// Non-negative float to the nearest IEEE half at or below it (down) or at or
+// above it (up); NaN gives 0 (down) and +inf (up).
+__device__ __forceinline__ uint32_t half_down(float x) {
+  if (!(x > 0.0f)) return 0u;
+  uint32_t h = (uint32_t)__half_as_ushort(__float2half_rn(x));
+  if (__half2float(__ushort_as_half((unsigned short)h)) > x) h -= 1u;
+  return h;
+}
+__device__ __forceinline__ uint32_t half_up(float x) {
+  if (!(x >= 0.0f)) return x < 0.0f ? 0u : 0x7C00u;
+  uint32_t h = (uint32_t)__half_as_ushort(__float2half_rn(x));
+  if (h < 0x7C00u && __half2float(__ushort_as_half((unsigned short)h)) < x) h += 1u;
+  return h;
+}
+__device__ __forceinline__ float half_value(uint32_t h) {
+  return __half2float(__ushort_as_half((unsigned short)(h & 0xFFFFu)));
 }
 
 }  // namespace epm

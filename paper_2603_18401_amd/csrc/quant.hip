@@ -74,7 +74,56 @@ __global__ __launch_bounds__(kThreads) void k_quant_fp8(const float* __restrict_
   }
 }
 
+// Norm of each row's rounding error, err[r] >= |x_r - dequant(code_r)|
+// (FP64 sums, inflated by 1e-6 for their rounding): the tight per-row term
+// that the reduced-precision bounds can use in place of the format's
+// worst case.  One wavefront per row.
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_round_err(const float* __restrict__ src,
+                                                        int64_t rows, int dim,
+                                                        const void* __restrict__ codes,
+                                                        const float* __restrict__ scale,
+                                                        float* __restrict__ err) {
+  const int lane = lane_id();
+  for (int64_t r = (int64_t)blockIdx.x * kWaves + wave_id(); r < rows;
+       r += (int64_t)gridDim.x * kWaves) {
+    double acc = 0.0;
+    const double s = FMT == 1 ? (double)scale[r] : 1.0;
+    for (int k = lane; k < dim; k += kWave) {
+      double y;
+      if (FMT == 0) {
+        y = (double)__uint_as_float((uint32_t)static_cast<const uint16_t*>(codes)[r * dim + k] << 16);
+      } else {
+        const uint32_t c = static_cast<const uint8_t*>(codes)[r * dim + k];
+        const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+        double v = e == 0 ? (double)m * 0.001953125
+                          : (double)__uint_as_float(((e + 120u) << 23) | (m << 20));
+        y = ((c & 0x80u) ? -v : v) * s;
+      }
+      const double d = (double)src[r * dim + k] - y;
+      acc += d * d;
+    }
+    #pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) err[r] = (float)(sqrt(acc) * (1.0 + 1e-6)) + 1e-30f;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_round_err(const float* src, int64_t rows, int dim, int fmt, const void* codes,
+                            const float* scale, float* err, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  int64_t blocks = (rows + kWaves - 1) / kWaves;
+  if (blocks > 65536) blocks = 65536;
+  if (fmt == 0)
+    hipLaunchKernelGGL((k_round_err<0>), dim3((unsigned)blocks), dim3(kThreads), 0, s, src, rows,
+                       dim, codes, scale, err);
+  else
+    hipLaunchKernelGGL((k_round_err<1>), dim3((unsigned)blocks), dim3(kThreads), 0, s, src, rows,
+                       dim, codes, scale, err);
+  return hipGetLastError();
+}
 
 hipError_t launch_quantize(const float* src, int64_t rows, int dim, int fmt, void* dst,
                            float* scale, hipStream_t s) {

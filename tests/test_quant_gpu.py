@@ -43,3 +43,30 @@ def test_fp8_codes_and_scales_equal_the_generator():
     c = codes.cpu().numpy()[901]
     assert c[1] == 0x38 and c[2] == 0x3A and c[3] == 0xB8
     assert np.all(codes.cpu().numpy()[902] == 0x80)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_rounding_error_bounds_the_dequantisation_error(fmt):
+    """epm_rounding_error: a bound on |x - dequant(x^)| per row, within 1e-5
+    (relative) of the exact norm, never below it."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(41)
+    x = synth.pairs._unit_rows(rng.standard_normal((3000, 128)))
+    x[7] = 0.0  # an all-zero row
+    if fmt == "bf16":
+        codes = synth.f32_to_bf16(x)
+        deq = synth.bf16_to_f32(codes).astype(np.float64)
+        err = E.rounding_error(torch.from_numpy(x).to(dev),
+                               torch.from_numpy(codes.view(np.int16)).to(dev), "bf16")
+    else:
+        codes, scale = synth.f32_to_fp8_e4m3(x)
+        deq = synth.fp8_e4m3_to_f32(codes) * scale[:, None].astype(np.float64)
+        err = E.rounding_error(torch.from_numpy(x).to(dev), torch.from_numpy(codes).to(dev),
+                               "fp8", scale=torch.from_numpy(scale).to(dev))
+    exact = np.linalg.norm(x.astype(np.float64) - deq, axis=1)
+    got = err.cpu().numpy().astype(np.float64)
+    assert (got >= exact).all()
+    assert (got <= exact * (1 + 1e-5) + 1e-29).all()
+    assert got[7] < 1e-20
