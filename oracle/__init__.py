@@ -26,6 +26,9 @@ Parity status of each function (pins are the tests in tests/test_oracle*.py):
                     with the transposed matrix; the cross-check on a hand case.
   gms.*             pinned: hand-built motions, the threshold boundary, the
                     tie rule, invariance under the query order.
+  pose_eps.*        pinned: zero covariance, the rectified-stereo closed form,
+                    sqrt(Sigma) scaling, the spread under sampled poses, hand
+                    cases of the reverse epipolar segment.
 """
 
 import ctypes
