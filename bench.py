@@ -870,6 +870,52 @@ def noise_workload(args):
         sel = np.isin(qpair, [k for k, v in enumerate(lv) if v == L])
         per.append({"level": L, "candidate_recall": round(float(cand_hit[sel].mean()), 5),
                     "match_recall": round(float(match_hit[sel].mean()), 5)})
+    # ---- per-keypoint tolerance from the pose covariance of each level
+    # (epm_pose_eps: eps0 2 px + 3 standard deviations of the first-order
+    # spread of the point-line distance) against fixed tolerances: candidate
+    # recall of the true correspondences and candidates per query, one draw
+    # of each pair per level
+    def recall_kbar(eps2=None, eps=0.0, sel=None):
+        kp1 = torch.from_numpy(np.concatenate([pairs[k].kp1 for k in sel])).to(dev)
+        kp2 = torch.from_numpy(np.concatenate([pairs[k].kp2 for k in sel])).to(dev)
+        idx = E.Index([specs[k] for k in sel], kp2, eps2=eps2, eps=eps)
+        o, c = idx.query(kp1)
+        idx.close()
+        m = len(sel) * pairs[0].m
+        r = torch.repeat_interleave(torch.arange(m, device=dev), o[1:] - o[:-1])
+        kk = r * (n2 + 1) + c.to(torch.int64)
+        gs = torch.from_numpy(np.concatenate([pairs[k].gt12 for k in sel]).astype(np.int64)).to(dev)
+        tq = torch.nonzero(gs >= 0).flatten()
+        wk = tq * (n2 + 1) + gs[tq]
+        ps = torch.searchsorted(kk, wk).clamp(max=max(kk.numel() - 1, 0))
+        rec = float((kk[ps] == wk).float().mean().item()) if kk.numel() else 0.0
+        return round(rec, 5), round(float(o[-1].item()) / m, 2)
+
+    pose_cmp = []
+    for L in levels[1:]:
+        sel = [k for k, v in enumerate(lv) if v == L][::2]  # one draw per pair
+        priors = []
+        for k in sel:
+            b_i = 0 if pairs[k] is bases[0] else 1
+            R, t = synth.perturbed_pose(pairs[k], L, 9000 + 100 * b_i + 10 * int(L * 10) + 0)
+            # scene depths are 5-15 m in camera 1; 4-16 m bounds them in camera 2
+            priors.append(E.PosePrior(pairs[k].K1, pairs[k].K2, R, t, synth.noise_covariance(L),
+                                      pairs[k].W, pairs[k].H, 4.0, 16.0))
+        kp2s = torch.from_numpy(np.concatenate([pairs[k].kp2 for k in sel])).to(dev)
+        adaptive = []
+        for ks in (1.0, 2.0, 3.0):
+            e2 = E.pose_eps([specs[k] for k in sel], priors, kp2s, 2.0, ks, 4000.0)
+            rec, kb = recall_kbar(eps2=e2, sel=sel)
+            adaptive.append({"k_sigma": ks, "candidate_recall": rec, "kbar": kb,
+                             "eps_median": round(float(e2.median().item()), 1),
+                             "eps_max": round(float(e2.max().item()), 1)})
+        fixed = []
+        for ef in (50.0, 100.0, 200.0, 400.0, 800.0):
+            fr, fk = recall_kbar(eps=ef, sel=sel)
+            fixed.append({"eps": ef, "candidate_recall": fr, "kbar": fk})
+        pose_cmp.append({"level": L, "pose_eps": adaptive, "fixed": fixed})
+        print(f"noise level {L}: pose eps {adaptive}; fixed {fixed}", file=sys.stderr, flush=True)
+
     line = {"metric": METRIC, "value": round(N1 / sec, 1), "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -878,7 +924,7 @@ def noise_workload(args):
                                    "sideways+forward x noise levels {0,1,2,3.3,4} x 2 draws, "
                                    "eps 200 px", "queries_per_step": N1,
                        "candidates_per_step": nnz, "kbar": round(nnz / N1, 2)},
-            "recall_by_level": per}
+            "recall_by_level": per, "pose_eps_vs_fixed": pose_cmp}
     print(json.dumps(line), flush=True)
 
 

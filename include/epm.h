@@ -520,6 +520,52 @@ epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const 
                                const int32_t* best_idx, float* residual, int64_t* feat_index,
                                hipStream_t stream);
 
+/*
+ * Per-keypoint tolerance from the uncertainty of the relative pose (the
+ * noise-sensitivity setting of the paper's experiments, Sec. 5; per-keypoint
+ * tolerances are its Sec. 6 future work).  For each pair the caller gives the
+ * estimated pose and the covariance of theta = (w, tau) around it, with
+ * R(theta) = Exp([w]x) R and t(theta) = t + tau (w in radians).  The signed
+ * distance of Eq. 3, d = x2^T F(theta) x1 / |(F(theta) x1)_12| with
+ * F(theta) = K2^-T [t(theta)]x R(theta) K1^-1 (Eq. 1), spreads to first order
+ * by s^2 = g^T Sigma g, g = grad_theta d at the estimate.  An image-2
+ * keypoint's partner lies on its reverse epipolar line F^T x2 inside image 1
+ * ([0, w1] x [0, h1]).  With a scene depth range (0 < zmin < zmax, zmax may
+ * be +inf; camera-2 depths) the partners considered are the image-1
+ * projections K1 R^T (K2^-1 x2 - rho t) at 16 inverse depths rho evenly spaced
+ * over [1/zmax, 1/zmin], those in front of camera 1 and inside image 1;
+ * without one (zmin = 0), or when none of those is inside image 1, 16 evenly
+ * spaced points of the segment (the line's point nearest the image centre
+ * when it misses the image).  Points where (F x1)_12 vanishes are skipped.
+ * The largest s over the points gives
+ *     eps2[j] = min(eps0 + k_sigma * max s, eps_max)   (pixels, FP64, rounded).
+ * The result feeds eps2 of epm_build_intervals, where every candidate is
+ * still decided by the exact test of Eq. 3 at that tolerance.
+ *
+ * pairs: slices as in epm_build_intervals (F itself is taken from the
+ * priors); priors: [num_pairs]; kp2_xy [N2][2]; eps2 [N2] output.  Requires
+ * eps0 >= 0, k_sigma >= 0, eps_max >= eps0 finite, zmin = 0 or finite with
+ * zmax > zmin.  workspace: at least
+ * epm_pose_eps_workspace_bytes(num_pairs), 256-byte aligned.  Synchronises
+ * the host with `stream` once (upload of the per-pair table).  Errors:
+ * EPM_ERR_ARG, EPM_ERR_DEGENERATE_F (singular intrinsics, non-finite pose or
+ * covariance, F = 0), EPM_ERR_WORKSPACE, EPM_ERR_HIP.
+ */
+typedef struct {
+  double K1[9], K2[9];  /* intrinsics of the two cameras, row-major         */
+  double R[9];          /* estimated relative rotation, X2 = R X1 + t (Eq. 1) */
+  double t[3];          /* estimated translation                           */
+  double cov[36];       /* 6 x 6 covariance of (w, tau), row-major          */
+  int32_t w1, h1;       /* image-1 size                                     */
+  double zmin, zmax;    /* scene depth range in camera 2 (m); zmin = 0: none */
+} epm_pose_prior;
+
+size_t epm_pose_eps_workspace_bytes(int32_t num_pairs);
+epm_status epm_pose_eps(const epm_pair* pairs, const epm_pose_prior* priors, int32_t num_pairs,
+                        const float* kp2_xy, float eps0, float k_sigma, float eps_max,
+                        float* eps2, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
 /* Counters of the last epm_query_candidates call on an index. */
 typedef struct {
   int64_t queries;          /* image-1 queries                                       */

@@ -18,6 +18,14 @@ per-keypoint tolerance the GPU library derives from a pose covariance:
             points of that segment (one point, the line's point nearest the
             image centre, when the line misses the image; points where
             (F x1)_12 vanishes are skipped);
+  depths    with a scene depth range 0 < zmin < zmax <= inf in camera 2
+            given, the partner is instead the projection into image 1 of the
+            3-D point seen at x2 with depth Z in that range:
+            X1 ~ R0^T (K2^-1 x2 - rho t0), rho = 1 / Z, at S = 16 inverse
+            depths evenly spaced from 1 / zmax to 1 / zmin, keeping those in
+            front of camera 1 and inside image 1 (the segment's spread grows
+            without bound towards the epipole, where the implied depth
+            vanishes); a keypoint with no such point takes the segment;
   tolerance eps_j = min(eps0 + k sigma_j, eps_max).
 
 Parity status (pins are tests/test_oracle_pose_eps.py):
@@ -25,7 +33,10 @@ Parity status (pins are tests/test_oracle_pose_eps.py):
                   stereo with only the translation's y uncertain has the
                   closed form sigma = sigma_ty * max(|x'|, |W1 - x'|) (the
                   disparity to the ends of the scanline); sigma scales as
-                  sqrt(Sigma); the segment of a hand case.
+                  sqrt(Sigma); the segment of a hand case; with a depth
+                  range, rectified stereo has sigma = sigma_ty * f / zmin
+                  (the largest disparity) and the sample points are the
+                  projections of points at known depths.
 """
 
 import numpy as np
@@ -113,13 +124,36 @@ def samples(line, W1, H1, S=SAMPLES):
     return [(px + (qx - px) * s / (S - 1), py + (qy - py) * s / (S - 1)) for s in range(S)]
 
 
-def sigma(x2, K1, K2, R0, t0, cov, W1, H1):
+def depth_samples(x2, K1, K2, R0, t0, W1, H1, zmin, zmax, S=SAMPLES):
+    """Image-1 projections of the 3-D points seen at image-2 pixel x2 at S
+    inverse depths evenly spaced over [1 / zmax, 1 / zmin] (camera-2 depths,
+    X2 = R0 X1 + t0), those in front of camera 1 and inside [0, W1] x [0, H1]."""
+    ray = np.linalg.inv(K2) @ np.array([x2[0], x2[1], 1.0])
+    lo, hi = 1.0 / zmax, 1.0 / zmin
+    out = []
+    for s in range(S):
+        rho = lo + (hi - lo) * s / (S - 1)
+        X1 = R0.T @ (ray - rho * np.asarray(t0, dtype=np.float64))  # X1 / Z
+        if not X1[2] > 0.0:
+            continue
+        p = K1 @ X1
+        x, y = p[0] / p[2], p[1] / p[2]
+        if 0.0 <= x <= W1 and 0.0 <= y <= H1:
+            out.append((x, y))
+    return out
+
+
+def sigma(x2, K1, K2, R0, t0, cov, W1, H1, zmin=0.0, zmax=np.inf):
     """Largest first-order spread of the distance of image-2 keypoint x2 over
-    its reverse epipolar segment in image 1."""
+    its possible partners in image 1 (the reverse epipolar segment, or the
+    points of the depth range when zmin > 0)."""
     F0 = F_of(np.zeros(6), K1, K2, R0, t0)
     line = F0.T @ np.array([x2[0], x2[1], 1.0])
     best = 0.0
-    for x1 in samples(line, W1, H1):
+    pts = depth_samples(x2, K1, K2, R0, t0, W1, H1, zmin, zmax) if zmin > 0.0 else []
+    if not pts:
+        pts = samples(line, W1, H1)
+    for x1 in pts:
         l = F0 @ np.array([x1[0], x1[1], 1.0])
         if not np.hypot(l[0], l[1]) > 1e-12 * np.abs(F0).max():
             continue
@@ -128,11 +162,11 @@ def sigma(x2, K1, K2, R0, t0, cov, W1, H1):
     return np.sqrt(best)
 
 
-def pose_eps(kp2, K1, K2, R0, t0, cov, W1, H1, eps0, k, eps_max):
+def pose_eps(kp2, K1, K2, R0, t0, cov, W1, H1, eps0, k, eps_max, zmin=0.0, zmax=np.inf):
     """Tolerance of every image-2 keypoint (pixels), FP64."""
     kp2 = np.asarray(kp2, dtype=np.float64).reshape(-1, 2)
     cov = np.asarray(cov, dtype=np.float64).reshape(6, 6)
     out = np.empty(len(kp2))
     for j, x2 in enumerate(kp2):
-        out[j] = min(eps0 + k * sigma(x2, K1, K2, R0, t0, cov, W1, H1), eps_max)
+        out[j] = min(eps0 + k * sigma(x2, K1, K2, R0, t0, cov, W1, H1, zmin, zmax), eps_max)
     return out

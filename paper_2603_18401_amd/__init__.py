@@ -43,7 +43,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
            "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc",
-           "epm_query_match_bf16", "epm_descriptor_distances", "epm_rounding_error"]
+           "epm_query_match_bf16", "epm_descriptor_distances", "epm_rounding_error",
+           "epm_pose_eps_workspace_bytes", "epm_pose_eps"]
 
 
 class EpmError(RuntimeError):
@@ -73,6 +74,13 @@ class _MatchOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("check_capacity", ctypes.c_int32),
                 ("col_capacity", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4),
                 ("qerr1", ctypes.c_void_p), ("qerr2", ctypes.c_void_p)]
+
+
+class _PosePrior(ctypes.Structure):
+    _fields_ = [("K1", ctypes.c_double * 9), ("K2", ctypes.c_double * 9),
+                ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("cov", ctypes.c_double * 36), ("w1", ctypes.c_int32), ("h1", ctypes.c_int32),
+                ("zmin", ctypes.c_double), ("zmax", ctypes.c_double)]
 
 
 class _Sched(ctypes.Structure):
@@ -209,6 +217,10 @@ def load_library(path=None):
     lib.epm_descriptor_distances.restype = ctypes.c_int
     lib.epm_rounding_error.argtypes = [V, i64, i32, ctypes.c_int, V, V, V, V]
     lib.epm_rounding_error.restype = ctypes.c_int
+    lib.epm_pose_eps_workspace_bytes.argtypes = [i32]
+    lib.epm_pose_eps_workspace_bytes.restype = ctypes.c_size_t
+    lib.epm_pose_eps.argtypes = [P, P, i32, V, f32, f32, f32, V, V, ctypes.c_size_t, V]
+    lib.epm_pose_eps.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -694,6 +706,44 @@ def quantize(desc, dtype, stream=None):
                           _stream(torch, desc.device, stream))
     _check(st, "epm_quantize")
     return (out, scale) if dtype == "fp8" else out
+
+
+class PosePrior:
+    """Estimated relative pose of one pair (X2 = R X1 + t), its intrinsics, the
+    6 x 6 covariance of (rotation vector, translation), the image-1 size and
+    optionally the scene's depth range in camera 2 (zmin = 0: none)."""
+
+    def __init__(self, K1, K2, R, t, cov, w1, h1, zmin=0.0, zmax=float("inf")):
+        self.K1 = np.asarray(K1, np.float64).reshape(9)
+        self.K2 = np.asarray(K2, np.float64).reshape(9)
+        self.R = np.asarray(R, np.float64).reshape(9)
+        self.t = np.asarray(t, np.float64).reshape(3)
+        self.cov = np.asarray(cov, np.float64).reshape(36)
+        self.w1, self.h1 = int(w1), int(h1)
+        self.zmin, self.zmax = float(zmin), float(zmax)
+
+
+def pose_eps(pairs, priors, kp2, eps0, k_sigma, eps_max, stream=None):
+    """epm_pose_eps: per image-2 keypoint tolerance (float32 [N2]) from the
+    pose covariance of every pair (a list of PosePrior)."""
+    torch = _torch()
+    lib = load_library()
+    specs = list(pairs)
+    arr, _, n2 = _pair_array(specs)
+    pri = (_PosePrior * len(specs))()
+    for c, p in zip(pri, priors):
+        c.K1[:], c.K2[:], c.R[:] = list(p.K1), list(p.K2), list(p.R)
+        c.t[:], c.cov[:] = list(p.t), list(p.cov)
+        c.w1, c.h1 = p.w1, p.h1
+        c.zmin, c.zmax = p.zmin, p.zmax
+    ws = torch.empty(lib.epm_pose_eps_workspace_bytes(len(specs)), dtype=torch.uint8,
+                     device=kp2.device)
+    eps2 = torch.empty(n2, dtype=torch.float32, device=kp2.device)
+    st = lib.epm_pose_eps(arr, pri, len(specs), _dptr(kp2), float(eps0), float(k_sigma),
+                          float(eps_max), _dptr(eps2), _dptr(ws), ws.numel(),
+                          _stream(torch, kp2.device, stream))
+    _check(st, "epm_pose_eps")
+    return eps2
 
 
 def rounding_error(src, codes, dtype, scale=None, stream=None):

@@ -1238,6 +1238,128 @@ epm_status epm_eps_features(const epm_pair* pairs, int32_t num_pairs, const floa
   return EPM_OK;
 }
 
+namespace {
+
+void mat3_mul(const double* A, const double* B, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+void skew3(const double* v, double* S) {
+  S[0] = 0.0;   S[1] = -v[2]; S[2] = v[1];
+  S[3] = v[2];  S[4] = 0.0;   S[5] = -v[0];
+  S[6] = -v[1]; S[7] = v[0];  S[8] = 0.0;
+}
+
+bool inv3(const double* M, double* I) {
+  const double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                     M[2] * (M[3] * M[7] - M[4] * M[6]);
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  I[0] = (M[4] * M[8] - M[5] * M[7]) / det;
+  I[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+  I[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+  I[3] = (M[5] * M[6] - M[3] * M[8]) / det;
+  I[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+  I[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+  I[6] = (M[3] * M[7] - M[4] * M[6]) / det;
+  I[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+  I[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+  return true;
+}
+
+// F = K2^-T [t]x R K1^-1 (Eq. 1) and its derivatives with respect to the
+// rotation vector w (R = Exp([w]x) R0: dR/dw_k = [e_k]x R0) and to t.
+bool pose_pair(const epm_pose_prior& pr, PosePair& P) {
+  double K1i[9], K2i[9], K2iT[9];
+  if (!inv3(pr.K1, K1i) || !inv3(pr.K2, K2i)) return false;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) K2iT[3 * r + c] = K2i[3 * c + r];
+  double Tx[9], RK[9], T1[9];
+  skew3(pr.t, Tx);
+  mat3_mul(pr.R, K1i, RK);  // R K1^-1
+  mat3_mul(K2iT, Tx, T1);   // K2^-T [t]x
+  mat3_mul(T1, RK, P.F0);
+  for (int k = 0; k < 3; ++k) {
+    double e[3] = {0.0, 0.0, 0.0}, Ek[9], A[9], B[9];
+    e[k] = 1.0;
+    skew3(e, Ek);
+    // rotation: K2^-T [t]x [e_k]x R K1^-1
+    mat3_mul(T1, Ek, A);
+    mat3_mul(A, RK, P.dF[k]);
+    // translation: K2^-T [e_k]x R K1^-1
+    mat3_mul(K2iT, Ek, B);
+    mat3_mul(B, RK, P.dF[3 + k]);
+  }
+  for (int k = 0; k < 36; ++k) {
+    if (!std::isfinite(pr.cov[k])) return false;
+    P.cov[k] = pr.cov[k];
+  }
+  P.w1 = pr.w1;
+  P.h1 = pr.h1;
+  for (int k = 0; k < 9; ++k) {
+    P.K1[k] = pr.K1[k];
+    P.K2i[k] = K2i[k];
+    P.Rt[k] = pr.R[3 * (k % 3) + k / 3];
+  }
+  for (int k = 0; k < 3; ++k) P.t[k] = pr.t[k];
+  P.rho_lo = P.rho_hi = 0.0;
+  if (pr.zmin > 0.0) {
+    P.rho_hi = 1.0 / pr.zmin;
+    P.rho_lo = std::isinf(pr.zmax) ? 0.0 : 1.0 / pr.zmax;
+  }
+  P.fmax = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(P.F0[k])) return false;
+    P.fmax = std::fmax(P.fmax, std::fabs(P.F0[k]));
+  }
+  return P.fmax > 0.0;
+}
+
+}  // namespace
+
+size_t epm_pose_eps_workspace_bytes(int32_t num_pairs) {
+  if (num_pairs < 0) return 0;
+  return align_up(sizeof(PosePair) * (size_t)num_pairs) +
+         align_up(sizeof(int64_t) * ((size_t)num_pairs + 1));
+}
+
+epm_status epm_pose_eps(const epm_pair* pairs, const epm_pose_prior* priors, int32_t num_pairs,
+                        const float* kp2_xy, float eps0, float k_sigma, float eps_max,
+                        float* eps2, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  int64_t n1, n2;
+  if (!validate_pairs(pairs, num_pairs, &n1, &n2) || !priors) return EPM_ERR_ARG;
+  if (n2 > 0 && (!kp2_xy || !eps2)) return EPM_ERR_ARG;
+  if (!(eps0 >= 0.0f) || !(k_sigma >= 0.0f) || !(eps_max >= eps0) || !std::isfinite(eps_max))
+    return EPM_ERR_ARG;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) ||
+      workspace_bytes < epm_pose_eps_workspace_bytes(num_pairs))
+    return EPM_ERR_WORKSPACE;
+  const size_t off_k = align_up(sizeof(PosePair) * (size_t)num_pairs);
+  std::vector<char> head(off_k + sizeof(int64_t) * ((size_t)num_pairs + 1), 0);
+  PosePair* pp = reinterpret_cast<PosePair*>(head.data());
+  int64_t* ks = reinterpret_cast<int64_t*>(head.data() + off_k);
+  for (int p = 0; p < num_pairs; ++p) {
+    if (priors[p].w1 <= 0 || priors[p].h1 <= 0) return EPM_ERR_ARG;
+    const double zmin = priors[p].zmin, zmax = priors[p].zmax;
+    if (!(zmin == 0.0 || (zmin > 0.0 && std::isfinite(zmin) && zmax > zmin)))
+      return EPM_ERR_ARG;
+    if (!pose_pair(priors[p], pp[p])) return EPM_ERR_DEGENERATE_F;
+    ks[p] = pairs[p].k_begin;
+  }
+  ks[num_pairs] = n2;
+  if (n2 == 0) return EPM_OK;
+  char* ws = static_cast<char*>(workspace);
+  EPM_HIP(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, stream));
+  EPM_HIP(launch_pose_eps(reinterpret_cast<const PosePair*>(ws),
+                          reinterpret_cast<const int64_t*>(ws + off_k), num_pairs, n2, kp2_xy,
+                          eps0, k_sigma, eps_max, eps2, stream));
+  // the host table must outlive the copy
+  EPM_HIP(hipStreamSynchronize(stream));
+  return EPM_OK;
+}
+
 epm_status epm_eps_infer(const float* features, int64_t n, const float* params, float* eps2,
                          hipStream_t stream) {
   if (n < 0) return EPM_ERR_ARG;

@@ -274,6 +274,24 @@ hipError_t launch_residuals(const PairDev* pairs, const int64_t* qstart, int num
                             int64_t n1, const float* kp1, const float* kp2, const int32_t* best,
                             float* residual, int64_t* feat_index, hipStream_t s);
 
+// Pose-uncertainty tolerance (see pose_eps.hip): per pair F, the six
+// derivatives of F with respect to the pose (rotation vector, translation),
+// their covariance and the image-1 size.
+struct PosePair {
+  double F0[9];
+  double dF[6][9];
+  double cov[36];
+  double w1, h1;
+  double fmax;  // largest |F0| entry
+  // depth range: image-1 partners of x2 are K1 R^T (K2^-1 x2 - rho t) for
+  // inverse depths rho in [rho_lo, rho_hi]; rho_hi = 0 when no range is given
+  double K1[9], K2i[9], Rt[9], t[3];
+  double rho_lo, rho_hi;
+};
+hipError_t launch_pose_eps(const PosePair* pairs, const int64_t* kstart, int num_pairs,
+                           int64_t n2, const float* kp2, float eps0, float k_sigma,
+                           float eps_max, float* eps2, hipStream_t s);
+
 // GMS validation (see gms.hip).
 constexpr int kGmsMaxGrid = 32;
 constexpr int kGmsMaxCells = kGmsMaxGrid * kGmsMaxGrid;

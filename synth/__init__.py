@@ -21,7 +21,9 @@ from .pairs import (  # noqa: F401
     fundamental_from_cameras,
     intrinsics,
     make_pair,
+    noise_covariance,
     perturbed_F,
+    perturbed_pose,
     rot_axis_angle,
     skew,
 )

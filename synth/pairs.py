@@ -368,16 +368,30 @@ def batch_pairs(pairs):
     return b
 
 
-def perturbed_F(pair, level, seed):
-    """F from a relative pose perturbed at a noise level (the paper's noise
+def perturbed_pose(pair, level, seed):
+    """A relative pose perturbed at a noise level (the paper's noise
     sensitivity experiment, Sec. 5): level 1 rotates by angles U(-1, 1) deg
-    about each axis and moves the translation by U(-0.25, 0.25) m per
-    component; level L scales both ranges by L.  The keypoints keep the true
-    geometry."""
+    about each axis (applied before the true rotation) and moves the
+    translation by U(-0.25, 0.25) m per component; level L scales both ranges
+    by L.  Returns (R, t)."""
     rng = _rng(seed)
     ang = np.deg2rad(rng.uniform(-1.0, 1.0, 3) * level)
     Rn = (rot_axis_angle([1.0, 0.0, 0.0], ang[0]) @ rot_axis_angle([0.0, 1.0, 0.0], ang[1])
           @ rot_axis_angle([0.0, 0.0, 1.0], ang[2]))
-    R = Rn @ pair.R
-    t = pair.t + rng.uniform(-0.25, 0.25, 3) * level
+    return Rn @ pair.R, pair.t + rng.uniform(-0.25, 0.25, 3) * level
+
+
+def perturbed_F(pair, level, seed):
+    """F of perturbed_pose(pair, level, seed); the keypoints keep the true
+    geometry."""
+    R, t = perturbed_pose(pair, level, seed)
     return fundamental_from_cameras(pair.K1, pair.K2, R, t)
+
+
+def noise_covariance(level):
+    """Covariance of the perturbation law of perturbed_pose as (rotation
+    vector, translation), to first order: independent uniforms of half-widths
+    level deg and 0.25 level m, whose variances are a^2 / 3."""
+    r = np.deg2rad(level) ** 2 / 3.0
+    t = (0.25 * level) ** 2 / 3.0
+    return np.diag([r, r, r, t, t, t])

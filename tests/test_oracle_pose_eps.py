@@ -86,3 +86,49 @@ def test_segment_hand_cases():
     # 16 evenly spaced samples including both ends
     s = P.samples((0.0, 1.0, -2.0), 10, 5)
     assert len(s) == 16 and s[0] == (0.0, 2.0) and s[-1] == (10.0, 2.0)
+
+
+def test_depth_range_rectified_stereo_closed_form():
+    """Rectified stereo (f = 500, baseline 1 along x) with a depth range of
+    [4, 16] m: the partner of x2 = (x', y') at depth Z is x1 = x' - f / Z, so
+    sigma = sigma_ty * (largest disparity whose partner is inside image 1).
+    The 16 inverse depths 1/16 + k (1/4 - 1/16) / 15 give disparities
+    31.25 + 6.25 k: x' >= 125 reaches 125; x' = 60 reaches 56.25 (k = 4);
+    x' = 10 has no partner in the image and takes the segment
+    (max(10, 640 - 10) = 630)."""
+    W, H, f = 640, 480, 500.0
+    K = _K(f, W, H)
+    cov = np.zeros((6, 6))
+    cov[4, 4] = 0.03 ** 2
+    kp2 = np.array([[125.0, 17.0], [400.0, 240.0], [639.0, 300.0], [60.0, 5.0], [10.0, 100.0]])
+    eps = P.pose_eps(kp2, K, K, np.eye(3), np.array([1.0, 0.0, 0.0]), cov, W, H, 2.0, 3.0, 1e9,
+                     4.0, 16.0)
+    want = 2.0 + 3.0 * 0.03 * np.array([125.0, 125.0, 125.0, 56.25, 630.0])
+    assert np.allclose(eps, want, rtol=1e-9, atol=1e-9)
+
+
+def test_depth_samples_are_projections_of_points_at_those_depths():
+    """A 3-D point placed in front of both cameras at camera-2 depth
+    Z = 1 / (1/12 + 5 (1/3 - 1/12) / 15) (the sixth of the 16 inverse depths of
+    [3, 12]) projects into image 1 onto one of the sample points of its image-2
+    projection."""
+    K1 = _K(600.0, 800, 600)
+    K2 = _K(650.0, 800, 600)
+    R0 = P.rodrigues(np.array([0.03, -0.2, 0.05]))
+    t0 = np.array([-0.9, 0.1, 0.25])
+    Z = 1.0 / (1.0 / 12.0 + 5.0 * (1.0 / 3.0 - 1.0 / 12.0) / 15.0)
+    X2 = Z * np.array([0.05, -0.04, 1.0])
+    X1 = R0.T @ (X2 - t0)
+    x2 = (K2 @ X2)[:2] / X2[2]
+    x1 = (K1 @ X1)[:2] / X1[2]
+    assert 0 <= x1[0] <= 800 and 0 <= x1[1] <= 600
+    pts = np.array(P.depth_samples(x2, K1, K2, R0, t0, 800, 600, 3.0, 12.0))
+    assert np.min(np.hypot(*(pts - x1).T)) < 1e-9
+    # every sample lies on the reverse epipolar line of x2
+    F0 = P.fundamental(K1, K2, R0, t0)
+    l = F0.T @ np.array([x2[0], x2[1], 1.0])
+    assert np.all(np.abs(pts @ l[:2] + l[2]) / np.hypot(l[0], l[1]) < 1e-9)
+    # an infinite far end: the first sample is the image of the direction
+    inf_pts = P.depth_samples(x2, K1, K2, R0, t0, 800, 600, 3.0, np.inf)
+    d = K1 @ R0.T @ np.linalg.inv(K2) @ np.array([x2[0], x2[1], 1.0])
+    assert np.allclose(inf_pts[0], d[:2] / d[2], atol=1e-9)
