@@ -481,8 +481,9 @@ size_t epm_eps_workspace_bytes(int32_t num_pairs);
 
 /* features [N2][6] float32 for the image-2 keypoints of `pairs` (slices as in
  * epm_build_intervals).  attrs [N2][3] float32: scale (px), detector
- * response, orientation (rad).  Synchronises the host with `stream` once
- * (upload of the per-pair epipoles).  Errors: EPM_ERR_ARG,
+ * response, orientation (rad).  Does not wait for `stream`: the per-pair
+ * epipole table goes up from a library-held host image (a call waits only
+ * when eight uploads of the device are still pending).  Errors: EPM_ERR_ARG,
  * EPM_ERR_DEGENERATE_F, EPM_ERR_WORKSPACE, EPM_ERR_HIP. */
 epm_status epm_eps_features(const epm_pair* pairs, int32_t num_pairs, const float* kp2_xy,
                             const float* attrs, float* features, void* workspace,
@@ -546,8 +547,9 @@ epm_status epm_match_residuals(const epm_index* idx, const float* kp1_xy, const 
  * priors); priors: [num_pairs]; kp2_xy [N2][2]; eps2 [N2] output.  Requires
  * eps0 >= 0, k_sigma >= 0, eps_max >= eps0 finite, zmin = 0 or finite with
  * zmax > zmin.  workspace: at least
- * epm_pose_eps_workspace_bytes(num_pairs), 256-byte aligned.  Synchronises
- * the host with `stream` once (upload of the per-pair table).  Errors:
+ * epm_pose_eps_workspace_bytes(num_pairs), 256-byte aligned.  Does not
+ * wait for `stream` (the per-pair table goes up as in epm_eps_features).
+ * Errors:
  * EPM_ERR_ARG, EPM_ERR_DEGENERATE_F (singular intrinsics, non-finite pose or
  * covariance, F = 0), EPM_ERR_WORKSPACE, EPM_ERR_HIP.
  */
@@ -640,8 +642,8 @@ epm_status epm_mutual_check(const epm_index* idx, const int32_t* best12, const i
  * out_idx     [N1] the kept matches, -1 elsewhere (may not alias best_idx).
  * workspace   caller-owned device memory of epm_gms_workspace_bytes(idx,
  *             grid) bytes, 256-byte aligned.
- * Host synchronisation: the pair-table upload.  Errors: EPM_ERR_ARG,
- * EPM_ERR_WORKSPACE, EPM_ERR_HIP.
+ * No host synchronisation (the pair table goes up as in epm_eps_features).
+ * Errors: EPM_ERR_ARG, EPM_ERR_WORKSPACE, EPM_ERR_HIP.
  */
 size_t epm_gms_workspace_bytes(const epm_index* idx, int32_t grid);
 epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, float alpha,

@@ -777,6 +777,46 @@ struct NoAllocDevice {
 std::mutex g_noalloc_mu;
 NoAllocDevice g_noalloc[kNoAllocMaxDevices];
 
+// Host images of the per-call tables of epm_eps_features, epm_pose_eps and
+// epm_gms.  Each upload keeps its image in a slot of a ring (one per device)
+// until an event after the copy has completed, so those calls return without
+// waiting for their stream; a call waits only when the slot it takes still
+// holds an upload that has not run (more than kSlots calls in flight).
+struct UploadRing {
+  static constexpr int kSlots = 8;
+  std::vector<char> img[kSlots];
+  hipEvent_t done[kSlots] = {};
+  bool pending[kSlots] = {};
+  int next = 0;
+};
+
+std::mutex g_upload_mu;
+UploadRing g_upload[kNoAllocMaxDevices];
+
+// Copies `head` (taken over) to device address dst on `stream`, which must
+// belong to the current device.
+epm_status upload_table(std::vector<char>& head, void* dst, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return EPM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_upload_mu);
+  UploadRing& R = g_upload[dev];
+  const int s = R.next;
+  R.next = (s + 1) % UploadRing::kSlots;
+  if (!R.done[s] && hipEventCreateWithFlags(&R.done[s], hipEventDisableTiming) != hipSuccess)
+    return EPM_ERR_HIP;
+  if (R.pending[s]) {
+    if (hipEventSynchronize(R.done[s]) != hipSuccess) return EPM_ERR_HIP;
+    R.pending[s] = false;
+  }
+  std::swap(R.img[s], head);
+  if (hipMemcpyAsync(dst, R.img[s].data(), R.img[s].size(), hipMemcpyHostToDevice, stream) !=
+      hipSuccess)
+    return EPM_ERR_HIP;
+  if (hipEventRecord(R.done[s], stream) != hipSuccess) return EPM_ERR_HIP;
+  R.pending[s] = true;
+  return EPM_OK;
+}
+
 // Set-up on the current device: the array's address and the two events.
 epm_status noalloc_setup(NoAllocDevice& d) {
   if (d.ready) return EPM_OK;
@@ -1229,12 +1269,11 @@ epm_status epm_eps_features(const epm_pair* pairs, int32_t num_pairs, const floa
   ks[num_pairs] = n2;
   if (n2 == 0) return EPM_OK;
   char* ws = static_cast<char*>(workspace);
-  EPM_HIP(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, stream));
+  const epm_status up = upload_table(head, ws, stream);
+  if (up != EPM_OK) return up;
   EPM_HIP(launch_eps_features(reinterpret_cast<const EpsPair*>(ws),
                               reinterpret_cast<const int64_t*>(ws + off_k), num_pairs, n2, kp2_xy,
                               attrs, features, stream));
-  // the host table must outlive the copy
-  EPM_HIP(hipStreamSynchronize(stream));
   return EPM_OK;
 }
 
@@ -1351,12 +1390,11 @@ epm_status epm_pose_eps(const epm_pair* pairs, const epm_pose_prior* priors, int
   ks[num_pairs] = n2;
   if (n2 == 0) return EPM_OK;
   char* ws = static_cast<char*>(workspace);
-  EPM_HIP(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, stream));
+  const epm_status up = upload_table(head, ws, stream);
+  if (up != EPM_OK) return up;
   EPM_HIP(launch_pose_eps(reinterpret_cast<const PosePair*>(ws),
                           reinterpret_cast<const int64_t*>(ws + off_k), num_pairs, n2, kp2_xy,
                           eps0, k_sigma, eps_max, eps2, stream));
-  // the host table must outlive the copy
-  EPM_HIP(hipStreamSynchronize(stream));
   return EPM_OK;
 }
 
@@ -1457,7 +1495,8 @@ epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, flo
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) ||
       workspace_bytes < L.total)
     return EPM_ERR_WORKSPACE;
-  std::vector<GmsPair> table((size_t)idx->P);
+  std::vector<char> head(sizeof(GmsPair) * (size_t)idx->P);
+  GmsPair* table = reinterpret_cast<GmsPair*>(head.data());
   for (int p = 0; p < idx->P; ++p) {
     table[p].w1 = size1[2 * p];
     table[p].h1 = size1[2 * p + 1];
@@ -1465,8 +1504,8 @@ epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, flo
     table[p].h2 = 2.0 * idx->pairs[p].cy;
   }
   char* ws = static_cast<char*>(workspace);
-  EPM_HIP(hipMemcpyAsync(ws + L.pairs, table.data(), sizeof(GmsPair) * table.size(),
-                         hipMemcpyHostToDevice, stream));
+  const epm_status up = upload_table(head, ws + L.pairs, stream);
+  if (up != EPM_OK) return up;
   GmsArgs A;
   A.pairs = reinterpret_cast<const GmsPair*>(ws + L.pairs);
   A.qstart = idx->at<int64_t>(idx->L.qstart);
@@ -1486,8 +1525,6 @@ epm_status epm_gms(const epm_index* idx, const int32_t* size1, int32_t grid, flo
   A.offsets = reinterpret_cast<const int64_t*>(ws + L.offsets);
   A.list = reinterpret_cast<uint32_t*>(ws + L.list);
   EPM_HIP(launch_gms(A, reinterpret_cast<int64_t*>(ws + L.partials), stream));
-  // the host table must outlive the copy
-  EPM_HIP(hipStreamSynchronize(stream));
   return EPM_OK;
 }
 

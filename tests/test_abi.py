@@ -120,7 +120,10 @@ int main(void) {
   O(epm_batch_desc, eps_scalar); O(epm_batch_desc, row_offsets); O(epm_batch_desc, capacity);
   O(epm_batch_desc, dtype); O(epm_batch_desc, dim); O(epm_batch_desc, desc1);
   O(epm_batch_desc, ratio); O(epm_batch_desc, best_idx); O(epm_batch_desc, algo);
-  O(epm_batch_desc, sched);
+  O(epm_batch_desc, sched); O(epm_batch_desc, F_dev);
+  S(epm_pose_prior); O(epm_pose_prior, t); O(epm_pose_prior, cov); O(epm_pose_prior, w1);
+  O(epm_pose_prior, zmin); O(epm_pose_prior, zmax);
+  O(epm_match_opts, qerr1); O(epm_match_opts, qerr2);
   return 0;
 }
 """
@@ -145,7 +148,7 @@ def test_struct_layouts_match_header(tmp_path):
         c[" ".join(name)] = int(v)
     mirrors = {"epm_pair": E._Pair, "epm_match_opts": E._MatchOpts, "epm_sched": E._Sched,
                "epm_query_stats": E._QueryStats, "epm_match_stats": E._MatchStats,
-               "epm_batch_desc": E._BatchDesc}
+               "epm_batch_desc": E._BatchDesc, "epm_pose_prior": E._PosePrior}
     for key, v in c.items():
         parts = key.split()
         cls = mirrors[parts[0]]

@@ -74,3 +74,25 @@ def test_zero_covariance_is_the_base_tolerance():
     e = E.pose_eps([E.PairSpec(p.F, p.W, p.H, p.m, p.n)], [prior], _dev(torch, p.kp2), 1.5, 3.0,
                    10.0).cpu().numpy()
     assert (e == np.float32(1.5)).all()
+
+
+def test_back_to_back_calls_keep_their_tables():
+    """Twelve calls in a row without waiting (more than the eight upload slots
+    of the library, so some calls reuse a slot) equal the same calls made one
+    at a time."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    p = synth.cfg0_pair(2)
+    R, t = synth.perturbed_pose(p, 1.0, 77)
+    spec = [E.PairSpec(synth.fundamental_from_cameras(p.K1, p.K2, R, t), p.W, p.H, p.m, p.n)]
+    kp2 = _dev(torch, p.kp2)
+    covs = [synth.noise_covariance(0.1 * (k + 1)) for k in range(12)]
+    burst = [E.pose_eps(spec, [E.PosePrior(p.K1, p.K2, R, t, c, p.W, p.H, 4.0, 16.0)], kp2, 1.0,
+                        2.0, 1e4) for c in covs]
+    torch.cuda.synchronize()
+    for c, got in zip(covs, burst):
+        one = E.pose_eps(spec, [E.PosePrior(p.K1, p.K2, R, t, c, p.W, p.H, 4.0, 16.0)], kp2, 1.0,
+                         2.0, 1e4)
+        torch.cuda.synchronize()
+        assert torch.equal(got, one)
+    assert not torch.equal(burst[0], burst[-1])
