@@ -347,7 +347,11 @@ typedef struct {
   int32_t stab_workgroups;   /* 0: one per tile; > 0: persistent launch        */
   int32_t match_workgroups;  /* 0: one per tile; > 0: persistent launch        */
   int32_t lpt;               /* persistent launches: 1 = longest tiles first   */
-  int32_t reserved[5];       /* zero                                           */
+  int32_t stab_chunk;        /* tile shape of the stabbing pass: window records
+                                staged in LDS per round, 256, 512 or 1024
+                                (0: 512); larger rounds need fewer barriers,
+                                smaller ones less LDS                          */
+  int32_t reserved[4];       /* zero                                           */
 } epm_sched;
 
 /* Profiling aid: with start and stop not NULL, later epm_query_candidates /
@@ -367,7 +371,8 @@ typedef enum { EPM_TIMED_STAB = 0, EPM_TIMED_WIDE = 1 } epm_timed_kernel;
 epm_status epm_index_set_timing_kernel(epm_index* idx, epm_timed_kernel kernel);
 
 /* Sets the work distribution used by later calls on idx (host only).
- * Errors: EPM_ERR_ARG (NULL, negative counts, lpt not 0/1, reserved != 0). */
+ * Errors: EPM_ERR_ARG (NULL, negative counts, lpt not 0/1, stab_chunk not
+ * 0/256/512/1024, reserved != 0). */
 epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched);
 
 /*

@@ -85,7 +85,8 @@ class _PosePrior(ctypes.Structure):
 
 class _Sched(ctypes.Structure):
     _fields_ = [("stab_workgroups", ctypes.c_int32), ("match_workgroups", ctypes.c_int32),
-                ("lpt", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("lpt", ctypes.c_int32), ("stab_chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 _V = ctypes.c_void_p
@@ -102,31 +103,37 @@ class _BatchDesc(ctypes.Structure):
 
 
 class Sched:
-    """Work distribution of the tile kernels (epm_sched): 0 workgroups = one
-    workgroup per angle tile; n > 0 = persistent launch of n workgroups;
-    lpt = take tiles longest first (persistent launches)."""
+    """Work distribution and tile shape of the tile kernels (epm_sched):
+    0 workgroups = one workgroup per angle tile; n > 0 = persistent launch of
+    n workgroups; lpt = take tiles longest first (persistent launches);
+    stab_chunk = window records staged per round of the stabbing pass (256,
+    512 or 1024; 0 = 512)."""
 
-    def __init__(self, stab_workgroups=0, match_workgroups=0, lpt=0):
+    def __init__(self, stab_workgroups=0, match_workgroups=0, lpt=0, stab_chunk=0):
         self.stab_workgroups = int(stab_workgroups)
         self.match_workgroups = int(match_workgroups)
         self.lpt = int(lpt)
+        self.stab_chunk = int(stab_chunk)
 
     def as_dict(self):
         return {"stab_workgroups": self.stab_workgroups,
-                "match_workgroups": self.match_workgroups, "lpt": self.lpt}
+                "match_workgroups": self.match_workgroups, "lpt": self.lpt,
+                "stab_chunk": self.stab_chunk}
 
     @classmethod
     def from_dict(cls, d):
-        return cls(d.get("stab_workgroups", 0), d.get("match_workgroups", 0), d.get("lpt", 0))
+        return cls(d.get("stab_workgroups", 0), d.get("match_workgroups", 0), d.get("lpt", 0),
+                   d.get("stab_chunk", 0))
 
     def _c(self):
         c = _Sched()
-        c.stab_workgroups, c.match_workgroups, c.lpt = (self.stab_workgroups,
-                                                        self.match_workgroups, self.lpt)
+        c.stab_workgroups, c.match_workgroups, c.lpt, c.stab_chunk = (
+            self.stab_workgroups, self.match_workgroups, self.lpt, self.stab_chunk)
         return c
 
     def __repr__(self):
-        return f"Sched({self.stab_workgroups}, {self.match_workgroups}, lpt={self.lpt})"
+        return (f"Sched({self.stab_workgroups}, {self.match_workgroups}, lpt={self.lpt}, "
+                f"stab_chunk={self.stab_chunk})")
 
 
 def library_path():

@@ -1,9 +1,11 @@
-"""Autotuner for the work distribution of the angle-tile kernels.
+"""Autotuner for the work distribution and tile shape of the angle-tile
+kernels.
 
 A batch of image pairs of uneven sizes can run its stabbing and matching
 tiles one workgroup per tile, or as persistent launches of a few workgroups
 per compute unit that take tiles from a device queue, in angle order or
-longest first (Sched).  Which is fastest depends on the batch's shape and the
+longest first; the stabbing pass stages 256, 512 or 1024 window records in
+LDS per round (Sched).  Which is fastest depends on the batch's shape and the
 device, and every form gives the same results, so the choice is measured:
 each candidate is recorded as a HIP graph of the whole batch (Batch) and
 replayed a few times; the fastest is kept.
@@ -43,15 +45,21 @@ def shape_key(torch, device, specs, dtype):
             f"|n1 {_pow2(n1)}|n2 {_pow2(n2)}")
 
 
+STAB_CHUNKS = (256, 512, 1024)
+
+
 def candidates(num_cus):
     """One workgroup per tile, and persistent launches of 1-3 (stabbing) and
     1-2 (matching: its LDS allows two per CU) workgroups per compute unit, in
-    angle order and longest first."""
-    out = [Sched(0, 0, 0)]
-    for s in (1, 2, 3):
-        for m in (1, 2):
-            for lpt in (0, 1):
-                out.append(Sched(s * num_cus, m * num_cus, lpt))
+    angle order and longest first; each with 256, 512 and 1024 window records
+    per round of the stabbing pass."""
+    out = []
+    for ch in STAB_CHUNKS:
+        out.append(Sched(0, 0, 0, ch))
+        for s in (1, 2, 3):
+            for m in (1, 2):
+                for lpt in (0, 1):
+                    out.append(Sched(s * num_cus, m * num_cus, lpt, ch))
     return out
 
 

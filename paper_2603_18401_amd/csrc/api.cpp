@@ -501,7 +501,7 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   }
   const bool timed = idx->ev_start && idx->timed == EPM_TIMED_STAB;
   if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
-  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, mode, stream));
+  EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, mode, S.stab_chunk, stream));
   if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
   EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
@@ -899,7 +899,9 @@ epm_status epm_index_set_sched(epm_index* idx, const epm_sched* sched) {
   if (!idx || !sched) return EPM_ERR_ARG;
   if (sched->stab_workgroups < 0 || sched->match_workgroups < 0) return EPM_ERR_ARG;
   if (sched->lpt != 0 && sched->lpt != 1) return EPM_ERR_ARG;
-  for (int k = 0; k < 5; ++k)
+  const int ch = sched->stab_chunk;
+  if (ch != 0 && ch != 256 && ch != 512 && ch != 1024) return EPM_ERR_ARG;
+  for (int k = 0; k < 4; ++k)
     if (sched->reserved[k] != 0) return EPM_ERR_ARG;
   idx->sched = *sched;
   return EPM_OK;
@@ -1669,6 +1671,6 @@ const char* epm_status_string(epm_status s) {
   return "EPM_ERR_UNKNOWN";
 }
 
-const char* epm_version(void) { return "epm 0.1.0 (gfx950)"; }
+const char* epm_version(void) { return "epm 0.2.0 (gfx950)"; }
 
 }  // extern "C"

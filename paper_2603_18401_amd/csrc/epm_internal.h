@@ -80,7 +80,8 @@ constexpr int kRowSortMax = 2048;
 
 // Stabbing tiles: kTileQ consecutive angle-sorted queries of one pair share
 // one window search per width class; the window's records are staged in LDS
-// kChunk at a time.  Rows of up to kStage candidates are parked in a staging
+// a round at a time (256, 512 or 1024 records, a tile shape chosen per index;
+// kChunk by default).  Rows of up to kStage candidates are parked in a staging
 // buffer by the tile kernel and sorted by the copy pass; longer rows are
 // rebuilt by the fill kernel.
 constexpr int kTileQ = 64;

@@ -368,7 +368,8 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
 // global atomics on the same counters cost more than a barrier).
 constexpr int kFuseRows = 48;
 constexpr int kFuseStride = 132;  // floats per staged row: 16-byte reads of rows hit distinct banks
-constexpr int kRecBytes = kChunk * (4 + 4 + 8 + 4 + 4);
+// LDS bytes of a round of CH window records (C, H, x y, eps, j).
+constexpr int rec_bytes(int CH) { return CH * (4 + 4 + 8 + 4 + 4); }
 // The staged rows are copied straight from global memory to LDS (lane l of a
 // wavefront copy writes 16-byte chunk l of it): kFuseCopies wavefront copies
 // cover the rows with their padding, and the tail of the last one is slack.
@@ -510,12 +511,13 @@ struct BfState {
 // MODE: kStabCount (count and park rows), kStabF32 (FP32 selection fused),
 // kStabBF16 (BF16 bounds with an exact FP32 re-rank, fused).
 // Fused: three workgroups per CU (LDS and registers are sized for it)
-template <bool PERSIST, int MODE>
+// CH: window records staged in LDS per round of the pair test.
+template <bool PERSIST, int MODE, int CH>
 __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
   constexpr bool FUSE = MODE != kStabCount;
   // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps the window's j
   // in sJ_keep), reused for descriptor rows in the match phase
-  constexpr int kRecRaw = FUSE ? kRecBytes - kChunk * 4 : kRecBytes;
+  constexpr int kRecRaw = FUSE ? rec_bytes(CH) - CH * 4 : rec_bytes(CH);
   constexpr int kMatchRaw = MODE == kStabF32 ? kFuseBytes : MODE == kStabBF16 ? kBfScratch : 0;
   constexpr int kRaw = kMatchRaw > kRecRaw ? kMatchRaw : kRecRaw;
   __shared__ __attribute__((aligned(16))) unsigned char raw[kRaw];
@@ -524,10 +526,10 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
   __shared__ __attribute__((aligned(16))) uint8_t bfrows[MODE == kStabBF16 ? kBfRowBytes : 16];
   __shared__ int32_t sJ_keep[FUSE ? kKeepJ : 1];
   uint32_t* sC = reinterpret_cast<uint32_t*>(raw);
-  uint32_t* sH = sC + kChunk;
-  float2* sXY = reinterpret_cast<float2*>(sH + kChunk);
-  float* sE = reinterpret_cast<float*>(sXY + kChunk);
-  int32_t* sJ = reinterpret_cast<int32_t*>(sE + kChunk);  // not FUSE
+  uint32_t* sH = sC + CH;
+  float2* sXY = reinterpret_cast<float2*>(sH + CH);
+  float* sE = reinterpret_cast<float*>(sXY + CH);
+  int32_t* sJ = reinterpret_cast<int32_t*>(sE + CH);  // not FUSE
   // hit lists: image-2 indices, or (FUSE) 16-bit window positions
   __shared__ int32_t hits[FUSE ? 1 : kTileQ][FUSE ? 1 : kStage + 1];  // +1: rows in different banks
   __shared__ uint16_t hits_v[FUSE ? kTileQ : 1][FUSE ? kStage + 2 : 1];
@@ -597,8 +599,8 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
     const double la = qa[lq], lb = qb[lq], lc = qc[lq], ln = qn[lq];
     const uint64_t same_query = 0x0001000100010001ull << (lane & (kQPerWave - 1));
     uint32_t lcnt = 0;
-    for (int64_t base = 0; base < total_len; base += kChunk) {
-      const int clen = (int)(total_len - base < kChunk ? total_len - base : kChunk);
+    for (int64_t base = 0; base < total_len; base += CH) {
+      const int clen = (int)(total_len - base < CH ? total_len - base : CH);
       for (int v = tid; v < clen; v += kThreads) {
         const int64_t virt = base + v;
         int s = 0;  // last slot with slot_pref[s] <= virt
@@ -1231,7 +1233,31 @@ hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, hipStream_t s) {
+namespace {
+
+template <int MODE, int CH>
+void launch_stab_mode(const StabArgs& a, int grid, const dim3& g, hipStream_t s) {
+  if (grid > 0)
+    hipLaunchKernelGGL((k_stab_tile<true, MODE, CH>), g, dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stab_tile<false, MODE, CH>), g, dim3(kThreads), 0, s, a);
+}
+
+template <int CH>
+hipError_t launch_stab_chunk(const StabArgs& a, int grid, int mode, const dim3& g,
+                             hipStream_t s) {
+  switch (mode) {
+    case kStabCount: launch_stab_mode<kStabCount, CH>(a, grid, g, s); break;
+    case kStabF32: launch_stab_mode<kStabF32, CH>(a, grid, g, s); break;
+    case kStabBF16: launch_stab_mode<kStabBF16, CH>(a, grid, g, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
   if (grid > 0 && !a.queue) return hipErrorInvalidValue;
   if (mode != kStabCount &&
@@ -1239,29 +1265,13 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, hipStream_t 
     return hipErrorInvalidValue;
   if (mode == kStabBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
-  switch (mode) {
-    case kStabCount:
-      if (grid > 0)
-        hipLaunchKernelGGL((k_stab_tile<true, kStabCount>), g, dim3(kThreads), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_stab_tile<false, kStabCount>), g, dim3(kThreads), 0, s, a);
-      break;
-    case kStabF32:
-      if (grid > 0)
-        hipLaunchKernelGGL((k_stab_tile<true, kStabF32>), g, dim3(kThreads), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_stab_tile<false, kStabF32>), g, dim3(kThreads), 0, s, a);
-      break;
-    case kStabBF16:
-      if (grid > 0)
-        hipLaunchKernelGGL((k_stab_tile<true, kStabBF16>), g, dim3(kThreads), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_stab_tile<false, kStabBF16>), g, dim3(kThreads), 0, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  switch (chunk) {
+    case 256: return launch_stab_chunk<256>(a, grid, mode, g, s);
+    case 0: return launch_stab_chunk<kChunk>(a, grid, mode, g, s);
+    case 512: return launch_stab_chunk<512>(a, grid, mode, g, s);
+    case 1024: return launch_stab_chunk<1024>(a, grid, mode, g, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {

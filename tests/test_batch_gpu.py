@@ -14,7 +14,9 @@ from tests.gpu_util import assert_csr_equal, oracle_batch, specs_of, torch_gpu
 
 pytestmark = pytest.mark.gpu
 
-SCHEDS = [(0, 0, 0), (768, 512, 0), (768, 512, 1), (256, 256, 1), (7, 5, 1)]
+# (stabbing workgroups, matching workgroups, longest first, records per round)
+SCHEDS = [(0, 0, 0, 0), (0, 0, 0, 256), (0, 0, 0, 1024), (768, 512, 0, 0), (768, 512, 1, 1024),
+          (256, 256, 1, 256), (7, 5, 1, 0)]
 
 
 def log(msg):
@@ -182,7 +184,7 @@ def test_autotune_picks_and_caches(case, tmp_path):
     log("autotune on the mixed batch")
     nnz = int(case.ref[0][-1])
     cache = str(tmp_path / "tune.json")
-    cand = [E.Sched(0, 0, 0), E.Sched(256, 256, 0), E.Sched(768, 512, 1)]
+    cand = [E.Sched(0, 0, 0), E.Sched(256, 256, 0, 1024), E.Sched(768, 512, 1, 256)]
     best, info = autotune.tune(case.specs, case.kp1, case.kp2, case.q1, case.q2, nnz + 10,
                                dtype="bf16", eps=2.0, desc1_f32=case.m1, desc2_f32=case.m2,
                                cache=cache, sched_list=cand, steps=2, warmup=1, log=log)
@@ -197,3 +199,15 @@ def test_autotune_picks_and_caches(case, tmp_path):
     b.launch()
     _check(b.outputs(), case.ref, "tuned")
     torch.cuda.synchronize()
+
+
+def test_bad_tile_shape_is_refused():
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    p = synth.cfg0_pair(0)
+    idx = E.Index(specs_of([p]), torch.from_numpy(p.kp2).to(torch.device("cuda:0")), eps=2.0)
+    for bad in (E.Sched(0, 0, 0, 300), E.Sched(0, 0, 2, 0), E.Sched(-1, 0, 0, 0)):
+        with pytest.raises(RuntimeError):
+            idx.set_sched(bad)
+    idx.set_sched(E.Sched(0, 0, 0, 1024))
+    idx.close()
