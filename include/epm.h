@@ -349,7 +349,8 @@ typedef struct {
   int32_t lpt;               /* persistent launches: 1 = longest tiles first   */
   int32_t stab_chunk;        /* tile shape of the stabbing pass: window records
                                 staged in LDS per round, 256, 512 or 1024
-                                (0: 512); larger rounds need fewer barriers,
+                                (0: 256 for the fused BF16 pass, 512 for the
+                                others); larger rounds need fewer barriers,
                                 smaller ones less LDS                          */
   int32_t reserved[4];       /* zero                                           */
 } epm_sched;
@@ -579,7 +580,9 @@ typedef struct {
   int64_t empty_queries;    /* zero lines (a = b = 0): empty rows                     */
   int64_t scanned_queries;  /* lines missing the epipole by more than the intervals
                                absorb: tested against every keypoint of their pair   */
-  int64_t records_scanned;  /* (query, record) pairs read from the angle windows     */
+  int64_t records_scanned;  /* (query, record) pairs tested: the records of the angle
+                               window that can meet the key span of the query's
+                               group of 16 angle-sorted queries                     */
   int64_t angle_hits;       /* of those, inside the record's angular interval        */
   int64_t candidates;       /* confirmed by the FP64 test (= nnz)                     */
 } epm_query_stats;

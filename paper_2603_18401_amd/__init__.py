@@ -107,7 +107,7 @@ class Sched:
     0 workgroups = one workgroup per angle tile; n > 0 = persistent launch of
     n workgroups; lpt = take tiles longest first (persistent launches);
     stab_chunk = window records staged per round of the stabbing pass (256,
-    512 or 1024; 0 = 512)."""
+    512 or 1024; 0 = 256 for the fused BF16 pass, 512 for the others)."""
 
     def __init__(self, stab_workgroups=0, match_workgroups=0, lpt=0, stab_chunk=0):
         self.stab_workgroups = int(stab_workgroups)

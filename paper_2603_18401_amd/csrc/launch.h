@@ -154,7 +154,8 @@ hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t
 // desc1/desc2; the match is selected through certified MFMA bounds and an
 // exact re-rank on the masters (rows it cannot certify go to a.rest).
 constexpr int kStabCount = 0, kStabF32 = 1, kStabBF16 = 2;
-// chunk: window records staged per round (256, 512 or 1024; 0 = 512).
+// chunk: window records staged per round (256, 512 or 1024; 0 = 256 for the
+// BF16 pass, 512 for the others).
 hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, hipStream_t s);
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the
 // brute-force long rows.

@@ -429,13 +429,14 @@ __device__ __forceinline__ void wait_lds_copies() { __builtin_amdgcn_s_waitcnt(0
 // keeps its kBfKeep smallest D_lo (dropping those above its own running U2,
 // which only shrinks); a row whose smallest dropped bound is not above U2 is
 // left to the listed-query match, exact either way.
-constexpr int kBfRows = 64;                 // window rows per chunk
+constexpr int kBfRows = 32;  // window rows per chunk: with 256-record rounds, four workgroups per CU
+constexpr int kBfBlocks = kBfRows / 16;     // 16-row MFMA blocks per chunk
 constexpr int kBfStride = 256 + 16;         // LDS bytes per row: 16 rows' reads hit distinct banks
 constexpr int kBfPieces = kBfStride / 16;   // 16-byte pieces per row (the last repeats one)
 constexpr int kBfCopies = (kBfRows * kBfPieces + kWave - 1) / kWave;
 constexpr int kBfRowBytes = kBfCopies * kWave * 16;
 constexpr int kBfKeep = 3;
-static_assert(kBfRows == 64, "the hit mask of a chunk is one 64-bit word");
+static_assert(kBfRows % 16 == 0 && kBfRows <= 64, "the hit mask of a chunk is one 64-bit word");
 // Exact distances a query can list: kBfKeep per lane, four lanes.
 constexpr int kBfQTasks = 4 * kBfKeep;
 // After the pair test the record chunk holds the chunk's row terms and the
@@ -513,7 +514,7 @@ struct BfState {
 // Fused: three workgroups per CU (LDS and registers are sized for it)
 // CH: window records staged in LDS per round of the pair test.
 template <bool PERSIST, int MODE, int CH>
-__global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
+__global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
   constexpr bool FUSE = MODE != kStabCount;
   // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps the window's j
   // in sJ_keep), reused for descriptor rows in the match phase
@@ -598,7 +599,46 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
     const uint32_t lkey = qk[lq];
     const double la = qa[lq], lb = qb[lq], lc = qc[lq], ln = qn[lq];
     const uint64_t same_query = 0x0001000100010001ull << (lane & (kQPerWave - 1));
+    // the wavefront's key span [kmn, kmx] over its live queries: a record
+    // whose interval misses every key of the span (circular distance from the
+    // span's middle beyond its half-width plus the span's half-length, by the
+    // triangle inequality on the circle of keys) cannot meet any of them and
+    // is skipped without the per-query test
+    uint32_t kmn = line_live ? lkey : 0xFFFFFFFFu, kmx = line_live ? lkey : 0u;
+    #pragma unroll
+    for (int off = 1; off < kQPerWave; off <<= 1) {
+      kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, off));
+      kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, off));
+    }
+    const uint32_t kmid = kmn + ((kmx - kmn) >> 1);
+    const uint64_t khalf = ((uint64_t)(kmx - kmn) + 1u) >> 1;
     uint32_t lcnt = 0;
+    // BF16: the query rows are loaded before the pair test so that their
+    // latency hides behind it.  Lane l of wavefront w holds query
+    // 16 w + (l & 15): as MFMA B operands its BF16 values at dimensions
+    // 32 kk + 8 g .. + 7 (g = l >> 4), and its quarter, dimensions
+    // 32 g .. 32 g + 31, as BF16 codes and as the FP32 master (the exact
+    // chains pass their sum from quarter to quarter)
+    bf16x8 bq[4];
+    uint4 qcode[4];
+    float4 qx[8];
+    if constexpr (MODE == kStabBF16) {
+      const int g = lane >> 4;
+      const bool ld = line_live && lq < T.count && fusable;
+      const int64_t qi = qidx[lq];
+      #pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint4 c = ld ? reinterpret_cast<const uint4*>(A.codes1)[qi * 16 + kk * 4 + g]
+                           : make_uint4(0u, 0u, 0u, 0u);
+        bq[kk] = __builtin_bit_cast(bf16x8, c);
+        qcode[kk] = ld ? reinterpret_cast<const uint4*>(A.codes1)[qi * 16 + g * 4 + kk]
+                    : make_uint4(0u, 0u, 0u, 0u);
+      }
+      #pragma unroll
+      for (int u = 0; u < 8; ++u)
+        qx[u] = ld ? reinterpret_cast<const float4*>(A.desc1)[qi * 32 + g * 8 + u]
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     for (int64_t base = 0; base < total_len; base += CH) {
       const int clen = (int)(total_len - base < CH ? total_len - base : CH);
       for (int v = tid; v < clen; v += kThreads) {
@@ -626,32 +666,49 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
       }
       if (any_live) {
         // this wave's 16 queries (lane & 15) against four records per step
-        // (lane >> 4); a hit's slot is the query's count plus its rank among
-        // the query's lanes of the step, so every row lists its hits in
-        // ascending window position
-        if (line_live && lane < kQPerWave) scanned += (uint32_t)clen;
-        for (int r0 = 0; r0 < clen; r0 += 4) {
-          const int r = r0 + (lane >> 4);
-          bool hit = false;
-          if (line_live && r < clen) {
-            const uint32_t C = sC[r], H = sH[r];
-            const float2 xy = sXY[r];
-            const float e = sE[r];
-            const bool ang = key_distance(lkey, C) <= H;
-            angle_hits += ang ? 1u : 0u;
-            hit = ang && within_tolerance_n(la, lb, lc, ln, xy.x, xy.y, e);
-          }
-          const uint64_t m = ballot(hit) & same_query;
-          if (hit) {
-            const uint32_t slot = lcnt + lanes_below(m);
-            if (slot < (uint32_t)kStage) {
-              if (FUSE)
-                hits_v[lq][slot] = (uint16_t)(base + r);
-              else
-                hits[lq][slot] = sJ[r];
+        // (lane >> 4), over the records of each group of 64 that can meet
+        // the wave's key span; a hit's slot is the query's count plus its
+        // rank among the query's lanes of the step, so every row lists its
+        // hits in ascending window position
+        const int g4 = lane >> 4;
+        for (int g0 = 0; g0 < clen; g0 += kWave) {
+          bool rel = false;
+          if (g0 + lane < clen)
+            rel = (uint64_t)key_distance(kmid, sC[g0 + lane]) <= (uint64_t)sH[g0 + lane] + khalf;
+          uint64_t m = ballot(rel);
+          if (line_live && lane < kQPerWave) scanned += (uint32_t)__popcll(m);
+          while (m != 0ull) {
+            // the next four of them, in ascending position, one per lane group
+            int pick = kWave;
+            #pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int b = m != 0ull ? (int)__builtin_ctzll(m) : kWave;
+              pick = g4 == t ? b : pick;
+              m &= m - 1ull;
             }
+            const int r = g0 + pick;
+            bool hit = false;
+            if (line_live && pick < kWave) {
+              const uint32_t C = sC[r], H = sH[r];
+              const bool ang = key_distance(lkey, C) <= H;
+              angle_hits += ang ? 1u : 0u;
+              if (ang) {
+                const float2 xy = sXY[r];
+                hit = within_tolerance_n(la, lb, lc, ln, xy.x, xy.y, sE[r]);
+              }
+            }
+            const uint64_t hm = ballot(hit) & same_query;
+            if (hit) {
+              const uint32_t slot = lcnt + lanes_below(hm);
+              if (slot < (uint32_t)kStage) {
+                if (FUSE)
+                  hits_v[lq][slot] = (uint16_t)(base + r);
+                else
+                  hits[lq][slot] = sJ[r];
+              }
+            }
+            lcnt += (uint32_t)__popcll(hm);
           }
-          lcnt += (uint32_t)__popcll(m);
         }
       }
       __syncthreads();
@@ -820,31 +877,12 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
       // chunk is dead -- then the per-query task lists
       float4* w_terms = reinterpret_cast<float4*>(raw);
       uint16_t* qtask = reinterpret_cast<uint16_t*>(w_terms + kBfRows);  // [kTileQ][kBfQTasks]
-      // B operands: this lane's BF16 values of its query at dimensions
-      // 32 kk + 8 g .. + 7; and its quarter of the query, dimensions
-      // 32 g .. 32 g + 31, as BF16 codes and as the FP32 master (the exact
-      // chains pass their sum from quarter to quarter)
-      bf16x8 bq[4];
-      uint4 qc[4];
-      float4 qx[8];
-      #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const uint4 c = mine2 ? reinterpret_cast<const uint4*>(A.codes1)[qi2 * 16 + kk * 4 + g]
-                              : make_uint4(0u, 0u, 0u, 0u);
-        bq[kk] = __builtin_bit_cast(bf16x8, c);
-        qc[kk] = mine2 ? reinterpret_cast<const uint4*>(A.codes1)[qi2 * 16 + g * 4 + kk]
-                       : make_uint4(0u, 0u, 0u, 0u);
-      }
-      #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        qx[u] = mine2 ? reinterpret_cast<const float4*>(A.desc1)[qi2 * 32 + g * 8 + u]
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
       // the query's BF16 norm and the measured norm of its rounding error
       // (x - x^, exact in FP32), summed over its four quarters
       float qn_part = 0.0f, qe_part = 0.0f;
       #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const uint32_t w[4] = {qc[kk].x, qc[kk].y, qc[kk].z, qc[kk].w};
+        const uint32_t w[4] = {qcode[kk].x, qcode[kk].y, qcode[kk].z, qcode[kk].w};
         const float4 xa = qx[2 * kk], xb = qx[2 * kk + 1];
         const float x[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
         #pragma unroll
@@ -888,12 +926,14 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
           wait_lds_copies();
           __syncthreads();
           {
-            // norms of the chunk's rows: four threads per row, 32 values each
-            const int r = tid >> 2, part4 = tid & 3;
-            const uint4* rp = reinterpret_cast<const uint4*>(bfrows + r * kBfStride + part4 * 64);
+            // norms of the chunk's rows: kTpr threads per row
+            constexpr int kTpr = kThreads / kBfRows;
+            const int r = tid / kTpr, part4 = tid % kTpr;
+            const uint4* rp =
+                reinterpret_cast<const uint4*>(bfrows + r * kBfStride + part4 * (256 / kTpr));
             float sn = 0.0f;
             #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 16 / kTpr; ++t) {
               const uint4 c = rp[t];
               const uint32_t w[4] = {c.x, c.y, c.z, c.w};
               #pragma unroll
@@ -903,8 +943,8 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
                 sn = __builtin_fmaf(y, y, sn);
               }
             }
-            sn += __shfl_xor(sn, 1);
-            sn += __shfl_xor(sn, 2);
+            #pragma unroll
+            for (int off = 1; off < kTpr; off <<= 1) sn += __shfl_xor(sn, off);
             if (part4 == 0) {
               const float nb = sqrtf(sn) * (1.0f + 2e-5f);
               // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
@@ -915,11 +955,14 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
           }
           __syncthreads();
           if (ballot(hmask != 0ull) != 0ull) {
-            // S^T = W^ Q^T on MFMA: rows 16 cb + (l & 15) against the queries
-            f32x4 acc[4];
+            // S^T = W^ Q^T on MFMA: rows 16 cb + (l & 15) against the
+            // queries, for the row blocks where one of the wave's queries has
+            // a hit (the others are never read)
+            f32x4 acc[kBfBlocks];
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < kBfBlocks; ++cb) {
               acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+              if (ballot(((hmask >> (16 * cb)) & 0xFFFFull) != 0ull) == 0ull) continue;
               #pragma unroll
               for (int kk = 0; kk < 4; ++kk) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(
@@ -927,18 +970,19 @@ __global__ __launch_bounds__(kThreads, MODE != kStabCount ? 3 : 2) void k_stab_t
                 acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[kk], acc[cb], 0, 0, 0);
               }
             }
-            // this lane's hits among its 16 scores: slot 4 cb + i is row
+            // this lane's hits among its scores: slot 4 cb + i is row
             // 16 cb + 4 g + i; only set slots are visited
             uint32_t slots = 0u;
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < kBfBlocks; ++cb)
               slots |= (uint32_t)((hmask >> (16 * cb + 4 * g)) & 0xFull) << (4 * cb);
             while (slots != 0u) {
               const int sl = __builtin_ctz(slots);
               slots &= slots - 1u;
-              const f32x4 a01 = (sl & 4) ? acc[1] : acc[0];
-              const f32x4 a23 = (sl & 4) ? acc[3] : acc[2];
-              const f32x4 av = (sl & 8) ? a23 : a01;
+              f32x4 av = acc[0];
+              #pragma unroll
+              for (int cb = 1; cb < kBfBlocks; ++cb)
+                if ((sl >> 2) == cb) av = acc[cb];
               const float sc = (sl & 2) ? ((sl & 1) ? av[3] : av[2]) : ((sl & 1) ? av[1] : av[0]);
               const int r = 16 * (sl >> 2) + 4 * g + (sl & 3);
               const float4 wt = w_terms[r];
@@ -1265,9 +1309,11 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, h
     return hipErrorInvalidValue;
   if (mode == kStabBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
+  // default: 256 records for the BF16 pass (its LDS then allows four
+  // workgroups per CU), kChunk otherwise
+  if (chunk == 0) chunk = mode == kStabBF16 ? 256 : kChunk;
   switch (chunk) {
     case 256: return launch_stab_chunk<256>(a, grid, mode, g, s);
-    case 0: return launch_stab_chunk<kChunk>(a, grid, mode, g, s);
     case 512: return launch_stab_chunk<512>(a, grid, mode, g, s);
     case 1024: return launch_stab_chunk<1024>(a, grid, mode, g, s);
     default: return hipErrorInvalidValue;

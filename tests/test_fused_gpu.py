@@ -117,7 +117,9 @@ def test_sparse_queries_over_a_dense_image(eps):
     lens = np.diff(got[0])
     assert lens.max() <= 128
     st = idx.stats()
-    assert st["records_scanned"] > 2048 * (st["queries"] - st["empty_queries"])
+    # each group of 16 queries spans a wide angle range: hundreds of the
+    # window's records meet its key span and are tested per query
+    assert st["records_scanned"] > 256 * (st["queries"] - st["empty_queries"])
     _same(got, _oracle([p], eps, 0.8), f"sparse queries eps {eps}")
 
 
