@@ -68,36 +68,44 @@ __global__ __launch_bounds__(kThreads) void k_lpt_scatter(const uint32_t* __rest
   if (t < n) order[base[b] + rank] = (uint32_t)t;
 }
 
-// Per-XCD longest-first layout: tile t of XCD x and bucket b goes to rank
-// k = (tiles of XCD x in buckets above b) + (tiles of (x, b) in earlier
-// workgroups of this kernel) + its place among this workgroup's tiles of
-// (x, b), i.e. to the workgroup k * 8 + x.  Every workgroup counts all the
-// tiles' costs itself (4 B per tile), so no counters cross workgroups.
-__global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __restrict__ cost,
-                                                              int n,
-                                                              uint32_t* __restrict__ block_tile) {
-  constexpr int kBins = kNumXcd * kCostBuckets;
-  __shared__ uint32_t total[kBins], before[kBins], h[kBins];
-  const int tid = (int)threadIdx.x;
-  for (int k = tid; k < kBins; k += kThreads) {
-    total[k] = 0u;
-    before[k] = 0u;
-    h[k] = 0u;
+// Per-XCD longest-first layout: workgroup x handles the tiles that
+// xcd_tile gives XCD x, counts them per cost bucket, and deals them out most
+// expensive bucket first: the tile of rank k goes to workgroup k * 8 + x of
+// the tile launch (any order inside a bucket).
+constexpr int kXcdThreads = 1024;
+
+// i-th tile (0 <= i < tiles of XCD x) that xcd_tile sends to XCD x.
+__device__ __forceinline__ int xcd_member(int i, int x, int n) {
+  constexpr int round = kNumXcd * kXcdGroup;
+  const int full = (n / round) * round;
+  const int head = full / kNumXcd;  // XCD x's tiles among the first `full`
+  if (i < head) return ((i / kXcdGroup) * kNumXcd + x) * kXcdGroup + i % kXcdGroup;
+  return full + (i - head) * kNumXcd + x;
+}
+
+__global__ __launch_bounds__(kXcdThreads) void k_xcd_lpt_order(const uint32_t* __restrict__ cost,
+                                                               int n,
+                                                               uint32_t* __restrict__ block_tile) {
+  __shared__ uint32_t h[kCostBuckets], cursor[kCostBuckets];
+  const int x = (int)blockIdx.x, tid = (int)threadIdx.x;
+  constexpr int round = kNumXcd * kXcdGroup;
+  const int full = (n / round) * round;
+  const int rest = n - full - x;
+  const int nx = full / kNumXcd + (rest > 0 ? (rest + kNumXcd - 1) / kNumXcd : 0);
+  if (tid < kCostBuckets) h[tid] = 0u;
+  __syncthreads();
+  for (int i = tid; i < nx; i += kXcdThreads)
+    atomicAdd(&h[cost_bucket(cost[xcd_member(i, x, n)])], 1u);
+  __syncthreads();
+  if (tid < kCostBuckets) {
+    uint32_t start = 0;
+    for (int c = kCostBuckets - 1; c > tid; --c) start += h[c];
+    cursor[tid] = start;
   }
   __syncthreads();
-  const int first = (int)blockIdx.x * kThreads;
-  for (int t = tid; t < n; t += kThreads) {
-    const int bin = xcd_of_tile(t, n) * kCostBuckets + cost_bucket(cost[t]);
-    atomicAdd(&total[bin], 1u);
-    if (t < first) atomicAdd(&before[bin], 1u);
-  }
-  __syncthreads();
-  const int t = first + tid;
-  if (t < n) {
-    const int x = xcd_of_tile(t, n), b = cost_bucket(cost[t]);
-    const int bin = x * kCostBuckets + b;
-    uint32_t k = before[bin] + atomicAdd(&h[bin], 1u);
-    for (int c = kCostBuckets - 1; c > b; --c) k += total[x * kCostBuckets + c];
+  for (int i = tid; i < nx; i += kXcdThreads) {
+    const int t = xcd_member(i, x, n);
+    const uint32_t k = atomicAdd(&cursor[cost_bucket(cost[t])], 1u);
     block_tile[k * kNumXcd + (uint32_t)x] = (uint32_t)t;
   }
 }
@@ -107,8 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_xcd_lpt_scatter(const uint32_t* __
 hipError_t launch_xcd_lpt_order(const uint32_t* cost, int num_tiles, uint32_t* block_tile,
                                 hipStream_t s) {
   if (num_tiles == 0) return hipSuccess;
-  const int blocks = (num_tiles + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_xcd_lpt_scatter, dim3(blocks), dim3(kThreads), 0, s, cost, num_tiles,
+  hipLaunchKernelGGL(k_xcd_lpt_order, dim3(kNumXcd), dim3(kXcdThreads), 0, s, cost, num_tiles,
                      block_tile);
   return hipGetLastError();
 }

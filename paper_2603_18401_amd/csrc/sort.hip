@@ -134,8 +134,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 constexpr int kFusedTiles = 128;
 
-// One pass of the fused sort.  hist: this pass's per-tile digit counts;
-// hist_next: the next pass's (zero on entry), or NULL on the last pass.
+// Segments of more tiles than this get their tile offsets from
+// k_sort_offsets (one extra launch per pass, reading each count once) instead
+// of every tile summing the counts of the tiles before it (quadratic in the
+// segment's tiles).
+constexpr int kScanInPassTiles = 16;
+
+// One pass of the fused sort.  hist: this pass's per-tile digit counts, or
+// (READY) the tiles' start offsets that k_sort_offsets made of them;
+// hist_next: the next pass's counts (zero on entry), or NULL on the last pass.
+template <bool READY>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const SortTile* __restrict__ tiles,
@@ -158,8 +166,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     rv[r] = idx < t.count ? vin[t.begin + idx] : 0u;
   }
   const int mine = (int)blockIdx.x - sg.tile_begin;
-  // digit d = tid: count in the segment's earlier tiles, and in all of them
-  {
+  if constexpr (READY) {
+    run[tid] = hist[(int64_t)blockIdx.x * kRadix + tid];
+    __syncthreads();
+  } else {
+    // digit d = tid: count in the segment's earlier tiles, and in all of them
     uint32_t before = 0, total = 0;
     const uint32_t* hd = hist + (int64_t)sg.tile_begin * kRadix + tid;
     constexpr int kBatch = 16;  // tiles whose counts are in flight at once
@@ -198,6 +209,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
           for (int dd = 0; dd < kRadix; ++dd) seg_base[(int64_t)g * kRadix + dd] = (uint32_t)e.begin;
       }
     }
+    __syncthreads();
   }
   const int nshift = shift + 8;
   #pragma unroll
@@ -265,10 +277,22 @@ hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32
     for (int p = 0; p < npass; ++p) {
       const bool last = p + 1 == npass;
       uint32_t* h = hist + (int64_t)p * num_tiles * kRadix;
-      hipLaunchKernelGGL(k_sort_pass, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
-                         tiles, segs, num_segs, 8 * p, h,
-                         last ? nullptr : h + (int64_t)num_tiles * kRadix,
-                         last ? last_digit_base : nullptr);
+      uint32_t* hn = last ? nullptr : h + (int64_t)num_tiles * kRadix;
+      if (max_seg_tiles > kScanInPassTiles) {
+        // counts from LDS histograms of the keys (not global atomics in the
+        // previous pass's scatter), then the tile offsets, then the scatter
+        if (p > 0)
+          hipLaunchKernelGGL(k_sort_hist, dim3(num_tiles), dim3(kSortThreads), 0, s, ki, tiles,
+                             8 * p, h, 0);
+        hipLaunchKernelGGL(k_sort_offsets, dim3(num_segs), dim3(kSortThreads), 0, s, segs, h,
+                           last ? last_digit_base : nullptr);
+        hipLaunchKernelGGL((k_sort_pass<true>), dim3(num_tiles), dim3(kSortThreads), 0, s, ki, vi,
+                           ko, vo, tiles, segs, num_segs, 8 * p, h, nullptr, nullptr);
+      } else {
+        hipLaunchKernelGGL((k_sort_pass<false>), dim3(num_tiles), dim3(kSortThreads), 0, s, ki,
+                           vi, ko, vo, tiles, segs, num_segs, 8 * p, h, hn,
+                           last ? last_digit_base : nullptr);
+      }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       uint32_t* tk = ki; ki = ko; ko = tk;
