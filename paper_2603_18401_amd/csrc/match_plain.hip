@@ -118,8 +118,10 @@ hipError_t launch_match_listed_f32(const MatchArgs& a, const uint32_t* list,
                                    const unsigned long long* count, int64_t max_count,
                                    hipStream_t s) {
   if (max_count <= 0) return hipSuccess;
+  // the list is usually short and its rows latency-bound: enough
+  // workgroups that every listed query has its own wavefront up to 16384
   int64_t blocks = (max_count + kWaves - 1) / kWaves;
-  if (blocks > 1024) blocks = 1024;
+  if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_match_listed_f32, dim3((unsigned)blocks), dim3(kThreads), 0, s, a, list,
                      count);
   return hipGetLastError();

@@ -414,7 +414,7 @@ __device__ __forceinline__ void wait_lds_copies() { __builtin_amdgcn_s_waitcnt(0
 // and the final matches must be the canonical FP32 selection on the masters.
 // The window's BF16 rows are staged kBfRows at a time; wavefront w scores its
 // 16 queries against them on MFMA (A = the window rows, B = the queries, so
-// lane l holds query l & 15 against rows 16 cb + 4 (l >> 4) + i).  Every hit
+// lane l holds query l & 15 against rows 16 cb + 4 i + (l >> 4)).  Every hit
 // gets certified bounds D_lo <= D <= D_hi on its exact canonical distance D:
 //   |q^ - w^|^2 is within em = 3e-5 (|q^| + |w^|)^2 of |q^|^2 + |w^|^2 - 2 q^.w^
 //   (FP32 accumulation), |q - w| is within eps_q + eps_w of |q^ - w^| (eps_q
@@ -483,29 +483,25 @@ struct BfState {
     }
   }
 
+  // Branch-free: the two smallest D_hi, then (unless D_lo is above this
+  // lane's U2, hence above the row's) the sorted insertion of D_lo; the
+  // entry pushed out of the full list lowers `drop`.
   __device__ __forceinline__ void add(float dlo, float dhi, int32_t v) {
+    static_assert(kBfKeep == 3, "the insertion network keeps three entries");
     bad |= !(dlo == dlo) || !(dhi == dhi);
-    if (dhi < u1) {
-      u2 = u1;
-      u1 = dhi;
-    } else if (dhi < u2) {
-      u2 = dhi;
-    }
-    if (dlo > u2) return;  // above this lane's U2, hence above the row's
-    float x = dlo;
-    int32_t y = v;
-    #pragma unroll
-    for (int t = 0; t < kBfKeep; ++t) {
-      if (x < lo[t]) {
-        const float tx = lo[t];
-        const int32_t ty = pos[t];
-        lo[t] = x;
-        pos[t] = y;
-        x = tx;
-        y = ty;
-      }
-    }
-    if (y >= 0) drop = fminf(drop, x);  // the entry pushed out of the list
+    u2 = fminf(u2, fmaxf(u1, dhi));
+    u1 = fminf(u1, dhi);
+    const float x = dlo <= u2 ? dlo : __builtin_inff();
+    const bool c0 = x < lo[0], c1 = x < lo[1], c2 = x < lo[2];  // c0 => c1 => c2
+    const float out = c2 ? lo[2] : x;
+    const int32_t out_pos = c2 ? pos[2] : v;  // not inserted: x itself (+inf: nothing)
+    lo[2] = c1 ? lo[1] : (c2 ? x : lo[2]);
+    pos[2] = c1 ? pos[1] : (c2 ? v : pos[2]);
+    lo[1] = c0 ? lo[0] : (c1 ? x : lo[1]);
+    pos[1] = c0 ? pos[0] : (c1 ? v : pos[1]);
+    lo[0] = c0 ? x : lo[0];
+    pos[0] = c0 ? v : pos[0];
+    drop = out_pos >= 0 ? fminf(drop, out) : drop;
   }
 };
 
@@ -955,10 +951,14 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           }
           __syncthreads();
           if (ballot(hmask != 0ull) != 0ull) {
-            // S^T = W^ Q^T on MFMA: rows 16 cb + (l & 15) against the
-            // queries, for the row blocks where one of the wave's queries has
-            // a hit (the others are never read)
+            // S^T = W^ Q^T on MFMA, for the row blocks where one of the
+            // wave's queries has a hit (the others are never read).  Block
+            // position m of block cb holds window row 16 cb + 4 (m & 3) +
+            // (m >> 2), so that the scores of consecutive rows -- a query's
+            // hits come in runs of neighbouring window positions -- land in
+            // its four lane groups in turn and the lanes share the work
             f32x4 acc[kBfBlocks];
+            const int arow = ((lane & 3) << 2) | ((lane >> 2) & 3);
             #pragma unroll
             for (int cb = 0; cb < kBfBlocks; ++cb) {
               acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
@@ -966,16 +966,19 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               #pragma unroll
               for (int kk = 0; kk < 4; ++kk) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(
-                    bfrows + (cb * 16 + (lane & 15)) * kBfStride + (kk * 32 + g * 8) * 2);
+                    bfrows + (cb * 16 + arow) * kBfStride + (kk * 32 + g * 8) * 2);
                 acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[kk], acc[cb], 0, 0, 0);
               }
             }
-            // this lane's hits among its scores: slot 4 cb + i is row
-            // 16 cb + 4 g + i; only set slots are visited
+            // this lane's hits among its scores: slot 4 cb + i (element i of
+            // acc[cb]) is window row 16 cb + 4 i + g; only set slots are
+            // visited
             uint32_t slots = 0u;
             #pragma unroll
             for (int cb = 0; cb < kBfBlocks; ++cb)
-              slots |= (uint32_t)((hmask >> (16 * cb + 4 * g)) & 0xFull) << (4 * cb);
+              #pragma unroll
+              for (int i = 0; i < 4; ++i)
+                slots |= (uint32_t)((hmask >> (16 * cb + 4 * i + g)) & 1ull) << (4 * cb + i);
             while (slots != 0u) {
               const int sl = __builtin_ctz(slots);
               slots &= slots - 1u;
@@ -984,7 +987,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               for (int cb = 1; cb < kBfBlocks; ++cb)
                 if ((sl >> 2) == cb) av = acc[cb];
               const float sc = (sl & 2) ? ((sl & 1) ? av[3] : av[2]) : ((sl & 1) ? av[1] : av[0]);
-              const int r = 16 * (sl >> 2) + 4 * g + (sl & 3);
+              const int r = 16 * (sl >> 2) + 4 * (sl & 3) + g;
               const float4 wt = w_terms[r];
               const float sum = q_nb + wt.y;
               const float em = 3e-5f * sum * sum;
@@ -1325,7 +1328,9 @@ hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
   const int64_t cblocks = (a.n1 + kCopyQueries - 1) / kCopyQueries;
   hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)cblocks), dim3(kThreads), 0, s, a);
-  const int64_t lblocks = blocks < 512 ? blocks : 512;
+  // long rows are few and each is latency-bound: up to 2048 workgroups
+  // (8192 wavefronts) take them from the queue
+  const int64_t lblocks = blocks < 2048 ? blocks : 2048;
   hipLaunchKernelGGL(k_fill_long, dim3((unsigned)lblocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
