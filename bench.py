@@ -87,7 +87,7 @@ def parse():
 CSRC = os.path.join(ROOT, "paper_2603_18401_amd", "csrc")
 # dominant kernel of the timed step per --algo: (name, source, committed traffic summary)
 KERNELS = {
-    "fused": ("k_stab_tile<false, true> (stabbing + FP32 selection)",
+    "fused": ("k_stab_tile<false, 1, 512> (stabbing + FP32 selection)",
               os.path.join(CSRC, "stab.hip"),
               os.path.join(ROOT, "profiles", "stab_match_fused_traffic.md")),
     "tiled": ("k_match_window_f32", os.path.join(CSRC, "match_window.hip"),
@@ -95,7 +95,7 @@ KERNELS = {
     "auto": ("k_match_window_f32", os.path.join(CSRC, "match_window.hip"),
              os.path.join(ROOT, "profiles", "match_window_traffic.md")),
     "plain": ("k_match_plain_f32", os.path.join(CSRC, "match_plain.hip"), None),
-    "bf16": ("k_stab_tile<false, 2> (stabbing + BF16 bounds + exact FP32 re-rank)",
+    "bf16": ("k_stab_tile<false, 2, 256> (stabbing + BF16 bounds + exact FP32 re-rank)",
              os.path.join(CSRC, "stab.hip"),
              os.path.join(ROOT, "profiles", "stab_bf16_fused_traffic.md")),
 }

@@ -134,11 +134,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 constexpr int kFusedTiles = 128;
 
-// Segments of more tiles than this get their tile offsets from
-// k_sort_offsets (one extra launch per pass, reading each count once) instead
-// of every tile summing the counts of the tiles before it (quadratic in the
-// segment's tiles).
-constexpr int kScanInPassTiles = 16;
+// Sorts of more tiles than this take each pass's counts from LDS histograms
+// of the keys (k_sort_hist) and the tile offsets from k_sort_offsets, three
+// launches per pass: at that size the global atomics with which the one-launch
+// pass counts the next pass's digits dominate it.  Smaller sorts keep the one
+// launch per pass.
+constexpr int kSplitPassTiles = 2048;
 
 // One pass of the fused sort.  hist: this pass's per-tile digit counts, or
 // (READY) the tiles' start offsets that k_sort_offsets made of them;
@@ -278,7 +279,7 @@ hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32
       const bool last = p + 1 == npass;
       uint32_t* h = hist + (int64_t)p * num_tiles * kRadix;
       uint32_t* hn = last ? nullptr : h + (int64_t)num_tiles * kRadix;
-      if (max_seg_tiles > kScanInPassTiles) {
+      if (num_tiles > kSplitPassTiles) {
         // counts from LDS histograms of the keys (not global atomics in the
         // previous pass's scatter), then the tile offsets, then the scatter
         if (p > 0)
