@@ -26,7 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
   size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist, qhist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
-  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, partials, staging, stats, long_rows;
+  size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, qrec, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
       qline, tile_q, tile_counts;
   size_t total;
@@ -73,6 +73,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.qk1 = take(4 * N1);
   L.qv1 = take(4 * N1);
   L.counts = take(4 * N1);
+  L.qrec = take(16 * N1);
   L.partials = take(sizeof(int64_t) * (size_t)scan_partials_count(n1));
   L.staging = take(sizeof(int32_t) * kStage * N1);
   L.stats = take(sizeof(unsigned long long) * kNumStats);
@@ -411,6 +412,7 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.reps = idx->at<float>(L.reps);
   A.rinv = idx->at<uint32_t>(L.rinv);
   A.counts = idx->at<uint32_t>(L.counts);
+  A.qrec = nullptr;
   A.row_offsets = row_offsets;
   A.cols = col_indices;
   A.capacity = capacity;
@@ -503,7 +505,11 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
   if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
   EPM_HIP(launch_stab_tiles(A, S.stab_workgroups, mode, S.stab_chunk, stream));
   if (timed) EPM_HIP(hipEventRecord(idx->ev_stop, stream));
-  EPM_HIP(launch_scan_counts(A.counts, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
+  if (A.qrec)
+    EPM_HIP(launch_scan_counts(reinterpret_cast<const uint32_t*>(A.qrec), 4, n1, row_offsets,
+                               idx->at<int64_t>(L.partials), stream));
+  else
+    EPM_HIP(launch_scan_counts(A.counts, 1, n1, row_offsets, idx->at<int64_t>(L.partials), stream));
   return EPM_OK;
 }
 
@@ -718,6 +724,7 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   A.best_idx = c.best_idx;
   A.best_dist = c.best_dist;
   A.second_dist = c.second_dist;
+  A.qrec = idx->at<uint4>(idx->L.qrec);
   // counters of the wide-row selection (certified / listed rows)
   A.match_stats = idx->at<unsigned long long>(idx->L.match_stats);  // cleared with the counters
   idx->have_match_stats = true;

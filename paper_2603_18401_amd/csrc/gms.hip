@@ -142,7 +142,7 @@ hipError_t launch_gms(const GmsArgs& a, int64_t* partials, hipStream_t s) {
   e = launch_fill_u32(a.cursor, cells, 0u, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gms_cells, dim3((unsigned)qb), dim3(kThreads), 0, s, a);
-  e = launch_scan_counts(a.count, cells, const_cast<int64_t*>(a.offsets), partials, s);
+  e = launch_scan_counts(a.count, 1, cells, const_cast<int64_t*>(a.offsets), partials, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gms_scatter, dim3((unsigned)qb), dim3(kThreads), 0, s, a);
   const int64_t cb = (cells + kWaves - 1) / kWaves;

@@ -77,6 +77,12 @@ struct StabArgs {
   const float* reps;
   const uint32_t* rinv;
   uint32_t* counts;
+  // fused selection: per query (original index) one 16-byte record {row
+  // length, best index, best distance, second distance} written in one store
+  // (the count is read by the scan from it, the match by the copy pass);
+  // best index kMatchDeferred: the match comes from a later pass.  NULL: the
+  // counts array and no match.
+  uint4* qrec;
   const int64_t* row_offsets;
   int32_t* cols;
   int64_t capacity;
@@ -157,6 +163,7 @@ constexpr int kStabCount = 0, kStabF32 = 1, kStabBF16 = 2;
 // chunk: window records staged per round (256, 512 or 1024; 0 = 256 for the
 // BF16 pass, 512 for the others).
 hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, hipStream_t s);
+constexpr int32_t kMatchDeferred = INT32_MIN;
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the
 // brute-force long rows.
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
@@ -177,7 +184,9 @@ constexpr int kWideFill = 0, kWideFused = 1, kWideMatchF32 = 2, kWideMatchBF16 =
 hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
-hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,
+// counts[stride * i] is the length of row i (stride 4: the count words of
+// the fused pass's query records).
+hipError_t launch_scan_counts(const uint32_t* counts, int stride, int64_t n, int64_t* offsets,
                               int64_t* partials, hipStream_t s);
 int64_t scan_partials_count(int64_t n);
 

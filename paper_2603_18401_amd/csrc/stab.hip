@@ -183,6 +183,17 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
   wave_sync_lds();
 }
 
+// The fused pass's record of a query: its row length and its match (as
+// write_match_to would store it), or kMatchDeferred for a match that a later
+// pass writes.
+__device__ __forceinline__ uint4 query_record(uint32_t count, float ratio, const Top2& t,
+                                              bool matched) {
+  int32_t idx = t.bj == INT32_MAX ? -1 : t.bj;
+  if (idx >= 0 && ratio > 0.0f && !(t.bd < ratio * ratio * t.sd)) idx = -1;
+  if (!matched) idx = kMatchDeferred;
+  return make_uint4(count, (uint32_t)idx, __float_as_uint(t.bd), __float_as_uint(t.sd));
+}
+
 // ------------------------------------------------------------- tiled pass
 constexpr int kQPerWave = kTileQ / kWaves;
 static_assert(kQPerWave == 16, "the pair test packs four records of 16 queries per wavefront");
@@ -769,7 +780,9 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
     // row, each placing a quarter of its hits by rank (the j of a row are
     // distinct, so a hit's place is the number of smaller hits); a thread
     // ranks up to four of its hits in one pass over the row
-    if (part == 0 && q < T.count) A.counts[qidx[q]] = qmode[q] == kQueryEmpty ? 0u : cnt[q];
+    // (the fused modes write the row length with the match, in one record)
+    if (!FUSE && part == 0 && q < T.count)
+      A.counts[qidx[q]] = qmode[q] == kQueryEmpty ? 0u : cnt[q];
     {
       const uint32_t n = q < T.count && qmode[q] != kQueryEmpty ? cnt[q] : 0u;
       // FUSE keeps only the hits of normal queries in fused windows; other
@@ -803,10 +816,8 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
     if (FUSE) {
       if (part == 0 && q < T.count) {
         const uint32_t mode = qmode[q];
-        if (mode == kQueryEmpty) {
-          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], Top2(),
-                         false);
-        } else if (mode != kQueryNormal || (cnt[q] <= (uint32_t)kStage && !fusable)) {
+        if (mode != kQueryEmpty &&
+            (mode != kQueryNormal || (cnt[q] <= (uint32_t)kStage && !fusable))) {
           const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
           A.rest[at] = (uint32_t)qidx[q];
         }
@@ -858,8 +869,10 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         o.sj = __shfl_xor(best.sj, off);
         best = merge_top2(best, o);
       }
-      if (mine && part == 0)
-        write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qidx[q], best, false);
+      if (part == 0 && q < T.count) {
+        const bool empty = qmode[q] == kQueryEmpty;
+        A.qrec[qidx[q]] = query_record(empty ? 0u : cnt[q], A.ratio, best, mine || empty);
+      }
     } else if constexpr (MODE == kStabBF16) {
       // lane l of wavefront w: query 16 w + (l & 15), lane group g = l >> 4
       const int q2 = wave * kQPerWave + (lane & (kQPerWave - 1));
@@ -1078,10 +1091,10 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           for (int u = 0; u < 8; ++u) wcur[u] = wnext[u];
         }
       }
-      if (mine2 && g == 0) {  // lane group 0 holds the query's selection
-        if (cert) {
-          write_match_to(A.ratio, A.best_idx, A.best_dist, A.second_dist, qi2, best, false);
-        } else {
+      if (g == 0 && q2 < T.count) {  // lane group 0 holds the query's selection
+        const bool empty = qmode[q2] == kQueryEmpty;
+        A.qrec[qi2] = query_record(empty ? 0u : cnt[q2], A.ratio, best, (mine2 && cert) || empty);
+        if (mine2 && !cert) {
           const unsigned long long at = atomicAdd(&A.stats[kStatRest], 1ull);
           A.rest[at] = (uint32_t)qi2;
         }
@@ -1139,6 +1152,19 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   }
 }
 
+// The fused pass's matches, from its per-query records to the caller's
+// arrays (thread per query, all accesses coalesced), unless a later pass
+// writes the query's match.
+__global__ __launch_bounds__(kThreads) void k_write_matches(StabArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= A.n1) return;
+  const uint4 r = A.qrec[i];
+  if ((int32_t)r.y == kMatchDeferred) return;
+  A.best_idx[i] = (int32_t)r.y;
+  A.best_dist[i] = __uint_as_float(r.z);
+  A.second_dist[i] = __uint_as_float(r.w);
+}
+
 // Fill pass, part 2: rebuilds the queued long rows (grid-stride over the
 // queue, whose length only the device knows).
 __global__ __launch_bounds__(kThreads) void k_fill_long(StabArgs A) {
@@ -1172,7 +1198,7 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, 
   return incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(const uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(const uint32_t* __restrict__ counts, int stride,
                                                                 int64_t n,
                                                                 int64_t* __restrict__ partials) {
   __shared__ int64_t sh[kScanThreads];
@@ -1180,7 +1206,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(const uint32_t* 
   int64_t s = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
-    if (idx < n) s += counts[idx];
+    if (idx < n) s += counts[idx * stride];
   }
   int64_t tot;
   block_exclusive_scan(s, sh, &tot);
@@ -1215,7 +1241,7 @@ __device__ __forceinline__ int64_t block_sum(const int64_t* __restrict__ partial
 // Final pass without the top-level scan (few blocks): block b adds up the
 // partial sums of blocks 0 .. b - 1 itself; the last block writes offsets[n].
 __global__ __launch_bounds__(kScanThreads) void k_scan_final_direct(
-    const uint32_t* __restrict__ counts, int64_t n, const int64_t* __restrict__ partials,
+    const uint32_t* __restrict__ counts, int stride, int64_t n, const int64_t* __restrict__ partials,
     int64_t nb, int64_t* __restrict__ offsets) {
   __shared__ int64_t sh[kScanThreads];
   const int64_t before = block_sum(partials, (int64_t)blockIdx.x, sh);
@@ -1223,7 +1249,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final_direct(
   uint32_t v[kScanItems];
   int64_t s = 0;
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? counts[base + k] : 0u;
+    v[k] = base + k < n ? counts[(base + k) * stride] : 0u;
     s += v[k];
   }
   int64_t tot;
@@ -1235,7 +1261,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final_direct(
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) offsets[n] = before + tot;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __restrict__ counts, int stride,
                                                              int64_t n,
                                                              const int64_t* __restrict__ partials,
                                                              int64_t nb,
@@ -1246,7 +1272,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __r
   uint32_t v[kScanItems];
   int64_t s = 0;
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? counts[base + k] : 0u;
+    v[k] = base + k < n ? counts[(base + k) * stride] : 0u;
     s += v[k];
   }
   int64_t tot;
@@ -1307,8 +1333,8 @@ hipError_t launch_stab_chunk(const StabArgs& a, int grid, int mode, const dim3& 
 hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
   if (grid > 0 && !a.queue) return hipErrorInvalidValue;
-  if (mode != kStabCount &&
-      (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist || !a.second_dist || !a.rest))
+  if (mode != kStabCount && (!a.desc1 || !a.desc2 || !a.best_idx || !a.best_dist ||
+                             !a.second_dist || !a.rest || !a.qrec))
     return hipErrorInvalidValue;
   if (mode == kStabBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
@@ -1327,6 +1353,9 @@ hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
   const int64_t cblocks = (a.n1 + kCopyQueries - 1) / kCopyQueries;
+  if (a.qrec)
+    hipLaunchKernelGGL(k_write_matches, dim3((unsigned)((a.n1 + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, a);
   hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)cblocks), dim3(kThreads), 0, s, a);
   // long rows are few and each is latency-bound: up to 2048 workgroups
   // (8192 wavefronts) take them from the queue
@@ -1337,23 +1366,23 @@ hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
 
 int64_t scan_partials_count(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
-hipError_t launch_scan_counts(const uint32_t* counts, int64_t n, int64_t* offsets,
+hipError_t launch_scan_counts(const uint32_t* counts, int stride, int64_t n, int64_t* offsets,
                               int64_t* partials, hipStream_t s) {
   if (n == 0) {
     // offsets[0] = 0 is written by the caller
     return hipSuccess;
   }
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n,
-                     partials);
+  hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, stride,
+                     n, partials);
   if (nb <= kScanDirectBlocks) {  // every block sums the partials before it
     hipLaunchKernelGGL(k_scan_final_direct, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts,
-                       n, partials, nb, offsets);
+                       stride, n, partials, nb, offsets);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
-  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n,
-                     partials, nb, offsets);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, stride,
+                     n, partials, nb, offsets);
   return hipGetLastError();
 }
 
