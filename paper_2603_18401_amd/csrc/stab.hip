@@ -433,13 +433,17 @@ __device__ __forceinline__ void wait_lds_copies() { __builtin_amdgcn_s_waitcnt(0
 //   master; eps_w the BF16 bound u |w^| / (1 - u), u = 2^-8, of a row rounded
 //   to nearest even), and D is within 2e-5 (relative) of |q - w|^2 (130
 //   roundings of 2^-24).
-// Let U2 be the second smallest D_hi of the row.  Two candidates have D <= U2,
-// so a candidate with D_lo > U2 is strictly worse than both and is neither
-// best nor second: the candidates with D_lo <= U2 are evaluated exactly
-// (canonical chains on the masters) and their top-2 is the row's.  Each lane
-// keeps its kBfKeep smallest D_lo (dropping those above its own running U2,
-// which only shrinks); a row whose smallest dropped bound is not above U2 is
-// left to the listed-query match, exact either way.
+// Let U2 be the second smallest D_hi over any set of the row's candidates.
+// Two candidates have D <= U2, so a candidate with D_lo > U2 is strictly
+// worse than both and is neither best nor second: the candidates with
+// D_lo <= U2 are evaluated exactly (canonical chains on the masters) and
+// their top-2 is the row's.  Each lane keeps only the kBfKeep smallest
+// approximate distances A of its hits, with their rows' bound norms; after
+// the last chunk it works out D_lo and D_hi of those (U2 is taken over the
+// row's kept candidates) and, since D_lo grows with A and shrinks with the
+// row norm, a lower bound on D_lo of every pushed-out hit from the smallest
+// pushed-out A and the largest row norm.  A row whose pushed-out bound is not
+// above U2 is left to the listed-query match, exact either way.
 constexpr int kBfRows = 32;  // window rows per chunk: with 256-record rounds, four workgroups per CU
 constexpr int kBfBlocks = kBfRows / 16;     // 16-row MFMA blocks per chunk
 constexpr int kBfStride = 256 + 16;         // LDS bytes per row: 16 rows' reads hit distinct banks
@@ -478,43 +482,71 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Per-lane state of one query's bounds (lane group g of its four lanes).
-struct BfState {
-  float u1 = __builtin_inff(), u2 = __builtin_inff();  // two smallest D_hi seen by this lane
-  float lo[kBfKeep];                                   // kept D_lo, ascending
-  int32_t pos[kBfKeep];                                // their window positions
-  float drop = __builtin_inff();                       // smallest D_lo dropped while needed
-  bool bad = false;                                    // a non-finite bound: not certifiable
 
-  __device__ __forceinline__ BfState() {
+// Per-lane state of one query's selection with deferred bounds (lane group g
+// of its four lanes): the kBfKeep smallest approximate distances
+// A = |q^|^2 + |w^|^2 - 2 q^.w^ seen (FP32, as the bounds take them), with
+// their window positions and their rows' bound norms |w^| rounded up to
+// FP16, the smallest A pushed out of that list and the largest row bound norm
+// seen.  The certified bounds D_lo <= D <= D_hi of the kept candidates, and a
+// lower bound on D_lo of every pushed-out one (D_lo grows with A and shrinks
+// with the row's norm), are worked out once after the last chunk.
+constexpr uint32_t kNoPick = 0xFFFFFFFFu;
+struct BfKeep {
+  float a[kBfKeep];      // ascending
+  uint32_t pk[kBfKeep];  // window position | FP16 bound norm << 16, kNoPick: empty
+  float a_drop = __builtin_inff();
+  float nb_max = 0.0f;
+  bool bad = false;
+
+  __device__ __forceinline__ BfKeep() {
     #pragma unroll
     for (int t = 0; t < kBfKeep; ++t) {
-      lo[t] = __builtin_inff();
-      pos[t] = -1;
+      a[t] = __builtin_inff();
+      pk[t] = kNoPick;
     }
   }
 
-  // Branch-free: the two smallest D_hi, then (unless D_lo is above this
-  // lane's U2, hence above the row's) the sorted insertion of D_lo; the
-  // entry pushed out of the full list lowers `drop`.
-  __device__ __forceinline__ void add(float dlo, float dhi, int32_t v) {
+  __device__ __forceinline__ void add(float at, uint32_t p, float nb) {
     static_assert(kBfKeep == 3, "the insertion network keeps three entries");
-    bad |= !(dlo == dlo) || !(dhi == dhi);
-    u2 = fminf(u2, fmaxf(u1, dhi));
-    u1 = fminf(u1, dhi);
-    const float x = dlo <= u2 ? dlo : __builtin_inff();
-    const bool c0 = x < lo[0], c1 = x < lo[1], c2 = x < lo[2];  // c0 => c1 => c2
-    const float out = c2 ? lo[2] : x;
-    const int32_t out_pos = c2 ? pos[2] : v;  // not inserted: x itself (+inf: nothing)
-    lo[2] = c1 ? lo[1] : (c2 ? x : lo[2]);
-    pos[2] = c1 ? pos[1] : (c2 ? v : pos[2]);
-    lo[1] = c0 ? lo[0] : (c1 ? x : lo[1]);
-    pos[1] = c0 ? pos[0] : (c1 ? v : pos[1]);
-    lo[0] = c0 ? x : lo[0];
-    pos[0] = c0 ? v : pos[0];
-    drop = out_pos >= 0 ? fminf(drop, out) : drop;
+    bad |= !(at == at);
+    nb_max = fmaxf(nb_max, nb);
+    const bool c0 = at < a[0], c1 = at < a[1], c2 = at < a[2];  // c0 => c1 => c2
+    const float out = c2 ? a[2] : at;
+    const bool out_real = c2 ? pk[2] != kNoPick : true;
+    a[2] = c1 ? a[1] : (c2 ? at : a[2]);
+    pk[2] = c1 ? pk[1] : (c2 ? p : pk[2]);
+    a[1] = c0 ? a[0] : (c1 ? at : a[1]);
+    pk[1] = c0 ? pk[0] : (c1 ? p : pk[1]);
+    a[0] = c0 ? at : a[0];
+    pk[0] = c0 ? p : pk[0];
+    a_drop = out_real ? fminf(a_drop, out) : a_drop;
   }
 };
+
+// Certified bounds on the exact canonical distance of a candidate whose
+// approximate distance is `at` and whose row bound norm is at most nb (query
+// terms q_nb, q_db; see the comment above kBfRows).
+__device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float q_db, float& dlo,
+                                          float& dhi) {
+  const float sum = q_nb + nb;
+  const float em = 3e-5f * sum * sum;
+  // sqrt(at +- em) from the hardware reciprocal square root (within a few
+  // ulps): the 1e-6 factors cover it; arguments under 2^-100 take the
+  // trivially valid bounds 0 and 2^-50
+  const float th = fmaxf(at, 0.0f) + em;
+  const float tl = at - em;
+  const float r_hi = th > 0x1p-100f ? th * __builtin_amdgcn_rsqf(th) * (1.0f + 1e-6f) : 0x1p-50f;
+  const float r_lo = tl > 0x1p-100f ? tl * __builtin_amdgcn_rsqf(tl) * (1.0f - 1e-6f) : 0.0f;
+  // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
+  const float ew =
+      q_db + nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
+  // the 1e-6 r_lo term covers the rounding of the two subtractions
+  const float e_lo = fmaxf(r_lo - ew - 1e-6f * r_lo, 0.0f);
+  const float e_hi = r_hi + ew;
+  dlo = e_lo * e_lo * (1.0f - 3e-5f);
+  dhi = e_hi * e_hi * (1.0f + 3e-5f);
+}
 
 // MODE: kStabCount (count and park rows), kStabF32 (FP32 selection fused),
 // kStabBF16 (BF16 bounds with an exact FP32 re-rank, fused).
@@ -909,7 +941,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
       // per-query bound terms, inflated for the FP32 sums (2^-24 per term)
       const float q_nb = sqrtf(qn_part) * (1.0f + 2e-5f);
       const float q_db = sqrtf(qe_part) * (1.0f + 2e-5f) + 1e-30f;
-      BfState st;
+      BfKeep st;
       int cur = g;
       Top2 best;
       uint32_t evals = 0;
@@ -959,7 +991,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
               const float db =
                   nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
-              w_terms[r] = make_float4(sn, nb, db, 0.0f);
+              w_terms[r] = make_float4(sn, nb, db, __uint_as_float(half_up(nb)));
             }
           }
           __syncthreads();
@@ -992,41 +1024,44 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               #pragma unroll
               for (int i = 0; i < 4; ++i)
                 slots |= (uint32_t)((hmask >> (16 * cb + 4 * i + g)) & 1ull) << (4 * cb + i);
-            while (slots != 0u) {
-              const int sl = __builtin_ctz(slots);
-              slots &= slots - 1u;
-              f32x4 av = acc[0];
+            // the slots in a fixed order, a block's four row terms read
+            // together; a slot without a hit leaves the state unchanged
+            #pragma unroll
+            for (int cb = 0; cb < kBfBlocks; ++cb) {
+              if (((slots >> (4 * cb)) & 0xFu) == 0u) continue;
+              float4 wt[4];
               #pragma unroll
-              for (int cb = 1; cb < kBfBlocks; ++cb)
-                if ((sl >> 2) == cb) av = acc[cb];
-              const float sc = (sl & 2) ? ((sl & 1) ? av[3] : av[2]) : ((sl & 1) ? av[1] : av[0]);
-              const int r = 16 * (sl >> 2) + 4 * (sl & 3) + g;
-              const float4 wt = w_terms[r];
-              const float sum = q_nb + wt.y;
-              const float em = 3e-5f * sum * sum;
-              const float at = (qn_part + wt.x) - 2.0f * sc;
-              // sqrt(at +- em) from the hardware reciprocal square root (within
-              // a few ulps): the 1e-6 factors cover it; arguments under 2^-100
-              // take the trivially valid bounds 0 and 2^-50
-              const float th = fmaxf(at, 0.0f) + em;
-              const float tl = at - em;
-              const float r_hi =
-                  th > 0x1p-100f ? th * __builtin_amdgcn_rsqf(th) * (1.0f + 1e-6f) : 0x1p-50f;
-              const float r_lo =
-                  tl > 0x1p-100f ? tl * __builtin_amdgcn_rsqf(tl) * (1.0f - 1e-6f) : 0.0f;
-              const float ew = q_db + wt.z;
-              // the 1e-6 r_lo term covers the rounding of the two subtractions
-              const float e_lo = fmaxf(r_lo - ew - 1e-6f * r_lo, 0.0f);
-              const float e_hi = r_hi + ew;
-              const float dlo = e_lo * e_lo * (1.0f - 3e-5f);
-              const float dhi = e_hi * e_hi * (1.0f + 3e-5f);
-              st.add(dlo, dhi, c0 + r);
+              for (int i = 0; i < 4; ++i) wt[i] = w_terms[16 * cb + 4 * i + g];
+              #pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (!((slots >> (4 * cb + i)) & 1u)) continue;
+                const float at = (qn_part + wt[i].x) - 2.0f * acc[cb][i];
+                st.add(at, (uint32_t)(c0 + 16 * cb + 4 * i + g) | (__float_as_uint(wt[i].w) << 16),
+                       wt[i].y);
+              }
             }
           }
         }
+        // this lane's bounds: the kept candidates' D_lo and D_hi (two
+        // smallest D_hi), and a lower bound on D_lo of the pushed-out ones
+        float klo[kBfKeep];
+        float u1 = __builtin_inff(), u2 = __builtin_inff();
+        #pragma unroll
+        for (int t = 0; t < kBfKeep; ++t) {
+          float dlo = __builtin_inff(), dhi = __builtin_inff();
+          if (st.pk[t] != kNoPick)
+            bf_bounds(st.a[t], half_value(st.pk[t] >> 16), q_nb, q_db, dlo, dhi);
+          klo[t] = dlo;
+          u2 = fminf(u2, fmaxf(u1, dhi));
+          u1 = fminf(u1, dhi);
+        }
+        float dmin = __builtin_inff();
+        if (st.a_drop != __builtin_inff()) {
+          float dhi_unused;
+          bf_bounds(st.a_drop, st.nb_max, q_nb, q_db, dmin, dhi_unused);
+        }
+        bool bad = st.bad || !(u1 == u1) || !(u2 == u2) || !(dmin == dmin);
         // the row's U2 and smallest dropped bound over its four lanes
-        float u1 = st.u1, u2 = st.u2, dmin = st.drop;
-        bool bad = st.bad;
         #pragma unroll
         for (int off = 16; off < kWave; off <<= 1) {
           const float o1 = __shfl_xor(u1, off), o2 = __shfl_xor(u2, off);
@@ -1043,7 +1078,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         uint32_t tmask = 0u;
         #pragma unroll
         for (int t = 0; t < kBfKeep; ++t)
-          if (cert && st.pos[t] >= 0 && st.lo[t] <= u2) tmask |= 1u << t;
+          if (cert && st.pk[t] != kNoPick && klo[t] <= u2) tmask |= 1u << t;
         const uint32_t myn = (uint32_t)__popc(tmask);
         const int qlane = lane & (kQPerWave - 1);
         const uint32_t n0 = (uint32_t)__shfl((int)myn, qlane), n1 = (uint32_t)__shfl((int)myn, qlane + 16),
@@ -1055,7 +1090,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           uint32_t k = before;
           #pragma unroll
           for (int t = 0; t < kBfKeep; ++t)
-            if ((tmask >> t) & 1u) mylist[k++] = (uint16_t)st.pos[t];
+            if ((tmask >> t) & 1u) mylist[k++] = (uint16_t)(st.pk[t] & 0xFFFFu);
         }
         wave_sync_lds();
         // one task of each query per round: the query's four lanes load their
