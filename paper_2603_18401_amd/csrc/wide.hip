@@ -49,16 +49,16 @@ constexpr int kL = 64;                                   // rows per block
 constexpr int kSub = kSC / kL;                           // blocks per super-chunk
 constexpr int kRS = 256 + 16;  // LDS bytes per BF16 row: fragment reads of 16 rows hit distinct banks
 constexpr int kQS = 132;       // floats per FP32 query row of the re-rank (rows start 4 banks apart)
-constexpr int kScoreS = kL + 1;
 constexpr int kPicks = 8;      // exactly re-ranked candidates per query
+constexpr int kMergeMin = 10;  // more survivors than this: merged by wavefront minima
 constexpr int kQPerWave = kTileQ / kWaves;
 constexpr int kRowPer = kL * 32 / kThreads;  // 16-byte pieces of a block's rows per thread
-constexpr int kScoreBytes = kWaves * kQPerWave * kScoreS * 4;
-static_assert(kL == kWave, "one block row per lane");
+static_assert(kL == kWave && kQPerWave == 16, "one block row per lane, 16 queries per wavefront");
 static_assert(kRowPer == 8 && kThreads == 256, "row sums: eight rows per half-wavefront");
 static_assert(kPicks + 1 <= 16, "a query's kept keys are lanes 0 .. kPicks of the first DPP row");
 static_assert(kThreads * 4 == kSlabWords, "four bitmap words per thread in the prefix count");
-static_assert(kTileQ * kQS * 4 <= kL * kRS + kScoreBytes, "FP32 query rows fit the row area");
+static_assert((kTileQ / 2) * kQS * 4 <= kL * kRS, "FP32 rows of half the queries fit the row area");
+static_assert((kTileQ / 2) * kPicks == kThreads, "one pick per thread in the re-rank");
 static_assert(kTileQ * kPicks * 4 <= kSlabWords * 12, "exact distances fit the bitmap area");
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -151,10 +151,10 @@ __device__ __forceinline__ Rows fetch_query_rows(const float* __restrict__ desc,
 // Stores the BF16 copies of 64 rows (stride kRS) and, per row, the squared
 // norm of the BF16 row and the squared norm of its rounding error, summed
 // over the 32 lanes that hold the row's pieces by a transposing butterfly
-// (each step halves the rows a lane keeps); optionally the running maxima of
-// the bound terms sqrt(norm) and sqrt(error), slightly inflated, as float bits.
+// (each step halves the rows a lane keeps); optionally this thread's running
+// maxima of both sums over the rows it summed.
 __device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* nrm, float* err,
-                                           uint32_t* max_nb, uint32_t* max_db, int tid) {
+                                           float* mx_n, float* mx_e, int tid) {
   float sn[kRowPer], se[kRowPer];
   #pragma unroll
   for (int u = 0; u < kRowPer; ++u) {
@@ -195,13 +195,10 @@ __device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* n
     const int r = (tid >> 5) + 8 * (4 * b4 + 2 * b3 + b2);
     nrm[r] = vn;
     if (err) err[r] = ve;
-    if (max_nb) {
-      // relative slack 2e-5 covers the FP32 sums (at most 2^-24 per term)
-      const float nb = (float)(sqrt((double)vn) * (1.0 + 2e-5));
-      const float db = (float)(sqrt((double)ve) * (1.0 + 2e-5) + 1e-30);
-      atomicMax(max_nb, __float_as_uint(nb));
-      atomicMax(max_db, __float_as_uint(db));
-    }
+  }
+  if (mx_n) {  // every lane of the four holds the row's sums
+    *mx_n = fmaxf(*mx_n, vn);
+    *mx_e = fmaxf(*mx_e, ve);
   }
 }
 
@@ -246,10 +243,9 @@ __device__ __forceinline__ float bf16_sq4(uint32_t w0, uint32_t w1) {
 
 // Stores 64 BF16 rows (stride kRS) and their squared norms (sums over the 16
 // lanes of each row's pieces, transposing butterfly as in stage_bf16);
-// optionally the running maxima of sqrt(norm) and of the format's worst-case
-// rounding bound, slightly inflated, as float bits.
-__device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float* nrm,
-                                            uint32_t* max_nb, uint32_t* max_db, int tid) {
+// optionally this thread's running maximum of the norms it summed.
+__device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float* nrm, float* mx_n,
+                                            int tid) {
   float sn[kCodePer];
   #pragma unroll
   for (int u = 0; u < kCodePer; ++u) {
@@ -270,12 +266,8 @@ __device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float*
   if ((lane & 3) == 0) {
     const int r = (tid >> 4) + 16 * (2 * b3 + b2);
     nrm[r] = x;
-    if (max_nb) {
-      const double nb = sqrt((double)x) * (1.0 + 2e-5);
-      atomicMax(max_nb, __float_as_uint((float)nb));
-      atomicMax(max_db, __float_as_uint((float)(row_delta<0>(nb, 1.0) * (1.0 + 1e-6))));
-    }
   }
+  if (mx_n) *mx_n = fmaxf(*mx_n, x);
 }
 
 // One window entry in ascending j: its image-2 index and record.
@@ -285,6 +277,82 @@ struct Entry {
   float2 xy;
   float e;
 };
+
+// Minimum over the wavefront (every lane's value; the result is uniform).
+__device__ __forceinline__ float wave_min(float v) {
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0xB1, 0xF, 0xF, false)));  // quad [1,0,3,2]
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0x4E, 0xF, 0xF, false)));  // quad [2,3,0,1]
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0x141, 0xF, 0xF, false)));  // half-row mirror
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0x140, 0xF, 0xF, false)));  // row mirror
+  // every lane of a row holds the row's minimum: rows 1 and 3 take lane 15 of
+  // the row below, rows 2 and 3 lane 31; lane 63 ends with the minimum of all
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0x142, 0xA, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                          0x143, 0xC, 0xF, false)));
+  return readlane_f(v, kWave - 1);
+}
+
+// Maximum over the wavefront of non-negative values (uniform result).
+__device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
+
+// A 4 x 4 transpose of 16-lane rows across four registers: afterwards row g
+// of register r holds what row r of register g held (v_permlane32_swap swaps
+// the upper half of its first operand with the lower half of its second,
+// v_permlane16_swap the odd rows of its first with the even rows of its second).
+__device__ __forceinline__ void transpose_rows(float& r0, float& r1, float& r2, float& r3) {
+  auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r0), __float_as_uint(r2), false, false);
+  auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r1), __float_as_uint(r3), false, false);
+  auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+  auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+  r0 = __uint_as_float(s01[0]);
+  r1 = __uint_as_float(s01[1]);
+  r2 = __uint_as_float(s23[0]);
+  r3 = __uint_as_float(s23[1]);
+}
+
+// Merges a block's survivors into a query's kept list: lk / lj in lanes
+// 0 .. kK - 1 hold the list (ascending keys, +inf and -1 past its end), the
+// lanes of surv the survivors' keys kv and image-2 indices jv.  The kK
+// smallest keys of both are taken one at a time by wavefront minima and
+// leave lk / lj ascending; returns the largest kept key (+inf while fewer
+// than kK are kept).  Equal keys may be taken in any order.
+template <int kK>
+__device__ __forceinline__ float merge_list(float& lk, int32_t& lj, uint64_t surv, float kv,
+                                            int32_t jv) {
+  const int lane = lane_id();
+  float ca = lk;
+  float cb = (surv >> lane) & 1ull ? kv : __builtin_inff();
+  float nk = __builtin_inff();
+  int32_t nj = -1;
+  #pragma unroll 1
+  for (int r = 0; r < kK; ++r) {
+    const float mn = wave_min(fminf(ca, cb));
+    if (!(mn < __builtin_inff())) break;  // uniform: nothing left
+    const uint64_t at_a = ballot(ca == mn);
+    int32_t js;
+    if (at_a) {
+      const int L = __builtin_ctzll(at_a);
+      js = __builtin_amdgcn_readlane(lj, L);
+      if (lane == L) ca = __builtin_inff();
+    } else {
+      const int L = __builtin_ctzll(ballot(cb == mn));
+      js = __builtin_amdgcn_readlane(jv, L);
+      if (lane == L) cb = __builtin_inff();
+    }
+    if (lane == r) {
+      nk = mn;
+      nj = js;
+    }
+  }
+  lk = nk;
+  lj = nj;
+  return readlane_f(nk, kK - 1);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
@@ -301,16 +369,15 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   __shared__ uint32_t lC[kSC], lH[kSC];
   __shared__ float2 lXY[kSC];
   __shared__ float lE[kSC];
-  __shared__ double qa[kTileQ], qb[kTileQ], qc[kTileQ], qn[kTileQ];
+  __shared__ double4 qline_s[kTileQ];  // a, b, c and sqrt(a^2 + b^2) of each query's line
   __shared__ uint32_t qk[kTileQ], q_len[kTileQ], q_bad[kTileQ];
   __shared__ int64_t q_i[kTileQ], q_o0[kTileQ];
   __shared__ uint32_t slot_b[kSlots], slot_pref[kSlots + 1];
   __shared__ uint64_t wide_mask_s;
   // matching only
   constexpr int kQ = MATCH ? kTileQ : 1;
-  constexpr int kRaw = MATCH ? kL * kRS + kScoreBytes : 16;
-  __shared__ __attribute__((aligned(16))) uint8_t qrows[kQ * kRS];
-  // block rows and per-wavefront scores, then the FP32 query rows
+  constexpr int kRaw = MATCH ? kL * kRS : 16;
+  // BF16 query rows, then block rows, then FP32 query rows of the re-rank
   __shared__ __attribute__((aligned(16))) uint8_t raw[kRaw];
   __shared__ int64_t row_of[MATCH ? kSC : 1];  // global image-2 row of each entry, -1 past the end
   __shared__ float w_norm[MATCH ? kL : 1];
@@ -329,27 +396,21 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   const StabTile T = A.tiles[tile];
   const PairDev& pd = A.pairs[T.pair];
   const int64_t kb = pd.k_begin, n2 = pd.n;
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int tid = threadIdx.x, lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(wave_id());
 
   if (wave == 0) {
     const bool live = lane < T.count;
     int64_t i = 0, o0 = 0, len = 0;
     uint32_t flag = kQueryEmpty, key = 0;
-    double a = 0.0, b = 0.0, c = 0.0;
-    double nrm = 0.0;
+    double4 L = make_double4(0.0, 0.0, 0.0, 0.0);
     if (live) {
       i = A.qperm[T.begin + lane];
       flag = A.qflag[i];
       key = A.qkey[i];
       o0 = A.row_offsets[i];
       len = A.row_offsets[i + 1] - o0;
-      if (flag == kQueryNormal) {
-        const double4 L = A.qline[i];
-        a = L.x;
-        b = L.y;
-        c = L.z;
-        nrm = L.w;
-      }
+      if (flag == kQueryNormal) L = A.qline[i];
     }
     // writing: the long rows of normal queries; matching a caller's CSR:
     // every normal query of the tile
@@ -363,10 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
         if (A.match_stats) atomicAdd(&A.match_stats[2], 1ull);
       }
     }
-    qa[lane] = a;
-    qb[lane] = b;
-    qc[lane] = c;
-    qn[lane] = nrm;
+    qline_s[lane] = L;
     qk[lane] = key;
     q_i[lane] = i;
     q_o0[lane] = o0;
@@ -390,34 +448,37 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   const uint64_t wide_mask = wide_mask_s;
   const int q0 = wave * kQPerWave;  // this wavefront's queries
   const uint32_t wmask = (uint32_t)(wide_mask >> q0) & 0xFFFFu;
-  // lane l holds query q0 + (l & 15): its line, key and row start, its CSR
-  // write position and (match) the largest kept key of its list -- read
-  // through readlane, off the LDS
+  // lane l holds query q0 + (l & 15)'s row start, its CSR write position and
+  // (match) the largest kept key of its list -- read through readlane
   const int ql = q0 + (lane & (kQPerWave - 1));
-  const uint32_t qp_k = qk[ql];
-  const double qp_a = qa[ql], qp_b = qb[ql], qp_c = qc[ql], qp_n = qn[ql];
   const int64_t qp_o0 = q_o0[ql];
   const uint32_t qp_len = q_len[ql];
   uint32_t qp_run = 0u;
   float qp_thr = __builtin_inff();
   uint32_t badbits = 0u;  // matching a caller's CSR: queries whose row differs here
+  // largest squared norm (and rounding error) of the window rows this thread summed
+  float mx_n = 0.0f, mx_e = 0.0f;
 
+  // the MFMA's A operand: BF16 rows of this wavefront's queries, k-slices
+  // 32 kk + 8 (lane >> 4) .. + 7 of row q0 + (lane & 15)
+  bf16x8 afrag[4];
   if (MATCH) {
     for (int t = tid; t < kTileQ * kK; t += kThreads) {
       tkl[t] = __builtin_inff();
       tjl[t] = -1;
     }
+    if (CODES)  // zero rows for the queries that are not wide
+      stage_codes(fetch_query_codes(A.codes1, q_i, wide_mask, tid), raw, q_norm, nullptr, tid);
+    else
+      stage_bf16(fetch_query_rows(A.desc1, q_i, wide_mask, tid), raw, q_norm, q_err, nullptr,
+                 nullptr, tid);
+    __syncthreads();
+    #pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      afrag[kk] = *reinterpret_cast<const bf16x8*>(raw + ql * kRS + (kk * 32 + (lane >> 4) * 8) * 2);
+    // the block rows overwrite these only after the slab set-up's barriers
   }
   uint8_t* wrows = raw;
-  float* score = reinterpret_cast<float*>(raw + kL * kRS) + wave * kQPerWave * kScoreS;
-  if (CODES) {
-    // BF16 query rows (zero rows for the queries that are not wide)
-    stage_codes(fetch_query_codes(A.codes1, q_i, wide_mask, tid), qrows, q_norm, nullptr,
-                nullptr, tid);
-  } else if (MATCH) {
-    stage_bf16(fetch_query_rows(A.desc1, q_i, wide_mask, tid), qrows, q_norm, q_err, nullptr,
-               nullptr, tid);
-  }
 
   const int64_t total_len = slot_pref[kSlots];
   const int64_t nslabs = (n2 + kSlabBits - 1) / kSlabBits;
@@ -525,90 +586,108 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
       for (int sub = 0; sub < kSub; ++sub) {
         const int base = sub * kL;
         if (e0 + base >= E) break;  // uniform
-        float wn = 0.0f;
+        // approximate keys |w^|^2 - 2 q^.w^ of this lane's entry base + lane
+        // for the wavefront's 16 queries
+        float kf[kQPerWave];
         if (MATCH) {
-          if (CODES) stage_codes(prc, wrows, w_norm, &max_nb, &max_db, tid);
-          else stage_bf16(pre, wrows, w_norm, nullptr, &max_nb, &max_db, tid);
+          if (CODES) stage_codes(prc, wrows, w_norm, &mx_n, tid);
+          else stage_bf16(pre, wrows, w_norm, nullptr, &mx_n, &mx_e, tid);
           __syncthreads();  // block rows and norms complete
-          wn = w_norm[lane];
+          const float wn = w_norm[lane];
           if (sub + 1 < kSub && e0 + base + kL < E) {
             if (CODES) prc = fetch_codes(A.codes2, row_of + base + kL, tid);
             else pre = fetch_rows(A.desc2, row_of + base + kL, tid);
           }
-          // S = Q W^T: wavefront w owns queries 16w .. 16w + 15 against the 64 rows
+          // S = Q W^T: the wavefront's 16 queries against the 64 rows; lane
+          // (g, c) = (lane >> 4, lane & 15) gets S[4 g + i][16 cb + c] in acc[cb][i]
           f32x4 acc[4];
           #pragma unroll
           for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-          const int arow = q0 + (lane & 15);
           #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
             const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(qrows + arow * kRS + koff * 2);
             #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
               const bf16x8 b = *reinterpret_cast<const bf16x8*>(
                   wrows + (cb * 16 + (lane & 15)) * kRS + koff * 2);
-              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag[kk], b, acc[cb], 0, 0, 0);
             }
           }
-          #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
-            #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              score[((lane >> 4) * 4 + i) * kScoreS + cb * 16 + (lane & 15)] = acc[cb][i];
-          }
           __syncthreads();  // every wavefront has read the block rows
+          // exchange rows and blocks: lane (g, c) then holds S[4 r + i][16 g + c],
+          // the scores of its own entry 16 g + c, in acc[r][i]
+          #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float r0 = acc[0][i], r1 = acc[1][i], r2 = acc[2][i], r3 = acc[3][i];
+            transpose_rows(r0, r1, r2, r3);
+            kf[i] = __builtin_fmaf(-2.0f, r0, wn);
+            kf[4 + i] = __builtin_fmaf(-2.0f, r1, wn);
+            kf[8 + i] = __builtin_fmaf(-2.0f, r2, wn);
+            kf[12 + i] = __builtin_fmaf(-2.0f, r3, wn);
+          }
         }
         if (sub == 0 && nj >= 0) nxt = load_entry(nj);
-        // this lane's row of the block
+        // this lane's entry of the block
         const int32_t ej = lj[base + lane];
         const uint32_t eC = lC[base + lane], eH = lH[base + lane];
         const float2 exy = lXY[base + lane];
         const double ex = (double)exy.x, ey = (double)exy.y, ee = (double)lE[base + lane];
-        // keys |w^|^2 - 2 q^.w^ of the row for the wavefront's queries
-        float kf[kQPerWave];
-        if (MATCH) {
-          #pragma unroll
-          for (int qq = 0; qq < kQPerWave; ++qq)
-            kf[qq] = __builtin_fmaf(-2.0f, score[qq * kScoreS + lane], wn);
-        }
-        // every query of the wavefront against the block: one ballot gives
-        // the query's hits, which extend (or are checked against) its CSR row
-        // and feed its selection
-        int32_t got[kQPerWave];
+        const bool live_e = ej >= 0;
+        // 1. hit masks: every query of the wavefront against the block
+        // (angle test, then the FP64 test of Eq. 3), one ballot per query
+        int qb = q0;
+        asm volatile("" : "+s"(qb));  // the queries' terms are read here, not kept in registers
+        uint64_t hm[kQPerWave];
         #pragma unroll
         for (int qq = 0; qq < kQPerWave; ++qq) {
-          got[qq] = ej;
-          if (!((wmask >> qq) & 1u)) continue;
-          bool hit = false;
-          if (ej >= 0 && key_distance((uint32_t)__builtin_amdgcn_readlane((int)qp_k, qq), eC) <= eH)
-            hit = within_tolerance_d(readlane_d(qp_a, qq), readlane_d(qp_b, qq),
-                                     readlane_d(qp_c, qq), readlane_d(qp_n, qq), ex, ey, ee);
-          const uint64_t m = ballot(hit);
+          const double4 L = qline_s[qb + qq];
+          const uint32_t k = qk[qb + qq];
+          const bool hit = live_e & (key_distance(k, eC) <= eH) &
+                           within_tolerance_d(L.x, L.y, L.z, L.w, ex, ey, ee);
+          hm[qq] = ballot(hit) & (0ull - (uint64_t)((wmask >> qq) & 1u));
+          if ((qq & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four queries' terms at a time
+        }
+        // 2. the hits extend (or are checked against) the queries' CSR rows,
+        // in ascending j
+        #pragma unroll
+        for (int qq = 0; qq < kQPerWave; ++qq) {
+          const uint64_t m = hm[qq];
+          if (m == 0ull) continue;  // uniform
           const uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)qp_run, qq);
-          if (hit) {
+          if ((m >> lane) & 1ull) {
             const uint32_t k = run + lanes_below(m);
             const int64_t dst = (int64_t)readlane_u64((uint64_t)qp_o0, qq) + k;
             if (WRITE) {
               if (dst < A.capacity) A.cols[dst] = ej;
             } else {
               // the caller's row must hold this hit at this place
-              got[qq] = k < (uint32_t)__builtin_amdgcn_readlane((int)qp_len, qq) ? A.cols[dst] : -2;
+              const int32_t got =
+                  k < (uint32_t)__builtin_amdgcn_readlane((int)qp_len, qq) ? A.cols[dst] : -2;
+              if (got != ej) badbits |= 1u << qq;
             }
           }
           if ((lane & (kQPerWave - 1)) == qq) qp_run = run + (uint32_t)__popcll(m);
-          if (MATCH) {
-            // only hits below the kept (kPicks+1)-th key enter the list
+        }
+        // 3. (match) hits below a query's kept (kPicks+1)-th key enter its list
+        if (MATCH) {
+          // this lane's slot of the wavefront's first list (constant offsets from here)
+          float* const tk0 = tkl + q0 * kK + lane;
+          int32_t* const tj0 = tjl + q0 * kK + lane;
+          #pragma unroll
+          for (int qq = 0; qq < kQPerWave; ++qq) {
+            const uint64_t m = hm[qq];
+            if (m == 0ull) continue;
             const float th0 = readlane_f(qp_thr, qq);
-            uint64_t surv = ballot(hit && kf[qq] < th0);
-            if (surv) {
-              // the list in lanes 0 .. kPicks while the survivors enter it
-              const int q = q0 + qq;
-              const bool in = lane < kK;
-              float lk = in ? tkl[q * kK + lane] : __builtin_inff();
-              int32_t lji = in ? tjl[q * kK + lane] : -1;
-              float th = th0;
-              do {
+            uint64_t surv = m & ballot(kf[qq] < th0);
+            if (surv == 0ull) continue;
+            const bool in = lane < kK;
+            float lk = in ? tk0[qq * kK] : __builtin_inff();
+            int32_t lji = in ? tj0[qq * kK] : -1;
+            float th = th0;
+            if (__popcll(surv) > kMergeMin) {
+              th = merge_list<kK>(lk, lji, surv, kf[qq], ej);
+            } else {
+              do {  // one survivor at a time
                 const int sl = __builtin_ctzll(surv);
                 surv &= surv - 1;
                 const float ks = readlane_f(kf[qq], sl);
@@ -628,18 +707,13 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
                 }
                 th = readlane_f(lk, kPicks);
               } while (surv);
-              if (in) {
-                tkl[q * kK + lane] = lk;
-                tjl[q * kK + lane] = lji;
-              }
-              if ((lane & (kQPerWave - 1)) == qq) qp_thr = th;
             }
+            if (in) {
+              tk0[qq * kK] = lk;
+              tj0[qq * kK] = lji;
+            }
+            if ((lane & (kQPerWave - 1)) == qq) qp_thr = th;
           }
-        }
-        if (!WRITE) {
-          #pragma unroll
-          for (int qq = 0; qq < kQPerWave; ++qq)
-            if (got[qq] != ej) badbits |= 1u << qq;
         }
       }
       __syncthreads();  // the super-chunk's entries are dead
@@ -652,6 +726,19 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
   }
 
   if (!MATCH) return;
+  {
+    // the largest row terms of the window (the bound terms are monotone in
+    // the sums): relative slack 2e-5 covers the FP32 sums (at most 2^-24 per term)
+    const float wn_max = wave_max(mx_n);
+    const float we_max = wave_max(mx_e);
+    if (lane == 0) {
+      const double nb = sqrt((double)wn_max) * (1.0 + 2e-5);
+      const double db = CODES ? row_delta<0>(nb, 1.0) * (1.0 + 1e-6)
+                              : sqrt((double)we_max) * (1.0 + 2e-5) + 1e-30;
+      atomicMax(&max_nb, __float_as_uint((float)nb));
+      atomicMax(&max_db, __float_as_uint((float)db));
+    }
+  }
   if (!WRITE) {
     // rows that differ from the tile's candidate sets (a hit missing or out
     // of place, or a different length) are evaluated exactly
@@ -661,33 +748,32 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
       if (lane == qq) q_bad[q0 + qq] = bad || qp_run != qp_len ? 1u : 0u;
     }
   }
-  // the picks are the first kPicks of every list; the row area holds the
-  // FP32 query rows now, the bitmap area the exact distances
+  // the picks are the first kPicks of every list; the bitmap area holds their
+  // exact distances, the row area the FP32 rows of half the queries at a time
   const float* pk = tkl;
   const int32_t* pj = tjl;
   float* pdist = reinterpret_cast<float*>(slab_raw);  // [kTileQ][kPicks]
-  float* qf = reinterpret_cast<float*>(raw);          // [kTileQ][kQS]
-  {
-    const Rows R = fetch_query_rows(A.desc1, q_i, wide_mask, tid);
+  float* qf = reinterpret_cast<float*>(raw);          // [kTileQ / 2][kQS]
+  constexpr int kHalf = kTileQ / 2;
+  #pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();  // the row area is free
     #pragma unroll
-    for (int u = 0; u < kRowPer; ++u) {
-      const int f = tid + u * kThreads;
-      reinterpret_cast<float4*>(qf + (f >> 5) * kQS)[f & 31] = R.v[u];
+    for (int u = 0; u < kHalf * 32 / kThreads; ++u) {
+      const int f = tid + u * kThreads, r = f >> 5, q = kHalf * h + r;
+      reinterpret_cast<float4*>(qf + r * kQS)[f & 31] =
+          (wide_mask >> q) & 1ull ? reinterpret_cast<const float4*>(A.desc1)[q_i[q] * 32 + (f & 31)]
+                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-  }
-  __syncthreads();
-  // exact canonical distances of the picks: thread = (query, picks sp, sp + 4, ...)
-  {
-    const int sq = tid >> 2, sp = tid & 3;
-    #pragma unroll
-    for (int u = sp; u < kPicks; u += 4) {
-      float d = __builtin_inff();
-      const int32_t j = pj[sq * kK + u];
-      if (((wide_mask >> sq) & 1ull) && j >= 0)
-        d = exact_distance(reinterpret_cast<const float4*>(qf + sq * kQS),
-                           reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32);
-      pdist[sq * kPicks + u] = d;
-    }
+    __syncthreads();
+    // exact canonical distances of the picks: thread = (query, pick)
+    const int r = tid / kPicks, u = tid % kPicks, sq = kHalf * h + r;
+    float d = __builtin_inff();
+    const int32_t j = pj[sq * kK + u];
+    if (((wide_mask >> sq) & 1ull) && j >= 0)
+      d = exact_distance(reinterpret_cast<const float4*>(qf + r * kQS),
+                         reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32);
+    pdist[sq * kPicks + u] = d;
   }
   __syncthreads();
   if (tid < kTileQ && ((wide_mask >> tid) & 1ull)) {
