@@ -50,7 +50,7 @@ constexpr int kSub = kSC / kL;                           // blocks per super-chu
 constexpr int kRS = 256 + 16;  // LDS bytes per BF16 row: fragment reads of 16 rows hit distinct banks
 constexpr int kQS = 132;       // floats per FP32 query row of the re-rank (rows start 4 banks apart)
 constexpr int kPicks = 8;      // exactly re-ranked candidates per query
-constexpr int kMergeMin = 10;  // more survivors than this: merged by wavefront minima
+constexpr int kMergeMin = 16;  // more survivors than this: merged by wavefront minima
 constexpr int kQPerWave = kTileQ / kWaves;
 constexpr int kRowPer = kL * 32 / kThreads;  // 16-byte pieces of a block's rows per thread
 static_assert(kL == kWave && kQPerWave == 16, "one block row per lane, 16 queries per wavefront");
@@ -116,6 +116,18 @@ __device__ __forceinline__ float row_shift_up(float v) {
   return __int_as_float(row_shift_up(__float_as_int(v)));
 }
 
+// Value of lane l ^ M (M < 32): DPP quad permutations for 1 and 2, the
+// swizzle's bit mode (and 0x1F, xor M within each half) otherwise -- neither
+// needs an address register.
+template <int M>
+__device__ __forceinline__ float xor_lanes(float v) {
+  static_assert(M > 0 && M < 32 && (M & (M - 1)) == 0, "a single lane bit");
+  const int x = __float_as_int(v);
+  if (M == 1) return __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));
+  if (M == 2) return __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x1F | (M << 10)));
+}
+
 // 64 FP32 rows (row r = piece f >> 5 of this thread, f = tid + kThreads u),
 // loaded ahead of their use.
 struct Rows {
@@ -176,21 +188,21 @@ __device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* n
   float tn[4], te[4];
   #pragma unroll
   for (int v = 0; v < 4; ++v) {  // keep rows 4 b4 + v
-    tn[v] = (b4 ? sn[4 + v] : sn[v]) + __shfl_xor(b4 ? sn[v] : sn[4 + v], 16);
-    te[v] = (b4 ? se[4 + v] : se[v]) + __shfl_xor(b4 ? se[v] : se[4 + v], 16);
+    tn[v] = (b4 ? sn[4 + v] : sn[v]) + xor_lanes<16>(b4 ? sn[v] : sn[4 + v]);
+    te[v] = (b4 ? se[4 + v] : se[v]) + xor_lanes<16>(b4 ? se[v] : se[4 + v]);
   }
   float un[2], ue[2];
   #pragma unroll
   for (int v = 0; v < 2; ++v) {  // keep rows 4 b4 + 2 b3 + v
-    un[v] = (b3 ? tn[2 + v] : tn[v]) + __shfl_xor(b3 ? tn[v] : tn[2 + v], 8);
-    ue[v] = (b3 ? te[2 + v] : te[v]) + __shfl_xor(b3 ? te[v] : te[2 + v], 8);
+    un[v] = (b3 ? tn[2 + v] : tn[v]) + xor_lanes<8>(b3 ? tn[v] : tn[2 + v]);
+    ue[v] = (b3 ? te[2 + v] : te[v]) + xor_lanes<8>(b3 ? te[v] : te[2 + v]);
   }
-  float vn = (b2 ? un[1] : un[0]) + __shfl_xor(b2 ? un[0] : un[1], 4);
-  float ve = (b2 ? ue[1] : ue[0]) + __shfl_xor(b2 ? ue[0] : ue[1], 4);
-  vn += __shfl_xor(vn, 2);
-  ve += __shfl_xor(ve, 2);
-  vn += __shfl_xor(vn, 1);
-  ve += __shfl_xor(ve, 1);
+  float vn = (b2 ? un[1] : un[0]) + xor_lanes<4>(b2 ? un[0] : un[1]);
+  float ve = (b2 ? ue[1] : ue[0]) + xor_lanes<4>(b2 ? ue[0] : ue[1]);
+  vn += xor_lanes<2>(vn);
+  ve += xor_lanes<2>(ve);
+  vn += xor_lanes<1>(vn);
+  ve += xor_lanes<1>(ve);
   if ((lane & 3) == 0) {
     const int r = (tid >> 5) + 8 * (4 * b4 + 2 * b3 + b2);
     nrm[r] = vn;
@@ -259,10 +271,10 @@ __device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float*
   float t[2];
   #pragma unroll
   for (int v = 0; v < 2; ++v)  // keep rows 2 b3 + v of the group's four
-    t[v] = (b3 ? sn[2 + v] : sn[v]) + __shfl_xor(b3 ? sn[v] : sn[2 + v], 8);
-  float x = (b2 ? t[1] : t[0]) + __shfl_xor(b2 ? t[0] : t[1], 4);
-  x += __shfl_xor(x, 2);
-  x += __shfl_xor(x, 1);
+    t[v] = (b3 ? sn[2 + v] : sn[v]) + xor_lanes<8>(b3 ? sn[v] : sn[2 + v]);
+  float x = (b2 ? t[1] : t[0]) + xor_lanes<4>(b2 ? t[0] : t[1]);
+  x += xor_lanes<2>(x);
+  x += xor_lanes<1>(x);
   if ((lane & 3) == 0) {
     const int r = (tid >> 4) + 16 * (2 * b3 + b2);
     nrm[r] = x;
@@ -355,7 +367,7 @@ __device__ __forceinline__ float merge_list(float& lk, int32_t& lj, uint64_t sur
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
+__global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_tile(StabArgs A) {
   constexpr bool MATCH = MODE != kWideFill;
   constexpr bool WRITE = MODE == kWideFill || MODE == kWideFused;  // writes the CSR
   constexpr bool CODES = MODE == kWideMatchBF16;                     // caller's BF16 codes
@@ -586,44 +598,15 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
       for (int sub = 0; sub < kSub; ++sub) {
         const int base = sub * kL;
         if (e0 + base >= E) break;  // uniform
-        // approximate keys |w^|^2 - 2 q^.w^ of this lane's entry base + lane
-        // for the wavefront's 16 queries
-        float kf[kQPerWave];
+        float wn = 0.0f;
         if (MATCH) {
           if (CODES) stage_codes(prc, wrows, w_norm, &mx_n, tid);
           else stage_bf16(pre, wrows, w_norm, nullptr, &mx_n, &mx_e, tid);
           __syncthreads();  // block rows and norms complete
-          const float wn = w_norm[lane];
+          wn = w_norm[lane];
           if (sub + 1 < kSub && e0 + base + kL < E) {
             if (CODES) prc = fetch_codes(A.codes2, row_of + base + kL, tid);
             else pre = fetch_rows(A.desc2, row_of + base + kL, tid);
-          }
-          // S = Q W^T: the wavefront's 16 queries against the 64 rows; lane
-          // (g, c) = (lane >> 4, lane & 15) gets S[4 g + i][16 cb + c] in acc[cb][i]
-          f32x4 acc[4];
-          #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-          #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
-            #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-              const bf16x8 b = *reinterpret_cast<const bf16x8*>(
-                  wrows + (cb * 16 + (lane & 15)) * kRS + koff * 2);
-              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag[kk], b, acc[cb], 0, 0, 0);
-            }
-          }
-          __syncthreads();  // every wavefront has read the block rows
-          // exchange rows and blocks: lane (g, c) then holds S[4 r + i][16 g + c],
-          // the scores of its own entry 16 g + c, in acc[r][i]
-          #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float r0 = acc[0][i], r1 = acc[1][i], r2 = acc[2][i], r3 = acc[3][i];
-            transpose_rows(r0, r1, r2, r3);
-            kf[i] = __builtin_fmaf(-2.0f, r0, wn);
-            kf[4 + i] = __builtin_fmaf(-2.0f, r1, wn);
-            kf[8 + i] = __builtin_fmaf(-2.0f, r2, wn);
-            kf[12 + i] = __builtin_fmaf(-2.0f, r3, wn);
           }
         }
         if (sub == 0 && nj >= 0) nxt = load_entry(nj);
@@ -667,6 +650,38 @@ __global__ __launch_bounds__(kThreads) void k_wide_tile(StabArgs A) {
             }
           }
           if ((lane & (kQPerWave - 1)) == qq) qp_run = run + (uint32_t)__popcll(m);
+        }
+        // approximate keys |w^|^2 - 2 q^.w^ of this lane's entry base + lane
+        // for the wavefront's 16 queries
+        float kf[kQPerWave];
+        if (MATCH) {
+          // S = Q W^T: the wavefront's 16 queries against the 64 rows; lane
+          // (g, c) = (lane >> 4, lane & 15) gets S[4 g + i][16 cb + c] in acc[cb][i]
+          f32x4 acc[4];
+          #pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[cb] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+          #pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int koff = kk * 32 + (lane >> 4) * 8;  // element offset of this lane's 8 values
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                  wrows + (cb * 16 + (lane & 15)) * kRS + koff * 2);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag[kk], b, acc[cb], 0, 0, 0);
+            }
+          }
+          __syncthreads();  // every wavefront has read the block rows
+          // exchange rows and blocks: lane (g, c) then holds S[4 r + i][16 g + c],
+          // the scores of its own entry 16 g + c, in acc[r][i]
+          #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float r0 = acc[0][i], r1 = acc[1][i], r2 = acc[2][i], r3 = acc[3][i];
+            transpose_rows(r0, r1, r2, r3);
+            kf[i] = __builtin_fmaf(-2.0f, r0, wn);
+            kf[4 + i] = __builtin_fmaf(-2.0f, r1, wn);
+            kf[8 + i] = __builtin_fmaf(-2.0f, r2, wn);
+            kf[12 + i] = __builtin_fmaf(-2.0f, r3, wn);
+          }
         }
         // 3. (match) hits below a query's kept (kPicks+1)-th key enter its list
         if (MATCH) {
