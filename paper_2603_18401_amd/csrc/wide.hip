@@ -180,8 +180,8 @@ __device__ __forceinline__ void stage_bf16(const Rows& R, uint8_t* dst, float* n
                 y2 = __uint_as_float(w.y << 16), y3 = __uint_as_float(w.y & 0xFFFF0000u);
     // x - y is exact in FP32 (y is x rounded to fewer bits)
     const float e0 = x.x - y0, e1 = x.y - y1, e2 = x.z - y2, e3 = x.w - y3;
-    sn[u] = y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3;
-    se[u] = e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+    sn[u] = __builtin_fmaf(y3, y3, __builtin_fmaf(y2, y2, __builtin_fmaf(y1, y1, y0 * y0)));
+    se[u] = __builtin_fmaf(e3, e3, __builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
   }
   const int lane = lane_id();
   const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
@@ -290,27 +290,34 @@ struct Entry {
   float e;
 };
 
-// Minimum over the wavefront (every lane's value; the result is uniform).
-__device__ __forceinline__ float wave_min(float v) {
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0xB1, 0xF, 0xF, false)));  // quad [1,0,3,2]
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0x4E, 0xF, 0xF, false)));  // quad [2,3,0,1]
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0x141, 0xF, 0xF, false)));  // half-row mirror
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0x140, 0xF, 0xF, false)));  // row mirror
-  // every lane of a row holds the row's minimum: rows 1 and 3 take lane 15 of
-  // the row below, rows 2 and 3 lane 31; lane 63 ends with the minimum of all
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0x142, 0xA, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
-                                                          0x143, 0xC, 0xF, false)));
-  return readlane_f(v, kWave - 1);
+// Signed-integer image of a float that keeps the order of non-NaN values
+// (negative values get their magnitude bits flipped).
+__device__ __forceinline__ int32_t order_key(float f) {
+  const int32_t b = __float_as_int(f);
+  return b >= 0 ? b : b ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float order_key_inv(int32_t k) {
+  return __int_as_float(k >= 0 ? k : k ^ 0x7FFFFFFF);
 }
 
-// Maximum over the wavefront of non-negative values (uniform result).
-__device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
+// Minimum over the wavefront (uniform result): lanes take the minimum with a
+// neighbour's value by DPP, INT32_MAX standing in where no neighbour is given.
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x141, 0xF, 0xF, false));  // half-row mirror
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x140, 0xF, 0xF, false));  // row mirror
+  // every lane of a row holds the row's minimum: rows 1 and 3 take lane 15 of
+  // the row below, rows 2 and 3 lane 31; lane 63 ends with the minimum of all
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xA, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+// Maximum over the wavefront of non-negative floats (uniform result).
+__device__ __forceinline__ float wave_max(float v) {
+  return __int_as_float(-wave_min(-__float_as_int(v)));
+}
 
 // A 4 x 4 transpose of 16-lane rows across four registers: afterwards row g
 // of register r holds what row r of register g held (v_permlane32_swap swaps
@@ -337,27 +344,28 @@ template <int kK>
 __device__ __forceinline__ float merge_list(float& lk, int32_t& lj, uint64_t surv, float kv,
                                             int32_t jv) {
   const int lane = lane_id();
-  float ca = lk;
-  float cb = (surv >> lane) & 1ull ? kv : __builtin_inff();
+  constexpr int32_t kInf = 0x7F800000;  // order_key(+inf)
+  int32_t ca = order_key(lk);
+  int32_t cb = (surv >> lane) & 1ull ? order_key(kv) : INT32_MAX;
   float nk = __builtin_inff();
   int32_t nj = -1;
   #pragma unroll 1
   for (int r = 0; r < kK; ++r) {
-    const float mn = wave_min(fminf(ca, cb));
-    if (!(mn < __builtin_inff())) break;  // uniform: nothing left
+    const int32_t mn = wave_min(min(ca, cb));
+    if (mn >= kInf) break;  // uniform: nothing left
     const uint64_t at_a = ballot(ca == mn);
     int32_t js;
     if (at_a) {
       const int L = __builtin_ctzll(at_a);
       js = __builtin_amdgcn_readlane(lj, L);
-      if (lane == L) ca = __builtin_inff();
+      if (lane == L) ca = INT32_MAX;
     } else {
       const int L = __builtin_ctzll(ballot(cb == mn));
       js = __builtin_amdgcn_readlane(jv, L);
-      if (lane == L) cb = __builtin_inff();
+      if (lane == L) cb = INT32_MAX;
     }
     if (lane == r) {
-      nk = mn;
+      nk = order_key_inv(mn);
       nj = js;
     }
   }
@@ -436,6 +444,8 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
         if (A.match_stats) atomicAdd(&A.match_stats[2], 1ull);
       }
     }
+    // a NaN norm fails every test of Eq. 3: the queries that are not wide hit nothing
+    if (!wide) L.w = __builtin_nan("");
     qline_s[lane] = L;
     qk[lane] = key;
     q_i[lane] = i;
@@ -459,8 +469,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   __syncthreads();
   const uint64_t wide_mask = wide_mask_s;
   const int q0 = wave * kQPerWave;  // this wavefront's queries
-  const uint32_t wmask = (uint32_t)(wide_mask >> q0) & 0xFFFFu;
-  // lane l holds query q0 + (l & 15)'s row start, its CSR write position and
+  // lane l < 16 holds query q0 + l's row start, its CSR write position and
   // (match) the largest kept key of its list -- read through readlane
   const int ql = q0 + (lane & (kQPerWave - 1));
   const int64_t qp_o0 = q_o0[ql];
@@ -618,8 +627,10 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
         const bool live_e = ej >= 0;
         // 1. hit masks: every query of the wavefront against the block
         // (angle test, then the FP64 test of Eq. 3), one ballot per query
-        int qb = q0;
-        asm volatile("" : "+s"(qb));  // the queries' terms are read here, not kept in registers
+        // the queries' terms are read here and the lane tests made here, not
+        // kept in registers across blocks
+        int qb = q0, lsel = lane;
+        asm volatile("" : "+s"(qb), "+v"(lsel));
         uint64_t hm[kQPerWave];
         #pragma unroll
         for (int qq = 0; qq < kQPerWave; ++qq) {
@@ -627,7 +638,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
           const uint32_t k = qk[qb + qq];
           const bool hit = live_e & (key_distance(k, eC) <= eH) &
                            within_tolerance_d(L.x, L.y, L.z, L.w, ex, ey, ee);
-          hm[qq] = ballot(hit) & (0ull - (uint64_t)((wmask >> qq) & 1u));
+          hm[qq] = ballot(hit);
           if ((qq & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four queries' terms at a time
         }
         // 2. the hits extend (or are checked against) the queries' CSR rows,
@@ -649,7 +660,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
               if (got != ej) badbits |= 1u << qq;
             }
           }
-          if ((lane & (kQPerWave - 1)) == qq) qp_run = run + (uint32_t)__popcll(m);
+          if (lsel == qq) qp_run = run + (uint32_t)__popcll(m);
         }
         // approximate keys |w^|^2 - 2 q^.w^ of this lane's entry base + lane
         // for the wavefront's 16 queries
@@ -727,7 +738,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
               tk0[qq * kK] = lk;
               tj0[qq * kK] = lji;
             }
-            if ((lane & (kQPerWave - 1)) == qq) qp_thr = th;
+            if (lsel == qq) qp_thr = th;
           }
         }
       }
