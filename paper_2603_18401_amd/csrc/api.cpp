@@ -28,7 +28,7 @@ struct Layout {
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, qrec, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
-      qline, tile_q, tile_counts;
+      pair_wide, qline, tile_q, tile_counts;
   size_t total;
 };
 
@@ -87,6 +87,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.block_tile = take(sizeof(uint32_t) * ts);
   L.rest = take(sizeof(uint32_t) * N1);
   L.tile_wide = take(sizeof(uint32_t) * ts);
+  L.pair_wide = take(sizeof(uint32_t) * P);
   L.qline = take(sizeof(double4) * N1);
   L.tile_q = take(sizeof(TileQuery) * kTileQ * (size_t)ts);
   L.tile_counts = take(sizeof(unsigned long long) * kTileCounts * (size_t)ts);
@@ -436,6 +437,9 @@ StabArgs stab_args(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
   A.second_dist = nullptr;
   A.rest = idx->at<uint32_t>(L.rest);
   A.tile_wide = idx->at<uint32_t>(L.tile_wide);
+  A.pair_wide = idx->at<uint32_t>(L.pair_wide);
+  A.wcodes2 = nullptr;
+  A.wterms2 = nullptr;
   A.match_stats = nullptr;
   A.qline = idx->at<double4>(L.qline);
   A.codes1 = nullptr;
@@ -515,10 +519,25 @@ epm_status enqueue_count(epm_index* idx, StabArgs& A, int64_t* row_offsets,
 
 // CSR fill after the scan: parked short rows, brute-force long rows, then the
 // wide-row pass (match: with its FP32 selection, see launch_wide_tiles).
-epm_status enqueue_fill(epm_index* idx, const StabArgs& A, hipStream_t stream,
-                        bool match = false) {
+// BF16 copies of the image-2 rows of the pairs with wide tiles, for a
+// matching wide-row pass (A.desc2 set): they go to the staging area, whose
+// parked rows the fill pass has copied out by then, when it holds 256 bytes
+// of codes and 8 of terms per row; otherwise the pass rounds on chip.
+hipError_t prepare_wide_rows(epm_index* idx, StabArgs& A, hipStream_t stream) {
+  const size_t n2 = (size_t)idx->N2;
+  const size_t codes = align_up(n2 * 256), terms = n2 * sizeof(float2);
+  const size_t room = sizeof(int32_t) * kStage * (size_t)idx->N1;
+  if (n2 == 0 || !A.desc2 || codes + terms > room) return hipSuccess;
+  char* base = reinterpret_cast<char*>(idx->at<int32_t>(idx->L.staging));
+  A.wcodes2 = reinterpret_cast<const uint16_t*>(base);
+  A.wterms2 = reinterpret_cast<const float2*>(base + codes);
+  return launch_round_rows(A, (int64_t)n2, stream);
+}
+
+epm_status enqueue_fill(epm_index* idx, StabArgs& A, hipStream_t stream, bool match = false) {
   if (idx->N1 == 0) return EPM_OK;
   EPM_HIP(launch_fill_rows(A, stream));
+  if (match) EPM_HIP(prepare_wide_rows(idx, A, stream));
   const bool timed = idx->ev_start && idx->timed == EPM_TIMED_WIDE;
   if (timed) EPM_HIP(hipEventRecord(idx->ev_start, stream));
   EPM_HIP(launch_wide_tiles(A, match ? kWideFused : kWideFill, stream));
@@ -666,6 +685,10 @@ epm_status enqueue_match_kernels(epm_index* idx, const MatchCall& c, hipStream_t
     W.match_stats = A.match_stats;
     W.rest_count = A.match_stats + kMatchStatRest;
     W.block_tile = A.block_tile;
+    if (!bf) {
+      const hipError_t pe = prepare_wide_rows(idx, W, stream);
+      if (pe != hipSuccess) return pe;
+    }
     hipError_t e = launch_wide_tiles(W, bf ? kWideMatchBF16 : kWideMatchF32, stream);
     if (e != hipSuccess) return e;
     // the rows the pass could not certify or trust, exactly on the FP32 rows

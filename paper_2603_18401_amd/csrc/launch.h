@@ -96,6 +96,7 @@ struct StabArgs {
   unsigned long long* tile_counts;
   uint32_t* long_rows;        // [n1] queue of brute-force rows longer than kStage
   uint32_t* tile_wide;        // [num_tiles] 1: the tile has a normal row longer than kStage
+  uint32_t* pair_wide;        // [num_pairs] nonzero: some tile of the pair is wide
   TileWindow* windows;        // [num_tiles], written by launch_tile_windows
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
@@ -115,6 +116,11 @@ struct StabArgs {
   // wide-row matching of a caller's CSR (epm_match)
   const uint16_t* codes1;     // BF16 descriptor codes (desc1 / desc2 are then the FP32 masters)
   const uint16_t* codes2;
+  // BF16 copies of the image-2 FP32 rows (desc2) and per row the squared norm
+  // of the copy and of its rounding error, made by launch_round_rows for the
+  // wide-row pass (NULL: the pass rounds the rows on chip)
+  const uint16_t* wcodes2;
+  const float2* wterms2;
   unsigned long long* rest_count;  // length of the rest list the wide-row pass appends to
 };
 
@@ -182,6 +188,11 @@ hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
 // listed-query match.
 constexpr int kWideFill = 0, kWideFused = 1, kWideMatchF32 = 2, kWideMatchBF16 = 3;
 hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s);
+// Rounds the FP32 image-2 rows (a.desc2) of the pairs flagged in a.pair_wide
+// to BF16 (round to nearest even) into a.wcodes2, with their terms in
+// a.wterms2, for kWideFused and kWideMatchF32 passes that stage copies
+// instead of rounding on chip.  n2 rows.
+hipError_t launch_round_rows(const StabArgs& a, int64_t n2, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
 // counts[stride * i] is the length of row i (stride 4: the count words of

@@ -278,7 +278,11 @@ __global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
     tq.n = L.w;
   }
   A.tile_q[(int64_t)t * kTileQ + lane] = tq;
-  if (lane == 0) A.tile_wide[t] = 0u;  // set by the tile pass when a row is wide
+  if (lane == 0) {
+    A.tile_wide[t] = 0u;  // set by the tile pass when a row is wide
+    // the pair's flag likewise, cleared by the pair's first tile
+    if (A.pair_wide && T.begin == A.qstart[T.pair]) A.pair_wide[T.pair] = 0u;
+  }
   const uint32_t kmin = wave_min_u32(normal ? key : 0xFFFFFFFFu);
   const uint32_t kmax = wave_max_u32(normal ? key : 0u);
   const bool any = ballot(normal) != 0;
@@ -798,7 +802,10 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         atomicAdd(&tile_stats[1], angle_hits);
         atomicAdd(&tile_stats[2], nbrute);
         atomicAdd(&tile_stats[3], empty);
-        if (wm != 0ull) A.tile_wide[tile] = 1u;
+        if (wm != 0ull) {
+          A.tile_wide[tile] = 1u;
+          if (A.pair_wide) A.pair_wide[T.pair] = 1u;
+        }
       }
     }
     (void)brute;

@@ -282,6 +282,42 @@ __device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float*
   if (mx_n) *mx_n = fmaxf(*mx_n, x);
 }
 
+// 64 pre-rounded BF16 rows (launch_round_rows) with their terms: the codes as
+// in Codes, and for thread r < 64 the terms of row r.
+struct PreRows {
+  Codes c;
+  float2 t;
+};
+
+__device__ __forceinline__ PreRows fetch_pre(const uint16_t* __restrict__ codes,
+                                             const float2* __restrict__ terms,
+                                             const int64_t* row_of, int tid) {
+  PreRows P;
+  P.c = fetch_codes(codes, row_of, tid);
+  P.t = make_float2(0.0f, 0.0f);
+  if (tid < kL) {
+    const int64_t row = row_of[tid];
+    if (row >= 0) P.t = terms[row];
+  }
+  return P;
+}
+
+// Stores the rows (stride kRS) and their squared norms; this thread's running
+// maxima of the norms and rounding errors of its row.
+__device__ __forceinline__ void stage_pre(const PreRows& P, uint8_t* dst, float* nrm, float* mx_n,
+                                          float* mx_e, int tid) {
+  #pragma unroll
+  for (int u = 0; u < kCodePer; ++u) {
+    const int f = tid + u * kThreads;
+    *reinterpret_cast<uint4*>(dst + (f >> 4) * kRS + (f & 15) * 16) = P.c.v[u];
+  }
+  if (tid < kL) {
+    nrm[tid] = P.t.x;
+    *mx_n = fmaxf(*mx_n, P.t.x);
+    *mx_e = fmaxf(*mx_e, P.t.y);
+  }
+}
+
 // One window entry in ascending j: its image-2 index and record.
 struct Entry {
   int32_t j;
@@ -374,11 +410,13 @@ __device__ __forceinline__ float merge_list(float& lk, int32_t& lj, uint64_t sur
   return readlane_f(nk, kK - 1);
 }
 
-template <int MODE>
+// PRE: the FP32 image-2 rows come as pre-rounded copies (A.wcodes2, A.wterms2).
+template <int MODE, bool PRE>
 __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_tile(StabArgs A) {
   constexpr bool MATCH = MODE != kWideFill;
   constexpr bool WRITE = MODE == kWideFill || MODE == kWideFused;  // writes the CSR
   constexpr bool CODES = MODE == kWideMatchBF16;                     // caller's BF16 codes
+  static_assert(!PRE || (MATCH && !CODES), "copies of FP32 rows only");
   // bitmap slab and word prefix; after the window sweep the picks live here
   __shared__ __attribute__((aligned(16))) unsigned char slab_raw[kSlabWords * 12];
   unsigned long long* bits = reinterpret_cast<unsigned long long*>(slab_raw);
@@ -598,7 +636,9 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
     for (uint32_t e0 = 0; e0 < E; e0 += kSC) {
       Rows pre;
       Codes prc;
+      PreRows prp;
       if (CODES) prc = fetch_codes(A.codes2, row_of, tid);  // block 0
+      else if (PRE) prp = fetch_pre(A.wcodes2, A.wterms2, row_of, tid);
       else if (MATCH) pre = fetch_rows(A.desc2, row_of, tid);
       // the next super-chunk's entry: j now, its record during the blocks
       const int32_t nj = e0 + kSC < E ? entry_j(e0 + kSC + tid) : -1;
@@ -610,11 +650,13 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
         float wn = 0.0f;
         if (MATCH) {
           if (CODES) stage_codes(prc, wrows, w_norm, &mx_n, tid);
+          else if (PRE) stage_pre(prp, wrows, w_norm, &mx_n, &mx_e, tid);
           else stage_bf16(pre, wrows, w_norm, nullptr, &mx_n, &mx_e, tid);
           __syncthreads();  // block rows and norms complete
           wn = w_norm[lane];
           if (sub + 1 < kSub && e0 + base + kL < E) {
             if (CODES) prc = fetch_codes(A.codes2, row_of + base + kL, tid);
+            else if (PRE) prp = fetch_pre(A.wcodes2, A.wterms2, row_of + base + kL, tid);
             else pre = fetch_rows(A.desc2, row_of + base + kL, tid);
           }
         }
@@ -836,6 +878,44 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   }
 }
 
+// BF16 copies of the image-2 rows of the pairs with wide tiles: 32 threads per
+// row, four values each, rounded as stage_bf16 rounds them, with the squared
+// norm of the copy and of its rounding error (sums over the 32 threads).
+constexpr int kRoundRows = 8;  // rows per workgroup
+__global__ __launch_bounds__(kRoundRows * 32) void k_round_rows(StabArgs A, int64_t n2) {
+  const int64_t row = (int64_t)blockIdx.x * kRoundRows + (threadIdx.x >> 5);
+  const int c = (int)(threadIdx.x & 31);
+  if (row >= n2) return;  // whole groups of 32 leave together
+  int lo = 0, hi = A.num_pairs - 1;  // the last pair whose image-2 rows start at or before row
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.pairs[mid].k_begin <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  if (A.pair_wide[lo] == 0u) return;
+  const float4 x = reinterpret_cast<const float4*>(A.desc2)[row * 32 + c];
+  uint2 w;
+  w.x = bf16_pack(x.x, x.y);
+  w.y = bf16_pack(x.z, x.w);
+  reinterpret_cast<uint2*>(const_cast<uint16_t*>(A.wcodes2))[row * 32 + c] = w;
+  const float y0 = __uint_as_float(w.x << 16), y1 = __uint_as_float(w.x & 0xFFFF0000u),
+              y2 = __uint_as_float(w.y << 16), y3 = __uint_as_float(w.y & 0xFFFF0000u);
+  const float e0 = x.x - y0, e1 = x.y - y1, e2 = x.z - y2, e3 = x.w - y3;  // exact
+  float n = __builtin_fmaf(y3, y3, __builtin_fmaf(y2, y2, __builtin_fmaf(y1, y1, y0 * y0)));
+  float e = __builtin_fmaf(e3, e3, __builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
+  n += xor_lanes<16>(n);
+  e += xor_lanes<16>(e);
+  n += xor_lanes<8>(n);
+  e += xor_lanes<8>(e);
+  n += xor_lanes<4>(n);
+  e += xor_lanes<4>(e);
+  n += xor_lanes<2>(n);
+  e += xor_lanes<2>(e);
+  n += xor_lanes<1>(n);
+  e += xor_lanes<1>(e);
+  if (c == 0) const_cast<float2*>(A.wterms2)[row] = make_float2(n, e);
+}
+
 }  // namespace
 
 hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
@@ -847,13 +927,28 @@ hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
     return hipErrorInvalidValue;
   if (mode == kWideMatchBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(a.num_tiles), b(kThreads);
+  const bool pre = a.wcodes2 && a.wterms2;
   switch (mode) {
-    case kWideFill: hipLaunchKernelGGL(k_wide_tile<kWideFill>, g, b, 0, s, a); break;
-    case kWideFused: hipLaunchKernelGGL(k_wide_tile<kWideFused>, g, b, 0, s, a); break;
-    case kWideMatchF32: hipLaunchKernelGGL(k_wide_tile<kWideMatchF32>, g, b, 0, s, a); break;
-    case kWideMatchBF16: hipLaunchKernelGGL(k_wide_tile<kWideMatchBF16>, g, b, 0, s, a); break;
+    case kWideFill: hipLaunchKernelGGL((k_wide_tile<kWideFill, false>), g, b, 0, s, a); break;
+    case kWideFused:
+      if (pre) hipLaunchKernelGGL((k_wide_tile<kWideFused, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wide_tile<kWideFused, false>), g, b, 0, s, a);
+      break;
+    case kWideMatchF32:
+      if (pre) hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, false>), g, b, 0, s, a);
+      break;
+    case kWideMatchBF16: hipLaunchKernelGGL((k_wide_tile<kWideMatchBF16, false>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_round_rows(const StabArgs& a, int64_t n2, hipStream_t s) {
+  if (n2 == 0) return hipSuccess;
+  if (!a.desc2 || !a.wcodes2 || !a.wterms2 || !a.pair_wide || !a.pairs) return hipErrorInvalidValue;
+  const int64_t blocks = (n2 + kRoundRows - 1) / kRoundRows;
+  hipLaunchKernelGGL(k_round_rows, dim3((unsigned)blocks), dim3(kRoundRows * 32), 0, s, a, n2);
   return hipGetLastError();
 }
 
