@@ -7,18 +7,19 @@
 // ascending image-2 index j: its j are marked in an LDS bitmap over a slab of
 // 65536 j values, and an exclusive prefix count of the bitmap's words maps
 // the e-th marked j to its word and bit.  Chunks of 64 window entries are
-// then taken in j order:
-//   1. every entry is tested against every wide query of the tile (angle
-//      test, then the FP64 test of Eq. 3: the decisions of the counting
-//      pass); one ballot per entry gives its 64-bit query mask;
-//   2. one ballot per query over the chunk's masks appends the query's hits
-//      to its CSR row -- in ascending j by construction, so no row is sorted;
-//   3. (match) the entries' FP32 descriptor rows are rounded to BF16 in LDS
-//      and scored against the tile's BF16 query rows on MFMA; every hit gets
-//      the approximate key |w^|^2 - 2 q^.w^ and each query keeps the five
-//      smallest keys.
-// The four best keys of a query are re-ranked with canonical FP32 chains on
-// the FP32 rows.  The fifth key bounds every other candidate from below
+// then taken in j order; each wavefront owns 16 queries of the tile:
+//   1. every entry (one per lane) is tested against each of the wavefront's
+//      wide queries (angle test, then the FP64 test of Eq. 3: the decisions
+//      of the counting pass); one ballot per query gives its hit mask;
+//   2. each mask appends the query's hits to its CSR row -- in ascending j
+//      by construction, so no row is sorted;
+//   3. (match) the entries' descriptor rows, as BF16 (copies rounded once
+//      per call, or rounded on chip), are scored against the BF16 query rows
+//      on MFMA; every hit gets the approximate key |w^|^2 - 2 q^.w^, and a
+//      hit below the query's kPicks+1-th smallest key so far enters its list
+//      of the kPicks+1 smallest keys.
+// The kPicks best keys of a query are re-ranked with canonical FP32 chains on
+// the FP32 rows.  The last kept key bounds every other candidate from below
 // (the rounding bound of the BF16 rows, of the MFMA accumulation and of the
 // key itself, with the largest row terms of the window); when that bound
 // exceeds the exact second distance the match is certified, otherwise the
@@ -49,7 +50,7 @@ constexpr int kL = 64;                                   // rows per block
 constexpr int kSub = kSC / kL;                           // blocks per super-chunk
 constexpr int kRS = 256 + 16;  // LDS bytes per BF16 row: fragment reads of 16 rows hit distinct banks
 constexpr int kQS = 132;       // floats per FP32 query row of the re-rank (rows start 4 banks apart)
-constexpr int kPicks = 8;      // exactly re-ranked candidates per query
+constexpr int kPicks = 5;      // exactly re-ranked candidates per query
 constexpr int kMergeMin = 16;  // more survivors than this: merged by wavefront minima
 constexpr int kQPerWave = kTileQ / kWaves;
 constexpr int kRowPer = kL * 32 / kThreads;  // 16-byte pieces of a block's rows per thread
@@ -58,7 +59,7 @@ static_assert(kRowPer == 8 && kThreads == 256, "row sums: eight rows per half-wa
 static_assert(kPicks + 1 <= 16, "a query's kept keys are lanes 0 .. kPicks of the first DPP row");
 static_assert(kThreads * 4 == kSlabWords, "four bitmap words per thread in the prefix count");
 static_assert((kTileQ / 2) * kQS * 4 <= kL * kRS, "FP32 rows of half the queries fit the row area");
-static_assert((kTileQ / 2) * kPicks == kThreads, "one pick per thread in the re-rank");
+static_assert((kTileQ / 2) * kPicks <= kThreads, "one pick per thread in the re-rank");
 static_assert(kTileQ * kPicks * 4 <= kSlabWords * 12, "exact distances fit the bitmap area");
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -836,12 +837,14 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
     __syncthreads();
     // exact canonical distances of the picks: thread = (query, pick)
     const int r = tid / kPicks, u = tid % kPicks, sq = kHalf * h + r;
-    float d = __builtin_inff();
-    const int32_t j = pj[sq * kK + u];
-    if (((wide_mask >> sq) & 1ull) && j >= 0)
-      d = exact_distance(reinterpret_cast<const float4*>(qf + r * kQS),
-                         reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32);
-    pdist[sq * kPicks + u] = d;
+    if (r < kHalf) {
+      float d = __builtin_inff();
+      const int32_t j = pj[sq * kK + u];
+      if (((wide_mask >> sq) & 1ull) && j >= 0)
+        d = exact_distance(reinterpret_cast<const float4*>(qf + r * kQS),
+                           reinterpret_cast<const float4*>(A.desc2) + (kb + j) * 32);
+      pdist[sq * kPicks + u] = d;
+    }
   }
   __syncthreads();
   if (tid < kTileQ && ((wide_mask >> tid) & 1ull)) {
