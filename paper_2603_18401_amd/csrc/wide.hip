@@ -513,8 +513,14 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   const int ql = q0 + (lane & (kQPerWave - 1));
   const int64_t qp_o0 = q_o0[ql];
   const uint32_t qp_len = q_len[ql];
-  uint32_t qp_run = 0u;
-  float qp_thr = __builtin_inff();
+  uint32_t run[kQPerWave];  // hits so far of each query of the wavefront (uniform)
+  #pragma unroll
+  for (int qq = 0; qq < kQPerWave; ++qq) run[qq] = 0u;
+  // a CSR that fits the caller's buffer whole needs no check per hit
+  const bool fits = A.row_offsets[A.n1] <= A.capacity;
+  float thr[kQPerWave];  // (match) the largest kept key of each query's list (uniform)
+  #pragma unroll
+  for (int qq = 0; qq < kQPerWave; ++qq) thr[qq] = __builtin_inff();
   uint32_t badbits = 0u;  // matching a caller's CSR: queries whose row differs here
   // largest squared norm (and rounding error) of the window rows this thread summed
   float mx_n = 0.0f, mx_e = 0.0f;
@@ -690,12 +696,11 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
         for (int qq = 0; qq < kQPerWave; ++qq) {
           const uint64_t m = hm[qq];
           if (m == 0ull) continue;  // uniform
-          const uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)qp_run, qq);
           if ((m >> lane) & 1ull) {
-            const uint32_t k = run + lanes_below(m);
+            const uint32_t k = run[qq] + lanes_below(m);
             const int64_t dst = (int64_t)readlane_u64((uint64_t)qp_o0, qq) + k;
             if (WRITE) {
-              if (dst < A.capacity) A.cols[dst] = ej;
+              if (fits || dst < A.capacity) A.cols[dst] = ej;
             } else {
               // the caller's row must hold this hit at this place
               const int32_t got =
@@ -703,7 +708,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
               if (got != ej) badbits |= 1u << qq;
             }
           }
-          if (lsel == qq) qp_run = run + (uint32_t)__popcll(m);
+          run[qq] += (uint32_t)__popcll(m);
         }
         // approximate keys |w^|^2 - 2 q^.w^ of this lane's entry base + lane
         // for the wavefront's 16 queries
@@ -746,7 +751,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
           for (int qq = 0; qq < kQPerWave; ++qq) {
             const uint64_t m = hm[qq];
             if (m == 0ull) continue;
-            const float th0 = readlane_f(qp_thr, qq);
+            const float th0 = thr[qq];
             uint64_t surv = m & ballot(kf[qq] < th0);
             if (surv == 0ull) continue;
             const bool in = lane < kK;
@@ -781,7 +786,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
               tk0[qq * kK] = lk;
               tj0[qq * kK] = lji;
             }
-            if (lsel == qq) qp_thr = th;
+            thr[qq] = th;
           }
         }
       }
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
     #pragma unroll
     for (int qq = 0; qq < kQPerWave; ++qq) {
       const bool bad = ballot((badbits >> qq) & 1u) != 0ull;
-      if (lane == qq) q_bad[q0 + qq] = bad || qp_run != qp_len ? 1u : 0u;
+      if (lane == qq) q_bad[q0 + qq] = bad || run[qq] != qp_len ? 1u : 0u;
     }
   }
   // the picks are the first kPicks of every list; the bitmap area holds their
