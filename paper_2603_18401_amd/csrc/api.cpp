@@ -28,7 +28,7 @@ struct Layout {
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, qrec, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
-      pair_wide, qline, tile_q, tile_counts;
+      pair_wide, pre_pairs, qline, tile_q, tile_counts;
   size_t total;
 };
 
@@ -88,6 +88,7 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
   L.rest = take(sizeof(uint32_t) * N1);
   L.tile_wide = take(sizeof(uint32_t) * ts);
   L.pair_wide = take(sizeof(uint32_t) * P);
+  L.pre_pairs = take(sizeof(int64_t) * (2 * (size_t)P + 2));
   L.qline = take(sizeof(double4) * N1);
   L.tile_q = take(sizeof(TileQuery) * kTileQ * (size_t)ts);
   L.tile_counts = take(sizeof(unsigned long long) * kTileCounts * (size_t)ts);
@@ -531,7 +532,7 @@ hipError_t prepare_wide_rows(epm_index* idx, StabArgs& A, hipStream_t stream) {
   char* base = reinterpret_cast<char*>(idx->at<int32_t>(idx->L.staging));
   A.wcodes2 = reinterpret_cast<const uint16_t*>(base);
   A.wterms2 = reinterpret_cast<const float2*>(base + codes);
-  return launch_round_rows(A, (int64_t)n2, stream);
+  return launch_round_rows(A, (int64_t)n2, idx->at<int64_t>(idx->L.pre_pairs), stream);
 }
 
 epm_status enqueue_fill(epm_index* idx, StabArgs& A, hipStream_t stream, bool match = false) {

@@ -96,7 +96,7 @@ struct StabArgs {
   unsigned long long* tile_counts;
   uint32_t* long_rows;        // [n1] queue of brute-force rows longer than kStage
   uint32_t* tile_wide;        // [num_tiles] 1: the tile has a normal row longer than kStage
-  uint32_t* pair_wide;        // [num_pairs] nonzero: some tile of the pair is wide
+  uint32_t* pair_wide;        // [num_pairs] the pair's wide tiles
   TileWindow* windows;        // [num_tiles], written by launch_tile_windows
   uint32_t* tile_cost;        // [num_tiles] work estimate per tile, or NULL
   const uint32_t* order;      // persistent launch: tile order (NULL = angle order)
@@ -188,11 +188,13 @@ hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s);
 // listed-query match.
 constexpr int kWideFill = 0, kWideFused = 1, kWideMatchF32 = 2, kWideMatchBF16 = 3;
 hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s);
-// Rounds the FP32 image-2 rows (a.desc2) of the pairs flagged in a.pair_wide
-// to BF16 (round to nearest even) into a.wcodes2, with their terms in
-// a.wterms2, for kWideFused and kWideMatchF32 passes that stage copies
-// instead of rounding on chip.  n2 rows.
-hipError_t launch_round_rows(const StabArgs& a, int64_t n2, hipStream_t s);
+// Rounds the FP32 image-2 rows (a.desc2) of the pairs with many wide tiles
+// (a.pair_wide against the pair's size) to BF16 (round to nearest even) into
+// a.wcodes2, with their terms in a.wterms2, for kWideFused and kWideMatchF32
+// passes, whose tiles of those pairs stage the copies instead of rounding on
+// chip.  n2 rows; pre: 2 * num_pairs + 2 int64 of scratch (the list of those
+// pairs and their row prefix).
+hipError_t launch_round_rows(const StabArgs& a, int64_t n2, int64_t* pre, hipStream_t s);
 
 // Exclusive scan of counts[0..n) into offsets[0..n], offsets[n] = total.
 // counts[stride * i] is the length of row i (stride 4: the count words of

@@ -804,7 +804,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         atomicAdd(&tile_stats[3], empty);
         if (wm != 0ull) {
           A.tile_wide[tile] = 1u;
-          if (A.pair_wide) A.pair_wide[T.pair] = 1u;
+          if (A.pair_wide) atomicAdd(&A.pair_wide[T.pair], 1u);
         }
       }
     }
@@ -1178,14 +1178,20 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
 constexpr int kCopyLanes = 16;
 constexpr int kCopyQueries = kThreads / kCopyLanes;
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
+  static_assert(kCopyLanes <= kStage, "the first piece lies inside the staging slot");
   const int sub = (int)(threadIdx.x & (kCopyLanes - 1));
   const int64_t i = (int64_t)blockIdx.x * kCopyQueries + (threadIdx.x / kCopyLanes);
-  if (i >= A.n1) return;
+  if (i >= A.n1) return;  // whole groups of kCopyLanes leave together
+  const int32_t* src = A.staging + i * kStage;
+  // the slot's first piece is read beside the row offsets (before the row's
+  // length is known); its first word tells whether the row was parked
+  const int32_t v = src[sub];
   const int64_t o0 = A.row_offsets[i];
   const int64_t len = A.row_offsets[i + 1] - o0;
-  const int32_t* src = A.staging + i * kStage;
-  if (len <= kStage && (len == 0 || src[0] != kRowNotParked)) {
-    for (int k = sub; k < (int)len; k += kCopyLanes)
+  const int32_t first = __shfl(v, 0, kCopyLanes);
+  if (len <= kStage && (len == 0 || first != kRowNotParked)) {
+    if (sub < len && o0 + sub < A.capacity) A.cols[o0 + sub] = v;
+    for (int k = sub + kCopyLanes; k < (int)len; k += kCopyLanes)
       if (o0 + k < A.capacity) A.cols[o0 + k] = src[k];
   } else if (sub == 0 && (len <= kStage || A.qflag[i] != kQueryNormal)) {
     // long rows of normal queries belong to the wide-row pass of their tile

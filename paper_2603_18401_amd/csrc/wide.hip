@@ -283,39 +283,46 @@ __device__ __forceinline__ void stage_codes(const Codes& C, uint8_t* dst, float*
   if (mx_n) *mx_n = fmaxf(*mx_n, x);
 }
 
-// 64 pre-rounded BF16 rows (launch_round_rows) with their terms: the codes as
-// in Codes, and for thread r < 64 the terms of row r.
-struct PreRows {
-  Codes c;
-  float2 t;
-};
-
-__device__ __forceinline__ PreRows fetch_pre(const uint16_t* __restrict__ codes,
-                                             const float2* __restrict__ terms,
-                                             const int64_t* row_of, int tid) {
-  PreRows P;
-  P.c = fetch_codes(codes, row_of, tid);
-  P.t = make_float2(0.0f, 0.0f);
-  if (tid < kL) {
-    const int64_t row = row_of[tid];
-    if (row >= 0) P.t = terms[row];
-  }
-  return P;
+// Pairs whose image-2 rows get BF16 copies for the wide-row pass: those
+// with at least one wide tile per kPreRows image-2 rows (each wide tile
+// stages a window of more than kStage rows).
+constexpr uint32_t kPreRows = 256;
+__device__ __forceinline__ bool pair_pre(const StabArgs& A, int p) {
+  return (uint64_t)A.pair_wide[p] * kPreRows >= (uint64_t)A.pairs[p].n;
 }
 
-// Stores the rows (stride kRS) and their squared norms; this thread's running
-// maxima of the norms and rounding errors of its row.
-__device__ __forceinline__ void stage_pre(const PreRows& P, uint8_t* dst, float* nrm, float* mx_n,
+// 64 pre-rounded BF16 rows (launch_round_rows) with their terms, held in the
+// registers of a Rows: the codes as in Codes in v[0 .. kCodePer), and for
+// thread r < 64 the terms of row r in v[kCodePer].
+__device__ __forceinline__ void fetch_pre(Rows& R, const uint16_t* __restrict__ codes,
+                                          const float2* __restrict__ terms,
+                                          const int64_t* row_of, int tid) {
+  const Codes C = fetch_codes(codes, row_of, tid);
+  #pragma unroll
+  for (int u = 0; u < kCodePer; ++u) R.v[u] = __builtin_bit_cast(float4, C.v[u]);
+  float2 t = make_float2(0.0f, 0.0f);
+  if (tid < kL) {
+    const int64_t row = row_of[tid];
+    if (row >= 0) t = terms[row];
+  }
+  R.v[kCodePer] = make_float4(t.x, t.y, 0.0f, 0.0f);
+}
+
+// Stores the rows of fetch_pre (stride kRS) and their squared norms; this
+// thread's running maxima of the norms and rounding errors of its row.
+__device__ __forceinline__ void stage_pre(const Rows& R, uint8_t* dst, float* nrm, float* mx_n,
                                           float* mx_e, int tid) {
   #pragma unroll
   for (int u = 0; u < kCodePer; ++u) {
     const int f = tid + u * kThreads;
-    *reinterpret_cast<uint4*>(dst + (f >> 4) * kRS + (f & 15) * 16) = P.c.v[u];
+    *reinterpret_cast<uint4*>(dst + (f >> 4) * kRS + (f & 15) * 16) =
+        __builtin_bit_cast(uint4, R.v[u]);
   }
   if (tid < kL) {
-    nrm[tid] = P.t.x;
-    *mx_n = fmaxf(*mx_n, P.t.x);
-    *mx_e = fmaxf(*mx_e, P.t.y);
+    const float tn = R.v[kCodePer].x, te = R.v[kCodePer].y;
+    nrm[tid] = tn;
+    *mx_n = fmaxf(*mx_n, tn);
+    *mx_e = fmaxf(*mx_e, te);
   }
 }
 
@@ -411,13 +418,17 @@ __device__ __forceinline__ float merge_list(float& lk, int32_t& lj, uint64_t sur
   return readlane_f(nk, kK - 1);
 }
 
-// PRE: the FP32 image-2 rows come as pre-rounded copies (A.wcodes2, A.wterms2).
-template <int MODE, bool PRE>
+// Copies of the image-2 rows (A.wcodes2, A.wterms2, for the pairs pair_pre
+// picks) by PRE: kPreNone none (rounding on chip); kPreOnly the tiles of
+// those pairs only, staging the copies; kPreOthers the other tiles only,
+// rounding on chip; kPreMixed every tile, each as its pair has copies.
+constexpr int kPreNone = 0, kPreOnly = 1, kPreOthers = 2, kPreMixed = 3;
+template <int MODE, int PRE>
 __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_tile(StabArgs A) {
   constexpr bool MATCH = MODE != kWideFill;
   constexpr bool WRITE = MODE == kWideFill || MODE == kWideFused;  // writes the CSR
   constexpr bool CODES = MODE == kWideMatchBF16;                     // caller's BF16 codes
-  static_assert(!PRE || (MATCH && !CODES), "copies of FP32 rows only");
+  static_assert(PRE == kPreNone || (MATCH && !CODES), "copies of FP32 rows only");
   // bitmap slab and word prefix; after the window sweep the picks live here
   __shared__ __attribute__((aligned(16))) unsigned char slab_raw[kSlabWords * 12];
   unsigned long long* bits = reinterpret_cast<unsigned long long*>(slab_raw);
@@ -455,6 +466,13 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   const StabTile T = A.tiles[tile];
   const PairDev& pd = A.pairs[T.pair];
   const int64_t kb = pd.k_begin, n2 = pd.n;
+  bool pre = false;  // uniform
+  if (PRE == kPreOnly || PRE == kPreOthers) {
+    if (pair_pre(A, T.pair) != (PRE == kPreOnly)) return;
+    pre = PRE == kPreOnly;
+  } else if (PRE == kPreMixed) {
+    pre = pair_pre(A, T.pair);
+  }
   const int tid = threadIdx.x, lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(wave_id());
 
@@ -641,12 +659,11 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
     __syncthreads();
 
     for (uint32_t e0 = 0; e0 < E; e0 += kSC) {
-      Rows pre;
+      Rows rw;  // the next block's FP32 rows, or their copies (fetch_pre)
       Codes prc;
-      PreRows prp;
       if (CODES) prc = fetch_codes(A.codes2, row_of, tid);  // block 0
-      else if (PRE) prp = fetch_pre(A.wcodes2, A.wterms2, row_of, tid);
-      else if (MATCH) pre = fetch_rows(A.desc2, row_of, tid);
+      else if (pre) fetch_pre(rw, A.wcodes2, A.wterms2, row_of, tid);
+      else if (MATCH) rw = fetch_rows(A.desc2, row_of, tid);
       // the next super-chunk's entry: j now, its record during the blocks
       const int32_t nj = e0 + kSC < E ? entry_j(e0 + kSC + tid) : -1;
       Entry nxt;
@@ -657,14 +674,14 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
         float wn = 0.0f;
         if (MATCH) {
           if (CODES) stage_codes(prc, wrows, w_norm, &mx_n, tid);
-          else if (PRE) stage_pre(prp, wrows, w_norm, &mx_n, &mx_e, tid);
-          else stage_bf16(pre, wrows, w_norm, nullptr, &mx_n, &mx_e, tid);
+          else if (pre) stage_pre(rw, wrows, w_norm, &mx_n, &mx_e, tid);
+          else stage_bf16(rw, wrows, w_norm, nullptr, &mx_n, &mx_e, tid);
           __syncthreads();  // block rows and norms complete
           wn = w_norm[lane];
           if (sub + 1 < kSub && e0 + base + kL < E) {
             if (CODES) prc = fetch_codes(A.codes2, row_of + base + kL, tid);
-            else if (PRE) prp = fetch_pre(A.wcodes2, A.wterms2, row_of + base + kL, tid);
-            else pre = fetch_rows(A.desc2, row_of + base + kL, tid);
+            else if (pre) fetch_pre(rw, A.wcodes2, A.wterms2, row_of + base + kL, tid);
+            else rw = fetch_rows(A.desc2, row_of + base + kL, tid);
           }
         }
         if (sub == 0 && nj >= 0) nxt = load_entry(nj);
@@ -886,42 +903,89 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   }
 }
 
-// BF16 copies of the image-2 rows of the pairs with wide tiles: 32 threads per
-// row, four values each, rounded as stage_bf16 rounds them, with the squared
-// norm of the copy and of its rounding error (sums over the 32 threads).
-constexpr int kRoundRows = 8;  // rows per workgroup
-__global__ __launch_bounds__(kRoundRows * 32) void k_round_rows(StabArgs A, int64_t n2) {
-  const int64_t row = (int64_t)blockIdx.x * kRoundRows + (threadIdx.x >> 5);
-  const int c = (int)(threadIdx.x & 31);
-  if (row >= n2) return;  // whole groups of 32 leave together
-  int lo = 0, hi = A.num_pairs - 1;  // the last pair whose image-2 rows start at or before row
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (A.pairs[mid].k_begin <= row) lo = mid;
-    else hi = mid - 1;
+// The pairs pair_pre picks, compacted for k_round_rows: pre[0] = their
+// number c, pre[1 .. c + 1] the exclusive prefix of their image-2 row counts
+// (pre[1 + c] the total), pre[P + 2 + k] the k-th pair.  One workgroup.
+constexpr int kPreThreads = 256;
+__global__ __launch_bounds__(kPreThreads) void k_pre_pairs(StabArgs A, int64_t* __restrict__ pre) {
+  __shared__ int64_t sn[kPreThreads];
+  __shared__ int sc[kPreThreads];
+  const int tid = threadIdx.x, P = A.num_pairs;
+  int count = 0;
+  int64_t rows = 0;
+  for (int base = 0; base < P; base += kPreThreads) {
+    const int p = base + tid;
+    const bool take = p < P && pair_pre(A, p);
+    const int64_t n = take ? A.pairs[p].n : 0;
+    sn[tid] = n;
+    sc[tid] = take ? 1 : 0;
+    __syncthreads();
+    for (int off = 1; off < kPreThreads; off <<= 1) {  // inclusive scans
+      const int64_t on = tid >= off ? sn[tid - off] : 0;
+      const int oc = tid >= off ? sc[tid - off] : 0;
+      __syncthreads();
+      sn[tid] += on;
+      sc[tid] += oc;
+      __syncthreads();
+    }
+    if (take) {
+      const int k = count + sc[tid] - 1;
+      pre[1 + k] = rows + sn[tid] - n;
+      pre[P + 2 + k] = p;
+    }
+    count += sc[kPreThreads - 1];
+    rows += sn[kPreThreads - 1];
+    __syncthreads();  // the scan arrays are reused
   }
-  if (A.pair_wide[lo] == 0u) return;
-  const float4 x = reinterpret_cast<const float4*>(A.desc2)[row * 32 + c];
-  uint2 w;
-  w.x = bf16_pack(x.x, x.y);
-  w.y = bf16_pack(x.z, x.w);
-  reinterpret_cast<uint2*>(const_cast<uint16_t*>(A.wcodes2))[row * 32 + c] = w;
-  const float y0 = __uint_as_float(w.x << 16), y1 = __uint_as_float(w.x & 0xFFFF0000u),
-              y2 = __uint_as_float(w.y << 16), y3 = __uint_as_float(w.y & 0xFFFF0000u);
-  const float e0 = x.x - y0, e1 = x.y - y1, e2 = x.z - y2, e3 = x.w - y3;  // exact
-  float n = __builtin_fmaf(y3, y3, __builtin_fmaf(y2, y2, __builtin_fmaf(y1, y1, y0 * y0)));
-  float e = __builtin_fmaf(e3, e3, __builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-  n += xor_lanes<16>(n);
-  e += xor_lanes<16>(e);
-  n += xor_lanes<8>(n);
-  e += xor_lanes<8>(e);
-  n += xor_lanes<4>(n);
-  e += xor_lanes<4>(e);
-  n += xor_lanes<2>(n);
-  e += xor_lanes<2>(e);
-  n += xor_lanes<1>(n);
-  e += xor_lanes<1>(e);
-  if (c == 0) const_cast<float2*>(A.wterms2)[row] = make_float2(n, e);
+  if (tid == 0) {
+    pre[0] = count;
+    pre[1 + count] = rows;
+  }
+}
+
+// BF16 copies of the image-2 rows of the pairs listed by k_pre_pairs: 32
+// threads per row, four values each, rounded as stage_bf16 rounds them, with
+// the squared norm of the copy and of its rounding error (sums over the 32
+// threads).  Grid-stride over the listed rows.
+constexpr int kRoundRows = 8;  // rows per workgroup and step
+constexpr int kSplitTiles = 16384;
+__global__ __launch_bounds__(kRoundRows * 32) void k_round_rows(StabArgs A,
+                                                                 const int64_t* __restrict__ pre) {
+  const int P = A.num_pairs;
+  const int count = (int)pre[0];
+  const int64_t total = pre[1 + count];
+  const int c = (int)(threadIdx.x & 31);
+  for (int64_t r = (int64_t)blockIdx.x * kRoundRows + (threadIdx.x >> 5); r < total;
+       r += (int64_t)gridDim.x * kRoundRows) {
+    int lo = 0, hi = count - 1;  // the listed pair whose rows hold r
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[1 + mid] <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t row = A.pairs[pre[P + 2 + lo]].k_begin + (r - pre[1 + lo]);
+    const float4 x = reinterpret_cast<const float4*>(A.desc2)[row * 32 + c];
+    uint2 w;
+    w.x = bf16_pack(x.x, x.y);
+    w.y = bf16_pack(x.z, x.w);
+    reinterpret_cast<uint2*>(const_cast<uint16_t*>(A.wcodes2))[row * 32 + c] = w;
+    const float y0 = __uint_as_float(w.x << 16), y1 = __uint_as_float(w.x & 0xFFFF0000u),
+                y2 = __uint_as_float(w.y << 16), y3 = __uint_as_float(w.y & 0xFFFF0000u);
+    const float e0 = x.x - y0, e1 = x.y - y1, e2 = x.z - y2, e3 = x.w - y3;  // exact
+    float n = __builtin_fmaf(y3, y3, __builtin_fmaf(y2, y2, __builtin_fmaf(y1, y1, y0 * y0)));
+    float e = __builtin_fmaf(e3, e3, __builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
+    n += xor_lanes<16>(n);
+    e += xor_lanes<16>(e);
+    n += xor_lanes<8>(n);
+    e += xor_lanes<8>(e);
+    n += xor_lanes<4>(n);
+    e += xor_lanes<4>(e);
+    n += xor_lanes<2>(n);
+    e += xor_lanes<2>(e);
+    n += xor_lanes<1>(n);
+    e += xor_lanes<1>(e);
+    if (c == 0) const_cast<float2*>(A.wterms2)[row] = make_float2(n, e);
+  }
 }
 
 }  // namespace
@@ -935,28 +999,53 @@ hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
     return hipErrorInvalidValue;
   if (mode == kWideMatchBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(a.num_tiles), b(kThreads);
-  const bool pre = a.wcodes2 && a.wterms2;
+  // with copies: up to kSplitTiles tiles, one launch for the tiles of the
+  // pairs that have them and one for the others (each kernel lean); beyond,
+  // one launch that decides per tile (a launch costs about one workgroup
+  // slot per tile even where the tile has no wide row)
+  const bool copies = a.wcodes2 && a.wterms2;
+  const bool split = copies && a.num_tiles <= kSplitTiles;
   switch (mode) {
-    case kWideFill: hipLaunchKernelGGL((k_wide_tile<kWideFill, false>), g, b, 0, s, a); break;
+    case kWideFill: hipLaunchKernelGGL((k_wide_tile<kWideFill, kPreNone>), g, b, 0, s, a); break;
     case kWideFused:
-      if (pre) hipLaunchKernelGGL((k_wide_tile<kWideFused, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_wide_tile<kWideFused, false>), g, b, 0, s, a);
+      if (split) {
+        hipLaunchKernelGGL((k_wide_tile<kWideFused, kPreOnly>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_wide_tile<kWideFused, kPreOthers>), g, b, 0, s, a);
+      } else if (copies) {
+        hipLaunchKernelGGL((k_wide_tile<kWideFused, kPreMixed>), g, b, 0, s, a);
+      } else {
+        hipLaunchKernelGGL((k_wide_tile<kWideFused, kPreNone>), g, b, 0, s, a);
+      }
       break;
     case kWideMatchF32:
-      if (pre) hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, false>), g, b, 0, s, a);
+      if (split) {
+        hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, kPreOnly>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, kPreOthers>), g, b, 0, s, a);
+      } else if (copies) {
+        hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, kPreMixed>), g, b, 0, s, a);
+      } else {
+        hipLaunchKernelGGL((k_wide_tile<kWideMatchF32, kPreNone>), g, b, 0, s, a);
+      }
       break;
-    case kWideMatchBF16: hipLaunchKernelGGL((k_wide_tile<kWideMatchBF16, false>), g, b, 0, s, a); break;
+    case kWideMatchBF16:
+      hipLaunchKernelGGL((k_wide_tile<kWideMatchBF16, kPreNone>), g, b, 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_round_rows(const StabArgs& a, int64_t n2, hipStream_t s) {
+hipError_t launch_round_rows(const StabArgs& a, int64_t n2, int64_t* pre, hipStream_t s) {
   if (n2 == 0) return hipSuccess;
-  if (!a.desc2 || !a.wcodes2 || !a.wterms2 || !a.pair_wide || !a.pairs) return hipErrorInvalidValue;
-  const int64_t blocks = (n2 + kRoundRows - 1) / kRoundRows;
-  hipLaunchKernelGGL(k_round_rows, dim3((unsigned)blocks), dim3(kRoundRows * 32), 0, s, a, n2);
+  if (!a.desc2 || !a.wcodes2 || !a.wterms2 || !a.pair_wide || !a.pairs || !pre)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pre_pairs, dim3(1), dim3(kPreThreads), 0, s, a, pre);
+  // enough workgroups for every row of a large batch in a few steps; when no
+  // pair is listed they only read the count
+  const int64_t want = (n2 + kRoundRows - 1) / kRoundRows;
+  const int64_t blocks = want < 4096 ? want : 4096;
+  hipLaunchKernelGGL(k_round_rows, dim3((unsigned)blocks), dim3(kRoundRows * 32), 0, s, a,
+                     (const int64_t*)pre);
   return hipGetLastError();
 }
 
