@@ -149,18 +149,31 @@ __device__ void fill_row(const StabArgs& A, int64_t i, int32_t* buf) {
     // long row: rebuild it in ascending j directly from the definition
     const int64_t kb = pd.k_begin;
     uint32_t total = 0;
-    for (int64_t j0 = 0; j0 < pd.n; j0 += kWave) {
-      const int64_t j = j0 + lane;
-      bool hit = false;
-      if (j < pd.n) {
-        const uint32_t pos = A.rinv[kb + j];
-        const float2 xy = A.rxy[pos];
-        hit = within_tolerance(q.a, q.b, q.c, xy.x, xy.y, A.reps[pos]);
+    constexpr int kU = 4;  // blocks of 64 j whose gathers are in flight together
+    for (int64_t j0 = 0; j0 < pd.n; j0 += kU * kWave) {
+      uint32_t pos[kU];
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t j = j0 + u * kWave + lane;
+        pos[u] = j < pd.n ? A.rinv[kb + j] : 0u;
       }
-      const uint64_t m = ballot(hit);
-      const int64_t dst = o0 + total + lanes_below(m);
-      if (hit && dst < A.capacity) A.cols[dst] = (int32_t)j;
-      total += (uint32_t)__popcll(m);
+      float2 xy[kU];
+      float ee[kU];
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t j = j0 + u * kWave + lane;
+        xy[u] = j < pd.n ? A.rxy[pos[u]] : make_float2(0.0f, 0.0f);
+        ee[u] = j < pd.n ? A.reps[pos[u]] : 0.0f;
+      }
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t j = j0 + u * kWave + lane;
+        const bool hit = j < pd.n && within_tolerance(q.a, q.b, q.c, xy[u].x, xy[u].y, ee[u]);
+        const uint64_t m = ballot(hit);
+        const int64_t dst = o0 + total + lanes_below(m);
+        if (hit && dst < A.capacity) A.cols[dst] = (int32_t)j;
+        total += (uint32_t)__popcll(m);
+      }
     }
     return;
   }
@@ -251,9 +264,11 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // centres lie within [min key - 2^c + 1, max key + 2^c - 1] of the tile's
 // queries; lane c searches class c.  No LDS, so every tile's searches are in
 // flight at once.
-__global__ __launch_bounds__(kWave) void k_tile_windows(StabArgs A) {
+constexpr int kWindowTiles = 4;  // tiles (one wavefront each) per workgroup
+__global__ __launch_bounds__(kWave * kWindowTiles) void k_tile_windows(StabArgs A) {
   const int lane = lane_id();
-  const int t = blockIdx.x;
+  const int t = blockIdx.x * kWindowTiles + wave_id();
+  if (t >= A.num_tiles) return;  // whole wavefronts
   const StabTile T = A.tiles[t];
   bool normal = false, brute = false;
   uint32_t key = 0;
@@ -1350,7 +1365,8 @@ hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t
 
 hipError_t launch_tile_windows(const StabArgs& a, hipStream_t s) {
   if (a.num_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_windows, dim3(a.num_tiles), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL(k_tile_windows, dim3((a.num_tiles + kWindowTiles - 1) / kWindowTiles),
+                     dim3(kWave * kWindowTiles), 0, s, a);
   return hipGetLastError();
 }
 
