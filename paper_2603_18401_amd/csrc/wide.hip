@@ -903,13 +903,12 @@ __global__ __launch_bounds__(kThreads, MODE == kWideFill ? 1 : 3) void k_wide_ti
   }
 }
 
-// The pairs pair_pre picks, compacted for k_round_rows: pre[0] = their
-// number c, pre[1 .. c + 1] the exclusive prefix of their image-2 row counts
-// (pre[1 + c] the total), pre[P + 2 + k] the k-th pair.  One workgroup.
+// The pairs pair_pre picks, compacted: the k-th listed pair in pair_of[k],
+// the exclusive prefix of their image-2 row counts in start[k] (start[count]
+// the total); returns count.  The whole workgroup (kPreThreads) calls it.
 constexpr int kPreThreads = 256;
-__global__ __launch_bounds__(kPreThreads) void k_pre_pairs(StabArgs A, int64_t* __restrict__ pre) {
-  __shared__ int64_t sn[kPreThreads];
-  __shared__ int sc[kPreThreads];
+template <typename Start, typename Pair>
+__device__ int list_pre_pairs(const StabArgs& A, Start* start, Pair* pair_of, int64_t* sn, int* sc) {
   const int tid = threadIdx.x, P = A.num_pairs;
   int count = 0;
   int64_t rows = 0;
@@ -930,40 +929,57 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_pairs(StabArgs A, int64_t* 
     }
     if (take) {
       const int k = count + sc[tid] - 1;
-      pre[1 + k] = rows + sn[tid] - n;
-      pre[P + 2 + k] = p;
+      start[k] = rows + sn[tid] - n;
+      pair_of[k] = p;
     }
     count += sc[kPreThreads - 1];
     rows += sn[kPreThreads - 1];
     __syncthreads();  // the scan arrays are reused
   }
-  if (tid == 0) {
-    pre[0] = count;
-    pre[1 + count] = rows;
-  }
+  if (tid == 0) start[count] = rows;
+  __syncthreads();
+  return count;
 }
 
-// BF16 copies of the image-2 rows of the pairs listed by k_pre_pairs: 32
-// threads per row, four values each, rounded as stage_bf16 rounds them, with
-// the squared norm of the copy and of its rounding error (sums over the 32
-// threads).  Grid-stride over the listed rows.
+// The list of list_pre_pairs in global memory, for batches of more than
+// kPreLocal pairs: pre[0] = count, pre[1 ..] the starts, pre[P + 2 ..] the pairs.
+constexpr int kPreLocal = 1024;
+__global__ __launch_bounds__(kPreThreads) void k_pre_pairs(StabArgs A, int64_t* __restrict__ pre) {
+  __shared__ int64_t sn[kPreThreads];
+  __shared__ int sc[kPreThreads];
+  const int count = list_pre_pairs(A, pre + 1, pre + A.num_pairs + 2, sn, sc);
+  if (threadIdx.x == 0) pre[0] = count;
+}
+
+// BF16 copies of the image-2 rows of the listed pairs: 32 threads per row,
+// four values each, rounded as stage_bf16 rounds them, with the squared norm
+// of the copy and of its rounding error (sums over the 32 threads).
+// Grid-stride over the listed rows.  pre: the global list, or NULL for a
+// batch of at most kPreLocal pairs, whose list each workgroup makes in LDS.
 constexpr int kRoundRows = 8;  // rows per workgroup and step
-constexpr int kSplitTiles = 16384;
-__global__ __launch_bounds__(kRoundRows * 32) void k_round_rows(StabArgs A,
-                                                                 const int64_t* __restrict__ pre) {
+static_assert(kRoundRows * 32 == kPreThreads, "one workgroup shape");
+__global__ __launch_bounds__(kPreThreads) void k_round_rows(StabArgs A,
+                                                            const int64_t* __restrict__ pre) {
+  __shared__ int64_t l_start[kPreLocal + 1];
+  __shared__ int l_pair[kPreLocal];
+  __shared__ int64_t sn[kPreThreads];
+  __shared__ int sc[kPreThreads];
   const int P = A.num_pairs;
-  const int count = (int)pre[0];
-  const int64_t total = pre[1 + count];
+  const int64_t* g_start = pre ? pre + 1 : nullptr;
+  const int64_t* g_pair = pre ? pre + P + 2 : nullptr;
+  const int count = pre ? (int)pre[0] : list_pre_pairs(A, l_start, l_pair, sn, sc);
+  const int64_t total = pre ? g_start[count] : l_start[count];
   const int c = (int)(threadIdx.x & 31);
   for (int64_t r = (int64_t)blockIdx.x * kRoundRows + (threadIdx.x >> 5); r < total;
        r += (int64_t)gridDim.x * kRoundRows) {
     int lo = 0, hi = count - 1;  // the listed pair whose rows hold r
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (pre[1 + mid] <= r) lo = mid;
+      if ((pre ? g_start[mid] : l_start[mid]) <= r) lo = mid;
       else hi = mid - 1;
     }
-    const int64_t row = A.pairs[pre[P + 2 + lo]].k_begin + (r - pre[1 + lo]);
+    const int p = pre ? (int)g_pair[lo] : l_pair[lo];
+    const int64_t row = A.pairs[p].k_begin + (r - (pre ? g_start[lo] : l_start[lo]));
     const float4 x = reinterpret_cast<const float4*>(A.desc2)[row * 32 + c];
     uint2 w;
     w.x = bf16_pack(x.x, x.y);
@@ -988,6 +1004,8 @@ __global__ __launch_bounds__(kRoundRows * 32) void k_round_rows(StabArgs A,
   }
 }
 
+constexpr int kSplitTilesMin = 2048, kSplitTilesMax = 16384;
+
 }  // namespace
 
 hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
@@ -999,12 +1017,12 @@ hipError_t launch_wide_tiles(const StabArgs& a, int mode, hipStream_t s) {
     return hipErrorInvalidValue;
   if (mode == kWideMatchBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
   const dim3 g(a.num_tiles), b(kThreads);
-  // with copies: up to kSplitTiles tiles, one launch for the tiles of the
-  // pairs that have them and one for the others (each kernel lean); beyond,
-  // one launch that decides per tile (a launch costs about one workgroup
-  // slot per tile even where the tile has no wide row)
+  // with copies: one launch for the tiles of the pairs that have them and one
+  // for the others (each kernel lean), or one launch that decides per tile,
+  // where a second launch would cost more than it saves: a few microseconds
+  // on small grids, about one workgroup slot per tile on large ones
   const bool copies = a.wcodes2 && a.wterms2;
-  const bool split = copies && a.num_tiles <= kSplitTiles;
+  const bool split = copies && a.num_tiles > kSplitTilesMin && a.num_tiles <= kSplitTilesMax;
   switch (mode) {
     case kWideFill: hipLaunchKernelGGL((k_wide_tile<kWideFill, kPreNone>), g, b, 0, s, a); break;
     case kWideFused:
@@ -1039,13 +1057,13 @@ hipError_t launch_round_rows(const StabArgs& a, int64_t n2, int64_t* pre, hipStr
   if (n2 == 0) return hipSuccess;
   if (!a.desc2 || !a.wcodes2 || !a.wterms2 || !a.pair_wide || !a.pairs || !pre)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pre_pairs, dim3(1), dim3(kPreThreads), 0, s, a, pre);
-  // enough workgroups for every row of a large batch in a few steps; when no
-  // pair is listed they only read the count
+  const bool global_list = a.num_pairs > kPreLocal;
+  if (global_list) hipLaunchKernelGGL(k_pre_pairs, dim3(1), dim3(kPreThreads), 0, s, a, pre);
+  // grid-stride: enough workgroups to stream the rows of a large batch
   const int64_t want = (n2 + kRoundRows - 1) / kRoundRows;
-  const int64_t blocks = want < 4096 ? want : 4096;
-  hipLaunchKernelGGL(k_round_rows, dim3((unsigned)blocks), dim3(kRoundRows * 32), 0, s, a,
-                     (const int64_t*)pre);
+  const int64_t blocks = want < 1024 ? want : 1024;
+  hipLaunchKernelGGL(k_round_rows, dim3((unsigned)blocks), dim3(kPreThreads), 0, s, a,
+                     global_list ? (const int64_t*)pre : nullptr);
   return hipGetLastError();
 }
 
