@@ -204,3 +204,68 @@ def test_foreign_csr_on_wide_tiles(dtype):
     got = [x.cpu().numpy() for x in idx.match(_dev(torch, ro2), _dev(torch, rc2), algo="tiled",
                                               **_match_inputs(torch, p, dtype))]
     _same_matches(got, ref, "foreign")
+
+
+def _uneven_pair(m, n, seed, motion="sideways"):
+    """A 6048x4032 pair with m queries and n image-2 keypoints (most of the
+    surplus on either side outliers)."""
+    yaw = synth.pairs.rot_axis_angle([0.0, 1.0, 0.0], np.deg2rad(10.0 if motion == "sideways" else 3.0))
+    c2 = [1.0, 0.0, 0.0] if motion == "sideways" else [0.0, 0.0, 1.0]
+    t = min(m, n) * 4 // 5
+    return synth.make_pair(6048, 4032, 3400.0, yaw, c2, t, m - t, n - t, seed)
+
+
+def _batch_against_oracle(pairs, eps_list, what):
+    """Fused query + FP32 match and separate query + tiled match of one batch,
+    every pair compared with the oracle (CSR and matches)."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    kp1 = np.concatenate([p.kp1 for p in pairs])
+    kp2 = np.concatenate([p.kp2 for p in pairs])
+    eps2 = np.concatenate([np.full(p.n, e, np.float32) for p, e in zip(pairs, eps_list)])
+    d1 = np.concatenate([p.desc1 for p in pairs])
+    d2 = np.concatenate([p.desc2 for p in pairs])
+    idx = E.Index(specs_of(pairs), _dev(torch, kp2), eps2=_dev(torch, eps2))
+    fused = [x.cpu().numpy() for x in idx.query_match(_dev(torch, kp1), _dev(torch, d1), _dev(torch, d2))]
+    o, c = idx.query(_dev(torch, kp1))
+    sep = [x.cpu().numpy() for x in idx.match(o, c, _dev(torch, d1), _dev(torch, d2), dtype="f32",
+                                              algo="tiled")]
+    torch.cuda.synchronize()
+    q0 = k0 = 0
+    wide = []
+    for pi, (p, e) in enumerate(zip(pairs, eps_list)):
+        ref = _oracle(p, e)
+        wide.append(int((np.diff(ref[0]) > 128).sum()))
+        lo, hi = fused[0][q0], fused[0][q0 + p.m]
+        rows = (fused[0][q0:q0 + p.m + 1] - lo, fused[1][lo:hi])
+        assert_csr_equal(rows, ref[:2], f"{what}: pair {pi} CSR")
+        _same_matches([a[q0:q0 + p.m] for a in fused[2:]], ref[2:], f"{what}: pair {pi} fused")
+        _same_matches([a[q0:q0 + p.m] for a in sep], ref[2:], f"{what}: pair {pi} separate")
+        q0 += p.m
+        k0 += p.n
+    log(f"{what}: rows over 128 candidates per pair {wide}")
+    return wide
+
+
+def test_copies_and_on_chip_rows_in_one_launch():
+    """Below 2048 tiles one wide-row launch decides per tile: a pair with a
+    wide tile per 256 image-2 rows or more stages BF16 copies of its rows, a
+    pair with few queries against many image-2 keypoints (wide rows, but too
+    few tiles for copies) rounds on chip."""
+    a = _uneven_pair(30000, 12000, 5151)  # 469 wide tiles x 256 >= 12000: copies
+    b = _uneven_pair(2000, 40000, 5152, "forward")  # 32 x 256 < 40000: on chip
+    log(f"copies and on-chip rounding in one launch: {a.m}/{a.n} + {b.m}/{b.n} keypoints, eps 50")
+    wide = _batch_against_oracle([a, b], [50.0, 50.0], "mixed launch")
+    assert wide[0] > 0.9 * a.m and wide[1] > 0.9 * b.m
+
+
+def test_copies_and_on_chip_rows_in_two_launches():
+    """Between 2048 and 16384 tiles the tiles of pairs with copies and the
+    others go to two launches; a narrow pair adds tiles without wide rows."""
+    a = _uneven_pair(70000, 15000, 6161)   # 1094 tiles, copies
+    b = _uneven_pair(3000, 50000, 6162, "forward")  # 47 wide tiles, on chip
+    c = _uneven_pair(60000, 8000, 6163)    # 938 tiles, eps 2 px: no wide row
+    assert sum((p.m + 63) // 64 for p in (a, b, c)) > 2048
+    log("copies and on-chip rounding in two launches: 2079 tiles")
+    wide = _batch_against_oracle([a, b, c], [50.0, 50.0, 2.0], "split launches")
+    assert wide[0] > 0.9 * a.m and wide[1] > 0.9 * b.m and wide[2] == 0
