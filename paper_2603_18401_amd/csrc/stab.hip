@@ -649,10 +649,11 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
 
     const int64_t total_len = slot_pref[kSlots];
     const bool fusable = total_len <= kFuseMaxWindow;
-    uint32_t scanned = 0, angle_hits = 0;
+    uint32_t scanned = 0, angle_w = 0;  // angle_w: the wavefront's angle hits (uniform)
     // this lane's query of the pair test: its line stays in registers
     const int lq = wave * kQPerWave + (lane & (kQPerWave - 1));
     const bool line_live = qmode[lq] == kQueryNormal;
+    const uint64_t live_mask = ballot(line_live);
     const bool any_live = ballot(line_live) != 0;
     const uint32_t lkey = qk[lq];
     const double la = qa[lq], lb = qb[lq], lc = qc[lq], ln = qn[lq];
@@ -745,17 +746,21 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               m &= m - 1ull;
             }
             const int r = g0 + pick;
-            bool hit = false;
-            if (line_live && pick < kWave) {
-              const uint32_t C = sC[r], H = sH[r];
-              const bool ang = key_distance(lkey, C) <= H;
-              angle_hits += ang ? 1u : 0u;
-              if (ang) {
-                const float2 xy = sXY[r];
-                hit = within_tolerance_n(la, lb, lc, ln, xy.x, xy.y, sE[r]);
-              }
-            }
-            const uint64_t hm = ballot(hit) & same_query;
+            // branch-free: nearly every step has lanes that pass the angle
+            // test, and the SIMD runs the FP64 test for all of its lanes
+            // anyway; each test is balloted on its own (a ballot of one
+            // comparison is its lane mask as it stands)
+            const int rr = pick < kWave ? r : g0;  // an index inside the chunk
+            const uint32_t C = sC[rr], H = sH[rr];
+            const float2 xy = sXY[rr];
+            const bool key_ok = key_distance(lkey, C) <= H;
+            const bool fp_ok = within_tolerance_n(la, lb, lc, ln, xy.x, xy.y, sE[rr]);
+            const uint64_t vm = live_mask & ballot(pick < kWave);
+            const uint64_t am = vm & ballot(key_ok);
+            angle_w += (uint32_t)__popcll(am);
+            const uint64_t all_hits = am & ballot(fp_ok);
+            const bool hit = line_live & (pick < kWave) & key_ok & fp_ok;  // this lane's bit
+            const uint64_t hm = all_hits & same_query;
             if (hit) {
               const uint32_t slot = lcnt + lanes_below(hm);
               if (slot < (uint32_t)kStage) {
@@ -807,7 +812,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
       const uint32_t nbrute = (uint32_t)__popcll(ballot(own && qmode[lq] == kQueryBrute));
       const uint32_t empty = (uint32_t)__popcll(ballot(own && qmode[lq] == kQueryEmpty));
       scanned = wave_sum_u32(scanned);
-      angle_hits = wave_sum_u32(angle_hits);
+      const uint32_t angle_hits = angle_w;
       // rows longer than kStage of normal queries are written (and, fused,
       // matched) by the wide-row pass over the tile; the window pass cleared
       // the flag
