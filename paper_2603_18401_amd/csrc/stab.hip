@@ -1197,26 +1197,42 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
 // normal queries go to the wide-row pass).
 constexpr int kCopyLanes = 16;
 constexpr int kCopyQueries = kThreads / kCopyLanes;
+constexpr int kCopyUnroll = 4;  // rows per group
 __global__ __launch_bounds__(kThreads) void k_copy_rows(StabArgs A) {
   static_assert(kCopyLanes <= kStage, "the first piece lies inside the staging slot");
   const int sub = (int)(threadIdx.x & (kCopyLanes - 1));
-  const int64_t i = (int64_t)blockIdx.x * kCopyQueries + (threadIdx.x / kCopyLanes);
-  if (i >= A.n1) return;  // whole groups of kCopyLanes leave together
-  const int32_t* src = A.staging + i * kStage;
-  // the slot's first piece is read beside the row offsets (before the row's
+  // kCopyUnroll consecutive rows per group of kCopyLanes, their loads in flight together
+  const int64_t i0 =
+      ((int64_t)blockIdx.x * kCopyQueries + (threadIdx.x / kCopyLanes)) * kCopyUnroll;
+  if (i0 >= A.n1) return;  // whole groups of kCopyLanes leave together
+  // each slot's first piece is read beside the row offsets (before the row's
   // length is known); its first word tells whether the row was parked
-  const int32_t v = src[sub];
-  const int64_t o0 = A.row_offsets[i];
-  const int64_t len = A.row_offsets[i + 1] - o0;
-  const int32_t first = __shfl(v, 0, kCopyLanes);
-  if (len <= kStage && (len == 0 || first != kRowNotParked)) {
-    if (sub < len && o0 + sub < A.capacity) A.cols[o0 + sub] = v;
-    for (int k = sub + kCopyLanes; k < (int)len; k += kCopyLanes)
-      if (o0 + k < A.capacity) A.cols[o0 + k] = src[k];
-  } else if (sub == 0 && (len <= kStage || A.qflag[i] != kQueryNormal)) {
-    // long rows of normal queries belong to the wide-row pass of their tile
-    const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
-    A.long_rows[slot] = (uint32_t)i;
+  int32_t v[kCopyUnroll];
+  int64_t o0[kCopyUnroll], o1[kCopyUnroll];
+  #pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const int64_t i = i0 + u;
+    const bool in = i < A.n1;
+    v[u] = in ? A.staging[i * kStage + sub] : 0;
+    o0[u] = in ? A.row_offsets[i] : 0;
+    o1[u] = in ? A.row_offsets[i + 1] : 0;
+  }
+  #pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const int64_t i = i0 + u;
+    if (i >= A.n1) break;  // uniform in the group
+    const int64_t len = o1[u] - o0[u];
+    const int32_t first = __shfl(v[u], 0, kCopyLanes);
+    if (len <= kStage && (len == 0 || first != kRowNotParked)) {
+      if (sub < len && o0[u] + sub < A.capacity) A.cols[o0[u] + sub] = v[u];
+      const int32_t* src = A.staging + i * kStage;
+      for (int k = sub + kCopyLanes; k < (int)len; k += kCopyLanes)
+        if (o0[u] + k < A.capacity) A.cols[o0[u] + k] = src[k];
+    } else if (sub == 0 && (len <= kStage || A.qflag[i] != kQueryNormal)) {
+      // long rows of normal queries belong to the wide-row pass of their tile
+      const unsigned long long slot = atomicAdd(&A.stats[kStatLongRows], 1ull);
+      A.long_rows[slot] = (uint32_t)i;
+    }
   }
 }
 
@@ -1421,7 +1437,8 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, h
 hipError_t launch_fill_rows(const StabArgs& a, hipStream_t s) {
   if (a.n1 == 0) return hipSuccess;
   const int64_t blocks = (a.n1 + kWaves - 1) / kWaves;
-  const int64_t cblocks = (a.n1 + kCopyQueries - 1) / kCopyQueries;
+  const int64_t rows_per_block = (int64_t)kCopyQueries * kCopyUnroll;
+  const int64_t cblocks = (a.n1 + rows_per_block - 1) / rows_per_block;
   if (a.qrec)
     hipLaunchKernelGGL(k_write_matches, dim3((unsigned)((a.n1 + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, a);
