@@ -299,6 +299,35 @@ epm_status epm_query_match_bf16(epm_index* idx, const float* kp1_xy, int64_t* ro
                                 hipStream_t stream);
 
 /*
+ * epm_query_match with the image-2 descriptors stored as FP8 (Algorithm 1
+ * matching loop, selection of Sec. 4.3): desc2 holds OCP E4M3FN codes
+ * [N2][128] with one float32 scale per row in scale2 [N2] (dequantised value
+ * = code * scale, as epm_quantize writes them), err2 [N2] a bound on the
+ * norm of each row's rounding error |x - code * scale| (as epm_rounding_error
+ * writes it from the masters), and desc1_f32 / desc2_f32 [N][128] the FP32
+ * masters.  The queries are rounded to BF16 on chip from their masters.
+ * Every query's hits are scored on MFMA against the FP8 rows of its tile's
+ * window (decoded exactly to BF16) while they are on chip; each score gives
+ * certified lower and upper bounds on the exact canonical FP32 distance of
+ * the masters (err2 for the image-2 row, the measured rounding error of the
+ * query row, the FP32 accumulation bound), and only the candidates whose
+ * lower bound is not above the row's second-smallest upper bound are
+ * evaluated exactly on the masters.  Outputs -- the CSR with the capacity and
+ * nnz_host contract of epm_query_candidates, best_idx / best_dist /
+ * second_dist -- are identical to epm_query_candidates + epm_match(EPM_F32)
+ * on the masters whenever err2 bounds the rounding errors; rows whose bounds
+ * cannot be certified are matched exactly (counted by epm_get_match_stats).
+ * desc2, scale2, err2 and desc2_f32 may be NULL only when N2 = 0.
+ * Errors: EPM_ERR_ARG, EPM_ERR_CAPACITY, EPM_ERR_HIP.
+ */
+epm_status epm_query_match_fp8(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                               int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                               const uint8_t* desc2, const float* scale2, const float* err2,
+                               const float* desc1_f32, const float* desc2_f32, float ratio,
+                               int32_t* best_idx, float* best_dist, float* second_dist,
+                               hipStream_t stream);
+
+/*
  * Allocation-free form of epm_build_intervals followed by epm_query_match,
  * for callers that cannot allocate device memory or hand over a workspace
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -600,7 +629,7 @@ typedef struct {
   int64_t reranked_rows;  /* rows ranked on MFMA bounds with a few candidates re-ranked */
   int64_t fallback_rows;  /* of those, not certified: every candidate evaluated exactly */
   int64_t long_rows;      /* rows beyond a tile's 8192-entry list: evaluated exactly  */
-  int64_t exact_distances; /* epm_query_match_bf16: exact FP32 distances of the re-rank */
+  int64_t exact_distances; /* epm_query_match_bf16 / _fp8: exact FP32 distances of the re-rank */
 } epm_match_stats;
 
 /*

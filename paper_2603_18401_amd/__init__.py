@@ -43,7 +43,8 @@ EXPORTS = ["epm_workspace_bytes", "epm_build_intervals", "epm_query_candidates",
            "epm_eps_grad", "epm_eps_adam", "epm_match_residuals", "epm_query_match",
            "epm_index_set_timing_events", "epm_index_set_timing_kernel", "epm_quantize",
            "epm_mutual_check", "epm_gms_workspace_bytes", "epm_gms", "epm_query_match_noalloc",
-           "epm_query_match_bf16", "epm_descriptor_distances", "epm_rounding_error",
+           "epm_query_match_bf16", "epm_query_match_fp8", "epm_descriptor_distances",
+           "epm_rounding_error",
            "epm_pose_eps_workspace_bytes", "epm_pose_eps"]
 
 
@@ -211,6 +212,9 @@ def load_library(path=None):
     lib.epm_query_match_bf16.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, V, V, f32,
                                          V, V, V, V]
     lib.epm_query_match_bf16.restype = ctypes.c_int
+    lib.epm_query_match_fp8.argtypes = [V, V, V, V, i64, ctypes.POINTER(i64), V, V, V, V, V,
+                                        f32, V, V, V, V]
+    lib.epm_query_match_fp8.restype = ctypes.c_int
     lib.epm_index_set_timing_events.argtypes = [V, V, V]
     lib.epm_index_set_timing_events.restype = ctypes.c_int
     lib.epm_index_set_timing_kernel.argtypes = [V, i32]
@@ -424,6 +428,55 @@ class Index:
             col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
             st = call(col_indices, ctypes.byref(nnz))
         _check(st, "epm_query_match_bf16")
+        return row_offsets, col_indices[: nnz.value], best, bd, sd
+
+    def query_match_fp8(self, kp1, desc2, scale2, err2, desc1_f32, desc2_f32, ratio=0.0,
+                        capacity=None, row_offsets=None, col_indices=None, out=None,
+                        sync=True):
+        """epm_query_match_fp8: the candidate CSR and the matches of the FP32
+        masters, selected through MFMA bounds over FP8 image-2 rows (desc2:
+        uint8 E4M3FN codes [N2, 128] with float32 scales scale2 [N2] and
+        rounding-error bounds err2 [N2], see rounding_error).
+        Returns (row_offsets, col_indices, best_idx, best_dist, second_dist)."""
+        torch = self._torch
+        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
+            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
+        for name, t, shape, dt in (("desc2", desc2, (self.n2, 128), torch.uint8),
+                                   ("scale2", scale2, (self.n2,), torch.float32),
+                                   ("err2", err2, (self.n2,), torch.float32),
+                                   ("desc1_f32", desc1_f32, (self.n1, 128), torch.float32),
+                                   ("desc2_f32", desc2_f32, (self.n2, 128), torch.float32)):
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} {list(shape)} device tensor")
+        dev = self.device
+        if row_offsets is None:
+            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
+        if col_indices is None:
+            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
+            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if out is None:
+            out = (torch.empty(self.n1, dtype=torch.int32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev),
+                   torch.empty(self.n1, dtype=torch.float32, device=dev))
+        best, bd, sd = out
+        st_ptr = _stream(torch, dev, self.stream)
+
+        def call(cols, nnz_ref):
+            return self.lib.epm_query_match_fp8(self.handle, _dptr(kp1), _dptr(row_offsets),
+                                                _dptr(cols), cols.numel(), nnz_ref,
+                                                _dptr(desc2), _dptr(scale2), _dptr(err2),
+                                                _dptr(desc1_f32), _dptr(desc2_f32), float(ratio),
+                                                _dptr(best), _dptr(bd), _dptr(sd), st_ptr)
+
+        if not sync:
+            _check(call(col_indices, None), "epm_query_match_fp8")
+            return row_offsets, col_indices, best, bd, sd
+        nnz = ctypes.c_int64(0)
+        st = call(col_indices, ctypes.byref(nnz))
+        if st == 3:
+            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+            st = call(col_indices, ctypes.byref(nnz))
+        _check(st, "epm_query_match_fp8")
         return row_offsets, col_indices[: nnz.value], best, bd, sd
 
     def stats(self):

@@ -560,6 +560,9 @@ struct MatchCall {
   int64_t capacity;  // < 0: trusted
   const float* qerr1 = nullptr;  // measured rounding errors of the reduced rows, or NULL
   const float* qerr2 = nullptr;
+  // FP8 image-2 rows only (epm_query_match_fp8): the queries are their FP32
+  // masters, and the image-2 rows' measured rounding errors are required
+  bool f8_rows2_only = false;
 };
 
 epm_status validate_match(const epm_index* idx, const MatchCall& c) {
@@ -584,7 +587,10 @@ epm_status validate_match(const epm_index* idx, const MatchCall& c) {
   }
   const bool reduced = c.dtype == EPM_BF16 || c.dtype == EPM_FP8_E4M3;
   if (reduced && n1 > 0 && (!c.desc1_f32 || (idx->N2 > 0 && !c.desc2_f32))) return EPM_ERR_ARG;
-  if (c.dtype == EPM_FP8_E4M3 && n1 > 0 && (!c.scale1 || (idx->N2 > 0 && !c.scale2)))
+  if (c.dtype == EPM_FP8_E4M3 && n1 > 0 &&
+      ((!c.scale1 && !c.f8_rows2_only) || (idx->N2 > 0 && !c.scale2)))
+    return EPM_ERR_ARG;
+  if (c.f8_rows2_only && (c.dtype != EPM_FP8_E4M3 || (n1 > 0 && idx->N2 > 0 && !c.qerr2)))
     return EPM_ERR_ARG;
   return EPM_OK;
 }
@@ -737,13 +743,17 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
                                hipEvent_t records_ready = nullptr) {
   const int64_t n1 = idx->N1;
   const bool bf = c.dtype == EPM_BF16;
-  if (!bf && c.dtype != EPM_F32) return EPM_ERR_UNSUPPORTED;
-  // BF16: the codes feed the bounds, the FP32 masters every exact distance
-  // (and the wide-row pass, which rounds them to BF16 on chip itself)
-  A.desc1 = static_cast<const float*>(bf ? c.desc1_f32 : c.desc1);
-  A.desc2 = static_cast<const float*>(bf ? c.desc2_f32 : c.desc2);
+  const bool f8 = c.dtype == EPM_FP8_E4M3 && c.f8_rows2_only;
+  if (!bf && !f8 && c.dtype != EPM_F32) return EPM_ERR_UNSUPPORTED;
+  // BF16 / FP8: the codes feed the bounds, the FP32 masters every exact
+  // distance (and the wide-row pass, which rounds them to BF16 on chip itself)
+  A.desc1 = static_cast<const float*>(bf || f8 ? c.desc1_f32 : c.desc1);
+  A.desc2 = static_cast<const float*>(bf || f8 ? c.desc2_f32 : c.desc2);
   A.codes1 = bf ? static_cast<const uint16_t*>(c.desc1) : nullptr;
   A.codes2 = bf ? static_cast<const uint16_t*>(c.desc2) : nullptr;
+  A.f8codes2 = f8 ? static_cast<const uint8_t*>(c.desc2) : nullptr;
+  A.f8scale2 = f8 ? c.scale2 : nullptr;
+  A.f8err2 = f8 ? c.qerr2 : nullptr;
   A.ratio = c.ratio;
   A.best_idx = c.best_idx;
   A.best_dist = c.best_dist;
@@ -755,7 +765,8 @@ epm_status enqueue_query_match(epm_index* idx, StabArgs& A, int64_t* row_offsets
   idx->match_from_tiles = true;
   idx->match_stream = stream;
   const epm_status st =
-      enqueue_count(idx, A, row_offsets, stream, bf ? kStabBF16 : kStabF32, records_ready);
+      enqueue_count(idx, A, row_offsets, stream, bf ? kStabBF16 : f8 ? kStabFP8 : kStabF32,
+                    records_ready);
   if (st != EPM_OK) return st;
   if (n1 == 0) return EPM_OK;
   idx->last_stream = stream;
@@ -1051,6 +1062,40 @@ epm_status epm_query_match_bf16(epm_index* idx, const float* kp1_xy, int64_t* ro
   c.scale1 = c.scale2 = nullptr;
   c.desc1_f32 = desc1_f32;
   c.desc2_f32 = desc2_f32;
+  c.ratio = ratio;
+  c.best_idx = best_idx;
+  c.best_dist = best_dist;
+  c.second_dist = second_dist;
+  c.algo = EPM_ALGO_TILED;
+  c.capacity = nnz_host ? -1 : capacity;
+  const epm_status v = validate_match(idx, c);
+  if (v != EPM_OK) return v;
+  StabArgs A = stab_args(idx, kp1_xy, row_offsets, col_indices, capacity);
+  return enqueue_query_match(idx, A, row_offsets, nnz_host, c, stream);
+}
+
+epm_status epm_query_match_fp8(epm_index* idx, const float* kp1_xy, int64_t* row_offsets,
+                               int32_t* col_indices, int64_t capacity, int64_t* nnz_host,
+                               const uint8_t* desc2, const float* scale2, const float* err2,
+                               const float* desc1_f32, const float* desc2_f32, float ratio,
+                               int32_t* best_idx, float* best_dist, float* second_dist,
+                               hipStream_t stream) {
+  if (!idx || !row_offsets || capacity < 0) return EPM_ERR_ARG;
+  if (idx->N1 > 0 && !kp1_xy) return EPM_ERR_ARG;
+  if (capacity > 0 && !col_indices) return EPM_ERR_ARG;
+  MatchCall c;
+  c.row_offsets = row_offsets;
+  c.col_indices = col_indices;
+  c.dtype = EPM_FP8_E4M3;
+  c.dim = 128;
+  c.desc1 = desc1_f32;
+  c.desc2 = desc2;
+  c.scale1 = nullptr;
+  c.scale2 = scale2;
+  c.desc1_f32 = desc1_f32;
+  c.desc2_f32 = desc2_f32;
+  c.qerr2 = err2;
+  c.f8_rows2_only = true;
   c.ratio = ratio;
   c.best_idx = best_idx;
   c.best_dist = best_dist;

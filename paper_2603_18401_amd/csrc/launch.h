@@ -122,6 +122,12 @@ struct StabArgs {
   const uint16_t* wcodes2;
   const float2* wterms2;
   unsigned long long* rest_count;  // length of the rest list the wide-row pass appends to
+  // FP8 selection fused into the stabbing pass (kStabFP8): the image-2 rows as
+  // OCP E4M3FN codes [n2][128] with one FP32 scale per row and a bound on the
+  // norm of each row's rounding error (desc1 / desc2 are the FP32 masters)
+  const uint8_t* f8codes2 = nullptr;
+  const float* f8scale2 = nullptr;
+  const float* f8err2 = nullptr;
 };
 
 // Scheduling counters (u32 words of one workspace block).
@@ -165,9 +171,12 @@ hipError_t launch_clear_stats(unsigned long long* stats, hipStream_t s, uint32_t
 // mode kStabBF16: BF16 codes in codes1/codes2 with the FP32 masters in
 // desc1/desc2; the match is selected through certified MFMA bounds and an
 // exact re-rank on the masters (rows it cannot certify go to a.rest).
-constexpr int kStabCount = 0, kStabF32 = 1, kStabBF16 = 2;
+// mode kStabFP8: likewise over the FP8 image-2 rows in f8codes2 (scales
+// f8scale2, rounding-error bounds f8err2); the queries are rounded to BF16 on
+// chip from their masters.
+constexpr int kStabCount = 0, kStabF32 = 1, kStabBF16 = 2, kStabFP8 = 3;
 // chunk: window records staged per round (256, 512 or 1024; 0 = 256 for the
-// BF16 pass, 512 for the others).
+// BF16 and FP8 passes, 512 for the others).
 hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, hipStream_t s);
 constexpr int32_t kMatchDeferred = INT32_MIN;
 // Fill pass after launch_stab_tiles: copies parked rows, rebuilds the

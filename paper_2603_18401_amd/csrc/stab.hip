@@ -471,11 +471,19 @@ constexpr int kBfCopies = (kBfRows * kBfPieces + kWave - 1) / kWave;
 constexpr int kBfRowBytes = kBfCopies * kWave * 16;
 constexpr int kBfKeep = 3;
 static_assert(kBfRows % 16 == 0 && kBfRows <= 64, "the hit mask of a chunk is one 64-bit word");
-// Exact distances a query can list: kBfKeep per lane, four lanes.
-constexpr int kBfQTasks = 4 * kBfKeep;
-// After the pair test the record chunk holds the chunk's row terms and the
-// per-query task lists.
-constexpr int kBfScratch = 3 * kBfRows * 4 + kTileQ * kBfQTasks * 2;
+// MODE kStabFP8: the image-2 rows are 128 one-byte E4M3 codes with a scale
+// per row, staged at a stride of 144 bytes (the padding staggers the rows
+// over the LDS banks).  Their rounding errors are an order of
+// magnitude above BF16's, so more candidates per row fall within the row's
+// second upper bound: each lane keeps six.
+constexpr int kF8Stride = 128 + 16;
+constexpr int kF8Pieces = kF8Stride / 16;
+constexpr int kF8Copies = (kBfRows * kF8Pieces + kWave - 1) / kWave;
+constexpr int kF8RowBytes = kF8Copies * kWave * 16;
+constexpr int kF8Keep = 6;
+// After the pair test the record chunk holds the chunk's row terms (a float4
+// per row) and the per-query task lists (four lanes of `keep` entries).
+constexpr int red_scratch(int keep) { return kBfRows * 16 + kTileQ * 4 * keep * 2; }
 
 // Starts the copy of BF16 rows [c0, c0 + nr) of the window to LDS (stride
 // kBfStride, 0 < nr <= kBfRows); rows past nr and the padding piece repeat
@@ -495,6 +503,55 @@ __device__ __forceinline__ void bf16_stage(const StabArgs& A, int c0, int nr, in
   }
 }
 
+// Starts the copy of FP8 rows [c0, c0 + nr) of the window to LDS (stride
+// kF8Stride, 0 < nr <= kBfRows), as bf16_stage.
+__device__ __forceinline__ void f8_stage(const StabArgs& A, int c0, int nr, int64_t kb,
+                                         const int32_t* sJ, uint8_t* rows, int wave, int lane) {
+  for (int g = wave; g < kF8Copies; g += kWaves) {
+    const int p = g * kWave + lane;
+    int r = p / kF8Pieces;
+    int c = p - r * kF8Pieces;
+    r = r < nr ? r : nr - 1;
+    c = c < 8 ? c : 7;
+    const uint4* src = reinterpret_cast<const uint4*>(A.f8codes2) + (kb + sJ[c0 + r]) * 8 + c;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)(rows + g * kWave * 16),
+                                     16, 0, 0);
+  }
+}
+
+// Eight OCP E4M3FN codes (byte e is element e) as BF16 values.  Every E4M3
+// value has at most four significant bits and an exponent inside BF16's
+// range, so the upper half of the hardware's FP32 decode is the value itself.
+__device__ __forceinline__ bf16x8 e4m3x8_bf16(uint2 v) {
+  const uint32_t src[2] = {v.x, v.y};
+  uint32_t w[4];
+  #pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)src[h], false);  // bytes 0, 1
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)src[h], true);   // bytes 2, 3
+    w[2 * h] = (__float_as_uint(lo[0]) >> 16) | (__float_as_uint(lo[1]) & 0xFFFF0000u);
+    w[2 * h + 1] = (__float_as_uint(hi[0]) >> 16) | (__float_as_uint(hi[1]) & 0xFFFF0000u);
+  }
+  return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+// Sum of the squares of sixteen E4M3 codes (decoded exactly; each square is
+// exact in FP32).
+__device__ __forceinline__ float e4m3x16_sumsq(uint4 v, float acc) {
+  const uint32_t src[4] = {v.x, v.y, v.z, v.w};
+  #pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)src[h], false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)src[h], true);
+    acc = __builtin_fmaf(lo[0], lo[0], acc);
+    acc = __builtin_fmaf(lo[1], lo[1], acc);
+    acc = __builtin_fmaf(hi[0], hi[0], acc);
+    acc = __builtin_fmaf(hi[1], hi[1], acc);
+  }
+  return acc;
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, off);
   const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), off);
@@ -503,42 +560,51 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
 
 
 // Per-lane state of one query's selection with deferred bounds (lane group g
-// of its four lanes): the kBfKeep smallest approximate distances
+// of its four lanes): the K smallest approximate distances
 // A = |q^|^2 + |w^|^2 - 2 q^.w^ seen (FP32, as the bounds take them), with
-// their window positions and their rows' bound norms |w^| rounded up to
-// FP16, the smallest A pushed out of that list and the largest row bound norm
-// seen.  The certified bounds D_lo <= D <= D_hi of the kept candidates, and a
-// lower bound on D_lo of every pushed-out one (D_lo grows with A and shrinks
-// with the row's norm), are worked out once after the last chunk.
+// their window positions and a row bound term rounded up to FP16 (BF16 rows:
+// the bound norm |w^|; FP8 rows: the norm of the row's rounding error), the
+// smallest A pushed out of that list, the largest row bound norm and (FP8)
+// the largest rounding-error term seen.  The certified bounds D_lo <= D <=
+// D_hi of the kept candidates, and a lower bound on D_lo of every pushed-out
+// one (D_lo grows with A and shrinks with the row's norm and error), are
+// worked out once after the last chunk.
 constexpr uint32_t kNoPick = 0xFFFFFFFFu;
+template <int K>
 struct BfKeep {
-  float a[kBfKeep];      // ascending
-  uint32_t pk[kBfKeep];  // window position | FP16 bound norm << 16, kNoPick: empty
+  float a[K];      // ascending
+  uint32_t pk[K];  // window position | FP16 row term << 16, kNoPick: empty
   float a_drop = __builtin_inff();
   float nb_max = 0.0f;
+  uint32_t ew_max = 0u;  // FP16 bits: positive halves order as their bit patterns
   bool bad = false;
 
   __device__ __forceinline__ BfKeep() {
     #pragma unroll
-    for (int t = 0; t < kBfKeep; ++t) {
+    for (int t = 0; t < K; ++t) {
       a[t] = __builtin_inff();
       pk[t] = kNoPick;
     }
   }
 
-  __device__ __forceinline__ void add(float at, uint32_t p, float nb) {
-    static_assert(kBfKeep == 3, "the insertion network keeps three entries");
+  // sorted insertion: entry t moves down one place when A goes before entry
+  // t - 1, takes A when A goes between them, and the last entry drops out
+  __device__ __forceinline__ void add(float at, uint32_t p, float nb, uint32_t ew) {
     bad |= !(at == at);
     nb_max = fmaxf(nb_max, nb);
-    const bool c0 = at < a[0], c1 = at < a[1], c2 = at < a[2];  // c0 => c1 => c2
-    const float out = c2 ? a[2] : at;
-    const bool out_real = c2 ? pk[2] != kNoPick : true;
-    a[2] = c1 ? a[1] : (c2 ? at : a[2]);
-    pk[2] = c1 ? pk[1] : (c2 ? p : pk[2]);
-    a[1] = c0 ? a[0] : (c1 ? at : a[1]);
-    pk[1] = c0 ? pk[0] : (c1 ? p : pk[1]);
-    a[0] = c0 ? at : a[0];
-    pk[0] = c0 ? p : pk[0];
+    ew_max = ew_max > ew ? ew_max : ew;
+    bool c[K];  // c[t] => c[t + 1]
+    #pragma unroll
+    for (int t = 0; t < K; ++t) c[t] = at < a[t];
+    const float out = c[K - 1] ? a[K - 1] : at;
+    const bool out_real = c[K - 1] ? pk[K - 1] != kNoPick : true;
+    #pragma unroll
+    for (int t = K - 1; t > 0; --t) {
+      a[t] = c[t - 1] ? a[t - 1] : (c[t] ? at : a[t]);
+      pk[t] = c[t - 1] ? pk[t - 1] : (c[t] ? p : pk[t]);
+    }
+    a[0] = c[0] ? at : a[0];
+    pk[0] = c[0] ? p : pk[0];
     a_drop = out_real ? fminf(a_drop, out) : a_drop;
   }
 };
@@ -546,8 +612,9 @@ struct BfKeep {
 // Certified bounds on the exact canonical distance of a candidate whose
 // approximate distance is `at` and whose row bound norm is at most nb (query
 // terms q_nb, q_db; see the comment above kBfRows).
-__device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float q_db, float& dlo,
-                                          float& dhi) {
+// ew: a bound on |q - q^| + |w - w^|.
+__device__ __forceinline__ void bounds_from(float at, float nb, float q_nb, float ew, float& dlo,
+                                            float& dhi) {
   const float sum = q_nb + nb;
   const float em = 3e-5f * sum * sum;
   // sqrt(at +- em) from the hardware reciprocal square root (within a few
@@ -557,14 +624,19 @@ __device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float 
   const float tl = at - em;
   const float r_hi = th > 0x1p-100f ? th * __builtin_amdgcn_rsqf(th) * (1.0f + 1e-6f) : 0x1p-50f;
   const float r_lo = tl > 0x1p-100f ? tl * __builtin_amdgcn_rsqf(tl) * (1.0f - 1e-6f) : 0.0f;
-  // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
-  const float ew =
-      q_db + nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
   // the 1e-6 r_lo term covers the rounding of the two subtractions
   const float e_lo = fmaxf(r_lo - ew - 1e-6f * r_lo, 0.0f);
   const float e_hi = r_hi + ew;
   dlo = e_lo * e_lo * (1.0f - 3e-5f);
   dhi = e_hi * e_hi * (1.0f + 3e-5f);
+}
+
+// BF16 rows: |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even.
+__device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float q_db, float& dlo,
+                                          float& dhi) {
+  bounds_from(at, nb, q_nb,
+              q_db + nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f,
+              dlo, dhi);
 }
 
 // MODE: kStabCount (count and park rows), kStabF32 (FP32 selection fused),
@@ -574,15 +646,21 @@ __device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float 
 template <bool PERSIST, int MODE, int CH>
 __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
   constexpr bool FUSE = MODE != kStabCount;
+  // BF16 / FP8: MFMA bounds and an exact re-rank on the masters
+  constexpr bool RED = MODE == kStabBF16 || MODE == kStabFP8;
   // record chunk (sC, sH, sXY, sE; sJ too unless FUSE keeps the window's j
   // in sJ_keep), reused for descriptor rows in the match phase
   constexpr int kRecRaw = FUSE ? rec_bytes(CH) - CH * 4 : rec_bytes(CH);
-  constexpr int kMatchRaw = MODE == kStabF32 ? kFuseBytes : MODE == kStabBF16 ? kBfScratch : 0;
+  constexpr int kMatchRaw = MODE == kStabF32    ? kFuseBytes
+                           : MODE == kStabBF16 ? red_scratch(kBfKeep)
+                           : MODE == kStabFP8  ? red_scratch(kF8Keep)
+                                               : 0;
   constexpr int kRaw = kMatchRaw > kRecRaw ? kMatchRaw : kRecRaw;
   __shared__ __attribute__((aligned(16))) unsigned char raw[kRaw];
-  // BF16: the window's BF16 rows, kBfRows at a time (the first chunk is
-  // copied in while the pair test runs)
-  __shared__ __attribute__((aligned(16))) uint8_t bfrows[MODE == kStabBF16 ? kBfRowBytes : 16];
+  // BF16 / FP8: the window's reduced rows, kBfRows at a time (the first
+  // chunk is copied in while the pair test runs)
+  __shared__ __attribute__((aligned(16)))
+  uint8_t bfrows[MODE == kStabBF16 ? kBfRowBytes : MODE == kStabFP8 ? kF8RowBytes : 16];
   __shared__ int32_t sJ_keep[FUSE ? kKeepJ : 1];
   uint32_t* sC = reinterpret_cast<uint32_t*>(raw);
   uint32_t* sH = sC + CH;
@@ -681,6 +759,20 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
     bf16x8 bq[4];
     uint4 qcode[4];
     float4 qx[8];
+    // FP8: the master's values at the B operand's dimensions, rounded to
+    // BF16 after the pair test (the quarter for the exact chains is loaded
+    // then, behind the first chunk)
+    float4 qraw[8];
+    if constexpr (MODE == kStabFP8) {
+      const int g = lane >> 4;
+      const bool ld = line_live && lq < T.count && fusable;
+      const float4* m = reinterpret_cast<const float4*>(A.desc1) + qidx[lq] * 32;
+      #pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        qraw[2 * kk] = ld ? m[kk * 8 + g * 2] : make_float4(0.f, 0.f, 0.f, 0.f);
+        qraw[2 * kk + 1] = ld ? m[kk * 8 + g * 2 + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
     if constexpr (MODE == kStabBF16) {
       const int g = lane >> 4;
       const bool ld = line_live && lq < T.count && fusable;
@@ -717,11 +809,15 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           sJ_keep[virt] = A.rj[pos];
       }
       __syncthreads();
-      if constexpr (MODE == kStabBF16) {
-        // the first BF16 rows of the window go to LDS behind the pair test
-        if (base == 0 && fusable && total_len > 0)
-          bf16_stage(A, 0, total_len < kBfRows ? (int)total_len : kBfRows, pd.k_begin, sJ_keep,
-                     bfrows, wave, lane);
+      if constexpr (RED) {
+        // the first reduced rows of the window go to LDS behind the pair test
+        if (base == 0 && fusable && total_len > 0) {
+          const int nr0 = total_len < kBfRows ? (int)total_len : kBfRows;
+          if constexpr (MODE == kStabFP8)
+            f8_stage(A, 0, nr0, pd.k_begin, sJ_keep, bfrows, wave, lane);
+          else
+            bf16_stage(A, 0, nr0, pd.k_begin, sJ_keep, bfrows, wave, lane);
+        }
       }
       if (any_live) {
         // this wave's 16 queries (lane & 15) against four records per step
@@ -932,7 +1028,10 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         const bool empty = qmode[q] == kQueryEmpty;
         A.qrec[qidx[q]] = query_record(empty ? 0u : cnt[q], A.ratio, best, mine || empty);
       }
-    } else if constexpr (MODE == kStabBF16) {
+    } else if constexpr (RED) {
+      constexpr bool F8 = MODE == kStabFP8;
+      constexpr int kKeep = F8 ? kF8Keep : kBfKeep;
+      constexpr int kQTasks = 4 * kKeep;  // exact distances a query can list
       // lane l of wavefront w: query 16 w + (l & 15), lane group g = l >> 4
       const int q2 = wave * kQPerWave + (lane & (kQPerWave - 1));
       const int g = lane >> 4;
@@ -944,15 +1043,31 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
       // per chunk row: (|w^|^2, bound norm, rounding bound) -- the record
       // chunk is dead -- then the per-query task lists
       float4* w_terms = reinterpret_cast<float4*>(raw);
-      uint16_t* qtask = reinterpret_cast<uint16_t*>(w_terms + kBfRows);  // [kTileQ][kBfQTasks]
+      uint16_t* qtask = reinterpret_cast<uint16_t*>(w_terms + kBfRows);  // [kTileQ][kQTasks]
       // the query's BF16 norm and the measured norm of its rounding error
-      // (x - x^, exact in FP32), summed over its four quarters
+      // (x - x^, exact in FP32), summed over its four quarters (FP8: the
+      // query rounded to BF16 here, to nearest even, into the B operand)
       float qn_part = 0.0f, qe_part = 0.0f;
       #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const uint32_t w[4] = {qcode[kk].x, qcode[kk].y, qcode[kk].z, qcode[kk].w};
-        const float4 xa = qx[2 * kk], xb = qx[2 * kk + 1];
+        const float4 xa = F8 ? qraw[2 * kk] : qx[2 * kk];
+        const float4 xb = F8 ? qraw[2 * kk + 1] : qx[2 * kk + 1];
         const float x[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        uint32_t w[4];
+        if constexpr (F8) {
+          #pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const uint32_t u0 = __float_as_uint(x[2 * h]), u1 = __float_as_uint(x[2 * h + 1]);
+            w[h] = ((u0 + 0x7FFFu + ((u0 >> 16) & 1u)) >> 16) |
+                   ((u1 + 0x7FFFu + ((u1 >> 16) & 1u)) & 0xFFFF0000u);
+          }
+          bq[kk] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+        } else {
+          w[0] = qcode[kk].x;
+          w[1] = qcode[kk].y;
+          w[2] = qcode[kk].z;
+          w[3] = qcode[kk].w;
+        }
         #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const float y = __uint_as_float(e & 1 ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16));
@@ -961,6 +1076,12 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           qe_part = __builtin_fmaf(d, d, qe_part);
         }
       }
+      if constexpr (F8) {
+        const bool ld = mine2;
+        const float4* m = reinterpret_cast<const float4*>(A.desc1) + qi2 * 32 + g * 8;
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) qx[u] = ld ? m[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       qn_part += __shfl_xor(qn_part, 16);
       qe_part += __shfl_xor(qe_part, 16);
       qn_part += __shfl_xor(qn_part, 32);
@@ -968,7 +1089,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
       // per-query bound terms, inflated for the FP32 sums (2^-24 per term)
       const float q_nb = sqrtf(qn_part) * (1.0f + 2e-5f);
       const float q_db = sqrtf(qe_part) * (1.0f + 2e-5f) + 1e-30f;
-      BfKeep st;
+      BfKeep<kKeep> st;
       int cur = g;
       Top2 best;
       uint32_t evals = 0;
@@ -979,7 +1100,10 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           const int nr = wlen - c0 < kBfRows ? wlen - c0 : kBfRows;
           if (c0 > 0) {
             __syncthreads();  // the previous rows are no longer read
-            bf16_stage(A, c0, nr, kb, sJ_keep, bfrows, wave, lane);
+            if constexpr (F8)
+              f8_stage(A, c0, nr, kb, sJ_keep, bfrows, wave, lane);
+            else
+              bf16_stage(A, c0, nr, kb, sJ_keep, bfrows, wave, lane);
           }  // the first rows were started during the pair test
           // this query's hits in the chunk (the row is in ascending window
           // position; each lane resumes where the last chunk left it)
@@ -991,34 +1115,60 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
           }
           hmask |= shfl_xor_u64(hmask, 16);
           hmask |= shfl_xor_u64(hmask, 32);
+          // FP8: the scale and the rounding-error bound of the row whose
+          // terms this thread works out below, read beside the copies
+          float f8s = 1.0f, f8e = 0.0f;
+          if constexpr (F8) {
+            const int r = tid / (kThreads / kBfRows);
+            if (tid % (kThreads / kBfRows) == 0) {
+              const int64_t j = kb + sJ_keep[c0 + (r < nr ? r : nr - 1)];
+              f8s = A.f8scale2[j];
+              f8e = A.f8err2[j];
+            }
+          }
           wait_lds_copies();
           __syncthreads();
           {
             // norms of the chunk's rows: kTpr threads per row
             constexpr int kTpr = kThreads / kBfRows;
             const int r = tid / kTpr, part4 = tid % kTpr;
-            const uint4* rp =
-                reinterpret_cast<const uint4*>(bfrows + r * kBfStride + part4 * (256 / kTpr));
             float sn = 0.0f;
-            #pragma unroll
-            for (int t = 0; t < 16 / kTpr; ++t) {
-              const uint4 c = rp[t];
-              const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+            if constexpr (F8) {
+              static_assert(kTpr * 16 == 128, "sixteen codes per thread");
+              sn = e4m3x16_sumsq(
+                  *reinterpret_cast<const uint4*>(bfrows + r * kF8Stride + part4 * 16), 0.0f);
+            } else {
+              const uint4* rp =
+                  reinterpret_cast<const uint4*>(bfrows + r * kBfStride + part4 * (256 / kTpr));
               #pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                const float y =
-                    __uint_as_float(e & 1 ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16));
-                sn = __builtin_fmaf(y, y, sn);
+              for (int t = 0; t < 16 / kTpr; ++t) {
+                const uint4 c = rp[t];
+                const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+                #pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                  const float y =
+                      __uint_as_float(e & 1 ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16));
+                  sn = __builtin_fmaf(y, y, sn);
+                }
               }
             }
             #pragma unroll
             for (int off = 1; off < kTpr; off <<= 1) sn += __shfl_xor(sn, off);
             if (part4 == 0) {
-              const float nb = sqrtf(sn) * (1.0f + 2e-5f);
-              // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
-              const float db =
-                  nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
-              w_terms[r] = make_float4(sn, nb, db, __uint_as_float(half_up(nb)));
+              if constexpr (F8) {
+                // w^ = s c: |w^|^2 = s^2 |c|^2, and the MFMA scores of the
+                // codes are scaled by s; the last term is the row's
+                // rounding-error bound rounded up to FP16
+                const float wn = sn * (f8s * f8s);
+                const float nb = sqrtf(wn) * (1.0f + 2e-5f);
+                w_terms[r] = make_float4(wn, nb, f8s, __uint_as_float(half_up(f8e)));
+              } else {
+                const float nb = sqrtf(sn) * (1.0f + 2e-5f);
+                // |w - w^| <= u |w^| / (1 - u) for a row rounded to nearest even
+                const float db =
+                    nb * (float)(Fmt<0>::kUnit / (1.0 - Fmt<0>::kUnit) * (1.0 + 1e-6)) + 1e-30f;
+                w_terms[r] = make_float4(sn, nb, db, __uint_as_float(half_up(nb)));
+              }
             }
           }
           __syncthreads();
@@ -1037,8 +1187,13 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               if (ballot(((hmask >> (16 * cb)) & 0xFFFFull) != 0ull) == 0ull) continue;
               #pragma unroll
               for (int kk = 0; kk < 4; ++kk) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(
-                    bfrows + (cb * 16 + arow) * kBfStride + (kk * 32 + g * 8) * 2);
+                bf16x8 a;
+                if constexpr (F8)
+                  a = e4m3x8_bf16(*reinterpret_cast<const uint2*>(
+                      bfrows + (cb * 16 + arow) * kF8Stride + kk * 32 + g * 8));
+                else
+                  a = *reinterpret_cast<const bf16x8*>(bfrows + (cb * 16 + arow) * kBfStride +
+                                                       (kk * 32 + g * 8) * 2);
                 acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[kk], acc[cb], 0, 0, 0);
               }
             }
@@ -1062,22 +1217,28 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
               #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 if (!((slots >> (4 * cb + i)) & 1u)) continue;
-                const float at = (qn_part + wt[i].x) - 2.0f * acc[cb][i];
-                st.add(at, (uint32_t)(c0 + 16 * cb + 4 * i + g) | (__float_as_uint(wt[i].w) << 16),
-                       wt[i].y);
+                const float sc = F8 ? wt[i].z * acc[cb][i] : acc[cb][i];
+                const float at = (qn_part + wt[i].x) - 2.0f * sc;
+                const uint32_t term = __float_as_uint(wt[i].w);
+                st.add(at, (uint32_t)(c0 + 16 * cb + 4 * i + g) | (term << 16), wt[i].y,
+                       F8 ? term : 0u);
               }
             }
           }
         }
         // this lane's bounds: the kept candidates' D_lo and D_hi (two
         // smallest D_hi), and a lower bound on D_lo of the pushed-out ones
-        float klo[kBfKeep];
+        float klo[kKeep];
         float u1 = __builtin_inff(), u2 = __builtin_inff();
         #pragma unroll
-        for (int t = 0; t < kBfKeep; ++t) {
+        for (int t = 0; t < kKeep; ++t) {
           float dlo = __builtin_inff(), dhi = __builtin_inff();
-          if (st.pk[t] != kNoPick)
-            bf_bounds(st.a[t], half_value(st.pk[t] >> 16), q_nb, q_db, dlo, dhi);
+          if (st.pk[t] != kNoPick) {
+            if constexpr (F8)  // the lane's largest row norm for the MFMA term
+              bounds_from(st.a[t], st.nb_max, q_nb, q_db + half_value(st.pk[t] >> 16), dlo, dhi);
+            else
+              bf_bounds(st.a[t], half_value(st.pk[t] >> 16), q_nb, q_db, dlo, dhi);
+          }
           klo[t] = dlo;
           u2 = fminf(u2, fmaxf(u1, dhi));
           u1 = fminf(u1, dhi);
@@ -1085,7 +1246,11 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         float dmin = __builtin_inff();
         if (st.a_drop != __builtin_inff()) {
           float dhi_unused;
-          bf_bounds(st.a_drop, st.nb_max, q_nb, q_db, dmin, dhi_unused);
+          if constexpr (F8)
+            bounds_from(st.a_drop, st.nb_max, q_nb, q_db + half_value(st.ew_max), dmin,
+                        dhi_unused);
+          else
+            bf_bounds(st.a_drop, st.nb_max, q_nb, q_db, dmin, dhi_unused);
         }
         bool bad = st.bad || !(u1 == u1) || !(u2 == u2) || !(dmin == dmin);
         // the row's U2 and smallest dropped bound over its four lanes
@@ -1104,7 +1269,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
         // per query and dealt to its four lanes
         uint32_t tmask = 0u;
         #pragma unroll
-        for (int t = 0; t < kBfKeep; ++t)
+        for (int t = 0; t < kKeep; ++t)
           if (cert && st.pk[t] != kNoPick && klo[t] <= u2) tmask |= 1u << t;
         const uint32_t myn = (uint32_t)__popc(tmask);
         const int qlane = lane & (kQPerWave - 1);
@@ -1112,11 +1277,11 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
                        n2 = (uint32_t)__shfl((int)myn, qlane + 32), n3 = (uint32_t)__shfl((int)myn, qlane + 48);
         const uint32_t before = (g > 0 ? n0 : 0u) + (g > 1 ? n1 : 0u) + (g > 2 ? n2 : 0u);
         const uint32_t qtotal = n0 + n1 + n2 + n3;
-        uint16_t* mylist = qtask + q2 * kBfQTasks;
+        uint16_t* mylist = qtask + q2 * kQTasks;
         {
           uint32_t k = before;
           #pragma unroll
-          for (int t = 0; t < kBfKeep; ++t)
+          for (int t = 0; t < kKeep; ++t)
             if ((tmask >> t) & 1u) mylist[k++] = (uint16_t)(st.pk[t] & 0xFFFFu);
         }
         wave_sync_lds();
@@ -1174,7 +1339,7 @@ __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCoun
     // after adding its share (the match phase has one unless it was skipped);
     // written per tile, summed on the host when they are asked for
     // (the BF16 phase adds its counters after its last barrier: one more)
-    if (!FUSE || MODE == kStabBF16 || !(fusable && total_len > 0)) __syncthreads();
+    if (!FUSE || RED || !(fusable && total_len > 0)) __syncthreads();
     if (A.tile_counts && tid == 0) {
       const uint64_t nb = tile_stats[2];
       unsigned long long* tc = A.tile_counts + (int64_t)tile * kTileCounts;
@@ -1408,6 +1573,7 @@ hipError_t launch_stab_chunk(const StabArgs& a, int grid, int mode, const dim3& 
     case kStabCount: launch_stab_mode<kStabCount, CH>(a, grid, g, s); break;
     case kStabF32: launch_stab_mode<kStabF32, CH>(a, grid, g, s); break;
     case kStabBF16: launch_stab_mode<kStabBF16, CH>(a, grid, g, s); break;
+    case kStabFP8: launch_stab_mode<kStabFP8, CH>(a, grid, g, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1422,10 +1588,12 @@ hipError_t launch_stab_tiles(const StabArgs& a, int grid, int mode, int chunk, h
                              !a.second_dist || !a.rest || !a.qrec))
     return hipErrorInvalidValue;
   if (mode == kStabBF16 && (!a.codes1 || !a.codes2)) return hipErrorInvalidValue;
+  // (FP8: the image-2 pointers are read only through window records, so they
+  // may be NULL when image 2 is empty; the entry point checks them otherwise)
   const dim3 g(grid > 0 ? (grid < a.num_tiles ? grid : a.num_tiles) : a.num_tiles);
-  // default: 256 records for the BF16 pass (its LDS then allows four
-  // workgroups per CU), kChunk otherwise
-  if (chunk == 0) chunk = mode == kStabBF16 ? 256 : kChunk;
+  // default: 256 records for the BF16 and FP8 passes (their LDS then allows
+  // four workgroups per CU), kChunk otherwise
+  if (chunk == 0) chunk = mode == kStabBF16 || mode == kStabFP8 ? 256 : kChunk;
   switch (chunk) {
     case 256: return launch_stab_chunk<256>(a, grid, mode, g, s);
     case 512: return launch_stab_chunk<512>(a, grid, mode, g, s);
