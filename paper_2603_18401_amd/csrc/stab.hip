@@ -593,19 +593,39 @@ struct BfKeep {
     bad |= !(at == at);
     nb_max = fmaxf(nb_max, nb);
     ew_max = ew_max > ew ? ew_max : ew;
-    bool c[K];  // c[t] => c[t + 1]
-    #pragma unroll
-    for (int t = 0; t < K; ++t) c[t] = at < a[t];
-    const float out = c[K - 1] ? a[K - 1] : at;
-    const bool out_real = c[K - 1] ? pk[K - 1] != kNoPick : true;
-    #pragma unroll
-    for (int t = K - 1; t > 0; --t) {
-      a[t] = c[t - 1] ? a[t - 1] : (c[t] ? at : a[t]);
-      pk[t] = c[t - 1] ? pk[t - 1] : (c[t] ? p : pk[t]);
+    if constexpr (K == 3) {  // written out: the compiler keeps it free of branches
+      const bool c0 = at < a[0], c1 = at < a[1], c2 = at < a[2];  // c0 => c1 => c2
+      const float out = c2 ? a[2] : at;
+      const bool out_real = c2 ? pk[2] != kNoPick : true;
+      a[2] = c1 ? a[1] : (c2 ? at : a[2]);
+      pk[2] = c1 ? pk[1] : (c2 ? p : pk[2]);
+      a[1] = c0 ? a[0] : (c1 ? at : a[1]);
+      pk[1] = c0 ? pk[0] : (c1 ? p : pk[1]);
+      a[0] = c0 ? at : a[0];
+      pk[0] = c0 ? p : pk[0];
+      a_drop = out_real ? fminf(a_drop, out) : a_drop;
+    } else {
+      // new entry t: the old one, A, or the old entry t - 1, from the two
+      // comparisons around it (selects only)
+      float na[K];
+      uint32_t np[K];
+      bool prev = false;  // A goes before entry t - 1
+      #pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const bool ct = at < a[t];
+        na[t] = prev ? a[t - (t > 0)] : (ct ? at : a[t]);
+        np[t] = prev ? pk[t - (t > 0)] : (ct ? p : pk[t]);
+        prev = ct;
+      }
+      const float out = prev ? a[K - 1] : at;
+      const bool out_real = prev ? pk[K - 1] != kNoPick : true;
+      a_drop = out_real ? fminf(a_drop, out) : a_drop;
+      #pragma unroll
+      for (int t = 0; t < K; ++t) {
+        a[t] = na[t];
+        pk[t] = np[t];
+      }
     }
-    a[0] = c[0] ? at : a[0];
-    pk[0] = c[0] ? p : pk[0];
-    a_drop = out_real ? fminf(a_drop, out) : a_drop;
   }
 };
 
