@@ -59,3 +59,17 @@ def assert_csr_equal(got, ref, what=""):
     if not np.array_equal(gc, rc):
         bad = np.where(gc != rc)[0]
         raise AssertionError(f"{what}: col_indices differ at {bad[:10]} (of {len(bad)})")
+
+
+def fp8_rows(d):
+    """E4M3FN codes and scales of FP32 rows (synth's encoder) with an upper
+    bound on |x - code * scale| per row, in FP64 from the E4M3FN definition
+    and rounded up to float32: the rounding-error input of the fused FP8 pass."""
+    import synth
+    codes, scale = synth.f32_to_fp8_e4m3(d)
+    deq = synth.fp8_e4m3_to_f32(codes).astype(np.float64) * scale.astype(np.float64)[:, None]
+    err = np.sqrt(((d.astype(np.float64) - deq) ** 2).sum(axis=1)) * (1.0 + 1e-6)
+    err32 = err.astype(np.float32)
+    err32 = np.where(err32.astype(np.float64) < err, np.nextafter(err32, np.float32(np.inf)),
+                     err32).astype(np.float32)
+    return codes, scale, err32

@@ -63,7 +63,8 @@ def test_batch_workload_line(monkeypatch, capsys):
 def test_precision_workload_line(monkeypatch, capsys):
     line = _run(monkeypatch, capsys, ["--workload", "precision", "--steps", "1", "--warmup", "0"])
     assert set(line["paths"]) == {"f32", "f32_plain", "bf16", "fp8", "bf16_measured",
-                                  "fp8_measured", "bin256", "f32_fused", "bf16_fused"}
+                                  "fp8_measured", "bin256", "f32_fused", "bf16_fused",
+                                  "fp8_fused"}
     for name, entry in line["paths"].items():
         if name != "bin256":
             assert entry["identical_to_plain"], name

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import assert_csr_equal, specs_of, torch_gpu
+from tests.gpu_util import assert_csr_equal, fp8_rows, specs_of, torch_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +37,17 @@ def _run_all(pairs, eps, ratio=0.0):
     res = idx.match(o, c, d1, d2, ratio=ratio)
     out["separate"] = [x.cpu().numpy() for x in (o, c) + tuple(res)]
     out["fused"] = [x.cpu().numpy() for x in idx.query_match(kp1, d1, d2, ratio=ratio)]
+    # the BF16 and FP8 selections fused into the stabbing pass (exact on the masters)
+    h1, h2 = b.desc1.reshape(-1, 128), b.desc2.reshape(-1, 128)
+    q1 = g(synth.f32_to_bf16(h1).view(np.int16))
+    q2 = g(synth.f32_to_bf16(h2).view(np.int16))
+    out["fused_bf16"] = [x.cpu().numpy()
+                         for x in idx.query_match_bf16(kp1, q1, q2, d1, d2, ratio=ratio)]
+    if h2.shape[0] > 0:
+        c2, s2, e2 = fp8_rows(h2)
+        out["fused_fp8"] = [x.cpu().numpy()
+                            for x in idx.query_match_fp8(kp1, g(c2), g(s2), g(e2), d1, d2,
+                                                         ratio=ratio)]
     nnz = int(out["separate"][0][-1])
     bt = E.Batch(specs, kp1, kp2, d1, d2, nnz + 8, eps=eps, ratio=ratio)
     bt.launch()

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import assert_csr_equal, oracle_batch, specs_of, torch_gpu
+from tests.gpu_util import assert_csr_equal, fp8_rows, oracle_batch, specs_of, torch_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -29,23 +29,12 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
 
 
-def _fp8_rows(d):
-    """E4M3FN codes, scales and an upper bound on |x - code * scale| per row."""
-    codes, scale = synth.f32_to_fp8_e4m3(d)
-    deq = synth.fp8_e4m3_to_f32(codes).astype(np.float64) * scale.astype(np.float64)[:, None]
-    err = np.sqrt(((d.astype(np.float64) - deq) ** 2).sum(axis=1)) * (1.0 + 1e-6)
-    err32 = err.astype(np.float32)
-    err32 = np.where(err32.astype(np.float64) < err, np.nextafter(err32, np.float32(np.inf)),
-                     err32).astype(np.float32)
-    return codes, scale, err32
-
-
 def _fused_fp8(pairs, eps, ratio=0.0, desc=None, err_scale=1.0):
     import paper_2603_18401_amd as E
     torch = torch_gpu()
     b = synth.batch_pairs(pairs)
     d1, d2 = (b.desc1, b.desc2) if desc is None else desc
-    codes, scale, err = _fp8_rows(d2)
+    codes, scale, err = fp8_rows(d2)
     idx = E.Index(specs_of(pairs), _dev(torch, b.kp2), eps=eps)
     o, c, bi, bd, sd = idx.query_match_fp8(_dev(torch, b.kp1), _dev(torch, codes),
                                            _dev(torch, scale),
@@ -77,7 +66,7 @@ def test_rounding_error_bounds_hold():
     """The NumPy error bound is not below the FP64 error of any row (a check
     of the test's own input, against the decode of the E4M3FN definition)."""
     p = synth.cfg0_pair(0)
-    codes, scale, err = _fp8_rows(p.desc2)
+    codes, scale, err = fp8_rows(p.desc2)
     deq = synth.fp8_e4m3_to_f32(codes).astype(np.float64) * scale[:, None]
     exact = np.sqrt(((p.desc2.astype(np.float64) - deq) ** 2).sum(axis=1))
     assert np.all(err.astype(np.float64) >= exact)
@@ -177,7 +166,7 @@ def test_fp8_entry_rejects_missing_error_bounds():
     import paper_2603_18401_amd as E
     torch = torch_gpu()
     p = synth.cfg0_pair(0)
-    codes, scale, err = _fp8_rows(p.desc2)
+    codes, scale, err = fp8_rows(p.desc2)
     idx = E.Index(specs_of([p]), _dev(torch, p.kp2), eps=2.0)
     with pytest.raises(ValueError):
         idx.query_match_fp8(_dev(torch, p.kp1), _dev(torch, codes), _dev(torch, scale),
