@@ -410,7 +410,7 @@ def batch_workload(args):
                  "includes_pair_setup": "on the device, from F in device memory",
                  "autotune": {k: tinfo[k] for k in ("key", "cached")}}
 
-    fp32 = separate = None
+    fp32 = separate = fp8 = None
     if not args.no_separate:
         # ---- the same batch through the FP32 masters (fused FP32 selection)
         def f32_step():
@@ -420,6 +420,24 @@ def batch_workload(args):
         fsec = time_steps(torch, f32_step, args.steps, args.warmup)
         fp32 = {"value": round(N1 / fsec, 1), "ms_per_step": round(fsec * 1e3, 4),
                 "identical_matches": all(torch.equal(a, r) for a, r in zip(out, ref_out))}
+
+        # ---- FP8 image-2 rows (fused FP8 selection; the codes and the rows'
+        # measured rounding errors are made once, outside the timed steps)
+        c2, s2 = E.quantize(m2, "fp8")
+        e2 = E.rounding_error(m2, c2, "fp8", scale=s2)
+        holder = {}
+
+        def f8_step():
+            idx = E.Index(specs, kp2, eps=2.0, workspace=ws)
+            idx.query_match_fp8(kp1, c2, s2, e2, m1, m2, row_offsets=offs, col_indices=cols,
+                                out=out, sync=False)
+            holder["idx"] = idx
+
+        f8sec = time_steps(torch, f8_step, args.steps, args.warmup)
+        fp8 = {"value": round(N1 / f8sec, 1), "ms_per_step": round(f8sec * 1e3, 4),
+               "identical_matches": all(torch.equal(a, r) for a, r in zip(out, ref_out)),
+               "match_stats": holder["idx"].match_stats()}
+        del c2, s2, e2
 
         # ---- separate calls: query, then the BF16 window-kernel match
         def sep_step():
@@ -542,6 +560,7 @@ def batch_workload(args):
             "match_stats": mstats, "query_stats": qstats,
             "graph": graph,
             "fp32_masters_fused": fp32,
+            "fp8_rows_fused": fp8,
             "separate_calls_bf16": separate,
             "plain_gpu": plain,
             "speedup_vs_plain": round((N1 / sec) / plain["value"], 3) if plain else None}

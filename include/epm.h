@@ -462,6 +462,12 @@ typedef struct {
                                 when set, every replay first redoes the pair setup
                                 (epipole, pencil basis) on the device from it, so new
                                 F of the same pairs may be written between replays */
+  const float* err2;         /* EPM_FP8_E4M3 with a tiled algorithm: [N2] bounds on the
+                                image-2 rows' rounding errors, as for
+                                epm_query_match_fp8; when set the graph runs that
+                                fused pass (desc2 / scale2 the FP8 rows, desc1_f32 /
+                                desc2_f32 the masters; desc1 and scale1 unused).
+                                NULL: the separate FP8 match with the format's bound */
 } epm_batch_desc;
 
 typedef struct epm_batch epm_batch;

@@ -100,7 +100,7 @@ class _BatchDesc(ctypes.Structure):
                 ("scale1", _V), ("scale2", _V), ("desc1_f32", _V), ("desc2_f32", _V),
                 ("ratio", ctypes.c_float), ("best_idx", _V), ("best_dist", _V),
                 ("second_dist", _V), ("algo", ctypes.c_int32), ("sched", _Sched),
-                ("F_dev", _V)]
+                ("F_dev", _V), ("err2", _V)]
 
 
 class Sched:
@@ -608,14 +608,16 @@ class Batch:
     Inputs and outputs are fixed device tensors (new contents of the same
     sizes may be written between launches).  F_dev (float64 [P, 9], device):
     when given, every launch redoes the pair setup on the device from it, so
-    new F may be written there between launches.  capacity: length of the CSR
+    new F may be written there between launches.  dtype "fp8" with err2
+    (float32 [N2], the image-2 rows' rounding-error bounds): the fused FP8
+    pass of query_match_fp8 (desc1 may then be None).  capacity: length of the CSR
     column buffer; nnz() reports the total of the last launch and raises
     EpmError(EPM_ERR_CAPACITY) when it did not fit."""
 
     def __init__(self, pairs, kp1, kp2, desc1, desc2, capacity, eps2=None, eps=0.0,
                  dtype="f32", scale1=None, scale2=None, desc1_f32=None, desc2_f32=None,
                  ratio=0.0, algo="auto", sched=None, stream=None, workspace=None,
-                 F_dev=None):
+                 F_dev=None, err2=None):
         torch = _torch()
         self._torch = torch
         self.lib = load_library()
@@ -648,6 +650,7 @@ class Batch:
         ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
         d.desc1, d.desc2, d.scale1, d.scale2 = ptr(desc1), ptr(desc2), ptr(scale1), ptr(scale2)
         d.desc1_f32, d.desc2_f32 = ptr(desc1_f32), ptr(desc2_f32)
+        d.err2 = ptr(err2)
         d.ratio = float(ratio)
         d.best_idx, d.best_dist, d.second_dist = (self.best_idx.data_ptr(),
                                                   self.best_dist.data_ptr(),
@@ -660,7 +663,8 @@ class Batch:
                 raise ValueError("F_dev must be a contiguous float64 [num_pairs, 9] device tensor")
             d.F_dev = F_dev.data_ptr()
         # the graph reads these buffers on every replay
-        self._keep = (kp1, kp2, eps2, desc1, desc2, scale1, scale2, desc1_f32, desc2_f32, F_dev)
+        self._keep = (kp1, kp2, eps2, desc1, desc2, scale1, scale2, desc1_f32, desc2_f32, F_dev,
+                      err2)
         self.stream = stream
         h = ctypes.c_void_p()
         st = self.lib.epm_batch_create(self._pairs, len(self.specs), ctypes.byref(d),

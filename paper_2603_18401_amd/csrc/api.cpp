@@ -1215,6 +1215,13 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
   c.second_dist = d->second_dist;
   c.algo = d->algo;
   c.capacity = d->capacity;
+  // FP8 with the rows' error bounds: the fused FP8 pass (queries as masters)
+  if (d->dtype == EPM_FP8_E4M3 && d->err2 && d->algo != EPM_ALGO_PLAIN) {
+    c.f8_rows2_only = true;
+    c.qerr2 = d->err2;
+    c.desc1 = d->desc1_f32;
+    c.scale1 = nullptr;
+  }
   if (st == EPM_OK) st = validate_match(idx, c);
   if (st == EPM_OK) st = index_upload(idx, stream);
   if (st != EPM_OK) {
@@ -1250,8 +1257,10 @@ epm_status epm_batch_create(const epm_pair* pairs, int32_t num_pairs, const epm_
     if (r == EPM_OK && hipEventRecord(join, cs2) != hipSuccess) r = EPM_ERR_HIP;
     // after the build: the stab arguments name the sorted key buffer it chose
     StabArgs A = stab_args(idx, d->kp1_xy, d->row_offsets, d->col_indices, d->capacity);
-    // FP32 and BF16 on the tiled path: selection fused into the stabbing pass
-    const bool fused = (c.dtype == EPM_F32 || c.dtype == EPM_BF16) && c.algo != EPM_ALGO_PLAIN;
+    // FP32, BF16 and FP8 with error bounds on the tiled path: selection fused
+    // into the stabbing pass
+    const bool fused = (c.dtype == EPM_F32 || c.dtype == EPM_BF16 || c.f8_rows2_only) &&
+                       c.algo != EPM_ALGO_PLAIN;
     if (fused) {
       if (r == EPM_OK) r = enqueue_query_match(idx, A, d->row_offsets, nullptr, c, cs, join);
     } else {

@@ -120,7 +120,7 @@ int main(void) {
   O(epm_batch_desc, eps_scalar); O(epm_batch_desc, row_offsets); O(epm_batch_desc, capacity);
   O(epm_batch_desc, dtype); O(epm_batch_desc, dim); O(epm_batch_desc, desc1);
   O(epm_batch_desc, ratio); O(epm_batch_desc, best_idx); O(epm_batch_desc, algo);
-  O(epm_batch_desc, sched); O(epm_batch_desc, F_dev);
+  O(epm_batch_desc, sched); O(epm_batch_desc, F_dev); O(epm_batch_desc, err2);
   S(epm_pose_prior); O(epm_pose_prior, t); O(epm_pose_prior, cov); O(epm_pose_prior, w1);
   O(epm_pose_prior, zmin); O(epm_pose_prior, zmax);
   O(epm_match_opts, qerr1); O(epm_match_opts, qerr2);

@@ -54,7 +54,7 @@ def test_batch_workload_line(monkeypatch, capsys):
     c = line["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0
     assert line["oracle_check"]["identical"] and line["oracle_check"]["pairs"] == 4
-    for k in ("graph", "fp32_masters_fused", "separate_calls_bf16"):
+    for k in ("graph", "fp32_masters_fused", "fp8_rows_fused", "separate_calls_bf16"):
         assert line[k]["identical_matches"], k
     assert line["step_ms_cold"]["steps"] == 2
     assert line["speedup_vs_plain"] > 1

@@ -171,3 +171,29 @@ def test_fp8_entry_rejects_missing_error_bounds():
     with pytest.raises(ValueError):
         idx.query_match_fp8(_dev(torch, p.kp1), _dev(torch, codes), _dev(torch, scale),
                             _dev(torch, err[:-1]), _dev(torch, p.desc1), _dev(torch, p.desc2))
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_graph_fp8_fused(persistent):
+    """The fused FP8 pass recorded in a batch graph (epm_batch_desc.err2),
+    replayed three times: every replay equals the oracle."""
+    import paper_2603_18401_amd as E
+    torch = torch_gpu()
+    pairs = [synth.cfg3_pair(r, max_kp=3000) for r in range(16)]
+    b = synth.batch_pairs(pairs)
+    ref = _oracle(pairs, 2.0)
+    codes, scale, err = fp8_rows(b.desc2)
+    sched = E.Sched(64, 64, 1) if persistent else E.Sched()
+    log(f"fp8 fused graph, persistent={persistent}")
+    bt = E.Batch(specs_of(pairs), _dev(torch, b.kp1), _dev(torch, b.kp2), None,
+                 _dev(torch, codes), len(ref[1]) + 16, eps=2.0, dtype="fp8",
+                 scale2=_dev(torch, scale), desc1_f32=_dev(torch, b.desc1),
+                 desc2_f32=_dev(torch, b.desc2), err2=_dev(torch, err), sched=sched)
+    for rep in range(3):
+        bt.launch()
+        got = [x.cpu().numpy() for x in bt.outputs()]
+        _same(got, ref, f"replay {rep}")
+    ms = bt.match_stats()
+    log(f"  match stats {ms}")
+    assert ms["reranked_rows"] > 0.9 * len(ref[2])
+    bt.close()
