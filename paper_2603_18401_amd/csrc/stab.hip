@@ -10,7 +10,10 @@
 // the row lengths and parks short rows.  After the scan of the lengths the
 // fill pass copies the parked rows and rebuilds the long rows of brute-force
 // queries one wavefront per query (scan, LDS sort by j); long rows of normal
-// queries are written tile by tile by the wide-row pass.
+// queries are written tile by tile by the wide-row pass.  The tile pass can
+// also select every short row's match (Sec. 4.3) while its hits are on chip:
+// FP32 chains, or MFMA bounds over BF16 or FP8 rows with an exact FP32
+// re-rank.
 #include "device_common.h"
 #include "launch.h"
 #include "match_common.h"
@@ -471,11 +474,16 @@ constexpr int kBfCopies = (kBfRows * kBfPieces + kWave - 1) / kWave;
 constexpr int kBfRowBytes = kBfCopies * kWave * 16;
 constexpr int kBfKeep = 3;
 static_assert(kBfRows % 16 == 0 && kBfRows <= 64, "the hit mask of a chunk is one 64-bit word");
-// MODE kStabFP8: the image-2 rows are 128 one-byte E4M3 codes with a scale
-// per row, staged at a stride of 144 bytes (the padding staggers the rows
-// over the LDS banks).  Their rounding errors are an order of
-// magnitude above BF16's, so more candidates per row fall within the row's
-// second upper bound: each lane keeps six.
+// MODE kStabFP8: the image-2 rows are 128 one-byte E4M3 codes c with a scale
+// s per row (w^ = s c), staged at a stride of 144 bytes (the padding
+// staggers the rows over the LDS banks) and decoded to BF16 for the MFMA,
+// exactly; the queries are rounded to BF16 on chip from their masters (eps_q
+// measured as above).  The score of the codes times s is q^.w^ within the
+// same accumulation bound, |w^|^2 = s^2 |c|^2, and eps_w is the caller's
+// bound on |w - w^| for the row, carried per kept candidate rounded up to
+// FP16 (the accumulation term takes the lane's largest row norm).  These
+// errors are an order of magnitude above BF16's, so more candidates per row
+// fall within the row's second upper bound: each lane keeps six.
 constexpr int kF8Stride = 128 + 16;
 constexpr int kF8Pieces = kF8Stride / 16;
 constexpr int kF8Copies = (kBfRows * kF8Pieces + kWave - 1) / kWave;
@@ -660,8 +668,10 @@ __device__ __forceinline__ void bf_bounds(float at, float nb, float q_nb, float 
 }
 
 // MODE: kStabCount (count and park rows), kStabF32 (FP32 selection fused),
-// kStabBF16 (BF16 bounds with an exact FP32 re-rank, fused).
-// Fused: three workgroups per CU (LDS and registers are sized for it)
+// kStabBF16 / kStabFP8 (BF16 or FP8 image-2 rows: MFMA bounds with an exact
+// FP32 re-rank, fused).
+// Fused: three workgroups per CU (LDS and registers are sized for it; four
+// for kStabBF16)
 // CH: window records staged in LDS per round of the pair test.
 template <bool PERSIST, int MODE, int CH>
 __global__ __launch_bounds__(kThreads, MODE == kStabBF16 ? 4 : MODE != kStabCount ? 3 : 2) void k_stab_tile(StabArgs A) {
