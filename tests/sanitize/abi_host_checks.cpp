@@ -221,6 +221,14 @@ int main() {
     CHECK(epm_query_match(nullptr, a.as<float>(), a.as<int64_t>(), a.as<int32_t>(), 10, &nnz,
                           a.as<float>(), a.as<float>(), 0.0f, a.as<int32_t>(), a.as<float>(),
                           a.as<float>(), nullptr) == EPM_ERR_ARG);
+    CHECK(epm_query_match_bf16(nullptr, a.as<float>(), a.as<int64_t>(), a.as<int32_t>(), 10,
+                               &nnz, a.as<uint16_t>(), a.as<uint16_t>(), a.as<float>(),
+                               a.as<float>(), 0.0f, a.as<int32_t>(), a.as<float>(), a.as<float>(),
+                               nullptr) == EPM_ERR_ARG);
+    CHECK(epm_query_match_fp8(nullptr, a.as<float>(), a.as<int64_t>(), a.as<int32_t>(), 10, &nnz,
+                              a.as<uint8_t>(), a.as<float>(), a.as<float>(), a.as<float>(),
+                              a.as<float>(), 0.0f, a.as<int32_t>(), a.as<float>(), a.as<float>(),
+                              nullptr) == EPM_ERR_ARG);
     CHECK(epm_get_query_stats(nullptr, nullptr) == EPM_ERR_ARG);
     CHECK(epm_get_match_stats(nullptr, nullptr) == EPM_ERR_ARG);
     CHECK(epm_index_set_sched(nullptr, nullptr) == EPM_ERR_ARG);
