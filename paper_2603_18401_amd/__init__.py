@@ -351,11 +351,11 @@ class Index:
         _check(st, "epm_query_candidates")
         return row_offsets, col_indices[: nnz.value]
 
-    def query_match(self, kp1, desc1, desc2, ratio=0.0, capacity=None, row_offsets=None,
-                    col_indices=None, out=None, sync=True):
-        """epm_query_match: the candidate CSR and the FP32 matches in one pass.
-        Returns (row_offsets, col_indices, best_idx, best_dist, second_dist);
-        capacity / sync as in query()."""
+    def _fused_query(self, name, kp1, args, ratio, capacity, row_offsets, col_indices, out,
+                     sync):
+        """The shared body of the fused query calls: output buffers, the call
+        (entry point `name`, descriptor arguments `args` between nnz_host and
+        the ratio), and one retry with a CSR buffer of the reported size."""
         torch = self._torch
         if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
             raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
@@ -371,23 +371,31 @@ class Index:
                    torch.empty(self.n1, dtype=torch.float32, device=dev))
         best, bd, sd = out
         st_ptr = _stream(torch, dev, self.stream)
+        fn = getattr(self.lib, name)
 
         def call(cols, nnz_ref):
-            return self.lib.epm_query_match(self.handle, _dptr(kp1), _dptr(row_offsets),
-                                            _dptr(cols), cols.numel(), nnz_ref, _dptr(desc1),
-                                            _dptr(desc2), float(ratio), _dptr(best), _dptr(bd),
-                                            _dptr(sd), st_ptr)
+            return fn(self.handle, _dptr(kp1), _dptr(row_offsets), _dptr(cols), cols.numel(),
+                      nnz_ref, *[_dptr(a) for a in args], float(ratio), _dptr(best), _dptr(bd),
+                      _dptr(sd), st_ptr)
 
         if not sync:
-            _check(call(col_indices, None), "epm_query_match")
+            _check(call(col_indices, None), name)
             return row_offsets, col_indices, best, bd, sd
         nnz = ctypes.c_int64(0)
         st = call(col_indices, ctypes.byref(nnz))
         if st == 3:
             col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
             st = call(col_indices, ctypes.byref(nnz))
-        _check(st, "epm_query_match")
+        _check(st, name)
         return row_offsets, col_indices[: nnz.value], best, bd, sd
+
+    def query_match(self, kp1, desc1, desc2, ratio=0.0, capacity=None, row_offsets=None,
+                    col_indices=None, out=None, sync=True):
+        """epm_query_match: the candidate CSR and the FP32 matches in one pass.
+        Returns (row_offsets, col_indices, best_idx, best_dist, second_dist);
+        capacity / sync as in query()."""
+        return self._fused_query("epm_query_match", kp1, (desc1, desc2), ratio, capacity,
+                                 row_offsets, col_indices, out, sync)
 
     def query_match_bf16(self, kp1, desc1, desc2, desc1_f32, desc2_f32, ratio=0.0,
                          capacity=None, row_offsets=None, col_indices=None, out=None,
@@ -396,39 +404,9 @@ class Index:
         masters, selected through BF16 MFMA bounds (desc1/desc2: int16 BF16
         codes [N, 128], the round-to-nearest-even values of the masters).
         Returns (row_offsets, col_indices, best_idx, best_dist, second_dist)."""
-        torch = self._torch
-        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
-            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
-        dev = self.device
-        if row_offsets is None:
-            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
-        if col_indices is None:
-            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
-            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-        if out is None:
-            out = (torch.empty(self.n1, dtype=torch.int32, device=dev),
-                   torch.empty(self.n1, dtype=torch.float32, device=dev),
-                   torch.empty(self.n1, dtype=torch.float32, device=dev))
-        best, bd, sd = out
-        st_ptr = _stream(torch, dev, self.stream)
-
-        def call(cols, nnz_ref):
-            return self.lib.epm_query_match_bf16(self.handle, _dptr(kp1), _dptr(row_offsets),
-                                                 _dptr(cols), cols.numel(), nnz_ref,
-                                                 _dptr(desc1), _dptr(desc2), _dptr(desc1_f32),
-                                                 _dptr(desc2_f32), float(ratio), _dptr(best),
-                                                 _dptr(bd), _dptr(sd), st_ptr)
-
-        if not sync:
-            _check(call(col_indices, None), "epm_query_match_bf16")
-            return row_offsets, col_indices, best, bd, sd
-        nnz = ctypes.c_int64(0)
-        st = call(col_indices, ctypes.byref(nnz))
-        if st == 3:
-            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
-            st = call(col_indices, ctypes.byref(nnz))
-        _check(st, "epm_query_match_bf16")
-        return row_offsets, col_indices[: nnz.value], best, bd, sd
+        return self._fused_query("epm_query_match_bf16", kp1,
+                                 (desc1, desc2, desc1_f32, desc2_f32), ratio, capacity,
+                                 row_offsets, col_indices, out, sync)
 
     def query_match_fp8(self, kp1, desc2, scale2, err2, desc1_f32, desc2_f32, ratio=0.0,
                         capacity=None, row_offsets=None, col_indices=None, out=None,
@@ -439,8 +417,6 @@ class Index:
         rounding-error bounds err2 [N2], see rounding_error).
         Returns (row_offsets, col_indices, best_idx, best_dist, second_dist)."""
         torch = self._torch
-        if tuple(kp1.shape) != (self.n1, 2) or kp1.dtype != torch.float32 or not kp1.is_contiguous():
-            raise ValueError("kp1 must be a contiguous float32 [N1, 2] device tensor")
         for name, t, shape, dt in (("desc2", desc2, (self.n2, 128), torch.uint8),
                                    ("scale2", scale2, (self.n2,), torch.float32),
                                    ("err2", err2, (self.n2,), torch.float32),
@@ -448,36 +424,9 @@ class Index:
                                    ("desc2_f32", desc2_f32, (self.n2, 128), torch.float32)):
             if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous {dt} {list(shape)} device tensor")
-        dev = self.device
-        if row_offsets is None:
-            row_offsets = torch.empty(self.n1 + 1, dtype=torch.int64, device=dev)
-        if col_indices is None:
-            cap = int(capacity) if capacity is not None else max(1024, 64 * self.n1)
-            col_indices = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-        if out is None:
-            out = (torch.empty(self.n1, dtype=torch.int32, device=dev),
-                   torch.empty(self.n1, dtype=torch.float32, device=dev),
-                   torch.empty(self.n1, dtype=torch.float32, device=dev))
-        best, bd, sd = out
-        st_ptr = _stream(torch, dev, self.stream)
-
-        def call(cols, nnz_ref):
-            return self.lib.epm_query_match_fp8(self.handle, _dptr(kp1), _dptr(row_offsets),
-                                                _dptr(cols), cols.numel(), nnz_ref,
-                                                _dptr(desc2), _dptr(scale2), _dptr(err2),
-                                                _dptr(desc1_f32), _dptr(desc2_f32), float(ratio),
-                                                _dptr(best), _dptr(bd), _dptr(sd), st_ptr)
-
-        if not sync:
-            _check(call(col_indices, None), "epm_query_match_fp8")
-            return row_offsets, col_indices, best, bd, sd
-        nnz = ctypes.c_int64(0)
-        st = call(col_indices, ctypes.byref(nnz))
-        if st == 3:
-            col_indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
-            st = call(col_indices, ctypes.byref(nnz))
-        _check(st, "epm_query_match_fp8")
-        return row_offsets, col_indices[: nnz.value], best, bd, sd
+        return self._fused_query("epm_query_match_fp8", kp1,
+                                 (desc2, scale2, err2, desc1_f32, desc2_f32), ratio, capacity,
+                                 row_offsets, col_indices, out, sync)
 
     def stats(self):
         """Counters of the last query (dict; waits for its stream)."""
