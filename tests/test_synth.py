@@ -95,3 +95,17 @@ def test_batch_concatenation():
     assert b.kp1.shape[0] == sum(p.m for p in pairs)
     for k, p in enumerate(pairs):
         assert np.array_equal(b.kp2[b.k_begin[k]:b.k_begin[k] + p.n], p.kp2)
+
+
+def test_fp8_rounding_error_bounds_hold():
+    """The FP8 rows' rounding-error bounds that the fused FP8 tests pass in
+    (tests.gpu_util.fp8_rows) are not below the FP64 error of any row and
+    exceed it by no more than their rounding up."""
+    from tests.gpu_util import fp8_rows
+    p = synth.cfg0_pair(0)
+    codes, scale, err = fp8_rows(p.desc2)
+    deq = synth.fp8_e4m3_to_f32(codes).astype(np.float64) * scale[:, None]
+    exact = np.sqrt(((p.desc2.astype(np.float64) - deq) ** 2).sum(axis=1))
+    assert err.dtype == np.float32 and codes.dtype == np.uint8
+    assert np.all(err.astype(np.float64) >= exact)
+    assert np.all(err.astype(np.float64) <= exact * (1 + 1e-5) + 1e-30)
