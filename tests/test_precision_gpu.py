@@ -160,3 +160,40 @@ def test_descriptor_distance_error_against_fp64(cfg2):
         em = 3e-5 * (nq + nw) ** 2
         env = 2 * np.sqrt(d64) * (dq + dw) + (dq + dw) ** 2 + em
         assert (np.abs(approx.astype(np.float64) - d64) <= env).all(), name
+
+
+@pytest.mark.parametrize("ratio", [0.0, 0.8])
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_fused_reduced_precision_full_size(cfg2, fmt, ratio):
+    """The BF16 and FP8 selections fused into the stabbing pass at the
+    60000-keypoint pair: CSR and matches equal the oracle's, and at least
+    90 % of the rows are certified by their bounds (FP8 with the rows'
+    measured rounding errors, computed here in NumPy)."""
+    import paper_2603_18401_amd as E
+    from tests.gpu_util import fp8_rows
+    torch = torch_gpu()
+    p, ro, rc = cfg2
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    idx = E.Index([E.PairSpec(p.F, p.W, p.H, p.m, p.n)], g(p.kp2), eps=2.0)
+    m1, m2 = g(p.desc1), g(p.desc2)
+    log(f"fused {fmt} at 60000 keypoints, ratio={ratio}")
+    if fmt == "bf16":
+        res = idx.query_match_bf16(g(p.kp1), g(synth.f32_to_bf16(p.desc1).view(np.int16)),
+                                   g(synth.f32_to_bf16(p.desc2).view(np.int16)), m1, m2,
+                                   ratio=ratio)
+    else:
+        c2, s2, e2 = fp8_rows(p.desc2)
+        res = idx.query_match_fp8(g(p.kp1), g(c2), g(s2), g(e2), m1, m2, ratio=ratio)
+    torch.cuda.synchronize()
+    offs, cols, bi, bd, sd = [x.cpu().numpy() for x in res]
+    st = idx.match_stats()
+    log(f"  match stats {st}")
+    assert_csr_equal((offs, cols), (ro, rc), f"{fmt} csr")
+    rb, rbd, rsd = oracle.match(p.desc1, p.desc2, ro, rc, ratio=ratio)
+    assert np.array_equal(bi, rb)
+    assert np.array_equal(bd.view(np.uint32), rbd.view(np.uint32))
+    assert np.array_equal(sd.view(np.uint32), rsd.view(np.uint32))
+    assert st["reranked_rows"] > 0.9 * p.m
+    assert st["fallback_rows"] < 0.1 * st["reranked_rows"]
+    assert st["exact_distances"] < (0.1 if fmt == "bf16" else 0.2) * len(rc)
