@@ -9,6 +9,10 @@
 // Per 8-bit pass: k_sort_hist (per-tile digit counts), k_sort_offsets (one
 // workgroup per segment turns the counts into global start offsets, in place)
 // and k_sort_scatter (stable ranking with wavefront ballots, then the write).
+// Workgroups take their tiles through xcd_tile: groups of consecutive tiles
+// run on one XCD, so the short digit runs that neighbouring tiles of a
+// segment write side by side in every bucket meet in one L2 before they are
+// written back.
 // When no segment has more than kFusedTiles tiles, a pass is one launch:
 // k_sort_pass finds its tile's offsets from the per-tile counts of its
 // segment itself and, while writing, counts the next pass's digits into the
@@ -33,15 +37,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
                                                             int zero_passes) {
   __shared__ uint32_t h[kRadix];
   const int tid = threadIdx.x;
+  const int tb = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // this workgroup's tile
   h[tid] = 0;
   for (int p = 1; p <= zero_passes; ++p)
-    hist[((int64_t)p * gridDim.x + blockIdx.x) * kRadix + tid] = 0u;
+    hist[((int64_t)p * gridDim.x + tb) * kRadix + tid] = 0u;
   __syncthreads();
-  const SortTile t = tiles[blockIdx.x];
+  const SortTile t = tiles[tb];
   for (int k = tid; k < t.count; k += kSortThreads)
     atomicAdd(&h[(keys[t.begin + k] >> shift) & (kRadix - 1)], 1u);
   __syncthreads();
-  hist[(int64_t)blockIdx.x * kRadix + tid] = h[tid];
+  hist[(int64_t)tb * kRadix + tid] = h[tid];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_offsets(const SortSeg* __restrict__ segs,
@@ -95,8 +100,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   __shared__ uint32_t run[kRadix];
   __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const SortTile t = tiles[blockIdx.x];
-  run[tid] = offs[(int64_t)blockIdx.x * kRadix + tid];
+  const int tb = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const SortTile t = tiles[tb];
+  run[tid] = offs[(int64_t)tb * kRadix + tid];
   for (int base = 0; base < t.count; base += kSortThreads) {
     const int idx = base + tid;
     const bool valid = idx < t.count;
@@ -154,7 +160,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
   __shared__ uint32_t wsum[kWavesPerBlock];
   __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const SortTile t = tiles[blockIdx.x];
+  const int tb = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const SortTile t = tiles[tb];
   const SortSeg sg = segs[t.seg];
   static_assert(kSortThreads == kRadix, "one digit per thread");
   // the tile's keys and values, loaded while the offsets are worked out
@@ -166,9 +173,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     rk[r] = idx < t.count ? kin[t.begin + idx] : 0u;
     rv[r] = idx < t.count ? vin[t.begin + idx] : 0u;
   }
-  const int mine = (int)blockIdx.x - sg.tile_begin;
+  const int mine = tb - sg.tile_begin;
   if constexpr (READY) {
-    run[tid] = hist[(int64_t)blockIdx.x * kRadix + tid];
+    run[tid] = hist[(int64_t)tb * kRadix + tid];
     __syncthreads();
   } else {
     // digit d = tid: count in the segment's earlier tiles, and in all of them
