@@ -302,7 +302,9 @@ __global__ __launch_bounds__(256) void k_gather_records(
     int32_t* __restrict__ rj, float2* __restrict__ rxy, float* __restrict__ reps,
     uint32_t* __restrict__ rinv, const uint32_t* __restrict__ digit_base,
     int64_t* __restrict__ class_begin) {
-  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // blocks of neighbouring sorted positions run on one XCD (xcd_tile): the
+  // scattered reads and rinv writes of a pair's records then meet in one L2
+  const int64_t pos = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
   if (digit_base && pos < (int64_t)num_pairs * kClassSlots) {
     // the start of width class c of pair p: the last radix pass's digit
     // (class, top centre bits) starts, as the sort left them
