@@ -24,7 +24,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Offsets of every device buffer inside the caller's workspace.
 struct Layout {
-  size_t pairs, qstart, kstart, rtiles, rsegs, qtiles, qsegs, stiles, hist, qhist;
+  size_t pairs, qstart, kstart, rsegs, qsegs, stile_begin, head_end, rtiles, qtiles, stiles, hist,
+      qhist;
   size_t rk0, rv0, rk1, rv1, recC, recH, rC, rH, rj, rxy, reps, rinv, class_begin;
   size_t qkey, qflag, qk0, qv0, qk1, qv1, counts, qrec, partials, staging, stats, long_rows;
   size_t digit_base, windows, match_stats, sched, tile_cost, order, block_tile, rest, tile_wide,
@@ -41,13 +42,17 @@ Layout make_layout(int P, int64_t n1, int64_t n2, int64_t tr, int64_t tq, int64_
     return o;
   };
   const size_t N1 = (size_t)n1, N2 = (size_t)n2;
+  // the host tables (one upload), then the tile lists made from them on the
+  // device
   L.pairs = take(sizeof(PairDev) * P);
   L.qstart = take(sizeof(int64_t) * (P + 1));
   L.kstart = take(sizeof(int64_t) * (P + 1));
-  L.rtiles = take(sizeof(SortTile) * tr);
   L.rsegs = take(sizeof(SortSeg) * P);
-  L.qtiles = take(sizeof(SortTile) * tq);
   L.qsegs = take(sizeof(SortSeg) * P);
+  L.stile_begin = take(sizeof(int32_t) * (P + 1));
+  L.head_end = off;
+  L.rtiles = take(sizeof(SortTile) * tr);
+  L.qtiles = take(sizeof(SortTile) * tq);
   L.stiles = take(sizeof(StabTile) * ts);
   // per-tile digit counts of every pass of the record (3) and of the query
   // (2) sort: separate, so that the two sorts may run side by side
@@ -238,6 +243,7 @@ struct epm_index {
   int P = 0;
   int64_t N1 = 0, N2 = 0;
   std::vector<PairDev> pairs;
+  std::vector<int32_t> stile_begin;  // first stabbing tile of every pair, and the total
   std::vector<int64_t> qstart, kstart;
   std::vector<SortTile> rtiles, qtiles;
   std::vector<SortSeg> rsegs, qsegs;
@@ -313,7 +319,9 @@ epm_status index_prepare(const epm_pair* pairs, int32_t num_pairs, void* workspa
     pd.qtile_begin = idx->qsegs[p].tile_begin;
     pd.qtile_count = idx->qsegs[p].tile_count;
   }
+  idx->stile_begin.resize(num_pairs + 1);
   for (int p = 0; p < num_pairs; ++p) {
+    idx->stile_begin[p] = (int32_t)idx->stiles.size();
     for (int64_t o = 0; o < pairs[p].m; o += kTileQ) {
       StabTile t;
       t.begin = pairs[p].q_begin + o;
@@ -322,6 +330,7 @@ epm_status index_prepare(const epm_pair* pairs, int32_t num_pairs, void* workspa
       idx->stiles.push_back(t);
     }
   }
+  idx->stile_begin[num_pairs] = (int32_t)idx->stiles.size();
   idx->L = make_layout(num_pairs, n1, n2, (int64_t)idx->rtiles.size(), (int64_t)idx->qtiles.size(),
                        (int64_t)idx->stiles.size());
   if (workspace_bytes < idx->L.total) {
@@ -330,26 +339,36 @@ epm_status index_prepare(const epm_pair* pairs, int32_t num_pairs, void* workspa
   }
   idx->ws = static_cast<char*>(workspace);
   const Layout& L = idx->L;
-  // every host table goes up in one copy: they sit at the head of the
-  // workspace, in front of the histogram buffer
-  idx->head.assign(L.hist, 0);
+  // the host tables go up in one copy: they sit at the head of the
+  // workspace, and the tile lists behind them are made on the device
+  idx->head.assign(L.head_end, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(idx->head.data() + off, src, bytes);
   };
   put(L.pairs, idx->pairs.data(), sizeof(PairDev) * num_pairs);
   put(L.qstart, idx->qstart.data(), sizeof(int64_t) * (num_pairs + 1));
   put(L.kstart, idx->kstart.data(), sizeof(int64_t) * (num_pairs + 1));
-  put(L.rtiles, idx->rtiles.data(), sizeof(SortTile) * idx->rtiles.size());
   put(L.rsegs, idx->rsegs.data(), sizeof(SortSeg) * num_pairs);
-  put(L.qtiles, idx->qtiles.data(), sizeof(SortTile) * idx->qtiles.size());
   put(L.qsegs, idx->qsegs.data(), sizeof(SortSeg) * num_pairs);
-  put(L.stiles, idx->stiles.data(), sizeof(StabTile) * idx->stiles.size());
+  put(L.stile_begin, idx->stile_begin.data(), sizeof(int32_t) * (num_pairs + 1));
   *out = idx;
   return EPM_OK;
 }
 
+// The tile lists, from the uploaded tables (after their upload on `stream`).
+hipError_t expand_tiles(const epm_index* idx, hipStream_t stream) {
+  const Layout& L = idx->L;
+  return launch_expand_tiles(idx->at<SortSeg>(L.rsegs), idx->at<SortSeg>(L.qsegs),
+                             idx->at<int64_t>(L.qstart), idx->at<int32_t>(L.stile_begin), idx->P,
+                             idx->at<SortTile>(L.rtiles), (int64_t)idx->rtiles.size(),
+                             idx->at<SortTile>(L.qtiles), (int64_t)idx->qtiles.size(),
+                             idx->at<StabTile>(L.stiles), (int64_t)idx->stiles.size(), stream);
+}
+
 epm_status index_upload(epm_index* idx, hipStream_t stream) {
-  EPM_HIP(hipMemcpyAsync(idx->ws, idx->head.data(), idx->L.hist, hipMemcpyHostToDevice, stream));
+  EPM_HIP(hipMemcpyAsync(idx->ws, idx->head.data(), idx->L.head_end, hipMemcpyHostToDevice,
+                         stream));
+  EPM_HIP(expand_tiles(idx, stream));
   return EPM_OK;
 }
 
@@ -1162,9 +1181,10 @@ epm_status epm_query_match_noalloc(const epm_pair* pairs, int32_t num_pairs, con
     if (D.pending[slot] && hipEventSynchronize(D.uploaded[slot]) != hipSuccess) st = EPM_ERR_HIP;
     if (st == EPM_OK) {
       std::swap(D.head[slot], idx->head);
-      if (hipMemcpyAsync(D.ptr, D.head[slot].data(), idx->L.hist, hipMemcpyHostToDevice,
+      if (hipMemcpyAsync(D.ptr, D.head[slot].data(), idx->L.head_end, hipMemcpyHostToDevice,
                          stream) != hipSuccess ||
-          hipEventRecord(D.uploaded[slot], stream) != hipSuccess)
+          hipEventRecord(D.uploaded[slot], stream) != hipSuccess ||
+          expand_tiles(idx, stream) != hipSuccess)
         st = EPM_ERR_HIP;
       D.pending[slot] = true;
     }

@@ -52,6 +52,13 @@ hipError_t launch_class_bounds(const int64_t* kstart, int num_pairs, const uint3
 // hist: [sort_passes(bits)][num_tiles][256] words; max_seg_tiles: the most
 // tiles of one segment (up to 64 a pass is a single launch).
 int sort_passes(int bits);
+// The sort tiles of the records (tr) and the queries (tq) and the stabbing
+// tiles (ts), filled from the per-pair segments, the query slice starts and
+// each pair's first stabbing tile (num_pairs + 1 entries).
+hipError_t launch_expand_tiles(const SortSeg* rsegs, const SortSeg* qsegs, const int64_t* qstart,
+                               const int32_t* stile_begin, int num_pairs, SortTile* rtiles,
+                               int64_t tr, SortTile* qtiles, int64_t tq, StabTile* stiles,
+                               int64_t ts, hipStream_t s);
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
                                 int num_segs, int max_seg_tiles, uint32_t* hist, int bits,

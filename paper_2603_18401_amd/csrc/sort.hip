@@ -140,6 +140,53 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 constexpr int kFusedTiles = 128;
 
+// The tile lists of the record sort, the query sort and the stabbing pass,
+// filled on the device from the per-pair tables (segments, query slice starts
+// and the first stabbing tile of each pair), so that only those go up from
+// the host; the host builds the same lists for its launch sizes.  One thread
+// per tile: its segment (or pair) is the last one whose first tile is not
+// after it, which skips empty ones.
+__global__ __launch_bounds__(256) void k_expand_tiles(
+    const SortSeg* __restrict__ rsegs, const SortSeg* __restrict__ qsegs,
+    const int64_t* __restrict__ qstart, const int32_t* __restrict__ stile_begin, int num_pairs,
+    SortTile* __restrict__ rtiles, int64_t tr, SortTile* __restrict__ qtiles, int64_t tq,
+    StabTile* __restrict__ stiles, int64_t ts) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < tr + tq) {
+    const bool rec = g < tr;
+    const SortSeg* segs = rec ? rsegs : qsegs;
+    const int64_t t = rec ? g : g - tr;
+    int lo = 0, hi = num_pairs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)segs[mid].tile_begin <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const SortSeg sg = segs[lo];
+    const int64_t o = (t - sg.tile_begin) * kSortTile;
+    SortTile st;
+    st.begin = sg.begin + o;
+    st.count = (int32_t)(sg.count - o < kSortTile ? sg.count - o : kSortTile);
+    st.seg = lo;
+    (rec ? rtiles : qtiles)[t] = st;
+  } else if (g < tr + tq + ts) {
+    const int64_t t = g - tr - tq;
+    int lo = 0, hi = num_pairs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)stile_begin[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t o = (t - stile_begin[lo]) * kTileQ;
+    const int64_t m = qstart[lo + 1] - qstart[lo];
+    StabTile st;
+    st.begin = qstart[lo] + o;
+    st.count = (int32_t)(m - o < kTileQ ? m - o : kTileQ);
+    st.pair = lo;
+    stiles[t] = st;
+  }
+}
+
 // Sorts of more tiles than this take each pass's counts from LDS histograms
 // of the keys (k_sort_hist) and the tile offsets from k_sort_offsets, three
 // launches per pass: at that size the global atomics with which the one-launch
@@ -265,6 +312,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
 }  // namespace
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
+
+hipError_t launch_expand_tiles(const SortSeg* rsegs, const SortSeg* qsegs, const int64_t* qstart,
+                               const int32_t* stile_begin, int num_pairs, SortTile* rtiles,
+                               int64_t tr, SortTile* qtiles, int64_t tq, StabTile* stiles,
+                               int64_t ts, hipStream_t s) {
+  const int64_t n = tr + tq + ts;
+  if (n == 0 || num_pairs < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rsegs,
+                     qsegs, qstart, stile_begin, num_pairs, rtiles, tr, qtiles, tq, stiles, ts);
+  return hipGetLastError();
+}
 
 hipError_t segmented_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                 const SortTile* tiles, int num_tiles, const SortSeg* segs,
